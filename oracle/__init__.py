@@ -1,0 +1,240 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and it
+shares no code with it.  The numerical work is in ``oracle.c`` (plain loops in
+double precision, see its header); this module only marshals numpy arrays and
+writes out the two trivial reductions in numpy:
+
+* the probed imaging condition of Eq. 3, image = scale * sum_i Ubar[i] * Vbar[i]
+  (Section "Approximate gradient calculations"), and
+* the misfit J = 1/2 sum (d - d_obs)^2 with residual res = d - d_obs.
+
+``build()`` compiles ``oracle.c`` with gcc into ``liboracle.so`` beside it.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_long)
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle (gcc, -O2, OpenMP, IEEE double: no fast-math, no FMA)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_forward.restype = ctypes.c_int
+        L.orc_forward.argtypes = [
+            ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+            _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
+            ctypes.c_int, ctypes.c_long, _lp, _dp, _dp, _dp]
+        L.orc_adjoint.restype = ctypes.c_int
+        L.orc_adjoint.argtypes = [
+            ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+            _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
+            ctypes.c_long, _lp, _dp, _dp, _dp, _dp]
+        L.orc_laplacian.restype = None
+        L.orc_laplacian.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long,
+                                    ctypes.c_double, _dp, _dp]
+        L.orc_damping_profile.restype = None
+        L.orc_damping_profile.argtypes = [ctypes.c_long, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+@dataclasses.dataclass(frozen=True)
+class Grid:
+    ndim: int
+    shape: tuple      # (nz, ny, nx), ny == 1 in 2D
+    h: float
+    dt: float
+    nt: int
+    nb: int
+    c_ref: float
+    R: float = 1e-3
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.shape))
+
+    @classmethod
+    def of(cls, wl) -> "Grid":
+        return cls(wl.ndim, tuple(wl.shape), wl.h, wl.dt, wl.nt, wl.nb, wl.c_ref, wl.R)
+
+
+def _d(a):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def laplacian(ndim: int, u: np.ndarray, h: float) -> np.ndarray:
+    """8th-order Laplacian of u[nz][ny][nx] (ny == 1 in 2D), zero outside."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    nz, ny, nx = u.shape
+    out = np.empty_like(u)
+    lib().orc_laplacian(ndim, nz, ny, nx, h, u.ctypes.data_as(_dp), out.ctypes.data_as(_dp))
+    return out
+
+
+def damping_profile(n: int, nb: int, h: float, c_ref: float, R: float) -> np.ndarray:
+    out = np.empty(n, dtype=np.float64)
+    lib().orc_damping_profile(n, nb, h, c_ref, R, out.ctypes.data_as(_dp))
+    return out
+
+
+def forward(g: Grid, m, src_pos, q, rec_pos, Z=None, what: str = "utt", sample_idx=None,
+            hist: bool = False, final: bool = False, want_d: bool = True) -> dict:
+    """Forward sweep.  Returns dict with d [nt][nrec], Ubar [r][M] (if Z given),
+    hist [nt][N] (if hist), final [2][N] = (u^nt, u^{nt-1}) (if final)."""
+    nz, ny, nx = g.shape
+    N = g.N
+    m, mp = _d(np.ravel(m))
+    src, sp = _d(np.reshape(src_pos, (-1, 3)))
+    q, qp = _d(np.reshape(q, (g.nt, -1)))
+    rec, rp = _d(np.reshape(rec_pos, (-1, 3)))
+    assert m.size == N and q.shape[1] == src.shape[0]
+    out = {}
+    d = np.zeros((g.nt, rec.shape[0])) if want_d else None
+    r = 0
+    zp = up = None
+    sidx = None
+    M = N
+    if Z is not None:
+        Zd, zp = _d(Z)
+        r = Zd.shape[1]
+        assert Zd.shape[0] == g.nt
+        if sample_idx is not None:
+            sidx = np.ascontiguousarray(sample_idx, dtype=np.int64)
+            M = sidx.size
+        Ub = np.zeros((r, M))
+        up = Ub.ctypes.data_as(_dp)
+        out["Ubar"] = Ub
+    H = np.zeros((g.nt, N)) if hist else None
+    F = np.zeros((2, N)) if final else None
+    rc = lib().orc_forward(
+        g.ndim, nz, ny, nx, g.h, g.dt, g.nt, g.nb, g.c_ref, g.R, mp, src.shape[0], sp, qp,
+        rec.shape[0], rp, d.ctypes.data_as(_dp) if d is not None else None, r, zp,
+        1 if what == "utt" else 0, M if sidx is not None else 0,
+        sidx.ctypes.data_as(_lp) if sidx is not None else None, up,
+        H.ctypes.data_as(_dp) if H is not None else None,
+        F.ctypes.data_as(_dp) if F is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle forward rejected its input (code {rc})")
+    if d is not None:
+        out["d"] = d
+    if H is not None:
+        out["hist"] = H
+    if F is not None:
+        out["final"] = F
+    return out
+
+
+def adjoint(g: Grid, m, rec_pos, res, src_pos=None, Z=None, sample_idx=None,
+            fwd_hist=None, lam_hist: bool = False) -> dict:
+    """Adjoint sweep driven by res [nt][nrec].  Returns dict with qadj
+    [nt][nsrc] (if src_pos), Vbar [r][M] (if Z), corr [N] = sum_n fwd_hist[n]
+    * lam^n (if fwd_hist), hist [nt][N] (if lam_hist)."""
+    nz, ny, nx = g.shape
+    N = g.N
+    m, mp = _d(np.ravel(m))
+    rec, rp = _d(np.reshape(rec_pos, (-1, 3)))
+    res, resp = _d(np.reshape(res, (g.nt, -1)))
+    assert res.shape[1] == rec.shape[0]
+    out = {}
+    nsrc = 0
+    sp = qa = None
+    if src_pos is not None:
+        src, sp = _d(np.reshape(src_pos, (-1, 3)))
+        nsrc = src.shape[0]
+        qa = np.zeros((g.nt, nsrc))
+        out["qadj"] = qa
+    r = 0
+    zp = vp = None
+    sidx = None
+    M = N
+    if Z is not None:
+        Zd, zp = _d(Z)
+        r = Zd.shape[1]
+        if sample_idx is not None:
+            sidx = np.ascontiguousarray(sample_idx, dtype=np.int64)
+            M = sidx.size
+        Vb = np.zeros((r, M))
+        vp = Vb.ctypes.data_as(_dp)
+        out["Vbar"] = Vb
+    fh = fhp = corr = None
+    if fwd_hist is not None:
+        fh, fhp = _d(fwd_hist)
+        corr = np.zeros(N)
+        out["corr"] = corr
+    H = np.zeros((g.nt, N)) if lam_hist else None
+    rc = lib().orc_adjoint(
+        g.ndim, nz, ny, nx, g.h, g.dt, g.nt, g.nb, g.c_ref, g.R, mp, rec.shape[0], rp, resp,
+        nsrc, sp, qa.ctypes.data_as(_dp) if qa is not None else None, r, zp,
+        M if sidx is not None else 0, sidx.ctypes.data_as(_lp) if sidx is not None else None,
+        vp, fhp, corr.ctypes.data_as(_dp) if corr is not None else None,
+        H.ctypes.data_as(_dp) if H is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle adjoint rejected its input (code {rc})")
+    if H is not None:
+        out["hist"] = H
+    return out
+
+
+def image(Ubar: np.ndarray, Vbar: np.ndarray, scale: float) -> np.ndarray:
+    """Eq. 3: scale * sum over probes of Ubar[i] * Vbar[i] (per cell)."""
+    return scale * (np.asarray(Ubar, np.float64) * np.asarray(Vbar, np.float64)).sum(axis=0)
+
+
+def misfit(d: np.ndarray, d_obs: np.ndarray):
+    res = np.asarray(d, np.float64) - np.asarray(d_obs, np.float64)
+    return 0.5 * float((res * res).sum()), res
+
+
+def exact_gradient(g: Grid, m, src_pos, q, rec_pos, d_obs):
+    """Eq. 2 with the full history: J and g = -sum_n (d2u/dt2)^n * lam^n."""
+    f = forward(g, m, src_pos, q, rec_pos, what="utt", hist=True)
+    J, res = misfit(f["d"], d_obs)
+    a = adjoint(g, m, rec_pos, res, fwd_hist=f["hist"])
+    return J, -a["corr"]
+
+
+def probed_gradient(g: Grid, m, src_pos, q, rec_pos, d_obs, Z, sample_idx=None):
+    """Eq. 3: J and g_r = -(1/r) sum_i Ubar[i] * Vbar[i], Ubar probing d2u/dt2."""
+    f = forward(g, m, src_pos, q, rec_pos, Z=Z, what="utt", sample_idx=sample_idx)
+    J, res = misfit(f["d"], d_obs)
+    a = adjoint(g, m, rec_pos, res, Z=Z, sample_idx=sample_idx)
+    r = np.shape(Z)[1]
+    return J, image(f["Ubar"], a["Vbar"], -1.0 / r), f, a
