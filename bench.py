@@ -1,0 +1,163 @@
+"""Throughput of the probed FWI gradient on one MI355X.
+
+One step = one whole pass of the hot path over the 3D layered workload:
+forward sweep (FP32 8th-order stencil, source injection, receiver sampling,
+BF16X2 MFMA probing of u_tt every k steps), residual + FP64 misfit, adjoint
+sweep (receiver injection, probing of the adjoint field), probed imaging
+condition.  Workload: 384 x 512 x 512 cells (z, y, x) incl. 10 damping cells
+per face, h = 12.5 m, nt = 3000, dt = 1 ms, 12 layers 1.5-4.5 km/s with +-5 %
+perturbation, one shot, 512 x 512 receiver plane, r = 128 Rademacher probes,
+k = 32 (synthetic inputs, seeded).
+
+value = 2 N nt / wall time (Gcell-updates/s, forward + adjoint, inputs resident
+in HBM).  The roofline object covers the dominant kernel, timed with HIP events
+on the sweep's own stream during the timed steps (every --prof-stride-th
+stencil launch, every probe-GEMM launch).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=3000)
+    ap.add_argument("--k-block", type=int, default=32)
+    ap.add_argument("--probe", default="bf16x2", choices=["bf16x2", "bf16", "f32"])
+    ap.add_argument("--prof-stride", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=8)
+    ap.add_argument("--cpu-nt", type=int, default=20)
+    return ap.parse_args()
+
+
+def cpu_baseline(planes: int, nt: int, r: int):
+    """The FP64 oracle, as it stands, on a z-slab of the same model: `planes`
+    x 512 x 512 cells, `nt` steps, forward + adjoint with r-probe compression
+    and the probed image (Gcell-updates/s)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    wl = synth.workload_c2(nt=nt, r=r, shape=(planes, 512, 512))
+    g = oracle.Grid(3, wl.shape, wl.h, wl.dt, nt, min(wl.nb, (planes - 1) // 2), wl.c_ref, wl.R)
+    src = np.array([[planes // 2, 256.0, 256.0]])
+    rec = synth.plane_receivers(planes // 2 + 1, 512, 512)
+    d_obs = np.zeros((nt, rec.shape[0]))
+    t0 = time.perf_counter()
+    oracle.probed_gradient(g, wl.m, src, wl.q, rec, d_obs, wl.Z)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * g.N * nt / dt / 1e9, "unit": "Gcell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, {planes}x512x512 z-slab of the same model, nt={nt}, "
+                      f"r={r}, forward+adjoint with probing + image, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
+                                   "(shot or z-slab sharding across GPUs is not built)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2201_06914_amd as P
+    import synth
+
+    wl = synth.workload_c2(nt=a.nt, k_block=a.k_block)
+    N, nt, r, k = wl.N, wl.nt, wl.r, a.k_block
+    plan = P.Plan.for_workload(wl, field="f32", probe=a.probe, k_block=k)
+    m = torch.from_numpy(wl.m).cuda()
+    q = torch.from_numpy(wl.q).cuda()
+    Z = torch.from_numpy(wl.Z).cuda()
+    d_obs = torch.zeros((nt, wl.rec_pos.shape[0]), dtype=torch.float32, device="cuda")
+    bars = (torch.empty((r, N), dtype=torch.float32, device="cuda"),
+            torch.empty((r, N), dtype=torch.float32, device="cuda"))
+    work = plan.workspace("cuda")
+    src, rec = wl.src_pos, wl.rec_pos
+    del wl
+
+    def step():
+        return P.fwi_gradient(plan, m, src, q, rec, d_obs, Z, work=work, bars=bars)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.profile_enable(a.prof_stride)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.profile_enable(0)
+    st_ms, st_n = P.profile_read("stencil")
+    pr_ms, pr_n = P.profile_read("probe")
+    im_ms, im_n = P.profile_read("image")
+    misfit = float(out["misfit"].item())
+    finite = bool(torch.isfinite(out["grad"]).all().item())
+
+    ms_step = (t1 - t0) / a.steps * 1e3
+    value = 2.0 * N * nt / (ms_step / 1e3) / 1e9
+
+    # algorithmic bytes (FP32 fields, FP32 compressed fields)
+    st_bytes = 16.0 * N                                   # read u^n, u^{n-1}, m; write u^{n+1}
+    nblk = math.ceil(nt / k)
+    kbs = [min(k, nt - b * k) for b in range(nblk)]
+    pr_bytes_step = sum((4.0 * (kb + 2) + 8.0 * r) * N for kb in kbs) + \
+        sum((4.0 * kb + 8.0 * r) * N for kb in kbs)       # forward (u_tt) + adjoint blocks
+    st_avg = st_ms / max(st_n, 1)
+    pr_avg = pr_ms / max(pr_n, 1)
+    st_tot = st_avg * 2 * nt                              # ms per step
+    pr_tot = pr_avg * 2 * nblk
+    st_ach = st_bytes / (st_avg * 1e-3) / 1e9
+    pr_ach = pr_bytes_step * a.steps / (pr_ms * 1e-3) / 1e9 if pr_n else 0.0
+    stencil = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": round(st_ach / HBM_PEAK_GBS, 4), "traffic": None,
+               "kernel": "k_stencil3d_tiled", "avg_launch_us": round(st_avg * 1e3, 2),
+               "launches_timed": st_n, "bytes_per_launch": st_bytes, "ms_per_step": round(st_tot, 1)}
+    probe = {"bound": "hbm", "achieved": round(pr_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(pr_ach / HBM_PEAK_GBS, 4), "traffic": None,
+             "kernel": "k_probe_mfma", "avg_launch_us": round(pr_avg * 1e3, 2),
+             "launches_timed": pr_n, "bytes_per_launch_avg": pr_bytes_step / (2 * nblk),
+             "ms_per_step": round(pr_tot, 1),
+             "mfma_tflops": round((2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 *
+                                  math.ceil(k / 16) * N * 2 * nblk * a.steps /
+                                  (pr_ms * 1e-3) / 1e12, 2) if pr_n else None}
+    dominant, other = (probe, stencil) if pr_tot > st_tot else (stencil, probe)
+    path_bytes = 2 * nt * st_bytes + pr_bytes_step
+    rec_line = {
+        "metric": "Gcell-updates/s fwd+adj w/ probing, %HBM peak; gradient rel. error vs exact",
+        "value": round(value, 2), "unit": "Gcell-updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms_step, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"3d-layered-384x512x512-nt{nt}-r{r}-k{k}", "grid": [384, 512, 512],
+                   "nt": nt, "r": r, "k_block": k, "probe_operand": a.probe, "shots": 1,
+                   "parallelism": "single-gpu"},
+        "roofline": dominant, "roofline_other": other,
+        "hbm_frac_path": round(path_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "grad_rel_err_vs_exact": None,
+        "misfit": misfit, "grad_finite": finite,
+        "image_avg_ms": round(im_ms / max(im_n, 1), 2),
+    }
+    if not a.no_cpu_baseline:
+        del out
+        torch.cuda.empty_cache()
+        rec_line["cpu_baseline"] = cpu_baseline(a.cpu_planes, a.cpu_nt, r)
+    print(json.dumps(rec_line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

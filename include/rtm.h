@@ -1,0 +1,187 @@
+/*
+ * rtm.h - C ABI of librtm, an MI355X (gfx950) library for adjoint-state wave
+ * imaging with randomized trace estimation (Louboutin & Herrmann, "Enabling
+ * wave-based inversion on GPUs with randomized trace estimation").
+ *
+ * The method (Section "Methodology"):
+ *   - Eq. 1: tr(A) ~ (1/r) tr(Z^T A Z) for r random probe vectors (the
+ *     columns of Z, entries +-1).
+ *   - Eq. 2: the single-source gradient is the zero-lag correlation over time
+ *     of the second time derivative of the forward wavefield with the adjoint
+ *     wavefield, sum_t u_tt[t] v[t], cell by cell.
+ *   - Eq. 3: per cell this is a trace, so it is estimated from the compressed
+ *     fields Ubar = Q^T u_tt and Vbar = Q^T v (r rows instead of nt):
+ *     dm[x] ~ (1/r) sum_i Ubar[i][x] Vbar[i][x].  Here Q = Z.
+ *
+ * Discretisation (the paper prints none; this library fixes it):
+ *   2nd order in time, 8th order in space (Fornberg weights, field zero
+ *   outside the grid), a quadratic sponge eta over the nb outermost cells of
+ *   each face, m = slowness^2 (s^2/m^2).  For n = 0..nt-1:
+ *     u^{n+1} = [2 m u^n - (m - eta dt/2) u^{n-1}
+ *                + dt^2 (L u^n + Ps^T q[n])] / (m + eta dt/2),
+ *     d[n]    = Pr u^{n+1},
+ *   with u^{-1} = u^0 = 0.  The adjoint runs the same recursion backwards in
+ *   time, driven by Pr^T res[n], giving lam^n (n = nt-1..0) with
+ *   lam^{nt} = lam^{nt+1} = 0.  The exact gradient of
+ *   J = 1/2 sum_n |d[n] - d_obs[n]|^2 is -sum_n u_tt^n lam^n with
+ *   u_tt^n = (u^{n+1} - 2 u^n + u^{n-1}) / dt^2; probe row n of Z pairs with
+ *   step n in both sweeps.
+ *
+ * Conventions for every entry point:
+ *   - Arrays are C order; a field is [nz][ny][nx] (x fastest, ny = 1 in 2D),
+ *     N = nz*ny*nx cells.  Compressed fields are [r][N]; traces are
+ *     [nt][npoints]; Z is [nt][r].
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory read during the call only.
+ *   - Field-typed arrays (m, q, d, res, Ubar, Vbar, image, grad) have the
+ *     plan's field dtype: double for RTM_F64 plans, float for RTM_F32 plans.
+ *   - Positions are host double [n][3] = (z, y, x) in grid-index units, inside
+ *     [0, n_axis - 1]; off-grid points use multilinear weights and injection
+ *     is the exact transpose of sampling.  In 2D the y component is ignored.
+ *   - Calls are ordered on `stream` and return before the GPU finishes,
+ *     except that a call taking positions first uploads its point tables into
+ *     `work` and waits for that copy (host memory is then free to reuse).
+ *   - The library allocates no device memory: all scratch lives in `work`
+ *     (size from rtm_plan_workspace_bytes).  One workspace serves one call at
+ *     a time; calls on different streams need different workspaces.
+ *   - Errors are returned before any launch; on error nothing is written.
+ *     No exception crosses the ABI.
+ */
+#ifndef RTM_H
+#define RTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *rtm_stream; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  RTM_OK = 0,
+  RTM_E_ARG = 1,         /* NULL pointer, non-positive size or bad enum */
+  RTM_E_SHAPE = 2,       /* inconsistent or too large grid / counts */
+  RTM_E_DTYPE = 3,       /* unsupported dtype combination */
+  RTM_E_CFL = 4,         /* dt * c_max / h above the stability bound */
+  RTM_E_WORKSPACE = 5,   /* work buffer smaller than required */
+  RTM_E_HIP = 6,         /* a HIP runtime call failed */
+  RTM_E_UNSUPPORTED = 7, /* valid request this build does not implement */
+  RTM_E_POINTS = 8       /* a source / receiver position outside the grid */
+} rtm_status;
+
+typedef enum {
+  RTM_F64 = 0,    /* double */
+  RTM_F32 = 1,    /* float */
+  RTM_BF16 = 2,   /* probe operand: bfloat16, round to nearest even */
+  RTM_BF16X2 = 3, /* probe operand: bfloat16 hi + bfloat16 lo split (16-bit mantissa) */
+  RTM_I8 = 4      /* probe matrix entries +-1 stored as int8 */
+} rtm_dtype;
+
+typedef enum {
+  RTM_PROBE_U = 0,  /* forward sweep compresses u^n           */
+  RTM_PROBE_UTT = 1 /* forward sweep compresses u_tt^n (Eq. 2) */
+} rtm_probe_field;
+
+typedef struct {
+  int32_t ndim;         /* 2 or 3 */
+  int64_t nz, ny, nx;   /* computational grid including damping cells; ny = 1 if ndim = 2 */
+  double h;             /* grid spacing (m), equal on every axis */
+  double dt;            /* time step (s) */
+  int32_t nt;           /* number of time steps */
+  int32_t nb;           /* damping cells per face (0 = no sponge) */
+  double c_ref;         /* velocity in the sponge formula (m/s) */
+  double R;             /* nominal sponge reflection coefficient, 0 < R < 1 */
+  double c_max;         /* largest velocity in m, for the CFL check (m/s) */
+  rtm_dtype field_dtype;/* RTM_F64 or RTM_F32: fields, model, traces, outputs */
+  rtm_dtype probe_dtype;/* GEMM operand type: RTM_F64 (F64 fields), RTM_F32,
+                           RTM_BF16 or RTM_BF16X2 (F32 fields; Z must be RTM_I8) */
+  int32_t r;            /* number of probe vectors, 1..1024 */
+  int32_t k_block;      /* time steps per probe-GEMM block, 1..256 */
+  int32_t nsrc;         /* number of source points per call (>= 0) */
+  int32_t nrec;         /* number of receiver points per call (>= 0) */
+} rtm_desc;
+
+typedef struct rtm_plan rtm_plan;
+
+/* Validates `desc` (shapes, dtypes, CFL: dt*c_max/h <= 2/sqrt(ndim*S) with S
+ * the Nyquist symbol of the 8th-order weights) and creates a host-only plan.
+ * No HIP call is made.  Returns RTM_OK and sets *plan, or an error. */
+rtm_status rtm_plan_create(const rtm_desc *desc, rtm_plan **plan);
+void rtm_plan_destroy(rtm_plan *plan);
+/* Bytes of device workspace the plan's entry points need (256-byte aligned). */
+rtm_status rtm_plan_workspace_bytes(const rtm_plan *plan, size_t *bytes);
+/* The CFL bound 2/sqrt(ndim*S) the plan was checked against. */
+double rtm_cfl_bound(int32_t ndim);
+const char *rtm_status_str(rtm_status s);
+/* Tuning hook, process wide: stencil kernel of the sweeps.  -1 automatic
+ * (LDS-tiled for F32 3D grids, else one thread per cell), 0 one thread per
+ * cell, 1 LDS-tiled (3D only).  Every choice gives bitwise-identical levels. */
+void rtm_set_stencil_variant(int variant);
+/* Kernel timing, process wide and off by default.  With stride > 0 the
+ * sweeps record HIP events on their own stream around every stride-th
+ * stencil launch and around every probe-GEMM and image launch (0 turns it
+ * off).  rtm_profile_read(kind, ...) waits for the recorded events of one
+ * kind (0 stencil, 1 probe GEMM, 2 image), returns their summed duration in
+ * ms and their count, and forgets them. */
+void rtm_profile_enable(int32_t stride);
+rtm_status rtm_profile_read(int32_t kind, double *total_ms, int64_t *count);
+/* Message of the last HIP failure seen by this thread (empty if none). */
+const char *rtm_last_error(void);
+
+/* Forward sweep with on-the-fly probing (Eq. 3, Ubar = Z^T u_tt or Z^T u).
+ *   m        device [N]           slowness squared
+ *   src_pos  host   [nsrc][3]
+ *   q        device [nt][nsrc]    injected as is (a point source of signature
+ *                                 w is q = w / h^ndim)
+ *   rec_pos  host   [nrec][3]
+ *   d_pred   device [nt][nrec]    d[n] = Pr u^{n+1}; may be NULL
+ *   Z        device [nt][r]       dtype z_dtype (RTM_I8 for the BF16 paths,
+ *                                 else RTM_I8 or the field dtype)
+ *   Ubar     device [r][N]        overwritten
+ *   final_state device [2][N]     u^{nt}, u^{nt-1}; may be NULL
+ */
+rtm_status rtm_forward_probe(const rtm_plan *plan, const void *m, const double *src_pos,
+                             const void *q, const double *rec_pos, void *d_pred,
+                             const void *Z, rtm_dtype z_dtype, rtm_probe_field what,
+                             void *Ubar, void *final_state, void *work, size_t work_bytes,
+                             rtm_stream stream);
+
+/* Adjoint (time-reversed) sweep with probing: Vbar = Z^T lam, row n of Z
+ * paired with lam^n.
+ *   rec_pos host [nrec][3], res device [nt][nrec] (the adjoint source)
+ *   src_pos host [nsrc][3] and qadj device [nt][nsrc]: qadj[n] = Ps lam^n,
+ *           the adjoint of the map q -> d_pred; both may be NULL
+ *   Vbar    device [r][N] overwritten; may be NULL together with Z
+ */
+rtm_status rtm_adjoint_probe(const rtm_plan *plan, const void *m, const double *rec_pos,
+                             const void *res, const double *src_pos, void *qadj,
+                             const void *Z, rtm_dtype z_dtype, void *Vbar, void *work,
+                             size_t work_bytes, rtm_stream stream);
+
+/* Probed imaging condition (Eq. 3): image[x] = scale * sum_i Ubar[i][x] Vbar[i][x],
+ * summed in double.  scale = 1/r for the image, -1/r for the gradient. */
+rtm_status rtm_image(const rtm_plan *plan, const void *Ubar, const void *Vbar, double scale,
+                     void *image, rtm_stream stream);
+
+/* Probed FWI gradient of J = 1/2 sum |d_pred - d_obs|^2 (Eq. 2 estimated by
+ * Eq. 3): forward probing u_tt, residual, adjoint probing, image with scale
+ * -1/r.  Ubar, Vbar device [r][N] and resid device [nt][nrec] are outputs
+ * (resid = d_pred - d_obs); grad device [N]; misfit device double [1].  */
+rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_pos,
+                        const void *q, const double *rec_pos, const void *d_obs,
+                        const void *Z, rtm_dtype z_dtype, void *Ubar, void *Vbar,
+                        void *resid, void *grad, double *misfit, void *work,
+                        size_t work_bytes, rtm_stream stream);
+
+/* Double-precision inner product of two device arrays of the plan's field
+ * dtype: out[0] = sum_i a[i] b[i] (device double), deterministic order.
+ * Used for the adjoint test and for misfit / gradient norms. */
+rtm_status rtm_dot(const rtm_plan *plan, const void *a, const void *b, int64_t n,
+                   double *out, void *work, size_t work_bytes, rtm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTM_H */

@@ -206,10 +206,10 @@ static void update(long N, double dt, const double *m, const double *eta, const 
 static void probe_rank1(long N, int r, const double *z, long ns, const long *sidx,
                         const double *s, double *Ubar) {
   long M = sidx ? ns : N;
+  for (int i = 0; i < r; ++i) {
+    double *row = Ubar + (long)i * M;
 #pragma omp parallel for schedule(static)
-  for (long j = 0; j < M; ++j) {
-    double v = s[sidx ? sidx[j] : j];
-    for (int i = 0; i < r; ++i) Ubar[(long)i * M + j] += z[i] * v;
+    for (long j = 0; j < M; ++j) row[j] += z[i] * s[sidx ? sidx[j] : j];
   }
 }
 

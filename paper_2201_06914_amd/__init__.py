@@ -1,0 +1,12 @@
+"""MI355X (gfx950) library for adjoint-state wave imaging with randomized trace
+estimation (Louboutin & Herrmann): forward and adjoint finite-difference
+sweeps that compress the wavefield history on the fly against r random probe
+vectors (Eq. 3), the probed imaging condition, and the probed FWI gradient.
+
+The work runs in librtm.so (HIP kernels behind a C ABI, include/rtm.h); this
+package is its thin Python binding.  Importing it does not load the library;
+the first call does, and fails loudly if the library has not been built.
+"""
+from .api import (Plan, PlanSpec, RtmError, cfl_bound, fwi_gradient, rtm_adjoint_probe,  # noqa: F401
+                  rtm_dot, rtm_forward_probe, rtm_image, set_stencil_variant,
+                  profile_enable, profile_read)

@@ -1,0 +1,82 @@
+"""ctypes declarations of librtm.so (include/rtm.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtm.so")
+
+RTM_F64, RTM_F32, RTM_BF16, RTM_BF16X2, RTM_I8 = 0, 1, 2, 3, 4
+RTM_PROBE_U, RTM_PROBE_UTT = 0, 1
+
+# every symbol include/rtm.h declares
+EXPORTS = (
+    "rtm_plan_create", "rtm_plan_destroy", "rtm_plan_workspace_bytes", "rtm_cfl_bound",
+    "rtm_status_str", "rtm_set_stencil_variant", "rtm_last_error", "rtm_forward_probe",
+    "rtm_adjoint_probe", "rtm_image", "fwi_gradient", "rtm_dot", "rtm_profile_enable",
+    "rtm_profile_read",
+)
+
+
+class RtmDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("nz", ctypes.c_int64), ("ny", ctypes.c_int64), ("nx", ctypes.c_int64),
+        ("h", ctypes.c_double), ("dt", ctypes.c_double),
+        ("nt", ctypes.c_int32), ("nb", ctypes.c_int32),
+        ("c_ref", ctypes.c_double), ("R", ctypes.c_double), ("c_max", ctypes.c_double),
+        ("field_dtype", ctypes.c_int), ("probe_dtype", ctypes.c_int),
+        ("r", ctypes.c_int32), ("k_block", ctypes.c_int32),
+        ("nsrc", ctypes.c_int32), ("nrec", ctypes.c_int32),
+    ]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def load() -> ctypes.CDLL:
+    """Loads librtm.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc, gfx950); the library has no non-HIP fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, sz, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+    L.rtm_plan_create.argtypes = [ctypes.POINTER(RtmDesc), ctypes.POINTER(_vp)]
+    L.rtm_plan_create.restype = ctypes.c_int
+    L.rtm_plan_destroy.argtypes = [_vp]
+    L.rtm_plan_destroy.restype = None
+    L.rtm_plan_workspace_bytes.argtypes = [_vp, ctypes.POINTER(sz)]
+    L.rtm_plan_workspace_bytes.restype = ctypes.c_int
+    L.rtm_cfl_bound.argtypes = [i32]
+    L.rtm_cfl_bound.restype = dbl
+    L.rtm_status_str.argtypes = [ctypes.c_int]
+    L.rtm_status_str.restype = ctypes.c_char_p
+    L.rtm_last_error.argtypes = []
+    L.rtm_last_error.restype = ctypes.c_char_p
+    L.rtm_set_stencil_variant.argtypes = [ctypes.c_int]
+    L.rtm_set_stencil_variant.restype = None
+    L.rtm_forward_probe.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                    _vp, _vp, _vp, sz, _vp]
+    L.rtm_forward_probe.restype = ctypes.c_int
+    L.rtm_adjoint_probe.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, _vp, sz,
+                                    _vp]
+    L.rtm_adjoint_probe.restype = ctypes.c_int
+    L.rtm_image.argtypes = [_vp, _vp, _vp, dbl, _vp, _vp]
+    L.rtm_image.restype = ctypes.c_int
+    L.fwi_gradient.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
+                               _vp, _vp, sz, _vp]
+    L.fwi_gradient.restype = ctypes.c_int
+    L.rtm_dot.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, sz, _vp]
+    L.rtm_dot.restype = ctypes.c_int
+    L.rtm_profile_enable.argtypes = [i32]
+    L.rtm_profile_enable.restype = None
+    L.rtm_profile_read.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.rtm_profile_read.restype = ctypes.c_int
+    _lib = L
+    return L

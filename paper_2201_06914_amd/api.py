@@ -1,0 +1,283 @@
+"""Python binding of librtm: same names as the C ABI, torch tensors in and out.
+
+Only argument marshalling happens here - every step of the sweeps runs in the
+HIP kernels of librtm.so.  PyTorch provides device memory (outputs and the
+workspace) and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_FIELD = {"f64": _lib.RTM_F64, "f32": _lib.RTM_F32}
+_PROBE = {"f64": _lib.RTM_F64, "f32": _lib.RTM_F32, "bf16": _lib.RTM_BF16,
+          "bf16x2": _lib.RTM_BF16X2}
+_TORCH = {"f64": torch.float64, "f32": torch.float32}
+
+
+class RtmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        L = _lib.load()
+        msg = L.rtm_status_str(code).decode()
+        detail = L.rtm_last_error().decode()
+        super().__init__(f"{where}: {msg}" + (f" ({detail})" if detail else ""))
+        self.code = code
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise RtmError(code, where)
+
+
+@dataclasses.dataclass(frozen=True)
+class PlanSpec:
+    ndim: int
+    shape: tuple          # (nz, ny, nx)
+    h: float
+    dt: float
+    nt: int
+    nb: int
+    c_ref: float
+    R: float
+    c_max: float
+    field: str = "f32"    # "f64" | "f32"
+    probe: str = "bf16x2" # "f64" | "f32" | "bf16" | "bf16x2"
+    r: int = 1
+    k_block: int = 32
+    nsrc: int = 1
+    nrec: int = 0
+
+
+class Plan:
+    """Owns an rtm_plan (host object).  Immutable after creation."""
+
+    def __init__(self, spec: PlanSpec):
+        L = _lib.load()
+        self.spec = spec
+        d = _lib.RtmDesc()
+        d.ndim = spec.ndim
+        d.nz, d.ny, d.nx = (int(s) for s in spec.shape)
+        d.h, d.dt, d.nt, d.nb = spec.h, spec.dt, spec.nt, spec.nb
+        d.c_ref, d.R, d.c_max = spec.c_ref, spec.R, spec.c_max
+        d.field_dtype = _FIELD[spec.field]
+        d.probe_dtype = _PROBE[spec.probe]
+        d.r, d.k_block, d.nsrc, d.nrec = spec.r, spec.k_block, spec.nsrc, spec.nrec
+        h = ctypes.c_void_p()
+        _check(L.rtm_plan_create(ctypes.byref(d), ctypes.byref(h)), "rtm_plan_create")
+        self._h = h
+        self._destroy = L.rtm_plan_destroy
+        n = ctypes.c_size_t()
+        _check(L.rtm_plan_workspace_bytes(h, ctypes.byref(n)), "rtm_plan_workspace_bytes")
+        self.workspace_bytes = int(n.value)
+        self.N = int(np.prod(spec.shape))
+        self.dtype = _TORCH[spec.field]
+
+    @classmethod
+    def for_workload(cls, wl, field: str = "f32", probe: str = "bf16x2", k_block=None,
+                     c_max=None) -> "Plan":
+        m = np.asarray(wl.m, dtype=np.float64)
+        vmax = float(np.sqrt(1.0 / m.min())) if c_max is None else c_max
+        return cls(PlanSpec(wl.ndim, tuple(wl.shape), wl.h, wl.dt, wl.nt, wl.nb, wl.c_ref, wl.R,
+                            vmax, field, probe, wl.r, k_block or wl.k_block,
+                            int(np.shape(wl.src_pos)[0]), int(np.shape(wl.rec_pos)[0])))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+
+def cfl_bound(ndim: int) -> float:
+    return float(_lib.load().rtm_cfl_bound(ndim))
+
+
+def set_stencil_variant(v: int) -> None:
+    _lib.load().rtm_set_stencil_variant(int(v))
+
+
+KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2}
+
+
+def profile_enable(stride: int) -> None:
+    """Time every stride-th stencil launch and every probe / image launch with
+    HIP events on the sweep's stream (0 = off)."""
+    _lib.load().rtm_profile_enable(int(stride))
+
+
+def profile_read(kind: str):
+    """(total_ms, count) of the timed launches of one kernel kind."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.load().rtm_profile_read(KERNEL_KINDS[kind], ctypes.byref(ms), ctypes.byref(n)),
+           "rtm_profile_read")
+    return float(ms.value), int(n.value)
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def _dev(t: torch.Tensor, dtype, numel: int, name: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _pos(p, n: int, name: str):
+    if p is None:
+        return None, None
+    a = np.ascontiguousarray(np.reshape(p, (-1, 3)), dtype=np.float64)
+    if a.shape[0] != n:
+        raise ValueError(f"{name} has {a.shape[0]} points, the plan expects {n}")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _z(plan: Plan, Z: torch.Tensor):
+    s = plan.spec
+    if Z is None:
+        return None, _lib.RTM_I8
+    if Z.dtype == torch.int8:
+        zt = _lib.RTM_I8
+    elif Z.dtype == plan.dtype:
+        zt = _PROBE[s.field]
+    else:
+        raise TypeError("Z must be int8 (+-1) or the plan's field dtype")
+    return _dev(Z, Z.dtype, s.nt * s.r, "Z"), zt
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _work(plan: Plan, work, device):
+    if work is None:
+        work = plan.workspace(device)
+    if work.numel() < plan.workspace_bytes or not work.is_cuda:
+        raise ValueError("workspace too small")
+    return work
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+def rtm_forward_probe(plan: Plan, m, src_pos, q, rec_pos=None, Z=None, what: str = "utt",
+                      want_d: bool = True, final: bool = False, work=None) -> dict:
+    s = plan.spec
+    dev = m.device
+    out = {}
+    d = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev) if want_d else None
+    U = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev) if Z is not None else None
+    F = torch.empty((2, plan.N), dtype=plan.dtype, device=dev) if final else None
+    work = _work(plan, work, dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos") if want_d else (None, None)
+    zp, zt = _z(plan, Z)
+    code = _lib.load().rtm_forward_probe(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
+        _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp, _dev(d, plan.dtype, s.nt * s.nrec, "d"),
+        zp, zt, _lib.RTM_PROBE_UTT if what == "utt" else _lib.RTM_PROBE_U,
+        _dev(U, plan.dtype, s.r * plan.N, "Ubar"), _dev(F, plan.dtype, 2 * plan.N, "final"),
+        ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(dev))
+    _check(code, "rtm_forward_probe")
+    if d is not None:
+        out["d"] = d
+    if U is not None:
+        out["Ubar"] = U
+    if F is not None:
+        out["final"] = F
+    return out
+
+
+def rtm_adjoint_probe(plan: Plan, m, rec_pos, res, Z=None, src_pos=None, want_qadj=False,
+                      work=None) -> dict:
+    s = plan.spec
+    dev = m.device
+    V = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev) if Z is not None else None
+    qa = torch.empty((s.nt, s.nsrc), dtype=plan.dtype, device=dev) if want_qadj else None
+    work = _work(plan, work, dev)
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos") if want_qadj else (None, None)
+    zp, zt = _z(plan, Z)
+    code = _lib.load().rtm_adjoint_probe(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), rpp,
+        _dev(res, plan.dtype, s.nt * s.nrec, "res"), spp,
+        _dev(qa, plan.dtype, s.nt * s.nsrc, "qadj"), zp, zt,
+        _dev(V, plan.dtype, s.r * plan.N, "Vbar"), ctypes.c_void_p(work.data_ptr()),
+        work.numel(), _stream(dev))
+    _check(code, "rtm_adjoint_probe")
+    out = {}
+    if V is not None:
+        out["Vbar"] = V
+    if qa is not None:
+        out["qadj"] = qa
+    return out
+
+
+def rtm_image(plan: Plan, Ubar, Vbar, scale: float | None = None) -> torch.Tensor:
+    s = plan.spec
+    scale = 1.0 / s.r if scale is None else scale
+    img = torch.empty(plan.N, dtype=plan.dtype, device=Ubar.device)
+    _check(_lib.load().rtm_image(
+        plan.handle, _dev(Ubar, plan.dtype, s.r * plan.N, "Ubar"),
+        _dev(Vbar, plan.dtype, s.r * plan.N, "Vbar"), float(scale),
+        _dev(img, plan.dtype, plan.N, "image"), _stream(Ubar.device)), "rtm_image")
+    return img
+
+
+def fwi_gradient(plan: Plan, m, src_pos, q, rec_pos, d_obs, Z, work=None, bars=None) -> dict:
+    """Probed FWI gradient.  `bars` may pass preallocated (Ubar, Vbar)."""
+    s = plan.spec
+    dev = m.device
+    if bars is None:
+        U = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev)
+        V = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev)
+    else:
+        U, V = bars
+    res = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev)
+    g = torch.empty(plan.N, dtype=plan.dtype, device=dev)
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    work = _work(plan, work, dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")   # keep the arrays alive over the call
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    zp, zt = _z(plan, Z)
+    code = _lib.load().fwi_gradient(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
+        _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp,
+        _dev(d_obs, plan.dtype, s.nt * s.nrec, "d_obs"), zp, zt,
+        _dev(U, plan.dtype, s.r * plan.N, "Ubar"), _dev(V, plan.dtype, s.r * plan.N, "Vbar"),
+        _dev(res, plan.dtype, s.nt * s.nrec, "resid"), _dev(g, plan.dtype, plan.N, "grad"),
+        _dev(J, torch.float64, 1, "misfit"), ctypes.c_void_p(work.data_ptr()), work.numel(),
+        _stream(dev))
+    _check(code, "fwi_gradient")
+    return {"grad": g, "misfit": J, "Ubar": U, "Vbar": V, "resid": res}
+
+
+def rtm_dot(plan: Plan, a, b, work=None) -> torch.Tensor:
+    n = a.numel()
+    out = torch.empty(1, dtype=torch.float64, device=a.device)
+    work = _work(plan, work, a.device)
+    _check(_lib.load().rtm_dot(plan.handle, _dev(a, plan.dtype, n, "a"),
+                               _dev(b, plan.dtype, n, "b"), n, _dev(out, torch.float64, 1, "out"),
+                               ctypes.c_void_p(work.data_ptr()), work.numel(),
+                               _stream(a.device)), "rtm_dot")
+    return out

@@ -1,0 +1,679 @@
+// Host side of librtm: plan validation, workspace layout, point tables and
+// the sequencing of the forward / adjoint sweeps (include/rtm.h).
+//
+// Sweep structure (both directions).  The wavefield lives in a ring of
+// R = k_block + 2 levels in the workspace.  Sweep step s (s = 0..nt-1; the
+// time step is n = s forward, n = nt-1-s adjoint) reads levels s and s-1 and
+// writes level s+1; level j sits in slot (j+1) mod R, levels -1 and 0 are zero.
+// Per step: stencil kernel, injection of the step's point values into level
+// s+1, sampling of level s+1.  After every k_block steps (and after the last)
+// one probe-GEMM adds the block's k probed levels, weighted by the matching
+// rows of Z, into Ubar / Vbar - so the compressed history is built on the fly
+// and no level older than the ring is ever needed (Eq. 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rtm.h"
+#include "rtm_internal.h"
+
+using namespace rtm;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / kStencilTiled
+
+// Opt-in kernel timing: HIP events recorded on the sweep's stream around every
+// `stride`-th launch of the stencil and every probe-GEMM / image launch.
+enum { KT_STENCIL = 0, KT_PROBE = 1, KT_IMAGE = 2, KT_N = 3 };
+struct TimedLaunch {
+  int kind;
+  hipEvent_t a, b;
+};
+static int g_prof_stride = 0;  // 0 = off
+static std::vector<TimedLaunch> g_prof;
+
+static void prof_begin(int kind, int step, hipStream_t st, TimedLaunch *t) {
+  t->kind = -1;
+  if (g_prof_stride <= 0) return;
+  if (kind == KT_STENCIL && step % g_prof_stride) return;
+  if (hipEventCreate(&t->a) != hipSuccess) return;
+  if (hipEventCreate(&t->b) != hipSuccess) {
+    (void)hipEventDestroy(t->a);
+    return;
+  }
+  t->kind = kind;
+  (void)hipEventRecord(t->a, st);
+}
+
+static void prof_end(hipStream_t st, TimedLaunch *t) {
+  if (t->kind < 0) return;
+  (void)hipEventRecord(t->b, st);
+  g_prof.push_back(*t);
+}
+
+static rtm_status fail(rtm_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(RTM_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));           \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+// 8th-order central second-derivative weights (Fornberg), offsets 0..4.
+static const double kW[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+static double nyquist_symbol() {  // max over k of the 1D symbol times h^2
+  double s = -kW[0];
+  for (int j = 1; j <= 4; ++j) s -= 2.0 * kW[j] * ((j & 1) ? -1.0 : 1.0);
+  return s;
+}
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+struct PointRegion {  // device layout of one point set's tables
+  Region soff, sidx, sw, icell, ioff, ipt, iw;
+  int32_t cap = 0;  // points
+};
+
+struct rtm_plan {
+  rtm_desc d;
+  int64_t N = 0, ld = 0;
+  int R = 0;
+  size_t esz = 0;
+  Region ring, red;
+  PointRegion src, rec;
+  size_t tab_off = 0, tab_bytes = 0;
+  size_t total = 0;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static void place(size_t &cur, Region &r, size_t bytes) {
+  r.off = cur;
+  r.bytes = bytes;
+  cur = align256(cur + bytes);
+}
+
+static void place_points(size_t &cur, PointRegion &pr, int32_t n, size_t esz) {
+  const size_t c = (size_t)8 * n;  // at most 8 corners per point
+  pr.cap = n;
+  place(cur, pr.soff, 4 * ((size_t)n + 1));
+  place(cur, pr.sidx, 4 * c);
+  place(cur, pr.sw, esz * c);
+  place(cur, pr.icell, 4 * c);
+  place(cur, pr.ioff, 4 * (c + 1));
+  place(cur, pr.ipt, 4 * c);
+  place(cur, pr.iw, esz * c);
+}
+
+extern "C" double rtm_cfl_bound(int32_t ndim) {
+  if (ndim < 1) return 0.0;
+  return 2.0 / std::sqrt((double)ndim * nyquist_symbol());
+}
+
+extern "C" const char *rtm_status_str(rtm_status s) {
+  switch (s) {
+    case RTM_OK: return "ok";
+    case RTM_E_ARG: return "invalid argument";
+    case RTM_E_SHAPE: return "invalid shape";
+    case RTM_E_DTYPE: return "unsupported dtype";
+    case RTM_E_CFL: return "time step violates the CFL bound";
+    case RTM_E_WORKSPACE: return "workspace too small";
+    case RTM_E_HIP: return "HIP runtime error";
+    case RTM_E_UNSUPPORTED: return "unsupported request";
+    case RTM_E_POINTS: return "point outside the grid";
+  }
+  return "unknown status";
+}
+
+extern "C" const char *rtm_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void rtm_set_stencil_variant(int v) { g_stencil_variant = v; }
+
+extern "C" void rtm_profile_enable(int32_t stride) {
+  g_prof_stride = stride > 0 ? stride : 0;
+}
+
+extern "C" rtm_status rtm_profile_read(int32_t kind, double *total_ms, int64_t *count) {
+  if (!total_ms || !count || kind < 0 || kind >= KT_N) return fail(RTM_E_ARG, "bad profile query");
+  double tot = 0.0;
+  int64_t n = 0;
+  std::vector<TimedLaunch> keep;
+  for (TimedLaunch &t : g_prof) {
+    if (t.kind != kind) {
+      keep.push_back(t);
+      continue;
+    }
+    float ms = 0.f;
+    HIP_TRY(hipEventSynchronize(t.b));
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    tot += ms;
+    ++n;
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  g_prof.swap(keep);
+  *total_ms = tot;
+  *count = n;
+  return RTM_OK;
+}
+
+extern "C" rtm_status rtm_plan_create(const rtm_desc *desc, rtm_plan **out) {
+  g_last_error.clear();
+  if (!desc || !out) return fail(RTM_E_ARG, "desc and plan must be non-NULL");
+  const rtm_desc &d = *desc;
+  if (d.ndim != 2 && d.ndim != 3) return fail(RTM_E_SHAPE, "ndim must be 2 or 3 (got %d)", d.ndim);
+  if (d.nz < 1 || d.ny < 1 || d.nx < 1) return fail(RTM_E_SHAPE, "grid sizes must be >= 1");
+  if (d.ndim == 2 && d.ny != 1) return fail(RTM_E_SHAPE, "2D grids need ny == 1");
+  if (d.nz > (1 << 30) || d.ny > (1 << 30) || d.nx > (1 << 30))
+    return fail(RTM_E_SHAPE, "axis too long");
+  const int64_t N = d.nz * d.ny * d.nx;
+  if (N >= ((int64_t)1 << 31)) return fail(RTM_E_SHAPE, "grid has %lld cells (max 2^31-1)", (long long)N);
+  if (!(d.h > 0) || !(d.dt > 0)) return fail(RTM_E_ARG, "h and dt must be positive");
+  if (d.nt < 1) return fail(RTM_E_ARG, "nt must be >= 1");
+  if (d.nb < 0) return fail(RTM_E_ARG, "nb must be >= 0");
+  if (2 * (int64_t)d.nb >= d.nz || 2 * (int64_t)d.nb >= d.nx ||
+      (d.ndim == 3 && 2 * (int64_t)d.nb >= d.ny))
+    return fail(RTM_E_SHAPE, "damping layers (2 x %d) do not fit the grid", d.nb);
+  if (d.nb > 0 && !(d.c_ref > 0)) return fail(RTM_E_ARG, "c_ref must be positive");
+  if (d.nb > 0 && !(d.R > 0 && d.R < 1)) return fail(RTM_E_ARG, "R must be in (0, 1)");
+  if (!(d.c_max > 0)) return fail(RTM_E_ARG, "c_max must be positive");
+  const double courant = d.dt * d.c_max / d.h;
+  if (!(courant <= rtm_cfl_bound(d.ndim)))
+    return fail(RTM_E_CFL, "dt*c_max/h = %.6f exceeds the bound %.6f", courant,
+                rtm_cfl_bound(d.ndim));
+  if (d.field_dtype != RTM_F64 && d.field_dtype != RTM_F32)
+    return fail(RTM_E_DTYPE, "field dtype must be F64 or F32");
+  if (d.field_dtype == RTM_F64 && d.probe_dtype != RTM_F64)
+    return fail(RTM_E_DTYPE, "F64 fields need the F64 probe path");
+  if (d.field_dtype == RTM_F32 && d.probe_dtype != RTM_F32 && d.probe_dtype != RTM_BF16 &&
+      d.probe_dtype != RTM_BF16X2)
+    return fail(RTM_E_DTYPE, "F32 fields need an F32, BF16 or BF16X2 probe path");
+  if (d.r < 1 || d.r > 1024) return fail(RTM_E_ARG, "r must be in 1..1024");
+  if (d.k_block < 1 || d.k_block > 256) return fail(RTM_E_ARG, "k_block must be in 1..256");
+  if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
+    const int ks = (d.k_block + 15) / 16;
+    const int ksp = ks <= 1 ? 1 : ks <= 2 ? 2 : ks <= 4 ? 4 : 8;
+    if (d.k_block > 128 || ((d.r + 31) / 32) * ksp > 64)
+      return fail(RTM_E_UNSUPPORTED, "BF16 probe path needs k_block <= 128 and ceil(r/32)*ceil(k/16) <= 64");
+  }
+  if (d.nsrc < 0 || d.nrec < 0) return fail(RTM_E_ARG, "point counts must be >= 0");
+
+  rtm_plan *p = new (std::nothrow) rtm_plan();
+  if (!p) return fail(RTM_E_ARG, "out of host memory");
+  p->d = d;
+  p->N = N;
+  p->ld = (N + 63) / 64 * 64;
+  p->R = d.k_block + 2;
+  p->esz = d.field_dtype == RTM_F64 ? 8 : 4;
+  size_t cur = 0;
+  place(cur, p->ring, (size_t)p->R * p->ld * p->esz);
+  place(cur, p->red, sizeof(double) * (kReduceBlocks + 8));
+  p->tab_off = cur;
+  place_points(cur, p->src, d.nsrc, p->esz);
+  place_points(cur, p->rec, d.nrec, p->esz);
+  p->tab_bytes = cur - p->tab_off;
+  p->total = cur;
+  *out = p;
+  return RTM_OK;
+}
+
+extern "C" void rtm_plan_destroy(rtm_plan *p) { delete p; }
+
+extern "C" rtm_status rtm_plan_workspace_bytes(const rtm_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(RTM_E_ARG, "plan and bytes must be non-NULL");
+  *bytes = p->total;
+  return RTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// point tables
+// ---------------------------------------------------------------------------
+struct HostPoints {
+  std::vector<int32_t> soff, sidx, icell, ioff, ipt;
+  std::vector<double> sw, iw;
+};
+
+// Multilinear weights of each point; injection entries grouped by cell
+// (points in increasing order within a cell) so that the injection kernel
+// sums a cell's contributions in a fixed order without atomics.
+static rtm_status build_points(const rtm_plan *P, int32_t n, const double *pos, HostPoints &hp) {
+  const rtm_desc &d = P->d;
+  const int64_t dims[3] = {d.nz, d.ny, d.nx};
+  struct Entry {
+    int32_t cell, pt;
+    double w;
+  };
+  std::vector<Entry> ent;
+  ent.reserve((size_t)n * 8);
+  hp.soff.assign(1, 0);
+  for (int32_t p = 0; p < n; ++p) {
+    int64_t base[3];
+    double frac[3];
+    int ncor[3];
+    for (int a = 0; a < 3; ++a) {
+      double v = (a == 1 && d.ndim == 2) ? 0.0 : pos[3 * (size_t)p + a];
+      if (!(v >= 0.0 && v <= (double)(dims[a] - 1)))
+        return fail(RTM_E_POINTS, "point %d axis %d at %g is outside [0, %lld]", p, a, v,
+                    (long long)(dims[a] - 1));
+      const double f = std::floor(v);
+      base[a] = (int64_t)f;
+      frac[a] = v - f;
+      ncor[a] = frac[a] > 0.0 ? 2 : 1;
+    }
+    for (int iz = 0; iz < ncor[0]; ++iz)
+      for (int iy = 0; iy < ncor[1]; ++iy)
+        for (int ix = 0; ix < ncor[2]; ++ix) {
+          const double w = (iz ? frac[0] : 1.0 - frac[0]) * (iy ? frac[1] : 1.0 - frac[1]) *
+                           (ix ? frac[2] : 1.0 - frac[2]);
+          const int64_t cell = ((base[0] + iz) * d.ny + (base[1] + iy)) * d.nx + (base[2] + ix);
+          hp.sidx.push_back((int32_t)cell);
+          hp.sw.push_back(w);
+          ent.push_back({(int32_t)cell, p, w});
+        }
+    hp.soff.push_back((int32_t)hp.sidx.size());
+  }
+  std::stable_sort(ent.begin(), ent.end(),
+                   [](const Entry &a, const Entry &b) { return a.cell < b.cell; });
+  hp.ioff.assign(1, 0);
+  for (size_t e = 0; e < ent.size(); ++e) {
+    if (e == 0 || ent[e].cell != ent[e - 1].cell) {
+      if (e) hp.ioff.push_back((int32_t)e);
+      hp.icell.push_back(ent[e].cell);
+    }
+    hp.ipt.push_back(ent[e].pt);
+    hp.iw.push_back(ent[e].w);
+  }
+  hp.ioff.push_back((int32_t)ent.size());
+  if (ent.empty()) hp.ioff.assign(1, 0);
+  return RTM_OK;
+}
+
+template <typename T>
+static void stage_points(const rtm_plan *P, const PointRegion &pr, const HostPoints &hp,
+                         std::vector<unsigned char> &host) {
+  auto put = [&](const Region &r, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(host.data() + (r.off - P->tab_off), src, bytes);
+  };
+  put(pr.soff, hp.soff.data(), 4 * hp.soff.size());
+  put(pr.sidx, hp.sidx.data(), 4 * hp.sidx.size());
+  std::vector<T> sw(hp.sw.begin(), hp.sw.end()), iw(hp.iw.begin(), hp.iw.end());
+  put(pr.sw, sw.data(), sizeof(T) * sw.size());
+  put(pr.icell, hp.icell.data(), 4 * hp.icell.size());
+  put(pr.ioff, hp.ioff.data(), 4 * hp.ioff.size());
+  put(pr.ipt, hp.ipt.data(), 4 * hp.ipt.size());
+  put(pr.iw, iw.data(), sizeof(T) * iw.size());
+}
+
+template <typename T>
+static PointTables<T> device_points(const PointRegion &pr, char *work, int32_t npts,
+                                    int32_t ncell) {
+  PointTables<T> t;
+  t.soff = reinterpret_cast<const int32_t *>(work + pr.soff.off);
+  t.sidx = reinterpret_cast<const int32_t *>(work + pr.sidx.off);
+  t.sw = reinterpret_cast<const T *>(work + pr.sw.off);
+  t.icell = reinterpret_cast<const int32_t *>(work + pr.icell.off);
+  t.ioff = reinterpret_cast<const int32_t *>(work + pr.ioff.off);
+  t.ipt = reinterpret_cast<const int32_t *>(work + pr.ipt.off);
+  t.iw = reinterpret_cast<const T *>(work + pr.iw.off);
+  t.npts = npts;
+  t.ncell = ncell;
+  return t;
+}
+
+// Builds the tables of the given point sets and copies them into the
+// workspace (stream ordered; waits for the copy so host memory can go).
+template <typename T>
+static rtm_status upload_points(const rtm_plan *P, char *work, hipStream_t st,
+                                const double *src_pos, PointTables<T> *src_t,
+                                const double *rec_pos, PointTables<T> *rec_t) {
+  std::vector<unsigned char> host(P->tab_bytes, 0);
+  HostPoints hs, hr;
+  if (src_pos && src_t) {
+    rtm_status s = build_points(P, P->d.nsrc, src_pos, hs);
+    if (s) return s;
+    stage_points<T>(P, P->src, hs, host);
+    *src_t = device_points<T>(P->src, work, P->d.nsrc, (int32_t)hs.icell.size());
+  }
+  if (rec_pos && rec_t) {
+    rtm_status s = build_points(P, P->d.nrec, rec_pos, hr);
+    if (s) return s;
+    stage_points<T>(P, P->rec, hr, host);
+    *rec_t = device_points<T>(P->rec, work, P->d.nrec, (int32_t)hr.icell.size());
+  }
+  if (P->tab_bytes) {
+    HIP_TRY(hipMemcpyAsync(work + P->tab_off, host.data(), P->tab_bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return RTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sweeps
+// ---------------------------------------------------------------------------
+template <typename T>
+static StepArgs<T> step_args(const rtm_plan *P, const T *m) {
+  const rtm_desc &d = P->d;
+  StepArgs<T> a{};
+  a.m = m;
+  a.nz = (int)d.nz;
+  a.ny = (int)d.ny;
+  a.nx = (int)d.nx;
+  a.nb = d.nb;
+  a.N = P->N;
+  const double ih2 = 1.0 / (d.h * d.h);
+  a.c1 = (T)(kW[1] * ih2);
+  a.c2 = (T)(kW[2] * ih2);
+  a.c3 = (T)(kW[3] * ih2);
+  a.c4 = (T)(kW[4] * ih2);
+  a.cc = (T)(d.ndim * kW[0] * ih2);
+  a.dt2 = (T)(d.dt * d.dt);
+  double kd = 0.0;
+  if (d.nb > 0) {
+    const double A = 3.0 * std::log(1.0 / d.R) / (2.0 * d.nb * d.h * d.c_ref);
+    kd = A * d.dt * 0.5 / ((double)d.nb * d.nb);
+  }
+  a.kd = (T)kd;
+  return a;
+}
+
+struct SweepIO {
+  bool adjoint = false;
+  const void *m = nullptr;
+  const void *inj_vals = nullptr;  // [nt][n_inj]
+  void *smp_out = nullptr;         // [nt][n_smp] or NULL
+  const void *Z = nullptr;
+  rtm_dtype zt = RTM_I8;
+  int mode = PROBE_UTT;
+  void *bar = nullptr;             // [r][N] or NULL
+  void *final_state = nullptr;     // [2][N] or NULL
+};
+
+template <typename T>
+static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTables<T> &inj,
+                            const PointTables<T> &smp, char *work, hipStream_t st) {
+  const rtm_desc &d = P->d;
+  T *ring = reinterpret_cast<T *>(work + P->ring.off);
+  auto level = [&](int j) -> T * {
+    int slot = (j + 1) % P->R;
+    return ring + (int64_t)slot * P->ld;
+  };
+  const int ndim = d.ndim;
+  int variant = kStencilSimple;
+  if (ndim == 3 && sizeof(T) == 4) variant = kStencilTiled;
+  if (g_stencil_variant >= 0) variant = g_stencil_variant;
+  StepArgs<T> a = step_args<T>(P, static_cast<const T *>(io.m));
+  HIP_TRY(launch_fill<T>(level(-1), P->N, T(0), st));
+  HIP_TRY(launch_fill<T>(level(0), P->N, T(0), st));
+  T *bar = static_cast<T *>(io.bar);
+  if (bar) HIP_TRY(launch_fill<T>(bar, (int64_t)d.r * P->N, T(0), st));
+  const T *inj_vals = static_cast<const T *>(io.inj_vals);
+  T *smp_out = static_cast<T *>(io.smp_out);
+  int s0 = 0;
+  for (int s = 0; s < d.nt; ++s) {
+    const int n = io.adjoint ? d.nt - 1 - s : s;
+    a.cur = level(s);
+    a.prev = level(s - 1);
+    a.next = level(s + 1);
+    TimedLaunch tl;
+    prof_begin(KT_STENCIL, s, st, &tl);
+    HIP_TRY(launch_stencil<T>(ndim, a, variant, st));
+    prof_end(st, &tl);
+    if (inj.ncell > 0 && inj_vals)
+      HIP_TRY(launch_inject<T>(a, inj, inj_vals + (int64_t)n * inj.npts, a.next, st));
+    if (smp_out && smp.npts > 0)
+      HIP_TRY(launch_sample<T>(smp, a.next, smp_out + (int64_t)n * smp.npts, st));
+    if (bar && (s + 1 - s0 == d.k_block || s == d.nt - 1)) {
+      ProbeArgs<T> p{};
+      p.ring = ring;
+      p.ld = P->ld;
+      p.R = P->R;
+      p.s0 = s0;
+      p.kb = s + 1 - s0;
+      p.zrow0 = io.adjoint ? d.nt - 1 - s0 : s0;
+      p.zdir = io.adjoint ? -1 : 1;
+      p.r = d.r;
+      p.N = P->N;
+      p.bar = bar;
+      p.inv_dt2 = (T)(1.0 / (d.dt * d.dt));
+      p.mode = io.mode;
+      TimedLaunch tp;
+      prof_begin(KT_PROBE, s, st, &tp);
+      if constexpr (sizeof(T) == 4) {
+        if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
+          HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io.Z),
+                                    d.probe_dtype == RTM_BF16X2, st));
+        } else {
+          HIP_TRY(launch_probe_vec<T>(p, io.Z, io.zt == RTM_I8, st));
+        }
+      } else {
+        HIP_TRY(launch_probe_vec<T>(p, io.Z, io.zt == RTM_I8, st));
+      }
+      prof_end(st, &tp);
+      s0 = s + 1;
+    }
+  }
+  if (io.final_state) {
+    T *fs = static_cast<T *>(io.final_state);
+    HIP_TRY(launch_copy<T>(fs, level(d.nt), P->N, st));
+    HIP_TRY(launch_copy<T>(fs + P->N, level(d.nt - 1), P->N, st));
+  }
+  return RTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+static rtm_status check_common(const rtm_plan *P, const void *m, void *work, size_t work_bytes) {
+  g_last_error.clear();
+  if (!P) return fail(RTM_E_ARG, "plan is NULL");
+  if (!m) return fail(RTM_E_ARG, "m is NULL");
+  if (!work) return fail(RTM_E_ARG, "work is NULL");
+  if (work_bytes < P->total)
+    return fail(RTM_E_WORKSPACE, "work has %zu bytes, the plan needs %zu", work_bytes, P->total);
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(RTM_E_ARG, "work must be 256-byte aligned");
+  return RTM_OK;
+}
+
+static rtm_status check_probe(const rtm_plan *P, const void *Z, rtm_dtype zt, const void *bar) {
+  if ((Z == nullptr) != (bar == nullptr))
+    return fail(RTM_E_ARG, "Z and the compressed field must both be given or both be NULL");
+  if (!Z) return RTM_OK;
+  const rtm_dtype pd = P->d.probe_dtype;
+  if (pd == RTM_BF16 || pd == RTM_BF16X2) {
+    if (zt != RTM_I8) return fail(RTM_E_DTYPE, "the BF16 probe paths need +-1 probes (RTM_I8)");
+  } else if (zt != RTM_I8 && zt != P->d.field_dtype) {
+    return fail(RTM_E_DTYPE, "Z must be RTM_I8 or the field dtype");
+  }
+  return RTM_OK;
+}
+
+template <typename T>
+static rtm_status forward_impl(const rtm_plan *P, const void *m, const double *src_pos,
+                               const void *q, const double *rec_pos, void *d_pred, const void *Z,
+                               rtm_dtype zt, rtm_probe_field what, void *Ubar, void *fin,
+                               void *work, hipStream_t st) {
+  PointTables<T> src_t, rec_t;
+  rtm_status s = upload_points<T>(P, static_cast<char *>(work), st, src_pos, &src_t,
+                                  d_pred ? rec_pos : nullptr, &rec_t);
+  if (s) return s;
+  SweepIO io;
+  io.adjoint = false;
+  io.m = m;
+  io.inj_vals = q;
+  io.smp_out = d_pred;
+  io.Z = Z;
+  io.zt = zt;
+  io.mode = what == RTM_PROBE_U ? PROBE_CUR : PROBE_UTT;
+  io.bar = Ubar;
+  io.final_state = fin;
+  return run_sweep<T>(P, io, src_t, rec_t, static_cast<char *>(work), st);
+}
+
+extern "C" rtm_status rtm_forward_probe(const rtm_plan *P, const void *m, const double *src_pos,
+                                        const void *q, const double *rec_pos, void *d_pred,
+                                        const void *Z, rtm_dtype zt, rtm_probe_field what,
+                                        void *Ubar, void *final_state, void *work,
+                                        size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  if (P->d.nsrc > 0 && (!src_pos || !q)) return fail(RTM_E_ARG, "src_pos and q are required");
+  if (d_pred && P->d.nrec > 0 && !rec_pos) return fail(RTM_E_ARG, "rec_pos is required with d_pred");
+  if (what != RTM_PROBE_U && what != RTM_PROBE_UTT) return fail(RTM_E_ARG, "bad probe field");
+  if ((s = check_probe(P, Z, zt, Ubar))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return forward_impl<double>(P, m, src_pos, q, rec_pos, d_pred, Z, zt, what, Ubar,
+                                final_state, work, st);
+  return forward_impl<float>(P, m, src_pos, q, rec_pos, d_pred, Z, zt, what, Ubar, final_state,
+                             work, st);
+}
+
+template <typename T>
+static rtm_status adjoint_impl(const rtm_plan *P, const void *m, const double *rec_pos,
+                               const void *res, const double *src_pos, void *qadj, const void *Z,
+                               rtm_dtype zt, void *Vbar, void *work, hipStream_t st) {
+  PointTables<T> src_t, rec_t;
+  rtm_status s = upload_points<T>(P, static_cast<char *>(work), st, qadj ? src_pos : nullptr,
+                                  &src_t, rec_pos, &rec_t);
+  if (s) return s;
+  SweepIO io;
+  io.adjoint = true;
+  io.m = m;
+  io.inj_vals = res;
+  io.smp_out = qadj;
+  io.Z = Z;
+  io.zt = zt;
+  io.mode = PROBE_NEW;
+  io.bar = Vbar;
+  return run_sweep<T>(P, io, rec_t, src_t, static_cast<char *>(work), st);
+}
+
+extern "C" rtm_status rtm_adjoint_probe(const rtm_plan *P, const void *m, const double *rec_pos,
+                                        const void *res, const double *src_pos, void *qadj,
+                                        const void *Z, rtm_dtype zt, void *Vbar, void *work,
+                                        size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  if (P->d.nrec > 0 && (!rec_pos || !res)) return fail(RTM_E_ARG, "rec_pos and res are required");
+  if (qadj && P->d.nsrc > 0 && !src_pos) return fail(RTM_E_ARG, "src_pos is required with qadj");
+  if ((s = check_probe(P, Z, zt, Vbar))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return adjoint_impl<double>(P, m, rec_pos, res, src_pos, qadj, Z, zt, Vbar, work, st);
+  return adjoint_impl<float>(P, m, rec_pos, res, src_pos, qadj, Z, zt, Vbar, work, st);
+}
+
+extern "C" rtm_status rtm_image(const rtm_plan *P, const void *U, const void *V, double scale,
+                                void *image, rtm_stream stream) {
+  g_last_error.clear();
+  if (!P || !U || !V || !image) return fail(RTM_E_ARG, "NULL argument");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    HIP_TRY(launch_image<double>(static_cast<const double *>(U), static_cast<const double *>(V),
+                                 P->N, P->d.r, scale, static_cast<double *>(image), st));
+  else
+    HIP_TRY(launch_image<float>(static_cast<const float *>(U), static_cast<const float *>(V),
+                                P->N, P->d.r, scale, static_cast<float *>(image), st));
+  return RTM_OK;
+}
+
+extern "C" rtm_status rtm_dot(const rtm_plan *P, const void *a, const void *b, int64_t n,
+                              double *out, void *work, size_t work_bytes, rtm_stream stream) {
+  g_last_error.clear();
+  if (!P || !a || !b || !out || !work) return fail(RTM_E_ARG, "NULL argument");
+  if (n < 0) return fail(RTM_E_ARG, "n must be >= 0");
+  if (work_bytes < P->total) return fail(RTM_E_WORKSPACE, "workspace too small");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  double *part = reinterpret_cast<double *>(static_cast<char *>(work) + P->red.off);
+  if (P->d.field_dtype == RTM_F64)
+    HIP_TRY(launch_dot<double>(static_cast<const double *>(a), static_cast<const double *>(b), n,
+                               part, out, st));
+  else
+    HIP_TRY(launch_dot<float>(static_cast<const float *>(a), static_cast<const float *>(b), n,
+                              part, out, st));
+  return RTM_OK;
+}
+
+template <typename T>
+static rtm_status gradient_impl(const rtm_plan *P, const void *m, const double *src_pos,
+                                const void *q, const double *rec_pos, const void *d_obs,
+                                const void *Z, rtm_dtype zt, void *Ubar, void *Vbar, void *resid,
+                                void *grad, double *misfit, void *work, hipStream_t st) {
+  PointTables<T> src_t, rec_t;
+  char *w = static_cast<char *>(work);
+  rtm_status s = upload_points<T>(P, w, st, src_pos, &src_t, rec_pos, &rec_t);
+  if (s) return s;
+  SweepIO f;
+  f.adjoint = false;
+  f.m = m;
+  f.inj_vals = q;
+  f.smp_out = resid;  // d_pred first, turned into the residual below
+  f.Z = Z;
+  f.zt = zt;
+  f.mode = PROBE_UTT;
+  f.bar = Ubar;
+  if ((s = run_sweep<T>(P, f, src_t, rec_t, w, st))) return s;
+  double *part = reinterpret_cast<double *>(w + P->red.off);
+  const int64_t nd = (int64_t)P->d.nt * P->d.nrec;
+  HIP_TRY(launch_residual_misfit<T>(static_cast<const T *>(resid), static_cast<const T *>(d_obs),
+                                    static_cast<T *>(resid), nd, part, misfit, st));
+  SweepIO b;
+  b.adjoint = true;
+  b.m = m;
+  b.inj_vals = resid;
+  b.Z = Z;
+  b.zt = zt;
+  b.mode = PROBE_NEW;
+  b.bar = Vbar;
+  PointTables<T> none;
+  if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
+  TimedLaunch ti;
+  prof_begin(KT_IMAGE, 0, st, &ti);
+  HIP_TRY(launch_image<T>(static_cast<const T *>(Ubar), static_cast<const T *>(Vbar), P->N,
+                          P->d.r, -1.0 / P->d.r, static_cast<T *>(grad), st));
+  prof_end(st, &ti);
+  return RTM_OK;
+}
+
+extern "C" rtm_status fwi_gradient(const rtm_plan *P, const void *m, const double *src_pos,
+                                   const void *q, const double *rec_pos, const void *d_obs,
+                                   const void *Z, rtm_dtype zt, void *Ubar, void *Vbar,
+                                   void *resid, void *grad, double *misfit, void *work,
+                                   size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  if (!src_pos || !q || !rec_pos || !d_obs || !Z || !Ubar || !Vbar || !resid || !grad || !misfit)
+    return fail(RTM_E_ARG, "fwi_gradient needs every array");
+  if ((s = check_probe(P, Z, zt, Ubar))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return gradient_impl<double>(P, m, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid, grad,
+                                 misfit, work, st);
+  return gradient_impl<float>(P, m, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid, grad,
+                              misfit, work, st);
+}

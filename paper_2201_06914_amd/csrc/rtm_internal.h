@@ -1,0 +1,106 @@
+// Internal interface between the host side of librtm (plan, point tables,
+// sweep sequencing) and its HIP kernels.  Not installed; the public ABI is
+// include/rtm.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace rtm {
+
+// What one stencil step needs.  The 8th-order weights arrive already divided
+// by h^2; cc = ndim * c[0] is the centre weight of the full Laplacian.  The
+// sponge term a = eta * dt / 2 is rebuilt per cell from integer depths:
+// a = kd * (dz^2 + dy^2 + dx^2) with d = cells into the layer, kd = A dt / (2 nb^2)
+// and A = 3 ln(1/R) / (2 nb h c_ref).
+template <typename T>
+struct StepArgs {
+  const T *__restrict__ cur;   // level s   (u^n, or lam^{n+1} in the adjoint)
+  const T *__restrict__ prev;  // level s-1
+  T *__restrict__ next;        // level s+1 (distinct ring slot)
+  const T *__restrict__ m;     // slowness squared
+  int nz, ny, nx;
+  int nb;
+  int64_t N;
+  T c1, c2, c3, c4;  // off-centre weights / h^2
+  T cc;              // ndim * centre weight / h^2
+  T dt2;             // dt^2
+  T kd;              // sponge coefficient per squared cell depth
+};
+
+// Point tables in CSR form (device pointers into the workspace).
+template <typename T>
+struct PointTables {
+  // sampling: per point p, entries [soff[p], soff[p+1]) of (sidx, sw)
+  const int32_t *soff = nullptr;
+  const int32_t *sidx = nullptr;
+  const T *sw = nullptr;
+  // injection: per distinct cell c, entries [ioff[c], ioff[c+1]) of (ipt, iw)
+  const int32_t *icell = nullptr;
+  const int32_t *ioff = nullptr;
+  const int32_t *ipt = nullptr;
+  const T *iw = nullptr;
+  int32_t npts = 0;
+  int32_t ncell = 0;
+};
+
+enum ProbeMode : int {
+  PROBE_CUR = 0,  // level s          (forward u^n)
+  PROBE_UTT = 1,  // levels s-1, s, s+1, second difference / dt^2
+  PROBE_NEW = 2   // level s+1        (adjoint lam^n)
+};
+
+// One probe-GEMM block: bar[i][x] += sum_{t < kb} Z[zrow0 + zdir t][i] * S_t[x]
+// for the sweep steps s0 .. s0+kb-1, where S_t is read from the level ring.
+template <typename T>
+struct ProbeArgs {
+  const T *ring;     // R slots of ld elements; sweep level j lives in slot (j+1) mod R
+  int64_t ld;        // slot stride (elements)
+  int R;
+  int s0, kb;
+  int zrow0, zdir;
+  int r;
+  int64_t N;
+  T *bar;            // [r][N]
+  T inv_dt2;
+  int mode;
+};
+
+// launchers (stream-ordered; return the launch status)
+template <typename T>
+hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, hipStream_t st);
+template <typename T>
+hipError_t launch_inject(const StepArgs<T> &a, const PointTables<T> &pt, const T *vals,
+                         T *field, hipStream_t st);
+template <typename T>
+hipError_t launch_sample(const PointTables<T> &pt, const T *field, T *out, hipStream_t st);
+template <typename T>
+hipError_t launch_probe_vec(const ProbeArgs<T> &p, const void *Z, bool z_is_i8,
+                            hipStream_t st);
+hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const int8_t *Z, bool split,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_image(const T *U, const T *V, int64_t N, int r, double scale, T *img,
+                        hipStream_t st);
+// res = d - d_obs (in place over d when res == d), misfit = 0.5 * sum res^2
+template <typename T>
+hipError_t launch_residual_misfit(const T *d, const T *dobs, T *res, int64_t n,
+                                  double *partials, double *misfit, hipStream_t st);
+template <typename T>
+hipError_t launch_dot(const T *a, const T *b, int64_t n, double *partials, double *out,
+                      hipStream_t st);
+
+constexpr int kReduceBlocks = 1024;  // partial sums of the two-pass reductions
+
+// Stencil variants: 0 = one thread per cell (any ndim, any dtype),
+// 1 = LDS-tiled z-marching (3D).  Both share the per-cell arithmetic, so they
+// give bitwise-identical levels.
+constexpr int kStencilSimple = 0;
+constexpr int kStencilTiled = 1;
+
+}  // namespace rtm

@@ -1,0 +1,308 @@
+// Finite-difference time step of the damped acoustic wave equation:
+//   next = [2 m cur - (m - a) prev + dt^2 L cur] / (m + a),   a = eta dt / 2,
+// L the 8th-order Laplacian with the field taken as zero outside the grid.
+// Forward and adjoint sweeps use the same step (the operator is symmetric).
+//
+// Two kernels share one per-cell arithmetic (cell_lap / cell_update), so their
+// results are bitwise identical:
+//   k_stencil_simple  one thread per cell, neighbours from global memory
+//                     (2D grids, FP64 3D, reference for the tiled kernel)
+//   k_stencil3d_tiled 3D: a TX x TY column tile per workgroup marches down a
+//                     z-chunk; the current plane (with a 4-cell x/y halo)
+//                     sits in LDS, double buffered, and the z neighbours in a
+//                     9-deep register queue per column.  Loads of plane z+1
+//                     are issued before plane z is computed.
+#include "rtm_internal.h"
+
+namespace rtm {
+
+__device__ __forceinline__ int sponge_depth(int i, int n, int nb) {
+  const int a = nb - i;
+  const int b = i - (n - 1 - nb);
+  const int d = a > b ? a : b;
+  return d > 0 ? d : 0;
+}
+
+template <typename T>
+__device__ __forceinline__ T sponge_a(const StepArgs<T> &a, int z, int y, int x) {
+  if (a.nb <= 0) return T(0);
+  const int dz = sponge_depth(z, a.nz, a.nb);
+  const int dy = a.ny > 1 ? sponge_depth(y, a.ny, a.nb) : 0;
+  const int dx = sponge_depth(x, a.nx, a.nb);
+  return a.kd * T(dz * dz + dy * dy + dx * dx);
+}
+
+// c1 (p1 + m1) + c2 (p2 + m2) + c3 (p3 + m3) + c4 (p4 + m4), fixed order
+template <typename T>
+__device__ __forceinline__ T axis_sum(const StepArgs<T> &a, T p1, T m1, T p2, T m2, T p3,
+                                      T m3, T p4, T m4) {
+  T s = a.c1 * (p1 + m1);
+  s += a.c2 * (p2 + m2);
+  s += a.c3 * (p3 + m3);
+  s += a.c4 * (p4 + m4);
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T cell_update(const StepArgs<T> &a, T u, T up, T m, T lap, T damp) {
+  return (T(2) * m * u - (m - damp) * up + a.dt2 * lap) / (m + damp);
+}
+
+// ---------------------------------------------------------------------------
+// one thread per cell
+// ---------------------------------------------------------------------------
+template <typename T, int NDIM>
+__global__ __launch_bounds__(256) void k_stencil_simple(StepArgs<T> a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.N) return;
+  const int x = (int)(i % a.nx);
+  const int64_t zy = i / a.nx;
+  const int y = (int)(zy % a.ny);
+  const int z = (int)(zy / a.ny);
+  const T *u = a.cur;
+  auto U = [&](int zz, int yy, int xx) -> T {
+    return (zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny && xx >= 0 && xx < a.nx)
+               ? u[((int64_t)zz * a.ny + yy) * a.nx + xx]
+               : T(0);
+  };
+  const T c = u[i];
+  const T lz = axis_sum(a, U(z + 1, y, x), U(z - 1, y, x), U(z + 2, y, x), U(z - 2, y, x),
+                        U(z + 3, y, x), U(z - 3, y, x), U(z + 4, y, x), U(z - 4, y, x));
+  const T lx = axis_sum(a, U(z, y, x + 1), U(z, y, x - 1), U(z, y, x + 2), U(z, y, x - 2),
+                        U(z, y, x + 3), U(z, y, x - 3), U(z, y, x + 4), U(z, y, x - 4));
+  T lap;
+  if constexpr (NDIM == 3) {
+    const T ly = axis_sum(a, U(z, y + 1, x), U(z, y - 1, x), U(z, y + 2, x), U(z, y - 2, x),
+                          U(z, y + 3, x), U(z, y - 3, x), U(z, y + 4, x), U(z, y - 4, x));
+    lap = ((a.cc * c + lz) + ly) + lx;
+  } else {
+    lap = (a.cc * c + lz) + lx;
+  }
+  a.next[i] = cell_update(a, c, a.prev[i], a.m[i], lap, sponge_a(a, z, y, x));
+}
+
+// ---------------------------------------------------------------------------
+// 3D LDS tile + z-marching register queue
+// ---------------------------------------------------------------------------
+template <typename T, int TX, int TYT, int RY>
+__global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int ntx, int nty,
+                                                             int nzc, int zchunk) {
+  constexpr int NT = TX * TYT;
+  constexpr int TY = TYT * RY;
+  constexpr int LX = TX + 8;
+  constexpr int LY = TY + 8;
+  constexpr int NHY = (8 + TYT - 1) / TYT;        // y-halo rows per thread
+  constexpr int NHX = (8 * TY + NT - 1) / NT;     // x-halo cells per thread
+  __shared__ T lds[2][LY * LX];
+
+  // XCD-aware order: consecutive hardware block ids go round-robin over the 8
+  // XCDs; give each XCD a contiguous run of tiles so halo re-reads hit its L2.
+  const int nblk = ntx * nty * nzc;
+  int b = blockIdx.x;
+  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  const int bx = b % ntx;
+  const int by = (b / ntx) % nty;
+  const int bz = b / (ntx * nty);
+
+  const int tid = threadIdx.x;
+  const int tx = tid % TX;
+  const int ty = tid / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int x = x0 + tx;
+  const int z0 = bz * zchunk;
+  const int z1 = min(z0 + zchunk, a.nz);
+  const int64_t sp = (int64_t)a.ny * a.nx;
+  const T *__restrict__ u = a.cur;
+
+  int yr[RY];
+  bool in[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    yr[j] = y0 + ty + j * TYT;
+    in[j] = (x < a.nx) && (yr[j] < a.ny);
+  }
+  auto ldu = [&](int zz, int yy, int xx) -> T {
+    return (zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny && xx >= 0 && xx < a.nx)
+               ? u[(int64_t)zz * sp + (int64_t)yy * a.nx + xx]
+               : T(0);
+  };
+  // halo bookkeeping: y-halo rows hy = ty + TYT*k (LDS rows 0..3 and TY+4..TY+7),
+  // x-halo cells t = tid + NT*k over TY rows x 8 columns
+  int hyr[NHY], hyg[NHY];
+  bool hyon[NHY];
+#pragma unroll
+  for (int k = 0; k < NHY; ++k) {
+    const int hy = ty + TYT * k;
+    hyon[k] = hy < 8;
+    hyr[k] = hy < 4 ? hy : TY + hy;
+    hyg[k] = y0 - 4 + hyr[k];
+  }
+  int hxr[NHX], hxc[NHX];
+  bool hxon[NHX];
+#pragma unroll
+  for (int k = 0; k < NHX; ++k) {
+    const int t = tid + NT * k;
+    hxon[k] = t < 8 * TY;
+    const int row = t / 8, col = t % 8;
+    hxr[k] = 4 + row;
+    hxc[k] = col < 4 ? col : TX + col;
+  }
+
+  T q[RY][9];
+  T front[RY], pv[RY], mm[RY], hyv[NHY], hxv[NHX];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[j][k] = ldu(z0 - 4 + k, yr[j], x);
+    front[j] = ldu(z0 + 4, yr[j], x);
+    const int64_t o = (int64_t)z0 * sp + (int64_t)yr[j] * a.nx + x;
+    pv[j] = in[j] ? a.prev[o] : T(0);
+    mm[j] = in[j] ? a.m[o] : T(1);
+  }
+#pragma unroll
+  for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z0, hyg[k], x) : T(0);
+#pragma unroll
+  for (int k = 0; k < NHX; ++k) hxv[k] = hxon[k] ? ldu(z0, y0 - 4 + hxr[k], x0 - 4 + hxc[k]) : T(0);
+
+  for (int z = z0; z < z1; ++z) {
+    T pvc[RY], mmc[RY], hyc[NHY], hxcv[NHX];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      q[j][8] = front[j];
+      pvc[j] = pv[j];
+      mmc[j] = mm[j];
+    }
+#pragma unroll
+    for (int k = 0; k < NHY; ++k) hyc[k] = hyv[k];
+#pragma unroll
+    for (int k = 0; k < NHX; ++k) hxcv[k] = hxv[k];
+    // prefetch plane z+1
+    if (z + 1 < z1) {
+#pragma unroll
+      for (int j = 0; j < RY; ++j) {
+        front[j] = ldu(z + 5, yr[j], x);
+        const int64_t o = (int64_t)(z + 1) * sp + (int64_t)yr[j] * a.nx + x;
+        pv[j] = in[j] ? a.prev[o] : T(0);
+        mm[j] = in[j] ? a.m[o] : T(1);
+      }
+#pragma unroll
+      for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z + 1, hyg[k], x) : T(0);
+#pragma unroll
+      for (int k = 0; k < NHX; ++k)
+        hxv[k] = hxon[k] ? ldu(z + 1, y0 - 4 + hxr[k], x0 - 4 + hxc[k]) : T(0);
+    }
+    T *L = lds[z & 1];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) L[(ty + j * TYT + 4) * LX + tx + 4] = q[j][4];
+#pragma unroll
+    for (int k = 0; k < NHY; ++k)
+      if (hyon[k]) L[hyr[k] * LX + tx + 4] = hyc[k];
+#pragma unroll
+    for (int k = 0; k < NHX; ++k)
+      if (hxon[k]) L[hxr[k] * LX + hxc[k]] = hxcv[k];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      const int ly = ty + j * TYT + 4, lx = tx + 4;
+      const T *row = L + ly * LX + lx;
+      const T c = q[j][4];
+      const T lz = axis_sum(a, q[j][5], q[j][3], q[j][6], q[j][2], q[j][7], q[j][1], q[j][8],
+                            q[j][0]);
+      const T lyv = axis_sum(a, row[LX], row[-LX], row[2 * LX], row[-2 * LX], row[3 * LX],
+                             row[-3 * LX], row[4 * LX], row[-4 * LX]);
+      const T lxv = axis_sum(a, row[1], row[-1], row[2], row[-2], row[3], row[-3], row[4],
+                             row[-4]);
+      const T lap = ((a.cc * c + lz) + lyv) + lxv;
+      if (in[j]) {
+        const int64_t o = (int64_t)z * sp + (int64_t)yr[j] * a.nx + x;
+        a.next[o] = cell_update(a, c, pvc[j], mmc[j], lap, sponge_a(a, z, yr[j], x));
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) q[j][k] = q[j][k + 1];
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, hipStream_t st) {
+  if (ndim == 3 && variant == kStencilTiled) {
+    constexpr int TX = 64, TYT = 4, RY = 4, TY = TYT * RY;
+    const int ntx = (a.nx + TX - 1) / TX;
+    const int nty = (a.ny + TY - 1) / TY;
+    // split z so that the launch has >= ~4 workgroups per CU on 256 CUs
+    int nzc = 1;
+    while ((int64_t)ntx * nty * nzc < 1024 && a.nz / (nzc * 2) >= 16) nzc *= 2;
+    const int zchunk = (a.nz + nzc - 1) / nzc;
+    nzc = (a.nz + zchunk - 1) / zchunk;
+    hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY>), dim3(ntx * nty * nzc),
+                       dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk);
+  } else {
+    const unsigned nblk = (unsigned)((a.N + 255) / 256);
+    if (ndim == 3)
+      hipLaunchKernelGGL((k_stencil_simple<T, 3>), dim3(nblk), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_stencil_simple<T, 2>), dim3(nblk), dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_stencil<float>(int, const StepArgs<float> &, int, hipStream_t);
+template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// point injection (after the step) and sampling
+// ---------------------------------------------------------------------------
+// field[cell] += dt^2 * (sum_j w_j vals[pt_j]) / (m + a): the source term of
+// the step added once the stencil part of the update is done.
+template <typename T>
+__global__ __launch_bounds__(256) void k_inject(StepArgs<T> a, PointTables<T> pt,
+                                                const T *__restrict__ vals, T *field) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= pt.ncell) return;
+  T acc = T(0);
+  for (int j = pt.ioff[c]; j < pt.ioff[c + 1]; ++j) acc += pt.iw[j] * vals[pt.ipt[j]];
+  const int64_t i = pt.icell[c];
+  const int x = (int)(i % a.nx);
+  const int64_t zy = i / a.nx;
+  const int y = (int)(zy % a.ny);
+  const int z = (int)(zy / a.ny);
+  field[i] += a.dt2 * acc / (a.m[i] + sponge_a(a, z, y, x));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample(PointTables<T> pt, const T *__restrict__ field,
+                                                T *__restrict__ out) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= pt.npts) return;
+  T s = T(0);
+  for (int j = pt.soff[p]; j < pt.soff[p + 1]; ++j) s += pt.sw[j] * field[pt.sidx[j]];
+  out[p] = s;
+}
+
+template <typename T>
+hipError_t launch_inject(const StepArgs<T> &a, const PointTables<T> &pt, const T *vals, T *field,
+                         hipStream_t st) {
+  if (pt.ncell <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_inject<T>), dim3((pt.ncell + 255) / 256), dim3(256), 0, st, a, pt, vals,
+                     field);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sample(const PointTables<T> &pt, const T *field, T *out, hipStream_t st) {
+  if (pt.npts <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sample<T>), dim3((pt.npts + 255) / 256), dim3(256), 0, st, pt, field,
+                     out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_inject<float>(const StepArgs<float> &, const PointTables<float> &,
+                                         const float *, float *, hipStream_t);
+template hipError_t launch_inject<double>(const StepArgs<double> &, const PointTables<double> &,
+                                          const double *, double *, hipStream_t);
+template hipError_t launch_sample<float>(const PointTables<float> &, const float *, float *,
+                                         hipStream_t);
+template hipError_t launch_sample<double>(const PointTables<double> &, const double *, double *,
+                                          hipStream_t);
+
+}  // namespace rtm
