@@ -92,14 +92,18 @@ def main():
     def step():
         return P.fwi_gradient(plan, m, src, q, rec, d_obs, Z, work=work, bars=bars)
 
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"warmup step {i} done", file=sys.stderr, flush=True)
     P.profile_enable(a.prof_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for i in range(a.steps):
         out = step()
+        if i + 1 < a.steps:      # one host round trip per step, for progress output
+            out["misfit"].item()
+            print(f"timed step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     P.profile_enable(0)

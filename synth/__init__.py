@@ -81,7 +81,7 @@ def pad_edge(v: np.ndarray, nb: int) -> np.ndarray:
     return np.pad(v, nb, mode="edge")
 
 
-def two_layer_2d(nz: int = 201, nx: int = 201, iface: int = 100,
+def two_layer_2d(nz: int = 201, nx: int = 201, iface: int = 50,
                  v1: float = 1500.0, v2: float = 2500.0) -> np.ndarray:
     v = np.full((nz, nx), v1, dtype=np.float64)
     v[iface:, :] = v2
@@ -173,7 +173,10 @@ class Workload:
 def workload_c1(dtype=np.float64) -> Workload:
     """2D two-layer acoustic case: 201x201 physical cells, h = 10 m, padded by
     10 damping cells per side, nt = 1000, dt = 1 ms, 15 Hz Ricker at
-    (x, z) = (1000 m, 20 m), 101 receivers at z = 20 m every 20 m, r = 32."""
+    (x, z) = (1000 m, 20 m), 101 receivers at z = 20 m every 20 m, r = 32.
+    The interface lies at 500 m depth so that its reflection returns within
+    the 1 s record (from 1000 m it would arrive at ~1.33 s and the residual
+    of the smoothed background would be round-off only)."""
     nb, h, dt, nt = 10, 10.0, 1e-3, 1000
     v_true = two_layer_2d()
     v0 = smooth(v_true, 5.0)

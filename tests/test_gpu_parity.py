@@ -3,6 +3,11 @@
 Tolerances:
   FP64 plans           1e-10 relative L2 (round-off of ~1e3 steps of double)
   FP32 propagation     1e-5  relative L2 on traces and final levels
+  FP32 compressed u_tt 5e-5: u_tt is the second difference of three FP32
+                       levels, which amplifies their rounding by about
+                       1/(omega dt)^2 (~175 at 12 Hz, dt = 1 ms): 2 eps_32 x 175
+                       ~ 2e-5 before the propagation error is added
+  FP32 compressed lam, image  2e-5
   BF16X2 probing       1e-4 on the compressed fields (16-bit operand mantissa,
                        2^-17 per term) and 1e-3 on the probed image
   plain BF16 probing   reported; its ~2^-9 operand rounding is expected to
@@ -111,7 +116,7 @@ def test_3d_f32_forward_adjoint_image(s3, probe):
     say("  " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()))
     assert e["d"] < 1e-5 and e["final"] < 1e-5
     if probe == "f32":
-        assert e["U"] < 1e-5 and e["V"] < 1e-5 and e["img"] < 1e-5
+        assert e["U"] < 5e-5 and e["V"] < 2e-5 and e["img"] < 2e-5
     elif probe == "bf16x2":
         assert e["U"] < 1e-4 and e["V"] < 1e-4 and e["img"] < 1e-3
     else:
