@@ -37,8 +37,8 @@ def parse():
     ap.add_argument("--probe", default="bf16x2", choices=["bf16x2", "bf16", "f32"])
     ap.add_argument("--prof-stride", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-planes", type=int, default=8)
-    ap.add_argument("--cpu-nt", type=int, default=20)
+    ap.add_argument("--cpu-planes", type=int, default=24)
+    ap.add_argument("--cpu-nt", type=int, default=80)
     return ap.parse_args()
 
 
