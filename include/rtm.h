@@ -29,8 +29,12 @@
  *
  * Conventions for every entry point:
  *   - Arrays are C order; a field is [nz][ny][nx] (x fastest, ny = 1 in 2D),
- *     N = nz*ny*nx cells.  Compressed fields are [r][N]; traces are
- *     [nt][npoints]; Z is [nt][r].
+ *     N = nz*ny*nx cells; traces are [nt][npoints]; Z is [nt][r].
+ *   - Compressed fields (Ubar, Vbar: r rows of N cells) are tile-major:
+ *     element (i, x) sits at ((x / 32) * r + i) * 32 + x % 32, in a buffer of
+ *     r * Npad elements, Npad = N rounded up to a multiple of 32 (padding
+ *     cells hold zeros).  One 32-cell tile's r x 32 block is contiguous, which
+ *     is what the probe GEMM streams.  rtm_bar_to_rows converts to [r][N].
  *   - "device" pointers are HIP device memory owned by the caller; "host"
  *     pointers are ordinary host memory read during the call only.
  *   - Field-typed arrays (m, q, d, res, Ubar, Vbar, image, grad) have the
@@ -139,7 +143,7 @@ const char *rtm_last_error(void);
  *   d_pred   device [nt][nrec]    d[n] = Pr u^{n+1}; may be NULL
  *   Z        device [nt][r]       dtype z_dtype (RTM_I8 for the BF16 paths,
  *                                 else RTM_I8 or the field dtype)
- *   Ubar     device [r][N]        overwritten
+ *   Ubar     device [r*Npad]      tile-major, overwritten
  *   final_state device [2][N]     u^{nt}, u^{nt-1}; may be NULL
  */
 rtm_status rtm_forward_probe(const rtm_plan *plan, const void *m, const double *src_pos,
@@ -153,7 +157,7 @@ rtm_status rtm_forward_probe(const rtm_plan *plan, const void *m, const double *
  *   rec_pos host [nrec][3], res device [nt][nrec] (the adjoint source)
  *   src_pos host [nsrc][3] and qadj device [nt][nsrc]: qadj[n] = Ps lam^n,
  *           the adjoint of the map q -> d_pred; both may be NULL
- *   Vbar    device [r][N] overwritten; may be NULL together with Z
+ *   Vbar    device [r*Npad] tile-major, overwritten; may be NULL together with Z
  */
 rtm_status rtm_adjoint_probe(const rtm_plan *plan, const void *m, const double *rec_pos,
                              const void *res, const double *src_pos, void *qadj,
@@ -167,13 +171,21 @@ rtm_status rtm_image(const rtm_plan *plan, const void *Ubar, const void *Vbar, d
 
 /* Probed FWI gradient of J = 1/2 sum |d_pred - d_obs|^2 (Eq. 2 estimated by
  * Eq. 3): forward probing u_tt, residual, adjoint probing, image with scale
- * -1/r.  Ubar, Vbar device [r][N] and resid device [nt][nrec] are outputs
- * (resid = d_pred - d_obs); grad device [N]; misfit device double [1].  */
+ * -1/r.  Ubar, Vbar device [r*Npad] (tile-major) and resid device [nt][nrec] are outputs
+ * (resid = d_pred - d_obs); grad device [N]; misfit device double [1].
+ * Vbar may be NULL on the BF16 / BF16X2 paths: the adjoint sweep then folds
+ * the imaging condition into its probe blocks (grad += -1/r sum_i Ubar[i]
+ * (Z_b^T Lambda_b)[i], equal to the image of Eq. 3 by linearity) and Vbar is
+ * never stored; the sum over blocks is then in float, not double. */
 rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_pos,
                         const void *q, const double *rec_pos, const void *d_obs,
                         const void *Z, rtm_dtype z_dtype, void *Ubar, void *Vbar,
                         void *resid, void *grad, double *misfit, void *work,
                         size_t work_bytes, rtm_stream stream);
+
+/* Converts a tile-major compressed field (device [r*Npad]) to rows (device
+ * [r][N], caller-owned): rows[i][x] = bar[((x/32)*r + i)*32 + x%32]. */
+rtm_status rtm_bar_to_rows(const rtm_plan *plan, const void *bar, void *rows, rtm_stream stream);
 
 /* Double-precision inner product of two device arrays of the plan's field
  * dtype: out[0] = sum_i a[i] b[i] (device double), deterministic order.

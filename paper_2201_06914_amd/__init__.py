@@ -7,6 +7,7 @@ The work runs in librtm.so (HIP kernels behind a C ABI, include/rtm.h); this
 package is its thin Python binding.  Importing it does not load the library;
 the first call does, and fails loudly if the library has not been built.
 """
-from .api import (Plan, PlanSpec, RtmError, cfl_bound, fwi_gradient, rtm_adjoint_probe,  # noqa: F401
+from .api import (Plan, PlanSpec, RtmError, bar_index, cfl_bound, fwi_gradient,  # noqa: F401
+                  rtm_adjoint_probe,
                   rtm_dot, rtm_forward_probe, rtm_image, set_stencil_variant,
-                  profile_enable, profile_read)
+                  profile_enable, profile_read, rtm_bar_to_rows)

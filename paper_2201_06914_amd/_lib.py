@@ -15,7 +15,7 @@ EXPORTS = (
     "rtm_plan_create", "rtm_plan_destroy", "rtm_plan_workspace_bytes", "rtm_cfl_bound",
     "rtm_status_str", "rtm_set_stencil_variant", "rtm_last_error", "rtm_forward_probe",
     "rtm_adjoint_probe", "rtm_image", "fwi_gradient", "rtm_dot", "rtm_profile_enable",
-    "rtm_profile_read",
+    "rtm_profile_read", "rtm_bar_to_rows",
 )
 
 
@@ -74,6 +74,8 @@ def load() -> ctypes.CDLL:
     L.fwi_gradient.restype = ctypes.c_int
     L.rtm_dot.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, sz, _vp]
     L.rtm_dot.restype = ctypes.c_int
+    L.rtm_bar_to_rows.argtypes = [_vp, _vp, _vp, _vp]
+    L.rtm_bar_to_rows.restype = ctypes.c_int
     L.rtm_profile_enable.argtypes = [i32]
     L.rtm_profile_enable.restype = None
     L.rtm_profile_read.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]

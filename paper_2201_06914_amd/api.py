@@ -75,6 +75,7 @@ class Plan:
         _check(L.rtm_plan_workspace_bytes(h, ctypes.byref(n)), "rtm_plan_workspace_bytes")
         self.workspace_bytes = int(n.value)
         self.N = int(np.prod(spec.shape))
+        self.Npad = (self.N + 31) // 32 * 32      # compressed fields: whole 32-cell tiles
         self.dtype = _TORCH[spec.field]
 
     @classmethod
@@ -98,6 +99,10 @@ class Plan:
 
     def workspace(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def empty_bar(self, device="cuda") -> torch.Tensor:
+        """A compressed-field buffer: tile-major [Npad/32][r][32]."""
+        return torch.empty((self.Npad // 32, self.spec.r, 32), dtype=self.dtype, device=device)
 
 
 def cfl_bound(ndim: int) -> float:
@@ -186,7 +191,7 @@ def rtm_forward_probe(plan: Plan, m, src_pos, q, rec_pos=None, Z=None, what: str
     dev = m.device
     out = {}
     d = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev) if want_d else None
-    U = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev) if Z is not None else None
+    U = plan.empty_bar(dev) if Z is not None else None
     F = torch.empty((2, plan.N), dtype=plan.dtype, device=dev) if final else None
     work = _work(plan, work, dev)
     sp, spp = _pos(src_pos, s.nsrc, "src_pos")
@@ -196,7 +201,7 @@ def rtm_forward_probe(plan: Plan, m, src_pos, q, rec_pos=None, Z=None, what: str
         plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
         _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp, _dev(d, plan.dtype, s.nt * s.nrec, "d"),
         zp, zt, _lib.RTM_PROBE_UTT if what == "utt" else _lib.RTM_PROBE_U,
-        _dev(U, plan.dtype, s.r * plan.N, "Ubar"), _dev(F, plan.dtype, 2 * plan.N, "final"),
+        _dev(U, plan.dtype, s.r * plan.Npad, "Ubar"), _dev(F, plan.dtype, 2 * plan.N, "final"),
         ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(dev))
     _check(code, "rtm_forward_probe")
     if d is not None:
@@ -212,7 +217,7 @@ def rtm_adjoint_probe(plan: Plan, m, rec_pos, res, Z=None, src_pos=None, want_qa
                       work=None) -> dict:
     s = plan.spec
     dev = m.device
-    V = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev) if Z is not None else None
+    V = plan.empty_bar(dev) if Z is not None else None
     qa = torch.empty((s.nt, s.nsrc), dtype=plan.dtype, device=dev) if want_qadj else None
     work = _work(plan, work, dev)
     rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
@@ -222,7 +227,7 @@ def rtm_adjoint_probe(plan: Plan, m, rec_pos, res, Z=None, src_pos=None, want_qa
         plan.handle, _dev(m, plan.dtype, plan.N, "m"), rpp,
         _dev(res, plan.dtype, s.nt * s.nrec, "res"), spp,
         _dev(qa, plan.dtype, s.nt * s.nsrc, "qadj"), zp, zt,
-        _dev(V, plan.dtype, s.r * plan.N, "Vbar"), ctypes.c_void_p(work.data_ptr()),
+        _dev(V, plan.dtype, s.r * plan.Npad, "Vbar"), ctypes.c_void_p(work.data_ptr()),
         work.numel(), _stream(dev))
     _check(code, "rtm_adjoint_probe")
     out = {}
@@ -238,21 +243,26 @@ def rtm_image(plan: Plan, Ubar, Vbar, scale: float | None = None) -> torch.Tenso
     scale = 1.0 / s.r if scale is None else scale
     img = torch.empty(plan.N, dtype=plan.dtype, device=Ubar.device)
     _check(_lib.load().rtm_image(
-        plan.handle, _dev(Ubar, plan.dtype, s.r * plan.N, "Ubar"),
-        _dev(Vbar, plan.dtype, s.r * plan.N, "Vbar"), float(scale),
+        plan.handle, _dev(Ubar, plan.dtype, s.r * plan.Npad, "Ubar"),
+        _dev(Vbar, plan.dtype, s.r * plan.Npad, "Vbar"), float(scale),
         _dev(img, plan.dtype, plan.N, "image"), _stream(Ubar.device)), "rtm_image")
     return img
 
 
-def fwi_gradient(plan: Plan, m, src_pos, q, rec_pos, d_obs, Z, work=None, bars=None) -> dict:
-    """Probed FWI gradient.  `bars` may pass preallocated (Ubar, Vbar)."""
+def fwi_gradient(plan: Plan, m, src_pos, q, rec_pos, d_obs, Z, work=None, bars=None,
+                 fused: bool = False) -> dict:
+    """Probed FWI gradient.  `bars` may pass preallocated (Ubar, Vbar).  With
+    fused=True (BF16 probe paths) the imaging condition is folded into the
+    adjoint probe blocks and no Vbar is produced."""
     s = plan.spec
     dev = m.device
     if bars is None:
-        U = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev)
-        V = torch.empty((s.r, plan.N), dtype=plan.dtype, device=dev)
+        U = plan.empty_bar(dev)
+        V = None if fused else plan.empty_bar(dev)
     else:
         U, V = bars
+        if fused:
+            V = None
     res = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev)
     g = torch.empty(plan.N, dtype=plan.dtype, device=dev)
     J = torch.empty(1, dtype=torch.float64, device=dev)
@@ -264,12 +274,30 @@ def fwi_gradient(plan: Plan, m, src_pos, q, rec_pos, d_obs, Z, work=None, bars=N
         plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
         _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp,
         _dev(d_obs, plan.dtype, s.nt * s.nrec, "d_obs"), zp, zt,
-        _dev(U, plan.dtype, s.r * plan.N, "Ubar"), _dev(V, plan.dtype, s.r * plan.N, "Vbar"),
+        _dev(U, plan.dtype, s.r * plan.Npad, "Ubar"), _dev(V, plan.dtype, s.r * plan.Npad, "Vbar"),
         _dev(res, plan.dtype, s.nt * s.nrec, "resid"), _dev(g, plan.dtype, plan.N, "grad"),
         _dev(J, torch.float64, 1, "misfit"), ctypes.c_void_p(work.data_ptr()), work.numel(),
         _stream(dev))
     _check(code, "fwi_gradient")
     return {"grad": g, "misfit": J, "Ubar": U, "Vbar": V, "resid": res}
+
+
+def rtm_bar_to_rows(plan: Plan, bar) -> torch.Tensor:
+    """Tile-major compressed field -> [r][N] rows (a copy, made on the GPU)."""
+    s = plan.spec
+    rows = torch.empty((s.r, plan.N), dtype=plan.dtype, device=bar.device)
+    _check(_lib.load().rtm_bar_to_rows(plan.handle, _dev(bar, plan.dtype, s.r * plan.Npad, "bar"),
+                                       _dev(rows, plan.dtype, s.r * plan.N, "rows"),
+                                       _stream(bar.device)), "rtm_bar_to_rows")
+    return rows
+
+
+def bar_index(plan: Plan, cells, rows=None) -> np.ndarray:
+    """Flat positions in a tile-major compressed field of (row i, cell x) for
+    the given cells (all rows, or the given rows): [len(rows)][len(cells)]."""
+    x = np.asarray(cells, dtype=np.int64)
+    i = np.arange(plan.spec.r, dtype=np.int64) if rows is None else np.asarray(rows, np.int64)
+    return ((x[None, :] // 32) * plan.spec.r + i[:, None]) * 32 + x[None, :] % 32
 
 
 def rtm_dot(plan: Plan, a, b, work=None) -> torch.Tensor:

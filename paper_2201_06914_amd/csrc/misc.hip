@@ -47,15 +47,17 @@ template hipError_t launch_fill<double>(double *, int64_t, double, hipStream_t);
 template hipError_t launch_copy<float>(float *, const float *, int64_t, hipStream_t);
 template hipError_t launch_copy<double>(double *, const double *, int64_t, hipStream_t);
 
-// image[x] = scale * sum_i U[i][x] V[i][x]  (Eq. 3), summed in double
+// image[x] = scale * sum_i U[i][x] V[i][x]  (Eq. 3), summed in double.
+// U, V tile-major: (i, x) at ((x / 32) r + i) 32 + x % 32.
 template <typename T>
 __global__ __launch_bounds__(256) void k_image(const T *__restrict__ U, const T *__restrict__ V,
                                                int64_t N, int r, double scale,
                                                T *__restrict__ img) {
   for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < N;
        x += (int64_t)gridDim.x * 256) {
+    const int64_t base = (x >> 5) * r * 32 + (x & 31);
     double acc = 0.0;
-    for (int i = 0; i < r; ++i) acc += (double)U[(int64_t)i * N + x] * (double)V[(int64_t)i * N + x];
+    for (int i = 0; i < r; ++i) acc += (double)U[base + i * 32] * (double)V[base + i * 32];
     img[x] = (T)(scale * acc);
   }
 }

@@ -4,12 +4,15 @@
 //     bar[r][N] += Z_b^T (r x k) * S_b (k x N).
 // This is the one dense contraction of the method.
 //
+// Compressed fields are stored tile-major: element (i, x) at
+//     ((x / 32) * r + i) * 32 + x % 32,
+// so the r x 32 block of one 32-cell tile is contiguous (16 KB at r = 128).
+//
 //   k_probe_mfma  +-1 probes on MFMA: v_mfma_f32_32x32x16_bf16, FP32
 //                 accumulate.  Z (+-1) is exact in bf16; S is rounded to bf16
 //                 (plain) or split into bf16 hi + bf16 lo (two MFMAs, 16-bit
-//                 mantissa).  One wave owns 32 cells and all r rows; the
-//                 accumulator tile is loaded from / stored to bar directly
-//                 (128-byte rows), Z sits in LDS in A-operand order.
+//                 mantissa).  One wave owns one 32-cell tile and up to 128
+//                 probe rows at a time; Z sits in LDS in A-operand order.
 //   k_probe_vec   FP64 / FP32 FMA path (any real Z), thread per cell, 32
 //                 probe rows per pass; the accumulation order is the per-step
 //                 order bar += z_n s^n.
@@ -20,10 +23,11 @@ namespace rtm {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
+// level j of the block, s0 - 1 <= j <= s0 + R - 2 (one wrap at most)
 template <typename T>
 __device__ __forceinline__ const T *ring_level(const ProbeArgs<T> &p, int j) {
-  int slot = (j + 1) % p.R;
-  if (slot < 0) slot += p.R;
+  int slot = p.slot0 + (j - p.s0 + 1);
+  if (slot >= p.R) slot -= p.R;
   return p.ring + (int64_t)slot * p.ld;
 }
 
@@ -38,6 +42,10 @@ __device__ __forceinline__ T probed(const ProbeArgs<T> &p, int t, int64_t c) {
     return (un - T(2) * u0 + um) * p.inv_dt2;
   }
   return ring_level(p, p.mode == PROBE_NEW ? s + 1 : s)[c];
+}
+
+__device__ __forceinline__ int64_t bar_index(int64_t x, int i, int r) {
+  return ((x >> 5) * r + i) * 32 + (x & 31);
 }
 
 // ---------------------------------------------------------------------------
@@ -61,7 +69,7 @@ __global__ __launch_bounds__(256) void k_probe_vec(ProbeArgs<T> p, const ZT *__r
     if (!valid) continue;
     T acc[RC];
 #pragma unroll
-    for (int i = 0; i < RC; ++i) acc[i] = i < rc ? p.bar[(int64_t)(r0 + i) * p.N + c] : T(0);
+    for (int i = 0; i < RC; ++i) acc[i] = i < rc ? p.bar[bar_index(c, r0 + i, p.r)] : T(0);
     for (int t = 0; t < p.kb; ++t) {
       const T s = probed(p, t, c);
 #pragma unroll
@@ -69,7 +77,7 @@ __global__ __launch_bounds__(256) void k_probe_vec(ProbeArgs<T> p, const ZT *__r
     }
 #pragma unroll
     for (int i = 0; i < RC; ++i)
-      if (i < rc) p.bar[(int64_t)(r0 + i) * p.N + c] = acc[i];
+      if (i < rc) p.bar[bar_index(c, r0 + i, p.r)] = acc[i];
   }
 }
 
@@ -97,14 +105,20 @@ template hipError_t launch_probe_vec<double>(const ProbeArgs<double> &, const vo
 //   A (32 x 16): lane l holds A[l % 32][8 (l / 32) + v], v = 0..7
 //   B (16 x 32): lane l holds B[8 (l / 32) + v][l % 32]
 //   C (32 x 32): lane l, register v holds C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]
-template <int KS, bool SPLIT, int MODE>
-__global__ __launch_bounds__(256) void k_probe_mfma(ProbeArgs<float> p,
-                                                    const int8_t *__restrict__ Z, int MT) {
-  extern __shared__ bf16x8 ldsA[];  // [MT][KS][64]
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  // A = Z_b^T: A[i][t] = Z[zrow0 + zdir t][i], zero for t >= kb or i >= r
-  for (int e = threadIdx.x; e < MT * KS * 64; e += 256) {
+// In the tile-major layout the C element of lane l, register v of row tile mt
+// sits at tile_base + (mt * 32 + 8 (v / 4) + v % 4) * 32 + (4 (l / 32) * 32 + l % 32):
+// one wave-uniform base, one per-lane offset, and immediate row offsets.
+//
+// FUSED (adjoint): instead of bar += W with W = Z_b^T S_b, the block's W is
+// contracted with the forward compressed field right away,
+//     img[c] += scale * sum_i Uf[i][c] W[i][c],
+// which sums to the probed image of Eq. 3 over the blocks (linearity) without
+// ever storing Vbar.
+// Z_b^T in A-operand order: ldsA[(mt KS + ks) 64 + l] holds A[mt 32 + l % 32][ks 16 + 8 (l / 32) + 0..7]
+// with A[i][t] = Z[zrow0 + zdir t][i], zero for t >= kb or i >= r.
+__device__ __forceinline__ void fill_probe_lds(const ProbeArgs<float> &p, const int8_t *Z, int MT,
+                                               int KS, bf16x8 *ldsA) {
+  for (int e = threadIdx.x; e < MT * KS * 64; e += blockDim.x) {
     const int l = e & 63;
     const int ks = (e >> 6) % KS;
     const int mt = (e >> 6) / KS;
@@ -120,50 +134,166 @@ __global__ __launch_bounds__(256) void k_probe_mfma(ProbeArgs<float> p,
     ldsA[e] = v;
   }
   __syncthreads();
+}
 
-  const int64_t ntiles = (p.N + 31) / 32;
+// The B operand of step chunk ks for this lane: its 8 probed values (local
+// steps tb .. tb+7, tb = 16 ks + 8 half), rounded to bf16 (hi) and, with
+// SPLIT, the bf16 rounding of the remainder (lo).  FAST: no masking needed.
+template <int MODE, bool SPLIT, bool FAST>
+__device__ __forceinline__ void probe_operand(const ProbeArgs<float> &p, int ks, int half,
+                                              int64_t c, bool valid, bf16x8 &bhi, bf16x8 &blo) {
+  const int tb = ks * 16 + 8 * half;
+  float sv[8];
+  if (MODE == PROBE_UTT) {
+    float lv[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const int t = tb + q - 1;  // level s0 + t, inside [-1, kb] whenever FAST
+      const bool ok = FAST || (valid && t >= -1 && t <= p.kb);
+      lv[q] = ok ? ring_level(p, p.s0 + t)[c] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float d2 = (lv[q + 2] - 2.f * lv[q + 1] + lv[q]) * p.inv_dt2;
+      sv[q] = (FAST || tb + q < p.kb) ? d2 : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int t = tb + q;
+      const int lev = p.s0 + t + (MODE == PROBE_NEW ? 1 : 0);
+      const bool ok = FAST || (valid && t < p.kb);
+      sv[q] = ok ? ring_level(p, lev)[c] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const __bf16 hb = (__bf16)sv[q];
+    bhi[q] = hb;
+    if (SPLIT) blo[q] = (__bf16)(sv[q] - (float)hb);
+  }
+}
+
+// Fast kernel: full 32-cell tiles [0, tile_end), kb == 16 KS, MT % MTC == 0 -
+// no load or store is masked.  MTC row tiles (32 probes each) are accumulated
+// together, so their 16 x MTC loads per lane are in flight at once.
+template <int KS, bool SPLIT, int MODE, bool FUSED, int MTC>
+__global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
+                                                         const int8_t *__restrict__ Z, int MT,
+                                                         const float *__restrict__ Uf,
+                                                         float *__restrict__ img, float scale,
+                                                         int64_t tile_end) {
+  extern __shared__ bf16x8 ldsA[];
+  fill_probe_lds(p, Z, MT, KS, ldsA);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int col = lane & 31;
   const int half = lane >> 5;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles;
+  const int loff = half * 4 * 32 + col;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tile_end;
+       tile += (int64_t)gridDim.x * 4) {
+    const int64_t c = tile * 32 + col;
+    const int64_t tbase = tile * (int64_t)p.r * 32;
+    // short blocks: build every step chunk's operand once per tile; long
+    // blocks (KS >= 4): build each right before its MFMAs to bound registers
+    constexpr bool kEarly = KS <= 2;
+    bf16x8 bhi_e[kEarly ? KS : 1], blo_e[kEarly ? KS : 1];
+    if (kEarly) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        probe_operand<MODE, SPLIT, true>(p, ks, half, c, true, bhi_e[kEarly ? ks : 0],
+                                         blo_e[kEarly ? ks : 0]);
+    }
+    float part = 0.f;
+    for (int mt0 = 0; mt0 < MT; mt0 += MTC) {
+      f32x16 acc[MTC];
+      if (FUSED) {
+#pragma unroll
+        for (int j = 0; j < MTC; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[j][v] = 0.f;
+      } else {
+        const float *Ut = p.bar + tbase + mt0 * 32 * 32 + loff;
+#pragma unroll
+        for (int j = 0; j < MTC; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[j][v] = Ut[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32];
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        bf16x8 bhi, blo;
+        if (kEarly) {
+          bhi = bhi_e[kEarly ? ks : 0];
+          blo = blo_e[kEarly ? ks : 0];
+        } else {
+          __builtin_amdgcn_sched_barrier(0);
+          probe_operand<MODE, SPLIT, true>(p, ks, half, c, true, bhi, blo);
+        }
+#pragma unroll
+        for (int j = 0; j < MTC; ++j) {
+          const bf16x8 a = ldsA[((mt0 + j) * KS + ks) * 64 + lane];
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bhi, acc[j], 0, 0, 0);
+          if (SPLIT) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo, acc[j], 0, 0, 0);
+        }
+      }
+      if (FUSED) {
+        const float *Ut = Uf + tbase + mt0 * 32 * 32 + loff;
+#pragma unroll
+        for (int j = 0; j < MTC; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) part += Ut[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32] * acc[j][v];
+      } else {
+        float *Uo = p.bar + tbase + mt0 * 32 * 32 + loff;
+#pragma unroll
+        for (int j = 0; j < MTC; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) Uo[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32] = acc[j][v];
+      }
+    }
+    if (FUSED) {
+      part += __shfl_xor(part, 32, 64);  // the two lanes that share cell c
+      if (half == 0) img[c] += scale * part;
+    }
+  }
+}
+
+// Edge kernel: tiles [tile_begin, ntiles) with any masking (ragged last tile,
+// a block shorter than 16 KS, r not a multiple of 32).  One row tile at a time.
+template <int KS, bool SPLIT, int MODE, bool FUSED>
+__global__ __launch_bounds__(256) void k_probe_mfma_edge(ProbeArgs<float> p,
+                                                         const int8_t *__restrict__ Z, int MT,
+                                                         const float *__restrict__ Uf,
+                                                         float *__restrict__ img, float scale,
+                                                         int64_t tile_begin) {
+  extern __shared__ bf16x8 ldsA[];
+  fill_probe_lds(p, Z, MT, KS, ldsA);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int col = lane & 31;
+  const int half = lane >> 5;
+  const int loff = half * 4 * 32 + col;
+  const int64_t ntiles = (p.N + 31) / 32;
+  for (int64_t tile = tile_begin + (int64_t)blockIdx.x * 4 + wave; tile < ntiles;
        tile += (int64_t)gridDim.x * 4) {
     const int64_t c = tile * 32 + col;
     const bool valid = c < p.N;
+    const int64_t tbase = tile * (int64_t)p.r * 32;
     bf16x8 bhi[KS], blo[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int tb = ks * 16 + 8 * half;  // first local step of this lane's 8
-      float sv[8];
-      if (MODE == PROBE_UTT) {
-        float lv[10];
-#pragma unroll
-        for (int q = 0; q < 10; ++q) {
-          const int t = tb + q - 1;  // level s0 + t
-          lv[q] = (valid && t >= -1 && t <= p.kb) ? ring_level(p, p.s0 + t)[c] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          sv[q] = (tb + q < p.kb) ? (lv[q + 2] - 2.f * lv[q + 1] + lv[q]) * p.inv_dt2 : 0.f;
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int t = tb + q;
-          const int lev = p.s0 + t + (MODE == PROBE_NEW ? 1 : 0);
-          sv[q] = (valid && t < p.kb) ? ring_level(p, lev)[c] : 0.f;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const __bf16 hb = (__bf16)sv[q];
-        bhi[ks][q] = hb;
-        if (SPLIT) blo[ks][q] = (__bf16)(sv[q] - (float)hb);
-      }
-    }
+    for (int ks = 0; ks < KS; ++ks)
+      probe_operand<MODE, SPLIT, false>(p, ks, half, c, valid, bhi[ks], blo[ks]);
+    float part = 0.f;
     for (int mt = 0; mt < MT; ++mt) {
+      const float *Ut = (FUSED ? Uf : p.bar) + tbase + mt * 32 * 32 + loff;
       f32x16 acc;
+      float uf[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int row = mt * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-        acc[v] = (valid && row < p.r) ? p.bar[(int64_t)row * p.N + c] : 0.f;
+        const int rr = 8 * (v >> 2) + (v & 3);
+        const bool ok = valid && mt * 32 + rr + 4 * half < p.r;
+        const float val = ok ? Ut[rr * 32] : 0.f;
+        acc[v] = FUSED ? 0.f : val;
+        uf[v] = val;
       }
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
@@ -171,59 +301,121 @@ __global__ __launch_bounds__(256) void k_probe_mfma(ProbeArgs<float> p,
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bhi[ks], acc, 0, 0, 0);
         if (SPLIT) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[ks], acc, 0, 0, 0);
       }
+      float *Uo = p.bar + tbase + mt * 32 * 32 + loff;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int row = mt * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-        if (valid && row < p.r) p.bar[(int64_t)row * p.N + c] = acc[v];
+        const int rr = 8 * (v >> 2) + (v & 3);
+        if (FUSED)
+          part += uf[v] * acc[v];
+        else if (valid && mt * 32 + rr + 4 * half < p.r)
+          Uo[rr * 32] = acc[v];
       }
+    }
+    if (FUSED) {
+      part += __shfl_xor(part, 32, 64);
+      if (half == 0 && valid) img[c] += scale * part;
     }
   }
 }
 
+struct FuseArgs {
+  const float *Uf = nullptr;
+  float *img = nullptr;
+  float scale = 0.f;
+};
+
+template <int KS, bool SPLIT, int MODE, bool FUSED>
+static void launch_probe_kernels(const ProbeArgs<float> &p, const int8_t *Z, int MT,
+                                 const FuseArgs &f, hipStream_t st) {
+  const size_t shm = sizeof(bf16x8) * (size_t)MT * KS * 64;
+  const int64_t ntiles = (p.N + 31) / 32;
+  const int64_t nfull = p.N / 32;
+  auto grid_for = [](int64_t tiles) -> unsigned {
+    const int64_t want = (tiles + 3) / 4;
+    return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+  };
+  // the fast kernel reads and writes whole 32-row tiles and whole 16-step chunks
+  const bool fastk = p.kb == 16 * KS && p.r % 32 == 0;
+  int64_t done = 0;
+  if (fastk && nfull > 0 && MT % 4 == 0 && !FUSED) {
+    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 4>), dim3(grid_for(nfull)),
+                       dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
+    done = nfull;
+  } else if (fastk && nfull > 0 && MT % 2 == 0) {
+    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 2>), dim3(grid_for(nfull)),
+                       dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
+    done = nfull;
+  }
+  if (done < ntiles)
+    hipLaunchKernelGGL((k_probe_mfma_edge<KS, SPLIT, MODE, FUSED>), dim3(grid_for(ntiles - done)),
+                       dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, done);
+}
+
 template <int KS, bool SPLIT>
-static void launch_mfma_mode(const ProbeArgs<float> &p, const int8_t *Z, int MT, unsigned grid,
-                             size_t shm, hipStream_t st) {
+static void launch_mfma_mode(const ProbeArgs<float> &p, const int8_t *Z, int MT,
+                             const FuseArgs &f, hipStream_t st) {
+  if (f.img) {  // fused imaging: adjoint levels only
+    launch_probe_kernels<KS, SPLIT, PROBE_NEW, true>(p, Z, MT, f, st);
+    return;
+  }
   switch (p.mode) {
-    case PROBE_UTT:
-      hipLaunchKernelGGL((k_probe_mfma<KS, SPLIT, PROBE_UTT>), dim3(grid), dim3(256), shm, st, p,
-                         Z, MT);
-      break;
-    case PROBE_NEW:
-      hipLaunchKernelGGL((k_probe_mfma<KS, SPLIT, PROBE_NEW>), dim3(grid), dim3(256), shm, st, p,
-                         Z, MT);
-      break;
-    default:
-      hipLaunchKernelGGL((k_probe_mfma<KS, SPLIT, PROBE_CUR>), dim3(grid), dim3(256), shm, st, p,
-                         Z, MT);
+    case PROBE_UTT: launch_probe_kernels<KS, SPLIT, PROBE_UTT, false>(p, Z, MT, f, st); break;
+    case PROBE_NEW: launch_probe_kernels<KS, SPLIT, PROBE_NEW, false>(p, Z, MT, f, st); break;
+    default: launch_probe_kernels<KS, SPLIT, PROBE_CUR, false>(p, Z, MT, f, st);
   }
 }
 
 template <int KS>
 static void launch_mfma_ks(const ProbeArgs<float> &p, const int8_t *Z, bool split, int MT,
-                           unsigned grid, size_t shm, hipStream_t st) {
+                           const FuseArgs &f, hipStream_t st) {
   if (split)
-    launch_mfma_mode<KS, true>(p, Z, MT, grid, shm, st);
+    launch_mfma_mode<KS, true>(p, Z, MT, f, st);
   else
-    launch_mfma_mode<KS, false>(p, Z, MT, grid, shm, st);
+    launch_mfma_mode<KS, false>(p, Z, MT, f, st);
 }
 
 hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const int8_t *Z, bool split,
-                             hipStream_t st) {
+                             const float *Uf, float *img, float scale, hipStream_t st) {
+  const FuseArgs f{Uf, img, scale};
   const int MT = (p.r + 31) / 32;
   int KS = (p.kb + 15) / 16;
   KS = KS <= 1 ? 1 : KS <= 2 ? 2 : KS <= 4 ? 4 : 8;
   if (p.kb > 128) return hipErrorInvalidValue;
-  const size_t shm = sizeof(bf16x8) * (size_t)MT * KS * 64;
-  const int64_t ntiles = (p.N + 31) / 32;
-  int64_t want = (ntiles + 3) / 4;
-  const unsigned grid = (unsigned)(want < 2048 ? want : 2048);
   switch (KS) {
-    case 1: launch_mfma_ks<1>(p, Z, split, MT, grid, shm, st); break;
-    case 2: launch_mfma_ks<2>(p, Z, split, MT, grid, shm, st); break;
-    case 4: launch_mfma_ks<4>(p, Z, split, MT, grid, shm, st); break;
-    default: launch_mfma_ks<8>(p, Z, split, MT, grid, shm, st); break;
+    case 1: launch_mfma_ks<1>(p, Z, split, MT, f, st); break;
+    case 2: launch_mfma_ks<2>(p, Z, split, MT, f, st); break;
+    case 4: launch_mfma_ks<4>(p, Z, split, MT, f, st); break;
+    default: launch_mfma_ks<8>(p, Z, split, MT, f, st); break;
   }
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// layout conversion: tile-major compressed field -> rows [r][N]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_bar_to_rows(const T *__restrict__ bar, int64_t N, int r,
+                                                     T *__restrict__ rows) {
+  const int64_t total = (int64_t)r * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e / N);
+    const int64_t x = e - (int64_t)i * N;
+    rows[e] = bar[bar_index(x, i, r)];
+  }
+}
+
+template <typename T>
+hipError_t launch_bar_to_rows(const T *bar, int64_t N, int r, T *rows, hipStream_t st) {
+  const int64_t total = (int64_t)r * N;
+  if (total <= 0) return hipSuccess;
+  int64_t b = (total + 255) / 256;
+  hipLaunchKernelGGL((k_bar_to_rows<T>), dim3((unsigned)(b < 16384 ? b : 16384)), dim3(256), 0,
+                     st, bar, N, r, rows);
+  return hipGetLastError();
+}
+template hipError_t launch_bar_to_rows<float>(const float *, int64_t, int, float *, hipStream_t);
+template hipError_t launch_bar_to_rows<double>(const double *, int64_t, int, double *,
+                                               hipStream_t);
 
 }  // namespace rtm

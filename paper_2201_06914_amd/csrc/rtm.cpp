@@ -102,6 +102,7 @@ struct PointRegion {  // device layout of one point set's tables
 struct rtm_plan {
   rtm_desc d;
   int64_t N = 0, ld = 0;
+  int64_t Npad = 0;  // N rounded up to whole 32-cell tiles (compressed-field layout)
   int R = 0;
   size_t esz = 0;
   Region ring, red;
@@ -228,6 +229,7 @@ extern "C" rtm_status rtm_plan_create(const rtm_desc *desc, rtm_plan **out) {
   p->d = d;
   p->N = N;
   p->ld = (N + 63) / 64 * 64;
+  p->Npad = (N + 31) / 32 * 32;
   p->R = d.k_block + 2;
   p->esz = d.field_dtype == RTM_F64 ? 8 : 4;
   size_t cur = 0;
@@ -411,6 +413,10 @@ struct SweepIO {
   int mode = PROBE_UTT;
   void *bar = nullptr;             // [r][N] or NULL
   void *final_state = nullptr;     // [2][N] or NULL
+  // fused adjoint imaging (MFMA paths): img += scale * sum_i fuse_U[i] (Z_b^T S_b)[i]
+  const void *fuse_U = nullptr;
+  void *fuse_img = nullptr;
+  double fuse_scale = 0.0;
 };
 
 template <typename T>
@@ -430,7 +436,7 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
   HIP_TRY(launch_fill<T>(level(-1), P->N, T(0), st));
   HIP_TRY(launch_fill<T>(level(0), P->N, T(0), st));
   T *bar = static_cast<T *>(io.bar);
-  if (bar) HIP_TRY(launch_fill<T>(bar, (int64_t)d.r * P->N, T(0), st));
+  if (bar) HIP_TRY(launch_fill<T>(bar, (int64_t)d.r * P->Npad, T(0), st));
   const T *inj_vals = static_cast<const T *>(io.inj_vals);
   T *smp_out = static_cast<T *>(io.smp_out);
   int s0 = 0;
@@ -447,12 +453,13 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       HIP_TRY(launch_inject<T>(a, inj, inj_vals + (int64_t)n * inj.npts, a.next, st));
     if (smp_out && smp.npts > 0)
       HIP_TRY(launch_sample<T>(smp, a.next, smp_out + (int64_t)n * smp.npts, st));
-    if (bar && (s + 1 - s0 == d.k_block || s == d.nt - 1)) {
+    if ((bar || io.fuse_img) && (s + 1 - s0 == d.k_block || s == d.nt - 1)) {
       ProbeArgs<T> p{};
       p.ring = ring;
       p.ld = P->ld;
       p.R = P->R;
       p.s0 = s0;
+      p.slot0 = s0 % P->R;
       p.kb = s + 1 - s0;
       p.zrow0 = io.adjoint ? d.nt - 1 - s0 : s0;
       p.zdir = io.adjoint ? -1 : 1;
@@ -466,7 +473,9 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       if constexpr (sizeof(T) == 4) {
         if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
           HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io.Z),
-                                    d.probe_dtype == RTM_BF16X2, st));
+                                    d.probe_dtype == RTM_BF16X2,
+                                    static_cast<const float *>(io.fuse_U),
+                                    static_cast<float *>(io.fuse_img), (float)io.fuse_scale, st));
         } else {
           HIP_TRY(launch_probe_vec<T>(p, io.Z, io.zt == RTM_I8, st));
         }
@@ -602,6 +611,20 @@ extern "C" rtm_status rtm_image(const rtm_plan *P, const void *U, const void *V,
   return RTM_OK;
 }
 
+extern "C" rtm_status rtm_bar_to_rows(const rtm_plan *P, const void *bar, void *rows,
+                                      rtm_stream stream) {
+  g_last_error.clear();
+  if (!P || !bar || !rows) return fail(RTM_E_ARG, "NULL argument");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    HIP_TRY(launch_bar_to_rows<double>(static_cast<const double *>(bar), P->N, P->d.r,
+                                       static_cast<double *>(rows), st));
+  else
+    HIP_TRY(launch_bar_to_rows<float>(static_cast<const float *>(bar), P->N, P->d.r,
+                                      static_cast<float *>(rows), st));
+  return RTM_OK;
+}
+
 extern "C" rtm_status rtm_dot(const rtm_plan *P, const void *a, const void *b, int64_t n,
                               double *out, void *work, size_t work_bytes, rtm_stream stream) {
   g_last_error.clear();
@@ -651,6 +674,13 @@ static rtm_status gradient_impl(const rtm_plan *P, const void *m, const double *
   b.mode = PROBE_NEW;
   b.bar = Vbar;
   PointTables<T> none;
+  if (!Vbar) {  // fused imaging: the adjoint blocks add straight into grad
+    HIP_TRY(launch_fill<T>(static_cast<T *>(grad), P->N, T(0), st));
+    b.fuse_U = Ubar;
+    b.fuse_img = grad;
+    b.fuse_scale = -1.0 / P->d.r;
+    return run_sweep<T>(P, b, rec_t, none, w, st);
+  }
   if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
   TimedLaunch ti;
   prof_begin(KT_IMAGE, 0, st, &ti);
@@ -667,8 +697,10 @@ extern "C" rtm_status fwi_gradient(const rtm_plan *P, const void *m, const doubl
                                    size_t work_bytes, rtm_stream stream) {
   rtm_status s = check_common(P, m, work, work_bytes);
   if (s) return s;
-  if (!src_pos || !q || !rec_pos || !d_obs || !Z || !Ubar || !Vbar || !resid || !grad || !misfit)
-    return fail(RTM_E_ARG, "fwi_gradient needs every array");
+  if (!src_pos || !q || !rec_pos || !d_obs || !Z || !Ubar || !resid || !grad || !misfit)
+    return fail(RTM_E_ARG, "fwi_gradient needs every array except Vbar");
+  if (!Vbar && P->d.probe_dtype != RTM_BF16 && P->d.probe_dtype != RTM_BF16X2)
+    return fail(RTM_E_UNSUPPORTED, "fused imaging (Vbar = NULL) needs a BF16 probe path");
   if ((s = check_probe(P, Z, zt, Ubar))) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (P->d.field_dtype == RTM_F64)

@@ -58,11 +58,12 @@ struct ProbeArgs {
   const T *ring;     // R slots of ld elements; sweep level j lives in slot (j+1) mod R
   int64_t ld;        // slot stride (elements)
   int R;
+  int slot0;         // slot of level s0 - 1, i.e. s0 mod R (levels s0-1 .. s0+R-2 follow)
   int s0, kb;
   int zrow0, zdir;
   int r;
   int64_t N;
-  T *bar;            // [r][N]
+  T *bar;            // tile-major [ceil(N/32)][r][32]
   T inv_dt2;
   int mode;
 };
@@ -78,8 +79,13 @@ hipError_t launch_sample(const PointTables<T> &pt, const T *field, T *out, hipSt
 template <typename T>
 hipError_t launch_probe_vec(const ProbeArgs<T> &p, const void *Z, bool z_is_i8,
                             hipStream_t st);
+// Uf / img / scale: non-NULL img selects the fused adjoint imaging variant
+// (img[c] += scale * sum_i Uf[i][c] (Z_b^T S_b)[i][c]; p.bar unused).
 hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const int8_t *Z, bool split,
-                             hipStream_t st);
+                             const float *Uf, float *img, float scale, hipStream_t st);
+// tile-major compressed field -> rows [r][N]
+template <typename T>
+hipError_t launch_bar_to_rows(const T *bar, int64_t N, int r, T *rows, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
 template <typename T>

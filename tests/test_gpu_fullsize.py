@@ -49,8 +49,9 @@ def test_fullsize_layered_3d_gradient_truncated():
     res = host(out["resid"])
     J = float(out["misfit"].item())
     ii = torch.from_numpy(idx).cuda()
-    U = host(out["Ubar"][:, ii])
-    V = host(out["Vbar"][:, ii])
+    bi = torch.from_numpy(P.bar_index(plan, idx)).cuda()
+    U = host(out["Ubar"].reshape(-1)[bi])
+    V = host(out["Vbar"].reshape(-1)[bi])
     gr = host(out["grad"][ii])
     del out
     torch.cuda.empty_cache()

@@ -38,6 +38,11 @@ def _grid(wl):
     return Grid.of(wl)
 
 
+def rows(plan, bar):
+    """Tile-major compressed field -> [r][N] host array (via the library)."""
+    return host(P.rtm_bar_to_rows(plan, bar))
+
+
 # ---------------------------------------------------------------------------
 # 2D FP64 two-layer case at its full size (221 x 221, nt = 1000, r = 32)
 # ---------------------------------------------------------------------------
@@ -60,14 +65,14 @@ def test_c1_forward_and_gradient_f64(c1):
     Z = dev(wl.Z, torch.int8)
     out = P.rtm_forward_probe(plan, m, wl.src_pos, q, wl.rec_pos, Z=Z, final=True)
     torch.cuda.synchronize()
-    e_d, e_u, e_f = rel(host(out["d"]), f["d"]), rel(host(out["Ubar"]), f["Ubar"]), \
+    e_d, e_u, e_f = rel(host(out["d"]), f["d"]), rel(rows(plan, out["Ubar"]), f["Ubar"]), \
         rel(host(out["final"]), fin)
     say(f"  d {e_d:.2e}  Ubar {e_u:.2e}  final {e_f:.2e}")
     assert e_d < 1e-10 and e_u < 1e-10 and e_f < 1e-10
     gr = P.fwi_gradient(plan, m, wl.src_pos, q, wl.rec_pos, dev(d_obs, torch.float64), Z)
     torch.cuda.synchronize()
     e_g = rel(host(gr["grad"]), gp)
-    e_v = rel(host(gr["Vbar"]), a["Vbar"])
+    e_v = rel(rows(plan, gr["Vbar"]), a["Vbar"])
     e_J = abs(float(gr["misfit"].item()) - J) / J
     say(f"  grad {e_g:.2e}  Vbar {e_v:.2e}  misfit {e_J:.2e}")
     assert e_g < 1e-10 and e_v < 1e-10 and e_J < 1e-12
@@ -111,7 +116,7 @@ def test_3d_f32_forward_adjoint_image(s3, probe):
     im = P.rtm_image(plan, out["Ubar"], adj["Vbar"])
     torch.cuda.synchronize()
     e = dict(d=rel(host(out["d"]), f["d"]), final=rel(host(out["final"]), f["final"]),
-             U=rel(host(out["Ubar"]), f["Ubar"]), V=rel(host(adj["Vbar"]), a["Vbar"]),
+             U=rel(rows(plan, out["Ubar"]), f["Ubar"]), V=rel(rows(plan, adj["Vbar"]), a["Vbar"]),
              img=rel(host(im), img))
     say("  " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()))
     assert e["d"] < 1e-5 and e["final"] < 1e-5
@@ -221,7 +226,7 @@ def test_ragged_probe_counts_and_blocks():
                                   dev(wl.q, torch.float32), wl.rec_pos,
                                   Z=dev(wl.Z, torch.int8), what=what)
         torch.cuda.synchronize()
-        e = rel(host(out["Ubar"]), f["Ubar"])
+        e = rel(rows(plan, out["Ubar"]), f["Ubar"])
         say(f"  ragged r=40 k=20 nt=45 {what}: Ubar {e:.2e}")
         assert e < 1e-4
 
@@ -236,7 +241,7 @@ def test_block_length_does_not_change_result(k_block):
     out = P.rtm_forward_probe(plan, dev(wl.m, torch.float64), wl.src_pos,
                               dev(wl.q, torch.float64), wl.rec_pos, Z=dev(wl.Z, torch.int8))
     torch.cuda.synchronize()
-    assert rel(host(out["Ubar"]), f["Ubar"]) < 1e-12
+    assert rel(rows(plan, out["Ubar"]), f["Ubar"]) < 1e-12
     assert rel(host(out["d"]), f["d"]) < 1e-12
 
 
@@ -261,7 +266,8 @@ def test_offgrid_and_shared_cells_f64():
                               want_qadj=True)
     torch.cuda.synchronize()
     for name, x, y in (("d", out["d"], f["d"]), ("final", out["final"], f["final"]),
-                       ("Ubar", out["Ubar"], f["Ubar"]), ("Vbar", adj["Vbar"], a["Vbar"]),
+                       ("Ubar", P.rtm_bar_to_rows(plan, out["Ubar"]), f["Ubar"]),
+                       ("Vbar", P.rtm_bar_to_rows(plan, adj["Vbar"]), a["Vbar"]),
                        ("qadj", adj["qadj"], a["qadj"])):
         e = rel(host(x), y)
         assert e < 1e-11, (name, e)
@@ -279,7 +285,7 @@ def test_degenerate_sizes():
                               final=True)
     torch.cuda.synchronize()
     assert rel(host(out["final"]), f["final"]) < 1e-5
-    assert rel(host(out["Ubar"]), f["Ubar"]) < 1e-4
+    assert rel(rows(plan, out["Ubar"]), f["Ubar"]) < 1e-4
     wl0 = synth.workload_small_3d(shape=(12, 10, 14), nt=20, r=4, nb=2)
     plan0 = P.Plan(P.PlanSpec(3, wl0.shape, wl0.h, wl0.dt, wl0.nt, wl0.nb, wl0.c_ref, wl0.R,
                               wl0.c_ref, "f32", "bf16x2", 4, 8, 0, wl0.rec_pos.shape[0]))
@@ -290,3 +296,41 @@ def test_degenerate_sizes():
     assert float(out0["final"].abs().max()) == 0.0
     assert float(out0["Ubar"].abs().max()) == 0.0
     assert float(out0["d"].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("r,k_block,shape", [(32, 32, (26, 22, 40)), (64, 16, (21, 19, 35)),
+                                             (128, 32, (24, 20, 48))])
+def test_fused_imaging_matches_unfused_and_oracle(r, k_block, shape):
+    """Folding the imaging condition into the adjoint probe blocks (Vbar never
+    stored) gives the probed gradient of Eq. 3: compare with the unfused GPU
+    gradient and with the FP64 oracle.  Shapes leave a ragged last tile."""
+    wl = synth.workload_small_3d(shape=shape, nt=70, r=r, nb=4)
+    g = _grid(wl)
+    d_obs = np.zeros((wl.nt, wl.rec_pos.shape[0]), dtype=np.float32)
+    _, go, _, _ = oracle.probed_gradient(g, wl.m, wl.src_pos, wl.q, wl.rec_pos, d_obs, wl.Z)
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=k_block)
+    args = (plan, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32), wl.rec_pos,
+            dev(d_obs, torch.float32), dev(wl.Z, torch.int8))
+    a = P.fwi_gradient(*args)
+    b = P.fwi_gradient(*args, fused=True)
+    torch.cuda.synchronize()
+    ga, gb = host(a["grad"]), host(b["grad"])
+    e_ab, e_bo = rel(gb, ga), rel(gb, go)
+    say(f"  fused r={r} k={k_block}: vs unfused {e_ab:.2e}  vs oracle {e_bo:.2e}")
+    assert "Vbar" not in b or b["Vbar"] is None
+    assert e_ab < 1e-5 and e_bo < 1e-3
+    assert float(a["misfit"].item()) == float(b["misfit"].item())
+
+
+def test_bar_layout_conversion():
+    """rtm_bar_to_rows and bar_index agree on the tile-major layout."""
+    wl = synth.workload_small_3d(shape=(10, 9, 13), nt=20, r=40, nb=2)
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=8)
+    out = P.rtm_forward_probe(plan, dev(wl.m, torch.float32), wl.src_pos,
+                              dev(wl.q, torch.float32), wl.rec_pos, Z=dev(wl.Z, torch.int8))
+    R = host(P.rtm_bar_to_rows(plan, out["Ubar"]))
+    flat = host(out["Ubar"]).ravel()
+    cells = np.arange(plan.N)
+    np.testing.assert_array_equal(flat[P.bar_index(plan, cells)], R)
+    pad = np.setdiff1d(np.arange(flat.size), P.bar_index(plan, cells).ravel())
+    assert np.all(flat[pad] == 0.0)
