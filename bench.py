@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--k-block", type=int, default=32)
     ap.add_argument("--probe", default="bf16x2", choices=["bf16x2", "bf16", "f32"])
     ap.add_argument("--prof-stride", type=int, default=50)
+    ap.add_argument("--unfused", action="store_true",
+                    help="store Vbar and run the separate imaging kernel (default: fused imaging)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=24)
     ap.add_argument("--cpu-nt", type=int, default=80)
@@ -83,14 +85,15 @@ def main():
     q = torch.from_numpy(wl.q).cuda()
     Z = torch.from_numpy(wl.Z).cuda()
     d_obs = torch.zeros((nt, wl.rec_pos.shape[0]), dtype=torch.float32, device="cuda")
-    bars = (torch.empty((r, N), dtype=torch.float32, device="cuda"),
-            torch.empty((r, N), dtype=torch.float32, device="cuda"))
+    bars = (plan.empty_bar("cuda"), plan.empty_bar("cuda"))
     work = plan.workspace("cuda")
     src, rec = wl.src_pos, wl.rec_pos
     del wl
 
-    def step():
-        return P.fwi_gradient(plan, m, src, q, rec, d_obs, Z, work=work, bars=bars)
+    fused = not a.unfused
+
+    def step(fz=fused):
+        return P.fwi_gradient(plan, m, src, q, rec, d_obs, Z, work=work, bars=bars, fused=fz)
 
     for i in range(a.warmup):
         step()
@@ -112,6 +115,14 @@ def main():
     im_ms, im_n = P.profile_read("image")
     misfit = float(out["misfit"].item())
     finite = bool(torch.isfinite(out["grad"]).all().item())
+    # one step of the other variant, for comparison
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    other = step(not fused)
+    torch.cuda.synchronize()
+    other_ms = (time.perf_counter() - t2) * 1e3
+    other_misfit = float(other["misfit"].item())
+    del other
 
     ms_step = (t1 - t0) / a.steps * 1e3
     value = 2.0 * N * nt / (ms_step / 1e3) / 1e9
@@ -120,8 +131,12 @@ def main():
     st_bytes = 16.0 * N                                   # read u^n, u^{n-1}, m; write u^{n+1}
     nblk = math.ceil(nt / k)
     kbs = [min(k, nt - b * k) for b in range(nblk)]
-    pr_bytes_step = sum((4.0 * (kb + 2) + 8.0 * r) * N for kb in kbs) + \
-        sum((4.0 * kb + 8.0 * r) * N for kb in kbs)       # forward (u_tt) + adjoint blocks
+    # forward blocks read kb + 2 levels (u_tt) and read + write Ubar; adjoint
+    # blocks read kb levels and either read + write Vbar, or (fused) read Ubar
+    # and read + write the image
+    fwd_b = sum((4.0 * (kb + 2) + 8.0 * r) * N for kb in kbs)
+    adj_b = sum((4.0 * kb + (4.0 * r + 8.0 if fused else 8.0 * r)) * N for kb in kbs)
+    pr_bytes_step = fwd_b + adj_b
     st_avg = st_ms / max(st_n, 1)
     pr_avg = pr_ms / max(pr_n, 1)
     st_tot = st_avg * 2 * nt                              # ms per step
@@ -134,7 +149,7 @@ def main():
                "launches_timed": st_n, "bytes_per_launch": st_bytes, "ms_per_step": round(st_tot, 1)}
     probe = {"bound": "hbm", "achieved": round(pr_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(pr_ach / HBM_PEAK_GBS, 4), "traffic": None,
-             "kernel": "k_probe_mfma", "avg_launch_us": round(pr_avg * 1e3, 2),
+             "kernel": "k_probe_mfma_fast", "avg_launch_us": round(pr_avg * 1e3, 2),
              "launches_timed": pr_n, "bytes_per_launch_avg": pr_bytes_step / (2 * nblk),
              "ms_per_step": round(pr_tot, 1),
              "mfma_tflops": round((2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 *
@@ -149,11 +164,13 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"3d-layered-384x512x512-nt{nt}-r{r}-k{k}", "grid": [384, 512, 512],
                    "nt": nt, "r": r, "k_block": k, "probe_operand": a.probe, "shots": 1,
-                   "parallelism": "single-gpu"},
+                   "imaging": "fused" if fused else "separate", "parallelism": "single-gpu"},
         "roofline": dominant, "roofline_other": other,
         "hbm_frac_path": round(path_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "grad_rel_err_vs_exact": None,
         "misfit": misfit, "grad_finite": finite,
+        ("unfused_ms_per_step" if fused else "fused_ms_per_step"): round(other_ms, 1),
+        "misfit_same_in_both": misfit == other_misfit,
         "image_avg_ms": round(im_ms / max(im_n, 1), 2),
     }
     if not a.no_cpu_baseline:

@@ -164,6 +164,16 @@ rtm_status rtm_adjoint_probe(const rtm_plan *plan, const void *m, const double *
                              const void *Z, rtm_dtype z_dtype, void *Vbar, void *work,
                              size_t work_bytes, rtm_stream stream);
 
+/* Adjoint sweep with the probed imaging condition folded into its probe
+ * blocks (BF16 / BF16X2 plans): image[x] = scale * sum_i Ubar[i][x] Vbar[i][x]
+ * with Vbar = Z^T lam accumulated block by block and never stored (by
+ * linearity the same image as rtm_adjoint_probe + rtm_image, summed in float).
+ *   Ubar device [r*Npad] tile-major (from rtm_forward_probe), image device [N]. */
+rtm_status rtm_adjoint_image(const rtm_plan *plan, const void *m, const double *rec_pos,
+                             const void *res, const void *Z, rtm_dtype z_dtype, const void *Ubar,
+                             double scale, void *image, void *work, size_t work_bytes,
+                             rtm_stream stream);
+
 /* Probed imaging condition (Eq. 3): image[x] = scale * sum_i Ubar[i][x] Vbar[i][x],
  * summed in double.  scale = 1/r for the image, -1/r for the gradient. */
 rtm_status rtm_image(const rtm_plan *plan, const void *Ubar, const void *Vbar, double scale,
@@ -182,6 +192,22 @@ rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_p
                         const void *Z, rtm_dtype z_dtype, void *Ubar, void *Vbar,
                         void *resid, void *grad, double *misfit, void *work,
                         size_t work_bytes, rtm_stream stream);
+
+/* Exact gradient of the same misfit (Eq. 2, full zero-lag correlation
+ * -sum_n u_tt^n lam^n), the comparator of the probed estimate.  The forward
+ * history is not stored: uniform checkpointing keeps (u^{jc}, u^{jc-1}) every
+ * c = checkpoint_every steps (0: c = ceil(sqrt(2 nt))), and the adjoint sweep
+ * recomputes each c-step segment from its checkpoint, keeping that segment's
+ * u_tt (c levels) for the correlation.  Cost: two forward sweeps and one
+ * adjoint; memory (3 + 2 ceil(nt/c) + c) levels on top of the probed
+ * workspace, from rtm_exact_workspace_bytes.  resid [nt][nrec], grad [N],
+ * misfit device double [1] as in fwi_gradient. */
+rtm_status rtm_exact_workspace_bytes(const rtm_plan *plan, int32_t checkpoint_every,
+                                     size_t *bytes);
+rtm_status fwi_gradient_exact(const rtm_plan *plan, const void *m, const double *src_pos,
+                              const void *q, const double *rec_pos, const void *d_obs,
+                              int32_t checkpoint_every, void *resid, void *grad, double *misfit,
+                              void *work, size_t work_bytes, rtm_stream stream);
 
 /* Converts a tile-major compressed field (device [r*Npad]) to rows (device
  * [r][N], caller-owned): rows[i][x] = bar[((x/32)*r + i)*32 + x%32]. */

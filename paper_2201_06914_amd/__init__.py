@@ -10,4 +10,5 @@ the first call does, and fails loudly if the library has not been built.
 from .api import (Plan, PlanSpec, RtmError, bar_index, cfl_bound, fwi_gradient,  # noqa: F401
                   rtm_adjoint_probe,
                   rtm_dot, rtm_forward_probe, rtm_image, set_stencil_variant,
-                  profile_enable, profile_read, rtm_bar_to_rows)
+                  profile_enable, profile_read, rtm_bar_to_rows,
+                  fwi_gradient_exact, exact_workspace_bytes)

@@ -15,7 +15,8 @@ EXPORTS = (
     "rtm_plan_create", "rtm_plan_destroy", "rtm_plan_workspace_bytes", "rtm_cfl_bound",
     "rtm_status_str", "rtm_set_stencil_variant", "rtm_last_error", "rtm_forward_probe",
     "rtm_adjoint_probe", "rtm_image", "fwi_gradient", "rtm_dot", "rtm_profile_enable",
-    "rtm_profile_read", "rtm_bar_to_rows",
+    "rtm_profile_read", "rtm_bar_to_rows", "rtm_exact_workspace_bytes", "fwi_gradient_exact",
+    "rtm_adjoint_image",
 )
 
 
@@ -74,6 +75,13 @@ def load() -> ctypes.CDLL:
     L.fwi_gradient.restype = ctypes.c_int
     L.rtm_dot.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, sz, _vp]
     L.rtm_dot.restype = ctypes.c_int
+    L.rtm_exact_workspace_bytes.argtypes = [_vp, i32, ctypes.POINTER(sz)]
+    L.rtm_exact_workspace_bytes.restype = ctypes.c_int
+    L.fwi_gradient_exact.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, i32, _vp, _vp, _vp, _vp, sz, _vp]
+    L.fwi_gradient_exact.restype = ctypes.c_int
+    L.rtm_adjoint_image.argtypes = [_vp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, dbl, _vp, _vp, sz,
+                                    _vp]
+    L.rtm_adjoint_image.restype = ctypes.c_int
     L.rtm_bar_to_rows.argtypes = [_vp, _vp, _vp, _vp]
     L.rtm_bar_to_rows.restype = ctypes.c_int
     L.rtm_profile_enable.argtypes = [i32]

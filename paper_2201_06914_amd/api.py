@@ -282,6 +282,41 @@ def fwi_gradient(plan: Plan, m, src_pos, q, rec_pos, d_obs, Z, work=None, bars=N
     return {"grad": g, "misfit": J, "Ubar": U, "Vbar": V, "resid": res}
 
 
+def fwi_gradient_exact(plan: Plan, m, src_pos, q, rec_pos, d_obs, checkpoint_every: int = 0,
+                       work=None) -> dict:
+    """Exact gradient (Eq. 2) with uniform checkpointing; the comparator of
+    the probed gradient.  checkpoint_every = 0 picks ceil(sqrt(2 nt))."""
+    s = plan.spec
+    dev = m.device
+    L = _lib.load()
+    n = ctypes.c_size_t()
+    _check(L.rtm_exact_workspace_bytes(plan.handle, int(checkpoint_every), ctypes.byref(n)),
+           "rtm_exact_workspace_bytes")
+    if work is None or work.numel() < n.value:
+        work = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    res = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev)
+    g = torch.empty(plan.N, dtype=plan.dtype, device=dev)
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    code = L.fwi_gradient_exact(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
+        _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp,
+        _dev(d_obs, plan.dtype, s.nt * s.nrec, "d_obs"), int(checkpoint_every),
+        _dev(res, plan.dtype, s.nt * s.nrec, "resid"), _dev(g, plan.dtype, plan.N, "grad"),
+        _dev(J, torch.float64, 1, "misfit"), ctypes.c_void_p(work.data_ptr()), work.numel(),
+        _stream(dev))
+    _check(code, "fwi_gradient_exact")
+    return {"grad": g, "misfit": J, "resid": res, "workspace_bytes": int(n.value)}
+
+
+def exact_workspace_bytes(plan: Plan, checkpoint_every: int = 0) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.load().rtm_exact_workspace_bytes(plan.handle, int(checkpoint_every),
+                                                 ctypes.byref(n)), "rtm_exact_workspace_bytes")
+    return int(n.value)
+
+
 def rtm_bar_to_rows(plan: Plan, bar) -> torch.Tensor:
     """Tile-major compressed field -> [r][N] rows (a copy, made on the GPU)."""
     s = plan.spec

@@ -47,6 +47,50 @@ template hipError_t launch_fill<double>(double *, int64_t, double, hipStream_t);
 template hipError_t launch_copy<float>(float *, const float *, int64_t, hipStream_t);
 template hipError_t launch_copy<double>(double *, const double *, int64_t, hipStream_t);
 
+// exact (full-history) imaging, one step at a time (Eq. 2):
+//   s = (un - 2 u0 + um) / dt^2            second time derivative of a step
+//   g -= s * lam                            zero-lag correlation with lam^n
+template <typename T>
+__global__ __launch_bounds__(256) void k_second_diff(const T *__restrict__ un,
+                                                     const T *__restrict__ u0,
+                                                     const T *__restrict__ um, T inv_dt2,
+                                                     int64_t n, T *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256)
+    out[i] = (un[i] - T(2) * u0[i] + um[i]) * inv_dt2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_correlate(T *__restrict__ g, const T *__restrict__ s,
+                                                   const T *__restrict__ lam, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256)
+    g[i] -= s[i] * lam[i];
+}
+
+template <typename T>
+hipError_t launch_second_diff(const T *un, const T *u0, const T *um, T inv_dt2, int64_t n, T *out,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_second_diff<T>), dim3(grid_for(n)), dim3(256), 0, st, un, u0, um, inv_dt2,
+                     n, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_correlate(T *g, const T *s, const T *lam, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_correlate<T>), dim3(grid_for(n)), dim3(256), 0, st, g, s, lam, n);
+  return hipGetLastError();
+}
+template hipError_t launch_second_diff<float>(const float *, const float *, const float *, float,
+                                              int64_t, float *, hipStream_t);
+template hipError_t launch_second_diff<double>(const double *, const double *, const double *,
+                                               double, int64_t, double *, hipStream_t);
+template hipError_t launch_correlate<float>(float *, const float *, const float *, int64_t,
+                                            hipStream_t);
+template hipError_t launch_correlate<double>(double *, const double *, const double *, int64_t,
+                                             hipStream_t);
+
 // image[x] = scale * sum_i U[i][x] V[i][x]  (Eq. 3), summed in double.
 // U, V tile-major: (i, x) at ((x / 32) r + i) 32 + x % 32.
 template <typename T>

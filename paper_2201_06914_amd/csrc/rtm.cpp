@@ -597,6 +597,45 @@ extern "C" rtm_status rtm_adjoint_probe(const rtm_plan *P, const void *m, const 
   return adjoint_impl<float>(P, m, rec_pos, res, src_pos, qadj, Z, zt, Vbar, work, st);
 }
 
+template <typename T>
+static rtm_status adjoint_image_impl(const rtm_plan *P, const void *m, const double *rec_pos,
+                                     const void *res, const void *Z, rtm_dtype zt,
+                                     const void *Ubar, double scale, void *image, void *work,
+                                     hipStream_t st) {
+  PointTables<T> src_t, rec_t;
+  rtm_status s = upload_points<T>(P, static_cast<char *>(work), st, nullptr, &src_t, rec_pos,
+                                  &rec_t);
+  if (s) return s;
+  HIP_TRY(launch_fill<T>(static_cast<T *>(image), P->N, T(0), st));
+  SweepIO io;
+  io.adjoint = true;
+  io.m = m;
+  io.inj_vals = res;
+  io.Z = Z;
+  io.zt = zt;
+  io.mode = PROBE_NEW;
+  io.fuse_U = Ubar;
+  io.fuse_img = image;
+  io.fuse_scale = scale;
+  PointTables<T> none;
+  return run_sweep<T>(P, io, rec_t, none, static_cast<char *>(work), st);
+}
+
+extern "C" rtm_status rtm_adjoint_image(const rtm_plan *P, const void *m, const double *rec_pos,
+                                        const void *res, const void *Z, rtm_dtype zt,
+                                        const void *Ubar, double scale, void *image, void *work,
+                                        size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  if (P->d.nrec > 0 && (!rec_pos || !res)) return fail(RTM_E_ARG, "rec_pos and res are required");
+  if (!Z || !Ubar || !image) return fail(RTM_E_ARG, "Z, Ubar and image are required");
+  if (P->d.probe_dtype != RTM_BF16 && P->d.probe_dtype != RTM_BF16X2)
+    return fail(RTM_E_UNSUPPORTED, "fused adjoint imaging needs a BF16 probe path");
+  if ((s = check_probe(P, Z, zt, Ubar))) return s;
+  return adjoint_image_impl<float>(P, m, rec_pos, res, Z, zt, Ubar, scale, image, work,
+                                   reinterpret_cast<hipStream_t>(stream));
+}
+
 extern "C" rtm_status rtm_image(const rtm_plan *P, const void *U, const void *V, double scale,
                                 void *image, rtm_stream stream) {
   g_last_error.clear();
@@ -708,4 +747,139 @@ extern "C" rtm_status fwi_gradient(const rtm_plan *P, const void *m, const doubl
                                  misfit, work, st);
   return gradient_impl<float>(P, m, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid, grad,
                               misfit, work, st);
+}
+
+// ---------------------------------------------------------------------------
+// exact gradient with uniform checkpointing (comparator for Eq. 3)
+// ---------------------------------------------------------------------------
+// Memory beyond the probed workspace: a 3-level ring for the recomputed
+// forward field, 2 levels per checkpoint (u^{jc}, u^{jc-1}) for ceil(nt/c)
+// checkpoints, and c levels holding one segment's u_tt.
+static int default_checkpoint_every(int nt) {
+  int c = (int)std::ceil(std::sqrt(2.0 * nt));
+  return c < 1 ? 1 : (c > nt ? nt : c);
+}
+
+static size_t exact_extra_bytes(const rtm_plan *P, int c) {
+  const int ncp = (P->d.nt + c - 1) / c;
+  return align256((size_t)(3 + 2 * (size_t)ncp + c) * P->ld * P->esz);
+}
+
+extern "C" rtm_status rtm_exact_workspace_bytes(const rtm_plan *P, int32_t checkpoint_every,
+                                                size_t *bytes) {
+  if (!P || !bytes) return fail(RTM_E_ARG, "plan and bytes must be non-NULL");
+  if (checkpoint_every < 0) return fail(RTM_E_ARG, "checkpoint_every must be >= 0");
+  const int c = checkpoint_every ? std::min<int>(checkpoint_every, P->d.nt)
+                                 : default_checkpoint_every(P->d.nt);
+  *bytes = P->total + exact_extra_bytes(P, c);
+  return RTM_OK;
+}
+
+template <typename T>
+static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *src_pos,
+                             const void *qv, const double *rec_pos, const void *dobs, int c,
+                             void *residv, void *gradv, double *misfit, void *work,
+                             hipStream_t st) {
+  const rtm_desc &d = P->d;
+  char *w = static_cast<char *>(work);
+  PointTables<T> src_t, rec_t;
+  rtm_status s = upload_points<T>(P, w, st, src_pos, &src_t, rec_pos, &rec_t);
+  if (s) return s;
+  const int nt = d.nt, ndim = d.ndim;
+  const int64_t N = P->N, ld = P->ld;
+  const int ncp = (nt + c - 1) / c;
+  T *ringA = reinterpret_cast<T *>(w + P->ring.off);  // main sweep ring (R levels)
+  T *F = reinterpret_cast<T *>(w + P->total);         // recompute ring (3 levels)
+  T *CP = F + 3 * ld;                                  // checkpoints [ncp][2]
+  T *S = CP + 2 * (int64_t)ncp * ld;                   // segment u_tt [c]
+  auto lvA = [&](int j) -> T * { return ringA + (int64_t)(((j + 1) % P->R + P->R) % P->R) * ld; };
+  auto lvF = [&](int j) -> T * { return F + (int64_t)(((j + 1) % 3 + 3) % 3) * ld; };
+  const T *m = static_cast<const T *>(mv);
+  const T *q = static_cast<const T *>(qv);
+  T *resid = static_cast<T *>(residv);
+  T *grad = static_cast<T *>(gradv);
+  int variant = kStencilSimple;
+  if (ndim == 3 && sizeof(T) == 4) variant = kStencilTiled;
+  if (g_stencil_variant >= 0) variant = g_stencil_variant;
+  StepArgs<T> a = step_args<T>(P, m);
+
+  // 1. forward sweep, traces, checkpoints (u^{jc}, u^{jc-1}) before step jc
+  HIP_TRY(launch_fill<T>(lvA(-1), N, T(0), st));
+  HIP_TRY(launch_fill<T>(lvA(0), N, T(0), st));
+  for (int n = 0; n < nt; ++n) {
+    if (n % c == 0) {
+      HIP_TRY(launch_copy<T>(CP + (int64_t)(2 * (n / c)) * ld, lvA(n), N, st));
+      HIP_TRY(launch_copy<T>(CP + (int64_t)(2 * (n / c) + 1) * ld, lvA(n - 1), N, st));
+    }
+    a.cur = lvA(n);
+    a.prev = lvA(n - 1);
+    a.next = lvA(n + 1);
+    TimedLaunch tl;
+    prof_begin(KT_STENCIL, n, st, &tl);
+    HIP_TRY(launch_stencil<T>(ndim, a, variant, st));
+    prof_end(st, &tl);
+    if (src_t.ncell > 0) HIP_TRY(launch_inject<T>(a, src_t, q + (int64_t)n * src_t.npts, a.next, st));
+    if (rec_t.npts > 0) HIP_TRY(launch_sample<T>(rec_t, a.next, resid + (int64_t)n * rec_t.npts, st));
+  }
+  // 2. residual and misfit
+  double *part = reinterpret_cast<double *>(w + P->red.off);
+  HIP_TRY(launch_residual_misfit<T>(resid, static_cast<const T *>(dobs), resid,
+                                    (int64_t)nt * d.nrec, part, misfit, st));
+  // 3. adjoint, segment by segment from the last; each segment's forward is
+  //    recomputed from its checkpoint and its u_tt kept for the correlation
+  HIP_TRY(launch_fill<T>(grad, N, T(0), st));
+  HIP_TRY(launch_fill<T>(lvA(-1), N, T(0), st));
+  HIP_TRY(launch_fill<T>(lvA(0), N, T(0), st));
+  const T inv_dt2 = (T)(1.0 / (d.dt * d.dt));
+  for (int j = ncp - 1; j >= 0; --j) {
+    const int n_lo = j * c, n_hi = std::min(nt, (j + 1) * c);
+    HIP_TRY(launch_copy<T>(lvF(n_lo), CP + (int64_t)(2 * j) * ld, N, st));
+    HIP_TRY(launch_copy<T>(lvF(n_lo - 1), CP + (int64_t)(2 * j + 1) * ld, N, st));
+    StepArgs<T> fa = a;
+    for (int n = n_lo; n < n_hi; ++n) {
+      fa.cur = lvF(n);
+      fa.prev = lvF(n - 1);
+      fa.next = lvF(n + 1);
+      HIP_TRY(launch_stencil<T>(ndim, fa, variant, st));
+      if (src_t.ncell > 0)
+        HIP_TRY(launch_inject<T>(fa, src_t, q + (int64_t)n * src_t.npts, fa.next, st));
+      HIP_TRY(launch_second_diff<T>(fa.next, fa.cur, fa.prev, inv_dt2, N,
+                                    S + (int64_t)(n - n_lo) * ld, st));
+    }
+    for (int n = n_hi - 1; n >= n_lo; --n) {
+      const int sa = nt - 1 - n;  // adjoint sweep step: lam^n is level sa + 1
+      a.cur = lvA(sa);
+      a.prev = lvA(sa - 1);
+      a.next = lvA(sa + 1);
+      HIP_TRY(launch_stencil<T>(ndim, a, variant, st));
+      if (rec_t.ncell > 0)
+        HIP_TRY(launch_inject<T>(a, rec_t, resid + (int64_t)n * rec_t.npts, a.next, st));
+      HIP_TRY(launch_correlate<T>(grad, S + (int64_t)(n - n_lo) * ld, a.next, N, st));
+    }
+  }
+  return RTM_OK;
+}
+
+extern "C" rtm_status fwi_gradient_exact(const rtm_plan *P, const void *m, const double *src_pos,
+                                         const void *q, const double *rec_pos, const void *d_obs,
+                                         int32_t checkpoint_every, void *resid, void *grad,
+                                         double *misfit, void *work, size_t work_bytes,
+                                         rtm_stream stream) {
+  g_last_error.clear();
+  if (!P) return fail(RTM_E_ARG, "plan is NULL");
+  if (checkpoint_every < 0) return fail(RTM_E_ARG, "checkpoint_every must be >= 0");
+  const int c = checkpoint_every ? std::min<int>(checkpoint_every, P->d.nt)
+                                 : default_checkpoint_every(P->d.nt);
+  if (!m || !work) return fail(RTM_E_ARG, "m and work are required");
+  if (!src_pos || !q || !rec_pos || !d_obs || !resid || !grad || !misfit)
+    return fail(RTM_E_ARG, "fwi_gradient_exact needs every array");
+  const size_t need = P->total + exact_extra_bytes(P, c);
+  if (work_bytes < need)
+    return fail(RTM_E_WORKSPACE, "work has %zu bytes, the exact gradient needs %zu", work_bytes,
+                need);
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(RTM_E_ARG, "work must be 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return exact_impl<double>(P, m, src_pos, q, rec_pos, d_obs, c, resid, grad, misfit, work, st);
+  return exact_impl<float>(P, m, src_pos, q, rec_pos, d_obs, c, resid, grad, misfit, work, st);
 }

@@ -83,6 +83,12 @@ hipError_t launch_probe_vec(const ProbeArgs<T> &p, const void *Z, bool z_is_i8,
 // (img[c] += scale * sum_i Uf[i][c] (Z_b^T S_b)[i][c]; p.bar unused).
 hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const int8_t *Z, bool split,
                              const float *Uf, float *img, float scale, hipStream_t st);
+// exact imaging: out = (un - 2 u0 + um) * inv_dt2 ; g -= s * lam
+template <typename T>
+hipError_t launch_second_diff(const T *un, const T *u0, const T *um, T inv_dt2, int64_t n, T *out,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_correlate(T *g, const T *s, const T *lam, int64_t n, hipStream_t st);
 // tile-major compressed field -> rows [r][N]
 template <typename T>
 hipError_t launch_bar_to_rows(const T *bar, int64_t N, int r, T *rows, hipStream_t st);
