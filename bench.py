@@ -111,7 +111,8 @@ def main():
     t1 = time.perf_counter()
     P.profile_enable(0)
     st_ms, st_n = P.profile_read("stencil")
-    pr_ms, pr_n = P.profile_read("probe")
+    pf_ms, pf_n = P.profile_read("probe")
+    pa_ms, pa_n = P.profile_read("probe_adj")
     im_ms, im_n = P.profile_read("image")
     misfit = float(out["misfit"].item())
     finite = bool(torch.isfinite(out["grad"]).all().item())
@@ -138,20 +139,29 @@ def main():
     adj_b = sum((4.0 * kb + (4.0 * r + 8.0 if fused else 8.0 * r)) * N for kb in kbs)
     pr_bytes_step = fwd_b + adj_b
     st_avg = st_ms / max(st_n, 1)
+    pr_ms, pr_n = pf_ms + pa_ms, pf_n + pa_n
     pr_avg = pr_ms / max(pr_n, 1)
     st_tot = st_avg * 2 * nt                              # ms per step
-    pr_tot = pr_avg * 2 * nblk
+    pr_tot = pr_ms / a.steps
     st_ach = st_bytes / (st_avg * 1e-3) / 1e9
     pr_ach = pr_bytes_step * a.steps / (pr_ms * 1e-3) / 1e9 if pr_n else 0.0
+    pf_ach = fwd_b * a.steps / (pf_ms * 1e-3) / 1e9 if pf_n else 0.0
+    pa_ach = adj_b * a.steps / (pa_ms * 1e-3) / 1e9 if pa_n else 0.0
     stencil = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": round(st_ach / HBM_PEAK_GBS, 4), "traffic": None,
                "kernel": "k_stencil3d_tiled", "avg_launch_us": round(st_avg * 1e3, 2),
                "launches_timed": st_n, "bytes_per_launch": st_bytes, "ms_per_step": round(st_tot, 1)}
     probe = {"bound": "hbm", "achieved": round(pr_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(pr_ach / HBM_PEAK_GBS, 4), "traffic": None,
-             "kernel": "k_probe_mfma_fast", "avg_launch_us": round(pr_avg * 1e3, 2),
-             "launches_timed": pr_n, "bytes_per_launch_avg": pr_bytes_step / (2 * nblk),
+             "kernel": "k_probe_mfma_fast (forward u_tt + adjoint" +
+                       (" fused imaging)" if fused else ")"),
+             "avg_launch_us": round(pr_avg * 1e3, 2), "launches_timed": pr_n,
+             "bytes_per_launch_avg": pr_bytes_step / (2 * nblk),
              "ms_per_step": round(pr_tot, 1),
+             "forward": {"avg_launch_us": round(pf_ms / max(pf_n, 1) * 1e3, 1),
+                         "GBps": round(pf_ach, 1), "bytes_per_launch": fwd_b / nblk},
+             "adjoint": {"avg_launch_us": round(pa_ms / max(pa_n, 1) * 1e3, 1),
+                         "GBps": round(pa_ach, 1), "bytes_per_launch": adj_b / nblk},
              "mfma_tflops": round((2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 *
                                   math.ceil(k / 16) * N * 2 * nblk * a.steps /
                                   (pr_ms * 1e-3) / 1e12, 2) if pr_n else None}

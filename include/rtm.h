@@ -127,8 +127,8 @@ void rtm_set_stencil_variant(int variant);
  * sweeps record HIP events on their own stream around every stride-th
  * stencil launch and around every probe-GEMM and image launch (0 turns it
  * off).  rtm_profile_read(kind, ...) waits for the recorded events of one
- * kind (0 stencil, 1 probe GEMM, 2 image), returns their summed duration in
- * ms and their count, and forgets them. */
+ * kind (0 stencil, 1 forward probe GEMM, 2 image, 3 adjoint probe GEMM),
+ * returns their summed duration in ms and their count, and forgets them. */
 void rtm_profile_enable(int32_t stride);
 rtm_status rtm_profile_read(int32_t kind, double *total_ms, int64_t *count);
 /* Message of the last HIP failure seen by this thread (empty if none). */

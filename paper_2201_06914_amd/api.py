@@ -113,7 +113,7 @@ def set_stencil_variant(v: int) -> None:
     _lib.load().rtm_set_stencil_variant(int(v))
 
 
-KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2}
+KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2, "probe_adj": 3}
 
 
 def profile_enable(stride: int) -> None:

@@ -207,11 +207,16 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
     float part = 0.f;
     for (int mt0 = 0; mt0 < MT; mt0 += MTC) {
       f32x16 acc[MTC];
-      if (FUSED) {
+      float uf[FUSED ? MTC : 1][16];
+      if (FUSED) {  // issue the forward-field loads before the MFMAs
+        const float *Ut = Uf + tbase + mt0 * 32 * 32 + loff;
 #pragma unroll
         for (int j = 0; j < MTC; ++j)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) acc[j][v] = 0.f;
+          for (int v = 0; v < 16; ++v) {
+            acc[j][v] = 0.f;
+            uf[FUSED ? j : 0][v] = Ut[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32];
+          }
       } else {
         const float *Ut = p.bar + tbase + mt0 * 32 * 32 + loff;
 #pragma unroll
@@ -237,11 +242,10 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
         }
       }
       if (FUSED) {
-        const float *Ut = Uf + tbase + mt0 * 32 * 32 + loff;
 #pragma unroll
         for (int j = 0; j < MTC; ++j)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) part += Ut[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32] * acc[j][v];
+          for (int v = 0; v < 16; ++v) part += uf[FUSED ? j : 0][v] * acc[j][v];
       } else {
         float *Uo = p.bar + tbase + mt0 * 32 * 32 + loff;
 #pragma unroll

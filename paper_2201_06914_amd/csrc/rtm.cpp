@@ -34,7 +34,7 @@ static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / kStencilTi
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
-enum { KT_STENCIL = 0, KT_PROBE = 1, KT_IMAGE = 2, KT_N = 3 };
+enum { KT_STENCIL = 0, KT_PROBE = 1, KT_IMAGE = 2, KT_PROBE_ADJ = 3, KT_N = 4 };
 struct TimedLaunch {
   int kind;
   hipEvent_t a, b;
@@ -469,7 +469,7 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       p.inv_dt2 = (T)(1.0 / (d.dt * d.dt));
       p.mode = io.mode;
       TimedLaunch tp;
-      prof_begin(KT_PROBE, s, st, &tp);
+      prof_begin(io.adjoint ? KT_PROBE_ADJ : KT_PROBE, s, st, &tp);
       if constexpr (sizeof(T) == 4) {
         if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
           HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io.Z),
