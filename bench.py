@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--k-block", type=int, default=32)
     ap.add_argument("--probe", default="bf16x2", choices=["bf16x2", "bf16", "f32"])
     ap.add_argument("--prof-stride", type=int, default=50)
+    ap.add_argument("--stencil-variant", type=int, default=None,
+                    help="fix the stencil kernel variant instead of autotuning it")
     ap.add_argument("--unfused", action="store_true",
                     help="store Vbar and run the separate imaging kernel (default: fused imaging)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -89,6 +91,12 @@ def main():
     work = plan.workspace("cuda")
     src, rec = wl.src_pos, wl.rec_pos
     del wl
+    if a.stencil_variant is None:
+        tune = P.autotune_stencil(plan, m, work=work, steps=20)
+    else:
+        P.set_stencil_variant(a.stencil_variant)
+        tune = {"best": a.stencil_variant, "fixed": True}
+    print(f"stencil variant {tune}", file=sys.stderr, flush=True)
 
     fused = not a.unfused
 
@@ -149,7 +157,8 @@ def main():
     pa_ach = adj_b * a.steps / (pa_ms * 1e-3) / 1e9 if pa_n else 0.0
     stencil = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": round(st_ach / HBM_PEAK_GBS, 4), "traffic": None,
-               "kernel": "k_stencil3d_tiled", "avg_launch_us": round(st_avg * 1e3, 2),
+               "kernel": f"k_stencil3d_tiled (variant {tune['best']})",
+               "avg_launch_us": round(st_avg * 1e3, 2), "autotune_us": tune.get("us"),
                "launches_timed": st_n, "bytes_per_launch": st_bytes, "ms_per_step": round(st_tot, 1)}
     probe = {"bound": "hbm", "achieved": round(pr_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(pr_ach / HBM_PEAK_GBS, 4), "traffic": None,

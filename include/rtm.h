@@ -119,10 +119,26 @@ rtm_status rtm_plan_workspace_bytes(const rtm_plan *plan, size_t *bytes);
 /* The CFL bound 2/sqrt(ndim*S) the plan was checked against. */
 double rtm_cfl_bound(int32_t ndim);
 const char *rtm_status_str(rtm_status s);
-/* Tuning hook, process wide: stencil kernel of the sweeps.  -1 automatic
- * (LDS-tiled for F32 3D grids, else one thread per cell), 0 one thread per
- * cell, 1 LDS-tiled (3D only).  Every choice gives bitwise-identical levels. */
+/* Tuning hooks, process wide: stencil kernel of the sweeps.  -1 automatic
+ * (LDS-tiled 64 x 16 for F32 3D grids, else one thread per cell), 0 one
+ * thread per cell, 1..8 LDS-tiled z-marching variants (3D; x-width x y-rows):
+ * 1: 64x16, 2: 64x32, 3: 64x16 with 512 threads, 4: 64x16 with 128 threads,
+ * 5: 32x32, 6: 128x8, 7: as 1 and 8: as 2 with non-temporal streaming loads
+ * and stores.  Every choice gives bitwise-identical levels.
+ * rtm_set_stencil_blocks: the tiled kernels split z until a launch has at
+ * least this many workgroups (default 1024). */
 void rtm_set_stencil_variant(int variant);
+void rtm_set_stencil_blocks(int32_t blocks);
+/* Autotuner and race check for the stencil: runs one step of every variant
+ * (0..8 in 3D, 0 in 2D) from the same pattern levels in the ring of `work`,
+ * counts elements that differ bitwise from variant 0 (mismatch[v]), times
+ * `steps` launches of each (us[v], microseconds per launch; us and mismatch
+ * may be NULL or hold 9 entries) and returns in *best the fastest variant
+ * with no mismatch.  It does not change the current variant.  Needs
+ * k_block >= 2; synchronises `stream`. */
+rtm_status rtm_autotune_stencil(const rtm_plan *plan, const void *m, void *work,
+                                size_t work_bytes, int32_t steps, int32_t *best, float *us,
+                                int64_t *mismatch, rtm_stream stream);
 /* Kernel timing, process wide and off by default.  With stride > 0 the
  * sweeps record HIP events on their own stream around every stride-th
  * stencil launch and around every probe-GEMM and image launch (0 turns it

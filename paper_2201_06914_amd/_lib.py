@@ -16,7 +16,7 @@ EXPORTS = (
     "rtm_status_str", "rtm_set_stencil_variant", "rtm_last_error", "rtm_forward_probe",
     "rtm_adjoint_probe", "rtm_image", "fwi_gradient", "rtm_dot", "rtm_profile_enable",
     "rtm_profile_read", "rtm_bar_to_rows", "rtm_exact_workspace_bytes", "fwi_gradient_exact",
-    "rtm_adjoint_image",
+    "rtm_adjoint_image", "rtm_set_stencil_blocks", "rtm_autotune_stencil",
 )
 
 
@@ -82,6 +82,11 @@ def load() -> ctypes.CDLL:
     L.rtm_adjoint_image.argtypes = [_vp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, dbl, _vp, _vp, sz,
                                     _vp]
     L.rtm_adjoint_image.restype = ctypes.c_int
+    L.rtm_set_stencil_blocks.argtypes = [i32]
+    L.rtm_set_stencil_blocks.restype = None
+    L.rtm_autotune_stencil.argtypes = [_vp, _vp, _vp, sz, i32, ctypes.POINTER(i32),
+                                       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i64), _vp]
+    L.rtm_autotune_stencil.restype = ctypes.c_int
     L.rtm_bar_to_rows.argtypes = [_vp, _vp, _vp, _vp]
     L.rtm_bar_to_rows.restype = ctypes.c_int
     L.rtm_profile_enable.argtypes = [i32]

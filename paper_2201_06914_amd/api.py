@@ -113,6 +113,57 @@ def set_stencil_variant(v: int) -> None:
     _lib.load().rtm_set_stencil_variant(int(v))
 
 
+N_STENCIL_VARIANTS = 9
+
+
+def set_stencil_blocks(blocks: int) -> None:
+    _lib.load().rtm_set_stencil_blocks(int(blocks))
+
+
+def autotune_stencil(plan: Plan, m, work=None, steps: int = 20, apply: bool = True,
+                     cache: str | None = None) -> dict:
+    """Times every stencil variant on this plan's grid (after checking each
+    against the one-thread-per-cell kernel bit for bit) and, with apply=True,
+    selects the fastest.  `cache`: a JSON file keyed by (arch, grid, dtype)
+    that stores the choice across runs."""
+    import json
+    import os
+    key = None
+    if cache:
+        props = torch.cuda.get_device_properties(m.device)
+        arch = getattr(props, "gcnArchName", props.name)
+        key = f"{arch}|{plan.spec.ndim}|{'x'.join(map(str, plan.spec.shape))}|{plan.spec.field}"
+        if os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                if apply:
+                    set_stencil_variant(table[key]["best"])
+                return dict(table[key], cached=True)
+    work = _work(plan, work, m.device)
+    best = ctypes.c_int32()
+    us = (ctypes.c_float * N_STENCIL_VARIANTS)()
+    mism = (ctypes.c_int64 * N_STENCIL_VARIANTS)()
+    _check(_lib.load().rtm_autotune_stencil(plan.handle, _dev(m, plan.dtype, plan.N, "m"),
+                                            ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                            int(steps), ctypes.byref(best), us, mism,
+                                            _stream(m.device)), "rtm_autotune_stencil")
+    last = N_STENCIL_VARIANTS if plan.spec.ndim == 3 else 1
+    res = {"best": int(best.value), "us": [round(float(us[i]), 2) for i in range(last)],
+           "mismatch": [int(mism[i]) for i in range(last)], "cached": False}
+    if apply:
+        set_stencil_variant(res["best"])
+    if cache and key:
+        table = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        table[key] = {k: v for k, v in res.items() if k != "cached"}
+        with open(cache, "w") as f:
+            json.dump(table, f, indent=1)
+    return res
+
+
 KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2, "probe_adj": 3}
 
 

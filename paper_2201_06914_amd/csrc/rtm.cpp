@@ -30,7 +30,8 @@ using namespace rtm;
 // errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
-static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / kStencilTiled
+static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled variant id
+static int g_stencil_blocks = 1024; // tiled stencil: split z until this many workgroups
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
@@ -153,7 +154,13 @@ extern "C" const char *rtm_status_str(rtm_status s) {
 
 extern "C" const char *rtm_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" void rtm_set_stencil_variant(int v) { g_stencil_variant = v; }
+extern "C" void rtm_set_stencil_variant(int v) {
+  g_stencil_variant = (v >= -1 && v <= kStencilVariants) ? v : -1;
+}
+
+extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
+  g_stencil_blocks = blocks > 0 ? blocks : 1024;
+}
 
 extern "C" void rtm_profile_enable(int32_t stride) {
   g_prof_stride = stride > 0 ? stride : 0;
@@ -447,7 +454,7 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
     a.next = level(s + 1);
     TimedLaunch tl;
     prof_begin(KT_STENCIL, s, st, &tl);
-    HIP_TRY(launch_stencil<T>(ndim, a, variant, st));
+    HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
     prof_end(st, &tl);
     if (inj.ncell > 0 && inj_vals)
       HIP_TRY(launch_inject<T>(a, inj, inj_vals + (int64_t)n * inj.npts, a.next, st));
@@ -816,7 +823,7 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
     a.next = lvA(n + 1);
     TimedLaunch tl;
     prof_begin(KT_STENCIL, n, st, &tl);
-    HIP_TRY(launch_stencil<T>(ndim, a, variant, st));
+    HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
     prof_end(st, &tl);
     if (src_t.ncell > 0) HIP_TRY(launch_inject<T>(a, src_t, q + (int64_t)n * src_t.npts, a.next, st));
     if (rec_t.npts > 0) HIP_TRY(launch_sample<T>(rec_t, a.next, resid + (int64_t)n * rec_t.npts, st));
@@ -840,7 +847,7 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
       fa.cur = lvF(n);
       fa.prev = lvF(n - 1);
       fa.next = lvF(n + 1);
-      HIP_TRY(launch_stencil<T>(ndim, fa, variant, st));
+      HIP_TRY(launch_stencil<T>(ndim, fa, variant, g_stencil_blocks, st));
       if (src_t.ncell > 0)
         HIP_TRY(launch_inject<T>(fa, src_t, q + (int64_t)n * src_t.npts, fa.next, st));
       HIP_TRY(launch_second_diff<T>(fa.next, fa.cur, fa.prev, inv_dt2, N,
@@ -851,7 +858,7 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
       a.cur = lvA(sa);
       a.prev = lvA(sa - 1);
       a.next = lvA(sa + 1);
-      HIP_TRY(launch_stencil<T>(ndim, a, variant, st));
+      HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
       if (rec_t.ncell > 0)
         HIP_TRY(launch_inject<T>(a, rec_t, resid + (int64_t)n * rec_t.npts, a.next, st));
       HIP_TRY(launch_correlate<T>(grad, S + (int64_t)(n - n_lo) * ld, a.next, N, st));
@@ -882,4 +889,81 @@ extern "C" rtm_status fwi_gradient_exact(const rtm_plan *P, const void *m, const
   if (P->d.field_dtype == RTM_F64)
     return exact_impl<double>(P, m, src_pos, q, rec_pos, d_obs, c, resid, grad, misfit, work, st);
   return exact_impl<float>(P, m, src_pos, q, rec_pos, d_obs, c, resid, grad, misfit, work, st);
+}
+
+// ---------------------------------------------------------------------------
+// stencil autotuner and race check
+// ---------------------------------------------------------------------------
+// Every candidate kernel runs one step from the same hash-pattern levels; its
+// output must equal the one-thread-per-cell kernel's bit for bit (the
+// per-cell arithmetic is shared, so any difference is a tiling or
+// synchronisation bug).  Passing candidates are timed over `steps` launches.
+template <typename T>
+static rtm_status autotune_impl(const rtm_plan *P, const void *mv, char *w, int steps,
+                                int32_t *best, float *us, int64_t *mismatch, hipStream_t st) {
+  const int64_t N = P->N, ld = P->ld;
+  T *ring = reinterpret_cast<T *>(w + P->ring.off);
+  T *s0 = ring, *s1 = ring + ld, *s2 = ring + 2 * ld, *s3 = ring + 3 * ld;
+  auto *cnt = reinterpret_cast<unsigned long long *>(w + P->red.off);
+  StepArgs<T> a = step_args<T>(P, static_cast<const T *>(mv));
+  a.prev = s0;
+  a.cur = s1;
+  a.next = s2;
+  const T amp = (T)1e-3;
+  HIP_TRY(launch_pattern<T>(s0, N, 0x1234567u, amp, st));
+  HIP_TRY(launch_pattern<T>(s1, N, 0x89abcdefu, amp, st));
+  HIP_TRY(launch_stencil<T>(P->d.ndim, a, kStencilSimple, g_stencil_blocks, st));
+  HIP_TRY(launch_copy<T>(s3, s2, N, st));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best_t = 0.f;
+  bool have_best = false;
+  int best_v = kStencilSimple;
+  const int last = P->d.ndim == 3 ? kStencilVariants : kStencilSimple;
+  rtm_status status = RTM_OK;
+  for (int v = kStencilSimple; v <= last && status == RTM_OK; ++v) {
+    unsigned long long diff = 0;
+    hipError_t e = launch_fill<double>(reinterpret_cast<double *>(cnt), 1, 0.0, st);
+    if (e == hipSuccess) e = launch_stencil<T>(P->d.ndim, a, v, g_stencil_blocks, st);
+    if (e == hipSuccess) e = launch_count_diff<T>(s2, s3, N, cnt, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&diff, cnt, sizeof diff, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < steps && e == hipSuccess; ++i)
+      e = launch_stencil<T>(P->d.ndim, a, v, g_stencil_blocks, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      status = fail(RTM_E_HIP, "autotune variant %d: %s", v, hipGetErrorString(e));
+      break;
+    }
+    const float t = steps > 0 ? 1e3f * ms / steps : 0.f;
+    if (us) us[v] = t;
+    if (mismatch) mismatch[v] = (int64_t)diff;
+    if (diff == 0 && (!have_best || t < best_t)) {  // fastest bitwise-correct candidate
+      have_best = true;
+      best_t = t;
+      best_v = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == RTM_OK && best) *best = best_v;
+  return status;
+}
+
+extern "C" rtm_status rtm_autotune_stencil(const rtm_plan *P, const void *m, void *work,
+                                           size_t work_bytes, int32_t steps, int32_t *best,
+                                           float *us, int64_t *mismatch, rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  if (P->R < 4) return fail(RTM_E_UNSUPPORTED, "autotuning needs k_block >= 2 (4 ring levels)");
+  if (steps < 0) return fail(RTM_E_ARG, "steps must be >= 0");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return autotune_impl<double>(P, m, static_cast<char *>(work), steps, best, us, mismatch, st);
+  return autotune_impl<float>(P, m, static_cast<char *>(work), steps, best, us, mismatch, st);
 }

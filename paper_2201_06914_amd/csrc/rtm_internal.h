@@ -70,7 +70,15 @@ struct ProbeArgs {
 
 // launchers (stream-ordered; return the launch status)
 template <typename T>
-hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, hipStream_t st);
+hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
+                          hipStream_t st);
+// autotuning: hash pattern fill, count of bitwise-different elements (atomic
+// integer add into *count)
+template <typename T>
+hipError_t launch_pattern(T *p, int64_t n, uint32_t seed, T scale, hipStream_t st);
+template <typename T>
+hipError_t launch_count_diff(const T *a, const T *b, int64_t n, unsigned long long *count,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_inject(const StepArgs<T> &a, const PointTables<T> &pt, const T *vals,
                          T *field, hipStream_t st);
@@ -113,6 +121,7 @@ constexpr int kReduceBlocks = 1024;  // partial sums of the two-pass reductions
 // 1 = LDS-tiled z-marching (3D).  Both share the per-cell arithmetic, so they
 // give bitwise-identical levels.
 constexpr int kStencilSimple = 0;
-constexpr int kStencilTiled = 1;
+constexpr int kStencilTiled = 1;     // first LDS-tiled variant
+constexpr int kStencilVariants = 8;  // last variant id
 
 }  // namespace rtm

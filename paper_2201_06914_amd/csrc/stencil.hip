@@ -84,15 +84,28 @@ __global__ __launch_bounds__(256) void k_stencil_simple(StepArgs<T> a) {
 // ---------------------------------------------------------------------------
 // 3D LDS tile + z-marching register queue
 // ---------------------------------------------------------------------------
-template <typename T, int TX, int TYT, int RY>
+// NT: streaming (non-temporal) loads of u^{n-1} and m and stores of u^{n+1};
+// each is touched once per step and a level (N x 4 B) exceeds the caches.
+template <typename T, bool NT>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename T, bool NT>
+__device__ __forceinline__ void st_stream(T *p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <typename T, int TX, int TYT, int RY, bool NT>
 __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int ntx, int nty,
                                                              int nzc, int zchunk) {
-  constexpr int NT = TX * TYT;
+  constexpr int NTH = TX * TYT;
   constexpr int TY = TYT * RY;
   constexpr int LX = TX + 8;
   constexpr int LY = TY + 8;
   constexpr int NHY = (8 + TYT - 1) / TYT;        // y-halo rows per thread
-  constexpr int NHX = (8 * TY + NT - 1) / NT;     // x-halo cells per thread
+  constexpr int NHX = (8 * TY + NTH - 1) / NTH;   // x-halo cells per thread
   __shared__ T lds[2][LY * LX];
 
   // XCD-aware order: consecutive hardware block ids go round-robin over the 8
@@ -127,7 +140,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
                : T(0);
   };
   // halo bookkeeping: y-halo rows hy = ty + TYT*k (LDS rows 0..3 and TY+4..TY+7),
-  // x-halo cells t = tid + NT*k over TY rows x 8 columns
+  // x-halo cells t = tid + NTH*k over TY rows x 8 columns
   int hyr[NHY], hyg[NHY];
   bool hyon[NHY];
 #pragma unroll
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
   bool hxon[NHX];
 #pragma unroll
   for (int k = 0; k < NHX; ++k) {
-    const int t = tid + NT * k;
+    const int t = tid + NTH * k;
     hxon[k] = t < 8 * TY;
     const int row = t / 8, col = t % 8;
     hxr[k] = 4 + row;
@@ -156,8 +169,8 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
     for (int k = 0; k < 8; ++k) q[j][k] = ldu(z0 - 4 + k, yr[j], x);
     front[j] = ldu(z0 + 4, yr[j], x);
     const int64_t o = (int64_t)z0 * sp + (int64_t)yr[j] * a.nx + x;
-    pv[j] = in[j] ? a.prev[o] : T(0);
-    mm[j] = in[j] ? a.m[o] : T(1);
+    pv[j] = in[j] ? ld_stream<T, NT>(a.prev + o) : T(0);
+    mm[j] = in[j] ? ld_stream<T, NT>(a.m + o) : T(1);
   }
 #pragma unroll
   for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z0, hyg[k], x) : T(0);
@@ -182,8 +195,8 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
       for (int j = 0; j < RY; ++j) {
         front[j] = ldu(z + 5, yr[j], x);
         const int64_t o = (int64_t)(z + 1) * sp + (int64_t)yr[j] * a.nx + x;
-        pv[j] = in[j] ? a.prev[o] : T(0);
-        mm[j] = in[j] ? a.m[o] : T(1);
+        pv[j] = in[j] ? ld_stream<T, NT>(a.prev + o) : T(0);
+        mm[j] = in[j] ? ld_stream<T, NT>(a.m + o) : T(1);
       }
 #pragma unroll
       for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z + 1, hyg[k], x) : T(0);
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
       const T lap = ((a.cc * c + lz) + lyv) + lxv;
       if (in[j]) {
         const int64_t o = (int64_t)z * sp + (int64_t)yr[j] * a.nx + x;
-        a.next[o] = cell_update(a, c, pvc[j], mmc[j], lap, sponge_a(a, z, yr[j], x));
+        st_stream<T, NT>(a.next + o, cell_update(a, c, pvc[j], mmc[j], lap, sponge_a(a, z, yr[j], x)));
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) q[j][k] = q[j][k + 1];
@@ -223,19 +236,42 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
   }
 }
 
+template <typename T, int TX, int TYT, int RY, bool NT>
+static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st) {
+  constexpr int TY = TYT * RY;
+  const int ntx = (a.nx + TX - 1) / TX;
+  const int nty = (a.ny + TY - 1) / TY;
+  // split z so that the launch has at least target_blocks workgroups
+  int nzc = 1;
+  while ((int64_t)ntx * nty * nzc < target_blocks && a.nz / (nzc * 2) >= 16) nzc *= 2;
+  const int zchunk = (a.nz + nzc - 1) / nzc;
+  nzc = (a.nz + zchunk - 1) / zchunk;
+  hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT>), dim3(ntx * nty * nzc),
+                     dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk);
+}
+
+// tiled variants: id -> (TX, threads in y, rows per thread, non-temporal)
+//   1: 64 x 16 (4 x 4)    2: 64 x 32 (4 x 8)    3: 64 x 16 (8 x 2, 512 thr)
+//   4: 64 x 16 (2 x 8, 128 thr)    5: 32 x 32 (8 x 4)    6: 128 x 8 (2 x 4)
+//   7: as 1, non-temporal          8: as 2, non-temporal
 template <typename T>
-hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, hipStream_t st) {
-  if (ndim == 3 && variant == kStencilTiled) {
-    constexpr int TX = 64, TYT = 4, RY = 4, TY = TYT * RY;
-    const int ntx = (a.nx + TX - 1) / TX;
-    const int nty = (a.ny + TY - 1) / TY;
-    // split z so that the launch has >= ~4 workgroups per CU on 256 CUs
-    int nzc = 1;
-    while ((int64_t)ntx * nty * nzc < 1024 && a.nz / (nzc * 2) >= 16) nzc *= 2;
-    const int zchunk = (a.nz + nzc - 1) / nzc;
-    nzc = (a.nz + zchunk - 1) / zchunk;
-    hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY>), dim3(ntx * nty * nzc),
-                       dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk);
+hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
+                          hipStream_t st) {
+  if (ndim == 3 && variant >= kStencilTiled && variant <= kStencilVariants) {
+    if constexpr (sizeof(T) == 4) {
+      switch (variant) {
+        case 2: launch_tiled<T, 64, 4, 8, false>(a, target_blocks, st); break;
+        case 3: launch_tiled<T, 64, 8, 2, false>(a, target_blocks, st); break;
+        case 4: launch_tiled<T, 64, 2, 8, false>(a, target_blocks, st); break;
+        case 5: launch_tiled<T, 32, 8, 4, false>(a, target_blocks, st); break;
+        case 6: launch_tiled<T, 128, 2, 4, false>(a, target_blocks, st); break;
+        case 7: launch_tiled<T, 64, 4, 4, true>(a, target_blocks, st); break;
+        case 8: launch_tiled<T, 64, 4, 8, true>(a, target_blocks, st); break;
+        default: launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st); break;
+      }
+    } else {
+      launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st);
+    }
   } else {
     const unsigned nblk = (unsigned)((a.N + 255) / 256);
     if (ndim == 3)
@@ -246,8 +282,51 @@ hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, hipStream
   return hipGetLastError();
 }
 
-template hipError_t launch_stencil<float>(int, const StepArgs<float> &, int, hipStream_t);
-template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, hipStream_t);
+template hipError_t launch_stencil<float>(int, const StepArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// autotuning helpers: a deterministic test pattern and a bitwise comparison
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_pattern(T *p, int64_t n, uint32_t seed, T scale) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    uint32_t h = (uint32_t)i * 2654435761u ^ seed;  // Knuth multiplicative hash
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    p[i] = scale * (T)((int32_t)(h & 0xffff) - 32768) / T(32768);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_count_diff(const T *a, const T *b, int64_t n,
+                                                    unsigned long long *count) {
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256)
+    c += (a[i] != b[i]) ? 1ull : 0ull;
+  if (c) atomicAdd(count, c);
+}
+
+template <typename T>
+hipError_t launch_pattern(T *p, int64_t n, uint32_t seed, T scale, hipStream_t st) {
+  hipLaunchKernelGGL((k_pattern<T>), dim3(4096), dim3(256), 0, st, p, n, seed, scale);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_count_diff(const T *a, const T *b, int64_t n, unsigned long long *count,
+                             hipStream_t st) {
+  hipLaunchKernelGGL((k_count_diff<T>), dim3(4096), dim3(256), 0, st, a, b, n, count);
+  return hipGetLastError();
+}
+template hipError_t launch_pattern<float>(float *, int64_t, uint32_t, float, hipStream_t);
+template hipError_t launch_pattern<double>(double *, int64_t, uint32_t, double, hipStream_t);
+template hipError_t launch_count_diff<float>(const float *, const float *, int64_t,
+                                             unsigned long long *, hipStream_t);
+template hipError_t launch_count_diff<double>(const double *, const double *, int64_t,
+                                              unsigned long long *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // point injection (after the step) and sampling

@@ -334,3 +334,20 @@ def test_bar_layout_conversion():
     np.testing.assert_array_equal(flat[P.bar_index(plan, cells)], R)
     pad = np.setdiff1d(np.arange(flat.size), P.bar_index(plan, cells).ravel())
     assert np.all(flat[pad] == 0.0)
+
+
+def test_autotuner_race_check_all_variants_bitwise_equal():
+    """Every LDS-tiled stencil variant (tile shapes, thread counts, streaming
+    hints, ragged tiles) reproduces the one-thread-per-cell kernel bit for bit
+    on a hash-pattern step, and the tuner picks one of them."""
+    wl = synth.workload_small_3d(shape=(45, 37, 83), nt=10)
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=4)
+    res = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=3, apply=False)
+    say(f"  autotune: best {res['best']} us {res['us']} mismatch {res['mismatch']}")
+    assert res["mismatch"] == [0] * len(res["mismatch"])
+    assert 1 <= res["best"] <= 8
+    for blocks in (64, 4096):          # z-chunking changes, results must not
+        P.set_stencil_blocks(blocks)
+        r2 = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=1, apply=False)
+        assert r2["mismatch"] == [0] * len(r2["mismatch"])
+    P.set_stencil_blocks(1024)
