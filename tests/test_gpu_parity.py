@@ -345,7 +345,7 @@ def test_autotuner_race_check_all_variants_bitwise_equal():
     res = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=3, apply=False)
     say(f"  autotune: best {res['best']} us {res['us']} mismatch {res['mismatch']}")
     assert res["mismatch"] == [0] * len(res["mismatch"])
-    assert 1 <= res["best"] <= 8
+    assert res["us"][res["best"]] == min(res["us"])   # on a grid this small variant 0 may win
     for blocks in (64, 4096):          # z-chunking changes, results must not
         P.set_stencil_blocks(blocks)
         r2 = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=1, apply=False)
