@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--unfused", action="store_true",
                     help="store Vbar and run the separate imaging kernel (default: fused imaging)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the exact (checkpointed FP32) comparator run")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (PMC calibration)")
     ap.add_argument("--cpu-planes", type=int, default=24)
     ap.add_argument("--cpu-nt", type=int, default=80)
     return ap.parse_args()
@@ -87,7 +91,7 @@ def main():
     q = torch.from_numpy(wl.q).cuda()
     Z = torch.from_numpy(wl.Z).cuda()
     d_obs = torch.zeros((nt, wl.rec_pos.shape[0]), dtype=torch.float32, device="cuda")
-    bars = (plan.empty_bar("cuda"), plan.empty_bar("cuda"))
+    bars = (plan.empty_bar("cuda"), None if not a.unfused else plan.empty_bar("cuda"))
     work = plan.workspace("cuda")
     src, rec = wl.src_pos, wl.rec_pos
     del wl
@@ -127,11 +131,54 @@ def main():
     # one step of the other variant, for comparison
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    other = step(not fused)
+    if fused:
+        other = P.fwi_gradient(plan, m, src, q, rec, d_obs, Z, work=work)
+    else:
+        other = step(True)
     torch.cuda.synchronize()
     other_ms = (time.perf_counter() - t2) * 1e3
     other_misfit = float(other["misfit"].item())
     del other
+    torch.cuda.empty_cache()
+    # the exact gradient (Eq. 2, FP32, uniform checkpointing) on the same inputs
+    exact = None
+    if not a.no_exact:
+        g_probed = out["grad"].double()
+        del out
+        torch.cuda.empty_cache()
+        ewb = P.exact_workspace_bytes(plan)
+        ework = torch.empty(ewb, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ex = P.fwi_gradient_exact(plan, m, src, q, rec, d_obs, work=ework)
+        torch.cuda.synchronize()
+        ex_ms = (time.perf_counter() - t3) * 1e3
+        ge = ex["grad"].double()
+        err = float(torch.linalg.vector_norm(g_probed - ge) / torch.linalg.vector_norm(ge))
+        cos = float((g_probed * ge).sum() / (torch.linalg.vector_norm(g_probed)
+                                             * torch.linalg.vector_norm(ge)))
+        probed_bytes = plan.workspace_bytes + r * plan.Npad * 4     # ring + Ubar (fused)
+        full_hist = nt * N * 4.0
+        exact = {"exact_ms_per_step": round(ex_ms, 1),
+                 "speedup_vs_exact": round(ex_ms / ms_step, 3),
+                 "grad_rel_err_vs_exact": round(err, 4), "grad_cosine_vs_exact": round(cos, 4),
+                 "misfit_rel_diff": abs(float(ex["misfit"].item()) - misfit) / misfit,
+                 "memory_gb": {"probed_ring_plus_ubar": round(probed_bytes / 1e9, 2),
+                               "exact_checkpointed": round(ewb / 1e9, 2),
+                               "full_history_fp32": round(full_hist / 1e9, 1)},
+                 "memory_reduction_vs_full_history": round(full_hist / probed_bytes, 1),
+                 "memory_ratio_vs_checkpointed": round(ewb / probed_bytes, 2)}
+        del ework, ex, ge, g_probed
+        torch.cuda.empty_cache()
+        print("exact comparator done", file=sys.stderr, flush=True)
+    if a.copy_calib_mb:
+        nel = a.copy_calib_mb * (1 << 20) // 4
+        x = torch.ones(nel, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     ms_step = (t1 - t0) / a.steps * 1e3
     value = 2.0 * N * nt / (ms_step / 1e3) / 1e9
@@ -186,14 +233,14 @@ def main():
                    "imaging": "fused" if fused else "separate", "parallelism": "single-gpu"},
         "roofline": dominant, "roofline_other": other,
         "hbm_frac_path": round(path_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "grad_rel_err_vs_exact": None,
+        "grad_rel_err_vs_exact": exact["grad_rel_err_vs_exact"] if exact else None,
+        "exact_comparator": exact,
         "misfit": misfit, "grad_finite": finite,
         ("unfused_ms_per_step" if fused else "fused_ms_per_step"): round(other_ms, 1),
         "misfit_same_in_both": misfit == other_misfit,
         "image_avg_ms": round(im_ms / max(im_n, 1), 2),
     }
     if not a.no_cpu_baseline:
-        del out
         torch.cuda.empty_cache()
         rec_line["cpu_baseline"] = cpu_baseline(a.cpu_planes, a.cpu_nt, r)
     print(json.dumps(rec_line), flush=True)
