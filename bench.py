@@ -27,6 +27,36 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(grid, r, k):
+    """HBM bytes per dispatch measured with rocprofv3 --pmc (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy of known size) for this workload, if the
+    kernel sources are unchanged since the counters were taken; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in ("stencil.hip", "probe.hip", "misc.hip"):
+        with open(os.path.join(ROOT, "paper_2201_06914_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if rec.get("source_hash") != h.hexdigest()[:16] or rec.get("grid") != list(grid) \
+            or rec.get("r") != r or rec.get("k") != k:
+        return None
+    kk = rec["kernels"]
+    st = kk.get("k_stencil3d_tiled")
+    fw = kk.get("k_probe_mfma_fast<2, true, 1, false, 4>")
+    ad = kk.get("k_probe_mfma_fast<2, true, 2, true, 2>")
+    out = {}
+    if st:
+        out["stencil"] = st["read_bytes"] + st["write_bytes"]
+    if fw and ad:
+        out["probe"] = 0.5 * (fw["read_bytes"] + fw["write_bytes"] + ad["read_bytes"]
+                              + ad["write_bytes"])
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +251,10 @@ def main():
              "mfma_tflops": round((2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 *
                                   math.ceil(k / 16) * N * 2 * nblk * a.steps /
                                   (pr_ms * 1e-3) / 1e12, 2) if pr_n else None}
+    tr = measured_traffic((384, 512, 512), r, k) if fused else None
+    if tr:
+        stencil["traffic"] = round(tr.get("stencil", 0.0))
+        probe["traffic"] = round(tr.get("probe", 0.0))
     dominant, other = (probe, stencil) if pr_tot > st_tot else (stencil, probe)
     path_bytes = 2 * nt * st_bytes + pr_bytes_step
     rec_line = {
