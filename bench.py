@@ -75,6 +75,9 @@ def parse():
                     help="skip the exact (checkpointed FP32) comparator run")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (PMC calibration)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 16-shot batched workload section")
+    ap.add_argument("--batched-nt", type=int, default=2000)
     ap.add_argument("--cpu-planes", type=int, default=24)
     ap.add_argument("--cpu-nt", type=int, default=80)
     return ap.parse_args()
@@ -100,6 +103,70 @@ def cpu_baseline(planes: int, nt: int, r: int):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"FP64 oracle, {planes}x512x512 z-slab of the same model, nt={nt}, "
                       f"r={r}, forward+adjoint with probing + image, {dt:.1f} s"}
+
+
+def bench_batched(nt: int, variant: int):
+    """16 shots on uneven windows 128^3 ... 256 x 320 x 320 (181,394,048 cells),
+    nt steps, r = 64, k = 32, BF16X2 probes, fused imaging: one stencil launch
+    per step for all shots; the whole gradient replayed as one HIP graph.
+    Compared with the same 16 gradients run one shot at a time."""
+    import torch
+
+    import paper_2201_06914_amd as P
+    import synth
+    wls = synth.workload_batched(nt=nt)
+    specs, shots = [], []
+    for wl in wls:
+        specs.append(P.PlanSpec(3, wl.shape, wl.h, wl.dt, wl.nt, wl.nb, wl.c_ref, wl.R, 4725.0,
+                                "f32", "bf16x2", wl.r, wl.k_block, 1, wl.rec_pos.shape[0]))
+        shots.append(dict(m=torch.from_numpy(wl.m).cuda(), src_pos=wl.src_pos,
+                          q=torch.from_numpy(wl.q).cuda(), rec_pos=wl.rec_pos,
+                          d_obs=torch.zeros((nt, wl.rec_pos.shape[0]), device="cuda"),
+                          Z=torch.from_numpy(wl.Z).cuda()))
+    cells = sum(int(np.prod(sp.shape)) for sp in specs)
+    del wls
+    B = P.Batch(specs)
+    outs = B.outputs()
+    J = torch.empty(len(shots), dtype=torch.float64, device="cuda")
+    work = torch.empty(B.workspace_bytes, dtype=torch.uint8, device="cuda")
+    P.set_stencil_variant(variant)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3
+
+    t_capture = timed(lambda: B.fwi_gradient(shots, outs=outs, misfit=J, use_graph=True,
+                                             work=work))
+    print("batched: graph captured", file=sys.stderr, flush=True)
+    t_graph = min(timed(lambda: B.fwi_gradient(shots, outs=outs, misfit=J, use_graph=True,
+                                               work=work)) for _ in range(2))
+    g_graph = [o["grad"].clone() for o in outs]
+    t_eager = timed(lambda: B.fwi_gradient(shots, outs=outs, misfit=J, use_graph=False,
+                                           work=work))
+    same = all(torch.equal(a, o["grad"]) for a, o in zip(g_graph, outs))
+    print("batched: eager done", file=sys.stderr, flush=True)
+    del work, g_graph
+    torch.cuda.empty_cache()
+
+    def one_by_one():
+        for sp, sh, o in zip(specs, shots, outs):
+            plan = P.Plan(sp)
+            P.fwi_gradient(plan, sh["m"], sh["src_pos"], sh["q"], sh["rec_pos"], sh["d_obs"],
+                           sh["Z"], bars=(o["Ubar"], None), fused=True)
+    t_single = timed(one_by_one)
+    print("batched: one-by-one done", file=sys.stderr, flush=True)
+    return {"workload": f"16 shots, windows 128^3..256x320x320 ({cells} cells), nt={nt}, "
+                        f"r=64, k=32, bf16x2, fused imaging",
+            "value": round(2.0 * cells * nt / (t_graph * 1e-3) / 1e9, 2),
+            "unit": "Gcell-updates/s", "ms_per_gradient_graph": round(t_graph, 1),
+            "ms_per_gradient_eager": round(t_eager, 1),
+            "ms_first_call_with_capture": round(t_capture, 1),
+            "ms_one_shot_at_a_time": round(t_single, 1),
+            "speedup_vs_one_shot_at_a_time": round(t_single / t_graph, 3),
+            "graph_equals_eager": bool(same), "stencil_variant": variant}
 
 
 def main():
@@ -274,6 +341,13 @@ def main():
         "misfit_same_in_both": misfit == other_misfit,
         "image_avg_ms": round(im_ms / max(im_n, 1), 2),
     }
+    if not a.no_batched:
+        del bars, work, m, q, Z, d_obs
+        if "out" in locals():
+            del out
+        torch.cuda.empty_cache()
+        rec_line["batched"] = bench_batched(a.batched_nt, tune["best"] if tune["best"] >= 1 else 7)
+        torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         torch.cuda.empty_cache()
         rec_line["cpu_baseline"] = cpu_baseline(a.cpu_planes, a.cpu_nt, r)

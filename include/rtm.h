@@ -225,6 +225,35 @@ rtm_status fwi_gradient_exact(const rtm_plan *plan, const void *m, const double 
                               int32_t checkpoint_every, void *resid, void *grad, double *misfit,
                               void *work, size_t work_bytes, rtm_stream stream);
 
+/* Batched shots (3D, F32 fields, BF16 / BF16X2 probes).  Each descriptor is
+ * one shot's sub-domain window (its own nz, ny, nx, nb, c_ref, c_max, nsrc,
+ * nrec); nt, dt, h, r, k_block and the probe dtype must agree.  One launch
+ * per time step advances every shot (a tile table spans all windows), one
+ * launch injects and one samples for all shots; the probe GEMMs run per shot
+ * every k_block steps.  fwi_gradient_batched computes every shot's probed
+ * gradient (fused imaging, no Vbar) and misfit[i] (device double [nshots]).
+ * use_graph != 0 captures the whole launch sequence into a HIP graph on the
+ * first call and replays it while the pointers, positions and stencil variant
+ * stay the same (the batch object caches it; not thread safe). */
+typedef struct rtm_batch rtm_batch;
+typedef struct {
+  const void *m;          /* device [N_i] slowness squared */
+  const double *src_pos;  /* host [nsrc_i][3] */
+  const void *q;          /* device [nt][nsrc_i] */
+  const double *rec_pos;  /* host [nrec_i][3] */
+  const void *d_obs;      /* device [nt][nrec_i] */
+  const void *Z;          /* device [nt][r] int8 +-1 */
+  void *Ubar;             /* device [r*Npad_i] tile-major, output */
+  void *resid;            /* device [nt][nrec_i], output */
+  void *grad;             /* device [N_i], output */
+} rtm_shot_io;
+rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rtm_batch **batch);
+void rtm_batch_destroy(rtm_batch *batch);
+rtm_status rtm_batch_workspace_bytes(const rtm_batch *batch, size_t *bytes);
+rtm_status fwi_gradient_batched(rtm_batch *batch, const rtm_shot_io *io, double *misfit,
+                                int32_t use_graph, void *work, size_t work_bytes,
+                                rtm_stream stream);
+
 /* Converts a tile-major compressed field (device [r*Npad]) to rows (device
  * [r][N], caller-owned): rows[i][x] = bar[((x/32)*r + i)*32 + x%32]. */
 rtm_status rtm_bar_to_rows(const rtm_plan *plan, const void *bar, void *rows, rtm_stream stream);

@@ -12,4 +12,4 @@ from .api import (Plan, PlanSpec, RtmError, bar_index, cfl_bound, fwi_gradient, 
                   rtm_dot, rtm_forward_probe, rtm_image, set_stencil_variant,
                   profile_enable, profile_read, rtm_bar_to_rows,
                   fwi_gradient_exact, exact_workspace_bytes,
-                  autotune_stencil, set_stencil_blocks)
+                  autotune_stencil, set_stencil_blocks, Batch)

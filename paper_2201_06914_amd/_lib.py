@@ -17,7 +17,15 @@ EXPORTS = (
     "rtm_adjoint_probe", "rtm_image", "fwi_gradient", "rtm_dot", "rtm_profile_enable",
     "rtm_profile_read", "rtm_bar_to_rows", "rtm_exact_workspace_bytes", "fwi_gradient_exact",
     "rtm_adjoint_image", "rtm_set_stencil_blocks", "rtm_autotune_stencil",
+    "rtm_batch_create", "rtm_batch_destroy", "rtm_batch_workspace_bytes", "fwi_gradient_batched",
 )
+
+
+class ShotIO(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_void_p), ("src_pos", ctypes.POINTER(ctypes.c_double)),
+                ("q", ctypes.c_void_p), ("rec_pos", ctypes.POINTER(ctypes.c_double)),
+                ("d_obs", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("Ubar", ctypes.c_void_p),
+                ("resid", ctypes.c_void_p), ("grad", ctypes.c_void_p)]
 
 
 class RtmDesc(ctypes.Structure):
@@ -87,6 +95,14 @@ def load() -> ctypes.CDLL:
     L.rtm_autotune_stencil.argtypes = [_vp, _vp, _vp, sz, i32, ctypes.POINTER(i32),
                                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i64), _vp]
     L.rtm_autotune_stencil.restype = ctypes.c_int
+    L.rtm_batch_create.argtypes = [ctypes.POINTER(RtmDesc), i32, ctypes.POINTER(_vp)]
+    L.rtm_batch_create.restype = ctypes.c_int
+    L.rtm_batch_destroy.argtypes = [_vp]
+    L.rtm_batch_destroy.restype = None
+    L.rtm_batch_workspace_bytes.argtypes = [_vp, ctypes.POINTER(sz)]
+    L.rtm_batch_workspace_bytes.restype = ctypes.c_int
+    L.fwi_gradient_batched.argtypes = [_vp, ctypes.POINTER(ShotIO), _vp, i32, _vp, sz, _vp]
+    L.fwi_gradient_batched.restype = ctypes.c_int
     L.rtm_bar_to_rows.argtypes = [_vp, _vp, _vp, _vp]
     L.rtm_bar_to_rows.restype = ctypes.c_int
     L.rtm_profile_enable.argtypes = [i32]

@@ -105,6 +105,100 @@ class Plan:
         return torch.empty((self.Npad // 32, self.spec.r, 32), dtype=self.dtype, device=device)
 
 
+def _desc(spec: PlanSpec) -> _lib.RtmDesc:
+    d = _lib.RtmDesc()
+    d.ndim = spec.ndim
+    d.nz, d.ny, d.nx = (int(v) for v in spec.shape)
+    d.h, d.dt, d.nt, d.nb = spec.h, spec.dt, spec.nt, spec.nb
+    d.c_ref, d.R, d.c_max = spec.c_ref, spec.R, spec.c_max
+    d.field_dtype = _FIELD[spec.field]
+    d.probe_dtype = _PROBE[spec.probe]
+    d.r, d.k_block, d.nsrc, d.nrec = spec.r, spec.k_block, spec.nsrc, spec.nrec
+    return d
+
+
+class Batch:
+    """Several shots (sub-domain windows of different sizes) advanced together:
+    one stencil launch per time step for all shots, optional HIP-graph replay
+    of the whole gradient (rtm_batch_create / fwi_gradient_batched)."""
+
+    def __init__(self, specs):
+        L = _lib.load()
+        self.specs = list(specs)
+        arr = (_lib.RtmDesc * len(self.specs))(*[_desc(sp) for sp in self.specs])
+        h = ctypes.c_void_p()
+        _check(L.rtm_batch_create(arr, len(self.specs), ctypes.byref(h)), "rtm_batch_create")
+        self._h = h
+        self._destroy = L.rtm_batch_destroy
+        n = ctypes.c_size_t()
+        _check(L.rtm_batch_workspace_bytes(h, ctypes.byref(n)), "rtm_batch_workspace_bytes")
+        self.workspace_bytes = int(n.value)
+        self.N = [int(np.prod(sp.shape)) for sp in self.specs]
+        self.Npad = [(n_ + 31) // 32 * 32 for n_ in self.N]
+        self._stream = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+    def outputs(self, device="cuda") -> list:
+        """Preallocated per-shot outputs (reuse them to replay a captured graph)."""
+        outs = []
+        for sp, n, npad in zip(self.specs, self.N, self.Npad):
+            outs.append({"Ubar": torch.empty((npad // 32, sp.r, 32), dtype=torch.float32,
+                                             device=device),
+                         "resid": torch.empty((sp.nt, sp.nrec), dtype=torch.float32, device=device),
+                         "grad": torch.empty(n, dtype=torch.float32, device=device)})
+        return outs
+
+    def fwi_gradient(self, shots, outs=None, misfit=None, use_graph=False, work=None):
+        """shots: per shot dict(m, src_pos, q, rec_pos, d_obs, Z).  Returns
+        (outs, misfit) with outs[i] = dict(Ubar, resid, grad)."""
+        dev = shots[0]["m"].device
+        outs = outs if outs is not None else self.outputs(dev)
+        misfit = misfit if misfit is not None else torch.empty(len(shots), dtype=torch.float64,
+                                                               device=dev)
+        if work is None:
+            work = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
+        io = (_lib.ShotIO * len(shots))()
+        keep = []
+        for i, (sp, sh, o) in enumerate(zip(self.specs, shots, outs)):
+            sa, sap = _pos(sh["src_pos"], sp.nsrc, "src_pos")
+            ra, rap = _pos(sh["rec_pos"], sp.nrec, "rec_pos")
+            keep += [sa, ra]
+            io[i].m = _dev(sh["m"], torch.float32, self.N[i], "m")
+            io[i].src_pos = sap
+            io[i].q = _dev(sh["q"], torch.float32, sp.nt * sp.nsrc, "q")
+            io[i].rec_pos = rap
+            io[i].d_obs = _dev(sh["d_obs"], torch.float32, sp.nt * sp.nrec, "d_obs")
+            io[i].Z = _dev(sh["Z"], torch.int8, sp.nt * sp.r, "Z")
+            io[i].Ubar = _dev(o["Ubar"], torch.float32, sp.r * self.Npad[i], "Ubar")
+            io[i].resid = _dev(o["resid"], torch.float32, sp.nt * sp.nrec, "resid")
+            io[i].grad = _dev(o["grad"], torch.float32, self.N[i], "grad")
+        L = _lib.load()
+        if use_graph:
+            # a capture needs a non-default stream (default priority)
+            if self._stream is None:
+                self._stream = torch.cuda.Stream(device=dev)
+            cur = torch.cuda.current_stream(dev)
+            self._stream.wait_stream(cur)
+            with torch.cuda.stream(self._stream):
+                code = L.fwi_gradient_batched(self._h, io, _dev(misfit, torch.float64,
+                                                                len(shots), "misfit"), 1,
+                                              ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                              _stream(dev))
+            cur.wait_stream(self._stream)
+        else:
+            code = L.fwi_gradient_batched(self._h, io, _dev(misfit, torch.float64, len(shots),
+                                                            "misfit"), 0,
+                                          ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                          _stream(dev))
+        _check(code, "fwi_gradient_batched")
+        return outs, misfit
+
+
 def cfl_bound(ndim: int) -> float:
     return float(_lib.load().rtm_cfl_bound(ndim))
 

@@ -967,3 +967,365 @@ extern "C" rtm_status rtm_autotune_stencil(const rtm_plan *P, const void *m, voi
     return autotune_impl<double>(P, m, static_cast<char *>(work), steps, best, us, mismatch, st);
   return autotune_impl<float>(P, m, static_cast<char *>(work), steps, best, us, mismatch, st);
 }
+
+// ---------------------------------------------------------------------------
+// batched shots: one launch per step for all shots, optional hipGraph
+// ---------------------------------------------------------------------------
+struct BatchPointRegion {
+  Region soff, sidx, sw, sshot, slocal, icell, ishot, ioff, ipt, iw;
+  int32_t cap = 0;
+};
+
+struct rtm_batch {
+  int ns = 0;
+  std::vector<rtm_plan *> P;
+  std::vector<size_t> ring_off;
+  Region red, shots, io_fwd, io_adj, tiles;
+  BatchPointRegion src, rec;
+  size_t tab_off = 0, tab_bytes = 0, total = 0;
+  std::vector<int4> tile_host;
+  int32_t nsrc_total = 0, nrec_total = 0;
+  // cached graph of the last fwi_gradient_batched launch sequence
+  hipGraphExec_t gexec = nullptr;
+  uint64_t gkey = 0;
+};
+
+static void place_batch_points(size_t &cur, BatchPointRegion &pr, int32_t n, size_t esz) {
+  const size_t c = (size_t)8 * n;
+  pr.cap = n;
+  place(cur, pr.soff, 4 * ((size_t)n + 1));
+  place(cur, pr.sidx, 4 * c);
+  place(cur, pr.sw, esz * c);
+  place(cur, pr.sshot, 4 * (size_t)n);
+  place(cur, pr.slocal, 4 * (size_t)n);
+  place(cur, pr.icell, 4 * c);
+  place(cur, pr.ishot, 4 * c);
+  place(cur, pr.ioff, 4 * (c + 1));
+  place(cur, pr.ipt, 4 * c);
+  place(cur, pr.iw, esz * c);
+}
+
+extern "C" void rtm_batch_destroy(rtm_batch *b) {
+  if (!b) return;
+  for (rtm_plan *p : b->P) rtm_plan_destroy(p);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  delete b;
+}
+
+extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rtm_batch **out) {
+  g_last_error.clear();
+  if (!shots || !out || nshots < 1) return fail(RTM_E_ARG, "need nshots >= 1 descriptors");
+  const rtm_desc &d0 = shots[0];
+  for (int i = 0; i < nshots; ++i) {
+    const rtm_desc &d = shots[i];
+    if (d.ndim != 3 || d.field_dtype != RTM_F32 ||
+        (d.probe_dtype != RTM_BF16 && d.probe_dtype != RTM_BF16X2))
+      return fail(RTM_E_UNSUPPORTED, "batched shots are 3D, F32 fields, BF16 / BF16X2 probes");
+    if (d.nt != d0.nt || d.dt != d0.dt || d.h != d0.h || d.r != d0.r ||
+        d.k_block != d0.k_block || d.probe_dtype != d0.probe_dtype)
+      return fail(RTM_E_ARG, "shot %d: nt, dt, h, r, k_block and probe dtype must agree", i);
+  }
+  rtm_batch *b = new (std::nothrow) rtm_batch();
+  if (!b) return fail(RTM_E_ARG, "out of host memory");
+  b->ns = nshots;
+  for (int i = 0; i < nshots; ++i) {
+    rtm_plan *p = nullptr;
+    rtm_status st = rtm_plan_create(&shots[i], &p);
+    if (st) {
+      rtm_batch_destroy(b);
+      return st;
+    }
+    b->P.push_back(p);
+    b->nsrc_total += shots[i].nsrc;
+    b->nrec_total += shots[i].nrec;
+  }
+  // tile table: 64 x 16 column tiles of every shot, z split until the launch
+  // has >= 1024 workgroups (each chunk >= 16 planes)
+  int nzc = 1;
+  auto count = [&](int z) {
+    int64_t t = 0;
+    for (auto *p : b->P) t += ((p->d.nx + 63) / 64) * ((p->d.ny + 15) / 16) * (int64_t)z;
+    return t;
+  };
+  int minz = INT32_MAX;
+  for (auto *p : b->P) minz = std::min<int>(minz, (int)p->d.nz);
+  while (count(nzc) < 1024 && minz / (nzc * 2) >= 16) nzc *= 2;
+  for (int i = 0; i < nshots; ++i) {
+    const rtm_desc &d = b->P[i]->d;
+    const int ntx = (int)((d.nx + 63) / 64), nty = (int)((d.ny + 15) / 16);
+    const int zc = (int)((d.nz + nzc - 1) / nzc);
+    if (ntx > 0xffff || nty > 0x7fff) {
+      rtm_batch_destroy(b);
+      return fail(RTM_E_SHAPE, "shot %d: too many tiles", i);
+    }
+    for (int z0 = 0; z0 < d.nz; z0 += zc)
+      for (int by = 0; by < nty; ++by)
+        for (int bx = 0; bx < ntx; ++bx)
+          b->tile_host.push_back(make_int4(i, bx | (by << 16), z0, (int)std::min<int64_t>(z0 + zc, d.nz)));
+  }
+  size_t cur = 0;
+  for (auto *p : b->P) {
+    b->ring_off.push_back(cur);
+    cur = align256(cur + (size_t)p->R * p->ld * 4);
+  }
+  place(cur, b->red, sizeof(double) * (kReduceBlocks + 8) * nshots);
+  b->tab_off = cur;
+  place(cur, b->shots, sizeof(ShotStep<float>) * nshots);
+  place(cur, b->io_fwd, sizeof(ShotIO<float>) * nshots);
+  place(cur, b->io_adj, sizeof(ShotIO<float>) * nshots);
+  place(cur, b->tiles, sizeof(int4) * b->tile_host.size());
+  place_batch_points(cur, b->src, b->nsrc_total, 4);
+  place_batch_points(cur, b->rec, b->nrec_total, 4);
+  b->tab_bytes = cur - b->tab_off;
+  b->total = cur;
+  *out = b;
+  return RTM_OK;
+}
+
+extern "C" rtm_status rtm_batch_workspace_bytes(const rtm_batch *b, size_t *bytes) {
+  if (!b || !bytes) return fail(RTM_E_ARG, "batch and bytes must be non-NULL");
+  *bytes = b->total;
+  return RTM_OK;
+}
+
+// merged CSR tables of one point set across shots (host staging)
+static rtm_status stage_batch_points(const rtm_batch *b, const BatchPointRegion &pr,
+                                     const rtm_shot_io *io, bool rec, std::vector<unsigned char> &host,
+                                     int32_t *npts, int32_t *ncell, uint64_t *hash) {
+  std::vector<int32_t> soff(1, 0), sidx, sshot, slocal, icell, ishot, ioff(1, 0), ipt;
+  std::vector<float> sw, iw;
+  for (int i = 0; i < b->ns; ++i) {
+    const rtm_plan *P = b->P[i];
+    const int32_t n = rec ? P->d.nrec : P->d.nsrc;
+    const double *pos = rec ? io[i].rec_pos : io[i].src_pos;
+    if (n > 0 && !pos) return fail(RTM_E_ARG, "shot %d: positions missing", i);
+    for (int32_t k = 0; k < 3 * n; ++k) {
+      uint64_t v;
+      std::memcpy(&v, pos + k, 8);
+      *hash = (*hash ^ v) * 1099511628211ull;
+    }
+    HostPoints hp;
+    rtm_status st = build_points(P, n, pos, hp);
+    if (st) return st;
+    for (int32_t p = 0; p < n; ++p) {
+      for (int32_t j = hp.soff[p]; j < hp.soff[p + 1]; ++j) {
+        sidx.push_back(hp.sidx[j]);
+        sw.push_back((float)hp.sw[j]);
+      }
+      soff.push_back((int32_t)sidx.size());
+      sshot.push_back(i);
+      slocal.push_back(p);
+    }
+    for (size_t c = 0; c < hp.icell.size(); ++c) {
+      icell.push_back(hp.icell[c]);
+      ishot.push_back(i);
+      for (int32_t j = hp.ioff[c]; j < hp.ioff[c + 1]; ++j) {
+        ipt.push_back(hp.ipt[j]);
+        iw.push_back((float)hp.iw[j]);
+      }
+      ioff.push_back((int32_t)ipt.size());
+    }
+  }
+  auto put = [&](const Region &r, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(host.data() + (r.off - b->tab_off), src, bytes);
+  };
+  put(pr.soff, soff.data(), 4 * soff.size());
+  put(pr.sidx, sidx.data(), 4 * sidx.size());
+  put(pr.sw, sw.data(), 4 * sw.size());
+  put(pr.sshot, sshot.data(), 4 * sshot.size());
+  put(pr.slocal, slocal.data(), 4 * slocal.size());
+  put(pr.icell, icell.data(), 4 * icell.size());
+  put(pr.ishot, ishot.data(), 4 * ishot.size());
+  put(pr.ioff, ioff.data(), 4 * ioff.size());
+  put(pr.ipt, ipt.data(), 4 * ipt.size());
+  put(pr.iw, iw.data(), 4 * iw.size());
+  *npts = (int32_t)sshot.size();
+  *ncell = (int32_t)icell.size();
+  return RTM_OK;
+}
+
+static BatchPoints<float> batch_points(const BatchPointRegion &pr, char *w, int32_t npts,
+                                       int32_t ncell) {
+  BatchPoints<float> t;
+  t.soff = reinterpret_cast<const int32_t *>(w + pr.soff.off);
+  t.sidx = reinterpret_cast<const int32_t *>(w + pr.sidx.off);
+  t.sw = reinterpret_cast<const float *>(w + pr.sw.off);
+  t.sshot = reinterpret_cast<const int32_t *>(w + pr.sshot.off);
+  t.slocal = reinterpret_cast<const int32_t *>(w + pr.slocal.off);
+  t.icell = reinterpret_cast<const int32_t *>(w + pr.icell.off);
+  t.ishot = reinterpret_cast<const int32_t *>(w + pr.ishot.off);
+  t.ioff = reinterpret_cast<const int32_t *>(w + pr.ioff.off);
+  t.ipt = reinterpret_cast<const int32_t *>(w + pr.ipt.off);
+  t.iw = reinterpret_cast<const float *>(w + pr.iw.off);
+  t.npts = npts;
+  t.ncell = ncell;
+  return t;
+}
+
+// The whole batched gradient as a stream-ordered launch sequence (captured
+// into a graph when requested).
+static rtm_status batch_enqueue(const rtm_batch *b, const rtm_shot_io *io, double *misfit,
+                                char *w, const BatchPoints<float> &src_t,
+                                const BatchPoints<float> &rec_t, int variant, hipStream_t st) {
+  const rtm_desc &d = b->P[0]->d;
+  const int nt = d.nt, k = d.k_block;
+  const auto *shots = reinterpret_cast<const ShotStep<float> *>(w + b->shots.off);
+  const auto *iof = reinterpret_cast<const ShotIO<float> *>(w + b->io_fwd.off);
+  const auto *ioa = reinterpret_cast<const ShotIO<float> *>(w + b->io_adj.off);
+  const auto *tiles = reinterpret_cast<const int4 *>(w + b->tiles.off);
+  const int ntiles = (int)b->tile_host.size();
+  auto ring = [&](int i) { return reinterpret_cast<float *>(w + b->ring_off[i]); };
+  auto lvl = [&](int i, int j) {
+    const rtm_plan *P = b->P[i];
+    return ring(i) + (int64_t)((j + 1) % P->R) * P->ld;
+  };
+  auto probe = [&](bool adj, int s0, int kb) -> rtm_status {
+    for (int i = 0; i < b->ns; ++i) {
+      const rtm_plan *P = b->P[i];
+      ProbeArgs<float> p{};
+      p.ring = ring(i);
+      p.ld = P->ld;
+      p.R = P->R;
+      p.s0 = s0;
+      p.slot0 = s0 % P->R;
+      p.kb = kb;
+      p.zrow0 = adj ? nt - 1 - s0 : s0;
+      p.zdir = adj ? -1 : 1;
+      p.r = d.r;
+      p.N = P->N;
+      p.bar = adj ? nullptr : static_cast<float *>(io[i].Ubar);
+      p.inv_dt2 = (float)(1.0 / (d.dt * d.dt));
+      p.mode = adj ? PROBE_NEW : PROBE_UTT;
+      HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io[i].Z),
+                                d.probe_dtype == RTM_BF16X2,
+                                adj ? static_cast<const float *>(io[i].Ubar) : nullptr,
+                                adj ? static_cast<float *>(io[i].grad) : nullptr,
+                                (float)(-1.0 / d.r), st));
+    }
+    return RTM_OK;
+  };
+  rtm_status s_;
+  // forward
+  for (int i = 0; i < b->ns; ++i) {
+    HIP_TRY(launch_fill<float>(lvl(i, -1), b->P[i]->N, 0.f, st));
+    HIP_TRY(launch_fill<float>(lvl(i, 0), b->P[i]->N, 0.f, st));
+    HIP_TRY(launch_fill<float>(static_cast<float *>(io[i].Ubar), (int64_t)d.r * b->P[i]->Npad, 0.f, st));
+  }
+  int s0 = 0;
+  for (int s = 0; s < nt; ++s) {
+    HIP_TRY(launch_stencil_batched<float>(shots, tiles, ntiles, s, variant, st));
+    HIP_TRY(launch_inject_batched<float>(shots, iof, src_t, s, s, st));
+    HIP_TRY(launch_sample_batched<float>(shots, iof, rec_t, s, s, st));
+    if (s + 1 - s0 == k || s == nt - 1) {
+      if ((s_ = probe(false, s0, s + 1 - s0))) return s_;
+      s0 = s + 1;
+    }
+  }
+  // residual and misfit per shot
+  for (int i = 0; i < b->ns; ++i) {
+    double *part = reinterpret_cast<double *>(w + b->red.off) + (size_t)i * (kReduceBlocks + 8);
+    float *res = static_cast<float *>(io[i].resid);
+    HIP_TRY(launch_residual_misfit<float>(res, static_cast<const float *>(io[i].d_obs), res,
+                                          (int64_t)nt * b->P[i]->d.nrec, part, misfit + i, st));
+  }
+  // adjoint with the imaging condition folded into its probe blocks
+  for (int i = 0; i < b->ns; ++i) {
+    HIP_TRY(launch_fill<float>(lvl(i, -1), b->P[i]->N, 0.f, st));
+    HIP_TRY(launch_fill<float>(lvl(i, 0), b->P[i]->N, 0.f, st));
+    HIP_TRY(launch_fill<float>(static_cast<float *>(io[i].grad), b->P[i]->N, 0.f, st));
+  }
+  s0 = 0;
+  for (int s = 0; s < nt; ++s) {
+    HIP_TRY(launch_stencil_batched<float>(shots, tiles, ntiles, s, variant, st));
+    HIP_TRY(launch_inject_batched<float>(shots, ioa, rec_t, s, nt - 1 - s, st));
+    if (s + 1 - s0 == k || s == nt - 1) {
+      if ((s_ = probe(true, s0, s + 1 - s0))) return s_;
+      s0 = s + 1;
+    }
+  }
+  return RTM_OK;
+}
+
+extern "C" rtm_status fwi_gradient_batched(rtm_batch *b, const rtm_shot_io *io, double *misfit,
+                                           int32_t use_graph, void *work, size_t work_bytes,
+                                           rtm_stream stream) {
+  g_last_error.clear();
+  if (!b || !io || !misfit || !work) return fail(RTM_E_ARG, "NULL argument");
+  if (work_bytes < b->total)
+    return fail(RTM_E_WORKSPACE, "work has %zu bytes, the batch needs %zu", work_bytes, b->total);
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(RTM_E_ARG, "work must be 256-byte aligned");
+  for (int i = 0; i < b->ns; ++i) {
+    const rtm_shot_io &x = io[i];
+    if (!x.m || !x.Z || !x.Ubar || !x.grad || !x.d_obs || !x.resid ||
+        (b->P[i]->d.nsrc > 0 && (!x.q || !x.src_pos)) || (b->P[i]->d.nrec > 0 && !x.rec_pos))
+      return fail(RTM_E_ARG, "shot %d: missing array", i);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(work);
+  // stage every table (shot steps, io, tiles, points) and upload once
+  std::vector<unsigned char> host(b->tab_bytes, 0);
+  auto put = [&](const Region &r, const void *src, size_t bytes) {
+    std::memcpy(host.data() + (r.off - b->tab_off), src, bytes);
+  };
+  std::vector<ShotStep<float>> shots(b->ns);
+  std::vector<ShotIO<float>> iof(b->ns), ioa(b->ns);
+  uint64_t key = 1469598103934665603ull;
+  auto mix = [&](const void *p) { key = (key ^ (uint64_t)(uintptr_t)p) * 1099511628211ull; };
+  mix(work);
+  mix(misfit);
+  for (int i = 0; i < b->ns; ++i) {
+    const rtm_plan *P = b->P[i];
+    shots[i].a = step_args<float>(P, static_cast<const float *>(io[i].m));
+    shots[i].ring = reinterpret_cast<float *>(w + b->ring_off[i]);
+    shots[i].ld = P->ld;
+    shots[i].R = P->R;
+    iof[i] = {static_cast<const float *>(io[i].q), static_cast<float *>(io[i].resid), P->d.nsrc,
+              P->d.nrec};
+    ioa[i] = {static_cast<const float *>(io[i].resid), nullptr, P->d.nrec, 0};
+    for (const void *p : {io[i].m, io[i].q, io[i].d_obs, io[i].Z, (const void *)io[i].Ubar,
+                          (const void *)io[i].resid, (const void *)io[i].grad})
+      mix(p);
+  }
+  put(b->shots, shots.data(), sizeof(ShotStep<float>) * b->ns);
+  put(b->io_fwd, iof.data(), sizeof(ShotIO<float>) * b->ns);
+  put(b->io_adj, ioa.data(), sizeof(ShotIO<float>) * b->ns);
+  put(b->tiles, b->tile_host.data(), sizeof(int4) * b->tile_host.size());
+  int32_t snp = 0, snc = 0, rnp = 0, rnc = 0;
+  rtm_status s = stage_batch_points(b, b->src, io, false, host, &snp, &snc, &key);
+  if (s) return s;
+  if ((s = stage_batch_points(b, b->rec, io, true, host, &rnp, &rnc, &key))) return s;
+  int variant = g_stencil_variant >= kStencilTiled ? g_stencil_variant : 7;
+  key = (key ^ (uint64_t)variant) * 1099511628211ull;
+  HIP_TRY(hipMemcpyAsync(w + b->tab_off, host.data(), b->tab_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  BatchPoints<float> src_t = batch_points(b->src, w, snp, snc);
+  BatchPoints<float> rec_t = batch_points(b->rec, w, rnp, rnc);
+  if (!use_graph) return batch_enqueue(b, io, misfit, w, src_t, rec_t, variant, st);
+  if (!b->gexec || b->gkey != key) {
+    if (b->gexec) {
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int saved = g_prof_stride;
+    g_prof_stride = 0;  // no event records inside a capture
+    s = batch_enqueue(b, io, misfit, w, src_t, rec_t, variant, st);
+    g_prof_stride = saved;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(RTM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->gexec = nullptr;
+      return fail(RTM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    b->gkey = key;
+  }
+  HIP_TRY(hipGraphLaunch(b->gexec, st));
+  return RTM_OK;
+}

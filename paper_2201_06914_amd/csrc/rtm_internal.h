@@ -29,6 +29,16 @@ struct StepArgs {
   T kd;              // sponge coefficient per squared cell depth
 };
 
+// One shot of a batched sweep: its step arguments (level pointers are
+// rebuilt per step from the ring: level j in slot (j+1) mod R).
+template <typename T>
+struct ShotStep {
+  StepArgs<T> a;
+  T *ring;
+  int64_t ld;
+  int R;
+};
+
 // Point tables in CSR form (device pointers into the workspace).
 template <typename T>
 struct PointTables {
@@ -43,6 +53,24 @@ struct PointTables {
   const T *iw = nullptr;
   int32_t npts = 0;
   int32_t ncell = 0;
+};
+
+// Point tables of a batch of shots: one CSR across all shots.  Sampling is
+// per global point (its shot and local index); injection per distinct
+// (shot, cell).  ShotIO gives each shot's value / output arrays of the sweep.
+template <typename T>
+struct BatchPoints {
+  const int32_t *soff = nullptr, *sidx = nullptr, *sshot = nullptr, *slocal = nullptr;
+  const T *sw = nullptr;
+  const int32_t *icell = nullptr, *ishot = nullptr, *ioff = nullptr, *ipt = nullptr;
+  const T *iw = nullptr;
+  int32_t npts = 0, ncell = 0;
+};
+template <typename T>
+struct ShotIO {
+  const T *inj;   // [nt][n_inj] values injected at this shot's points
+  T *out;         // [nt][n_smp] sampled traces, or NULL
+  int32_t n_inj, n_smp;
 };
 
 enum ProbeMode : int {
@@ -72,6 +100,17 @@ struct ProbeArgs {
 template <typename T>
 hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
                           hipStream_t st);
+// batched sweep step (all shots, one launch each): stencil over the tile
+// table, then injection / sampling of level s+1 for time index n
+template <typename T>
+hipError_t launch_stencil_batched(const ShotStep<T> *shots, const int4 *tiles, int ntiles, int s,
+                                  int variant, hipStream_t st);
+template <typename T>
+hipError_t launch_inject_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
+                                 const BatchPoints<T> &pt, int s, int n, hipStream_t st);
+template <typename T>
+hipError_t launch_sample_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
+                                 const BatchPoints<T> &pt, int s, int n, hipStream_t st);
 // autotuning: hash pattern fill, count of bitwise-different elements (atomic
 // integer add into *count)
 template <typename T>

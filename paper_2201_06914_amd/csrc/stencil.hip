@@ -97,9 +97,9 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
   else *p = v;
 }
 
+// One column tile (bx, by) over planes [z0, z1) of one level.
 template <typename T, int TX, int TYT, int RY, bool NT>
-__global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int ntx, int nty,
-                                                             int nzc, int zchunk) {
+__device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by, int z0, int z1) {
   constexpr int NTH = TX * TYT;
   constexpr int TY = TYT * RY;
   constexpr int LX = TX + 8;
@@ -108,22 +108,11 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
   constexpr int NHX = (8 * TY + NTH - 1) / NTH;   // x-halo cells per thread
   __shared__ T lds[2][LY * LX];
 
-  // XCD-aware order: consecutive hardware block ids go round-robin over the 8
-  // XCDs; give each XCD a contiguous run of tiles so halo re-reads hit its L2.
-  const int nblk = ntx * nty * nzc;
-  int b = blockIdx.x;
-  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-  const int bx = b % ntx;
-  const int by = (b / ntx) % nty;
-  const int bz = b / (ntx * nty);
-
   const int tid = threadIdx.x;
   const int tx = tid % TX;
   const int ty = tid / TX;
   const int x0 = bx * TX, y0 = by * TY;
   const int x = x0 + tx;
-  const int z0 = bz * zchunk;
-  const int z1 = min(z0 + zchunk, a.nz);
   const int64_t sp = (int64_t)a.ny * a.nx;
   const T *__restrict__ u = a.cur;
 
@@ -234,6 +223,39 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
       for (int k = 0; k < 8; ++k) q[j][k] = q[j][k + 1];
     }
   }
+}
+
+template <typename T, int TX, int TYT, int RY, bool NT>
+__global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int ntx, int nty,
+                                                             int nzc, int zchunk) {
+  // XCD-aware order: consecutive hardware block ids go round-robin over the 8
+  // XCDs; give each XCD a contiguous run of tiles so halo re-reads hit its L2.
+  const int nblk = ntx * nty * nzc;
+  int b = blockIdx.x;
+  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  const int bx = b % ntx;
+  const int by = (b / ntx) % nty;
+  const int bz = b / (ntx * nty);
+  const int z0 = bz * zchunk;
+  tiled_body<T, TX, TYT, RY, NT>(a, bx, by, z0, min(z0 + zchunk, a.nz));
+}
+
+// Several shots (independent grids, one ring each) in one launch: entry e of
+// the tile table names the shot and the tile; the shot's step arguments come
+// from a device table (level pointers rebuilt from the step index s).
+template <typename T, int TX, int TYT, int RY, bool NT>
+__global__ __launch_bounds__(TX *TYT) void k_stencil3d_batched(const ShotStep<T> *__restrict__ shots,
+                                                               const int4 *__restrict__ tiles,
+                                                               int ntiles, int s) {
+  int b = blockIdx.x;
+  if ((ntiles & 7) == 0) b = (b & 7) * (ntiles >> 3) + (b >> 3);
+  const int4 t = tiles[b];  // (shot, bx | by << 16, z0, z1)
+  StepArgs<T> a = shots[t.x].a;
+  const ShotStep<T> &sh = shots[t.x];
+  a.cur = sh.ring + (int64_t)(((s + 1) % sh.R)) * sh.ld;
+  a.prev = sh.ring + (int64_t)(((s + sh.R) % sh.R)) * sh.ld;
+  a.next = sh.ring + (int64_t)(((s + 2) % sh.R)) * sh.ld;
+  tiled_body<T, TX, TYT, RY, NT>(a, t.y & 0xffff, t.y >> 16, t.z, t.w);
 }
 
 template <typename T, int TX, int TYT, int RY, bool NT>
@@ -374,6 +396,99 @@ hipError_t launch_sample(const PointTables<T> &pt, const T *field, T *out, hipSt
                      out);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// batched shots
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_stencil_batched(const ShotStep<T> *shots, const int4 *tiles, int ntiles, int s,
+                                  int variant, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    switch (variant) {
+      case 3:
+        hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 8, 2, false>), dim3(ntiles), dim3(512), 0,
+                           st, shots, tiles, ntiles, s);
+        break;
+      case 7:
+        hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, true>), dim3(ntiles), dim3(256), 0,
+                           st, shots, tiles, ntiles, s);
+        break;
+      default:
+        hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, false>), dim3(ntiles), dim3(256), 0,
+                           st, shots, tiles, ntiles, s);
+    }
+  } else {
+    hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, false>), dim3(ntiles), dim3(256), 0, st,
+                       shots, tiles, ntiles, s);
+  }
+  return hipGetLastError();
+}
+
+// level s+1 of shot sh
+template <typename T>
+__device__ __forceinline__ T *next_level(const ShotStep<T> &sh, int s) {
+  return sh.ring + (int64_t)((s + 2) % sh.R) * sh.ld;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_inject_batched(const ShotStep<T> *__restrict__ shots,
+                                                        const ShotIO<T> *__restrict__ io,
+                                                        BatchPoints<T> pt, int s, int n) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= pt.ncell) return;
+  const int sh = pt.ishot[c];
+  const T *vals = io[sh].inj + (int64_t)n * io[sh].n_inj;
+  T acc = T(0);
+  for (int j = pt.ioff[c]; j < pt.ioff[c + 1]; ++j) acc += pt.iw[j] * vals[pt.ipt[j]];
+  const StepArgs<T> &a = shots[sh].a;
+  const int64_t i = pt.icell[c];
+  const int x = (int)(i % a.nx);
+  const int64_t zy = i / a.nx;
+  const int y = (int)(zy % a.ny);
+  const int z = (int)(zy / a.ny);
+  T *field = next_level(shots[sh], s);
+  field[i] += a.dt2 * acc / (a.m[i] + sponge_a(a, z, y, x));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample_batched(const ShotStep<T> *__restrict__ shots,
+                                                        const ShotIO<T> *__restrict__ io,
+                                                        BatchPoints<T> pt, int s, int n) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= pt.npts) return;
+  const int sh = pt.sshot[p];
+  if (!io[sh].out) return;
+  const T *field = next_level(shots[sh], s);
+  T v = T(0);
+  for (int j = pt.soff[p]; j < pt.soff[p + 1]; ++j) v += pt.sw[j] * field[pt.sidx[j]];
+  io[sh].out[(int64_t)n * io[sh].n_smp + pt.slocal[p]] = v;
+}
+
+template <typename T>
+hipError_t launch_inject_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
+                                 const BatchPoints<T> &pt, int s, int n, hipStream_t st) {
+  if (pt.ncell <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_inject_batched<T>), dim3((pt.ncell + 255) / 256), dim3(256), 0, st, shots,
+                     io, pt, s, n);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_sample_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
+                                 const BatchPoints<T> &pt, int s, int n, hipStream_t st) {
+  if (pt.npts <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sample_batched<T>), dim3((pt.npts + 255) / 256), dim3(256), 0, st, shots,
+                     io, pt, s, n);
+  return hipGetLastError();
+}
+template hipError_t launch_stencil_batched<float>(const ShotStep<float> *, const int4 *, int, int,
+                                                  int, hipStream_t);
+template hipError_t launch_inject_batched<float>(const ShotStep<float> *, const ShotIO<float> *,
+                                                 const BatchPoints<float> &, int, int,
+                                                 hipStream_t);
+template hipError_t launch_sample_batched<float>(const ShotStep<float> *, const ShotIO<float> *,
+                                                 const BatchPoints<float> &, int, int,
+                                                 hipStream_t);
 
 template hipError_t launch_inject<float>(const StepArgs<float> &, const PointTables<float> &,
                                          const float *, float *, hipStream_t);

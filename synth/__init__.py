@@ -23,7 +23,7 @@ __all__ = [
     "rademacher", "sylvester_hadamard", "ricker", "source_signature",
     "smooth", "pad_edge", "two_layer_2d", "layered_3d", "salt_ellipsoid",
     "plane_receivers", "line_receivers", "Workload", "workload_c1",
-    "workload_c2", "workload_small_3d", "workload_small_2d",
+    "workload_c2", "workload_small_3d", "workload_small_2d", "workload_batched",
 ]
 
 
@@ -241,3 +241,34 @@ def workload_small_2d(shape=(60, 75), nt: int = 200, r: int = 8, seed: int = 5,
     return Workload(f"2d-small-{nz}x{nx}-nt{nt}", 2, (nz, 1, nx), h, dt, nt, nb,
                     float(v.max()), 1e-3, m, None, src, q, rec,
                     rademacher(nt, r, seed + 1), 16)
+
+
+def batched_window_shapes(nshots: int = 16, lo=(128, 128, 128), hi=(256, 320, 320)):
+    """Uneven sub-domain windows (z, y, x) growing linearly from lo to hi."""
+    shapes = []
+    for s in range(nshots):
+        f = s / max(nshots - 1, 1)
+        shapes.append(tuple(int(round(a + (b - a) * f)) for a, b in zip(lo, hi)))
+    return shapes
+
+
+def workload_batched(nt: int = 2000, r: int = 64, k_block: int = 32, nshots: int = 16,
+                     shapes=None) -> list:
+    """16 shots on uneven windows 128^3 ... 256 x 320 x 320 (z, y, x), each the
+    layered recipe of the 384 x 512 x 512 case (12 layers 1.5-4.5 km/s, +-5 %,
+    seed 100 + s), a 10 Hz source at the window's top centre, a full receiver
+    plane at iz = 12, nt = 2000, dt = 1 ms, r = 64 probes (seed 200 + s)."""
+    shapes = shapes or batched_window_shapes(nshots)
+    h, dt, nb = 12.5, 1e-3, 10
+    out = []
+    for s, (nz, ny, nx) in enumerate(shapes):
+        v = layered_3d(nz, ny, nx, 12, 1500.0, 4500.0, pert=0.05, seed=100 + s)
+        m = (1.0 / v.astype(np.float64) ** 2).astype(np.float32).ravel()
+        del v
+        src = np.array([[12.0, ny // 2, nx // 2]], dtype=np.float64)
+        rec = plane_receivers(12.0, ny, nx)
+        q = source_signature(nt, dt, 10.0, h, 3).astype(np.float32)
+        out.append(Workload(f"batched-{s}-{nz}x{ny}x{nx}", 3, (nz, ny, nx), h, dt, nt, nb,
+                            4725.0, 1e-3, m, None, src, q, rec, rademacher(nt, r, 200 + s),
+                            k_block))
+    return out
