@@ -110,6 +110,7 @@ def bench_batched(nt: int, variant: int):
     nt steps, r = 64, k = 32, BF16X2 probes, fused imaging: one stencil launch
     per step for all shots; the whole gradient replayed as one HIP graph.
     Compared with the same 16 gradients run one shot at a time."""
+    import numpy as np
     import torch
 
     import paper_2201_06914_amd as P
