@@ -65,6 +65,15 @@ def lib():
         L.orc_damping_profile.argtypes = [ctypes.c_long, ctypes.c_int, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, _dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_tti_apply.restype = None
+        L.orc_tti_apply.argtypes = [ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+                                    _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
+        L.orc_tti_sweep.restype = ctypes.c_int
+        L.orc_tti_sweep.argtypes = [
+            ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+            _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp,
+            ctypes.c_int, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -238,3 +247,90 @@ def probed_gradient(g: Grid, m, src_pos, q, rec_pos, d_obs, Z, sample_idx=None):
     a = adjoint(g, m, rec_pos, res, Z=Z, sample_idx=sample_idx)
     r = np.shape(Z)[1]
     return J, image(f["Ubar"], a["Vbar"], -1.0 / r), f, a
+
+
+# ---------------------------------------------------------------------------
+# pseudo-acoustic TTI (coupled p, q); see the header of oracle.c
+# ---------------------------------------------------------------------------
+def tti_apply(eps, delta, theta, phi, p, q, h, transpose=False):
+    """The TTI spatial operator (or its transpose) on fields [nz][ny][nx]."""
+    p = np.ascontiguousarray(p, np.float64)
+    q = np.ascontiguousarray(q, np.float64)
+    nz, ny, nx = p.shape
+    a = [np.ascontiguousarray(np.broadcast_to(v, p.shape), np.float64)
+         for v in (eps, delta, theta, phi)]
+    op, oq = np.empty_like(p), np.empty_like(p)
+    lib().orc_tti_apply(nz, ny, nx, h, *(x.ctypes.data_as(_dp) for x in a), int(transpose),
+                        p.ctypes.data_as(_dp), q.ctypes.data_as(_dp), op.ctypes.data_as(_dp),
+                        oq.ctypes.data_as(_dp))
+    return op, oq
+
+
+def _tti_sweep(adjoint, g: Grid, m, aniso, inj_pos, inj_val, smp_pos, Z=None, hist=None,
+               want_hist=False):
+    nz, ny, nx = g.shape
+    N = g.N
+    m, mp = _d(np.ravel(m))
+    an = [_d(np.ravel(x)) for x in aniso]          # eps, delta, theta, phi
+    ip, ipp = _d(np.reshape(inj_pos, (-1, 3)))
+    iv, ivp = _d(np.reshape(inj_val, (g.nt, -1)))
+    out = {}
+    smp = sp = None
+    nsmp = 0
+    if smp_pos is not None:
+        sp_arr, spp = _d(np.reshape(smp_pos, (-1, 3)))
+        nsmp = sp_arr.shape[0]
+        smp = np.zeros((g.nt, nsmp))
+        sp = spp
+        out["d" if not adjoint else "qadj"] = smp
+    r = 0
+    zp = up = None
+    if Z is not None:
+        Zd, zp = _d(Z)
+        r = Zd.shape[1]
+        Ub = np.zeros((2, r, N))
+        up = Ub.ctypes.data_as(_dp)
+        out["bar"] = Ub
+    fh = corr = None
+    if not adjoint and want_hist:
+        fh = np.zeros((2, g.nt, N))
+        out["hist"] = fh
+    if adjoint and hist is not None:
+        fh = np.ascontiguousarray(hist, np.float64)
+        corr = np.zeros(N)
+        out["corr"] = corr
+    rc = lib().orc_tti_sweep(
+        int(adjoint), nz, ny, nx, g.h, g.dt, g.nt, g.nb, g.c_ref, g.R, mp,
+        *(x[1] for x in an), ip.shape[0], ipp, ivp, nsmp, sp,
+        smp.ctypes.data_as(_dp) if smp is not None else None, r, zp, up,
+        fh.ctypes.data_as(_dp) if fh is not None else None,
+        corr.ctypes.data_as(_dp) if corr is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle TTI sweep rejected its input (code {rc})")
+    return out
+
+
+def tti_forward(g: Grid, m, aniso, src_pos, q, rec_pos, Z=None, hist=False):
+    """d [nt][nrec] = p at the receivers; bar [2][r][N] = Z^T (p_tt, q_tt)."""
+    return _tti_sweep(False, g, m, aniso, src_pos, q, rec_pos, Z=Z, want_hist=hist)
+
+
+def tti_adjoint(g: Grid, m, aniso, rec_pos, res, src_pos=None, Z=None, fwd_hist=None):
+    """bar [2][r][N] = Z^T (lam_p, lam_q); qadj = Ps (lam_p + lam_q); corr."""
+    return _tti_sweep(True, g, m, aniso, rec_pos, res, src_pos, Z=Z, hist=fwd_hist)
+
+
+def tti_exact_gradient(g: Grid, m, aniso, src_pos, q, rec_pos, d_obs):
+    f = tti_forward(g, m, aniso, src_pos, q, rec_pos, hist=True)
+    J, res = misfit(f["d"], d_obs)
+    a = tti_adjoint(g, m, aniso, rec_pos, res, fwd_hist=f["hist"])
+    return J, -a["corr"]
+
+
+def tti_probed_gradient(g: Grid, m, aniso, src_pos, q, rec_pos, d_obs, Z):
+    f = tti_forward(g, m, aniso, src_pos, q, rec_pos, Z=Z)
+    J, res = misfit(f["d"], d_obs)
+    a = tti_adjoint(g, m, aniso, rec_pos, res, Z=Z)
+    r = np.shape(Z)[1]
+    img = image(f["bar"][0], a["bar"][0], -1.0 / r) + image(f["bar"][1], a["bar"][1], -1.0 / r)
+    return J, img, f, a

@@ -331,3 +331,240 @@ int orc_adjoint(int ndim, long nz, long ny, long nx, double h, double dt, int nt
   free(lap);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* pseudo-acoustic TTI (coupled p, q system)                                 */
+/* ------------------------------------------------------------------------ */
+/*
+ * Operators (8th order, field zero outside the grid):
+ *   D_a   first derivative on axis a, weights +-(4/5, -1/5, 4/105, -1/280)/h
+ *   D_aa  second derivative on axis a (the weights above), L = sum_a D_aa
+ *   n     symmetry axis (sin th cos ph, sin th sin ph, cos th) as (x, y, z)
+ *   Hz u  = sum_a n_a^2 D_aa u + sum_{a != b} n_a n_b D_a (D_b u)
+ *   H0 u  = L u - Hz u
+ * Forward:  m p_tt = (1+2 eps) H0 p + sqrt(1+2 delta) Hz q
+ *           m q_tt = sqrt(1+2 delta) H0 p + Hz q
+ * The transpose puts the coefficients inside the derivatives:
+ *   HzT w = sum_a D_aa (n_a^2 w) + sum_{a != b} D_a D_b (n_a n_b w)
+ *   adjoint p equation:  H0T (c1 lp + c2 lq),   q equation:  HzT (c2 lp + lq)
+ * with c1 = 1 + 2 eps, c2 = sqrt(1 + 2 delta), H0T w = L w - HzT w.
+ * Sources are injected into p and q; receivers record p.
+ */
+static const double W1[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+
+/* out = D_axis u (axis 0 = z, 1 = y, 2 = x) */
+static void first_deriv(long nz, long ny, long nx, double h, int axis, const double *u,
+                        double *out) {
+#pragma omp parallel for schedule(static)
+  for (long z = 0; z < nz; ++z)
+    for (long y = 0; y < ny; ++y)
+      for (long x = 0; x < nx; ++x) {
+        double s = 0.0;
+        for (int j = 1; j <= 4; ++j) {
+          long dz = axis == 0 ? j : 0, dy = axis == 1 ? j : 0, dx = axis == 2 ? j : 0;
+          s += W1[j] * (at(u, nz, ny, nx, z + dz, y + dy, x + dx) -
+                        at(u, nz, ny, nx, z - dz, y - dy, x - dx));
+        }
+        out[(z * ny + y) * nx + x] = s / h;
+      }
+}
+
+/* out = D_axis,axis u */
+static void second_deriv(long nz, long ny, long nx, double h, int axis, const double *u,
+                         double *out) {
+#pragma omp parallel for schedule(static)
+  for (long z = 0; z < nz; ++z)
+    for (long y = 0; y < ny; ++y)
+      for (long x = 0; x < nx; ++x) {
+        double s = W2[0] * at(u, nz, ny, nx, z, y, x);
+        for (int j = 1; j <= 4; ++j) {
+          long dz = axis == 0 ? j : 0, dy = axis == 1 ? j : 0, dx = axis == 2 ? j : 0;
+          s += W2[j] * (at(u, nz, ny, nx, z + dz, y + dy, x + dx) +
+                        at(u, nz, ny, nx, z - dz, y - dy, x - dx));
+        }
+        out[(z * ny + y) * nx + x] = s / (h * h);
+      }
+}
+
+/* axis components of the symmetry axis per cell: nax[0..2] = (n_z, n_y, n_x) */
+static void tti_axis(long N, const double *theta, const double *phi, double *nax) {
+  for (long i = 0; i < N; ++i) {
+    nax[i] = cos(theta[i]);                       /* z */
+    nax[N + i] = sin(theta[i]) * sin(phi[i]);     /* y */
+    nax[2 * N + i] = sin(theta[i]) * cos(phi[i]); /* x */
+  }
+}
+
+/* Hz u (transpose = 0) or HzT u (transpose = 1); work: 2 N doubles */
+static void apply_hz(long nz, long ny, long nx, double h, const double *nax, int transpose,
+                     const double *u, double *out, double *w1, double *w2) {
+  const long N = nz * ny * nx;
+  for (long i = 0; i < N; ++i) out[i] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double *na = nax + a * N;
+    if (transpose) {
+      for (long i = 0; i < N; ++i) w1[i] = na[i] * na[i] * u[i];
+      second_deriv(nz, ny, nx, h, a, w1, w2);
+      for (long i = 0; i < N; ++i) out[i] += w2[i];
+    } else {
+      second_deriv(nz, ny, nx, h, a, u, w2);
+      for (long i = 0; i < N; ++i) out[i] += na[i] * na[i] * w2[i];
+    }
+    for (int b = 0; b < 3; ++b) {
+      if (b == a) continue;
+      const double *nb = nax + b * N;
+      if (transpose) { /* D_a D_b (n_a n_b u) */
+        for (long i = 0; i < N; ++i) w1[i] = na[i] * nb[i] * u[i];
+        first_deriv(nz, ny, nx, h, b, w1, w2);
+        first_deriv(nz, ny, nx, h, a, w2, w1);
+        for (long i = 0; i < N; ++i) out[i] += w1[i];
+      } else { /* n_a n_b D_a (D_b u) */
+        first_deriv(nz, ny, nx, h, b, u, w1);
+        first_deriv(nz, ny, nx, h, a, w1, w2);
+        for (long i = 0; i < N; ++i) out[i] += na[i] * nb[i] * w2[i];
+      }
+    }
+  }
+}
+
+/* The TTI spatial operator (or its transpose) on (p, q): op, oq. */
+void orc_tti_apply(long nz, long ny, long nx, double h, const double *eps, const double *delta,
+                   const double *theta, const double *phi, int transpose, const double *p,
+                   const double *q, double *op, double *oq) {
+  const long N = nz * ny * nx;
+  double *nax = malloc(sizeof(double) * 3 * N);
+  double *w1 = malloc(sizeof(double) * N), *w2 = malloc(sizeof(double) * N);
+  double *t1 = malloc(sizeof(double) * N), *t2 = malloc(sizeof(double) * N);
+  double *lap = malloc(sizeof(double) * N);
+  tti_axis(N, theta, phi, nax);
+  if (!transpose) {
+    /* op = c1 (L p - Hz p) + c2 Hz q ; oq = c2 (L p - Hz p) + Hz q */
+    orc_laplacian(3, nz, ny, nx, h, p, lap);
+    apply_hz(nz, ny, nx, h, nax, 0, p, t1, w1, w2); /* Hz p */
+    apply_hz(nz, ny, nx, h, nax, 0, q, t2, w1, w2); /* Hz q */
+    for (long i = 0; i < N; ++i) {
+      const double c1 = 1.0 + 2.0 * eps[i], c2 = sqrt(1.0 + 2.0 * delta[i]);
+      const double h0p = lap[i] - t1[i];
+      op[i] = c1 * h0p + c2 * t2[i];
+      oq[i] = c2 * h0p + t2[i];
+    }
+  } else {
+    /* op = H0T (c1 p + c2 q) ; oq = HzT (c2 p + q) */
+    double *a = malloc(sizeof(double) * N), *b = malloc(sizeof(double) * N);
+    for (long i = 0; i < N; ++i) {
+      const double c1 = 1.0 + 2.0 * eps[i], c2 = sqrt(1.0 + 2.0 * delta[i]);
+      a[i] = c1 * p[i] + c2 * q[i];
+      b[i] = c2 * p[i] + q[i];
+    }
+    orc_laplacian(3, nz, ny, nx, h, a, lap);
+    apply_hz(nz, ny, nx, h, nax, 1, a, t1, w1, w2); /* HzT a */
+    apply_hz(nz, ny, nx, h, nax, 1, b, t2, w1, w2); /* HzT b */
+    for (long i = 0; i < N; ++i) {
+      op[i] = lap[i] - t1[i];
+      oq[i] = t2[i];
+    }
+    free(a);
+    free(b);
+  }
+  free(nax);
+  free(w1);
+  free(w2);
+  free(t1);
+  free(t2);
+  free(lap);
+}
+
+/*
+ * TTI sweep, forward (adjoint = 0) or adjoint (adjoint = 1), with the damped
+ * leapfrog of the acoustic case applied to p and q.
+ *   forward: q_src [nt][ninj] injected into p and q; d[n] = Pr p^{n+1}
+ *   adjoint: res [nt][ninj] injected into lam_p only; qadj[n] = Ps (lp + lq)^n
+ * Probing (Z, Ubar [2][r][M]): forward probes (p_tt, q_tt); adjoint (lp, lq).
+ * fhist [2][nt][N] (forward: written with p_tt, q_tt; adjoint: read) and
+ * corr [N]: adjoint only, corr += p_tt lp + q_tt lq.
+ */
+int orc_tti_sweep(int adjoint, long nz, long ny, long nx, double h, double dt, int nt, int nb,
+                  double c_ref, double R, const double *m, const double *eps,
+                  const double *delta, const double *theta, const double *phi, int ninj,
+                  const double *inj_pos, const double *inj_val, int nsmp, const double *smp_pos,
+                  double *smp_out, int r, const double *Z, double *Ubar, double *fhist,
+                  double *corr) {
+  const long N = nz * ny * nx;
+  int err = 0;
+  pt_t *ip = make_points(3, nz, ny, nx, ninj, inj_pos, &err);
+  pt_t *sp = make_points(3, nz, ny, nx, nsmp, smp_pos, &err);
+  if (err) {
+    free(ip);
+    free(sp);
+    return err;
+  }
+  double *eta = damping_field(3, nz, ny, nx, nb, h, c_ref, R);
+  double *p0 = calloc(N, 8), *p1 = calloc(N, 8), *p2 = calloc(N, 8);
+  double *q0 = calloc(N, 8), *q1 = calloc(N, 8), *q2 = calloc(N, 8);
+  double *rp = calloc(N, 8), *rq = calloc(N, 8), *sfp = calloc(N, 8), *sfq = calloc(N, 8);
+  double *tmp = calloc(N, 8);
+  /* p1, q1: current level; p0, q0: previous; p2, q2: next */
+  for (int s = 0; s < nt; ++s) {
+    const int n = adjoint ? nt - 1 - s : s;
+    orc_tti_apply(nz, ny, nx, h, eps, delta, theta, phi, adjoint, p1, q1, rp, rq);
+    if (!adjoint) {
+      inject(ip, ninj, inj_val + (long)n * ninj, rp);
+      inject(ip, ninj, inj_val + (long)n * ninj, rq);
+    } else {
+      inject(ip, ninj, inj_val + (long)n * ninj, rp);
+    }
+    update(N, dt, m, eta, p1, p0, rp, p2);
+    update(N, dt, m, eta, q1, q0, rq, q2);
+    if (smp_out) {
+      if (!adjoint) {
+        sample(sp, nsmp, p2, smp_out + (long)n * nsmp);
+      } else {
+        for (long i = 0; i < N; ++i) tmp[i] = p2[i] + q2[i];
+        sample(sp, nsmp, tmp, smp_out + (long)n * nsmp);
+      }
+    }
+    if (!adjoint) {
+      for (long i = 0; i < N; ++i) {
+        sfp[i] = (p2[i] - 2.0 * p1[i] + p0[i]) / (dt * dt);
+        sfq[i] = (q2[i] - 2.0 * q1[i] + q0[i]) / (dt * dt);
+      }
+      if (fhist) {
+        memcpy(fhist + (long)n * N, sfp, 8 * N);
+        memcpy(fhist + ((long)nt + n) * N, sfq, 8 * N);
+      }
+    } else {
+      memcpy(sfp, p2, 8 * N);
+      memcpy(sfq, q2, 8 * N);
+      if (fhist && corr)
+        for (long i = 0; i < N; ++i)
+          corr[i] += fhist[(long)n * N + i] * sfp[i] + fhist[((long)nt + n) * N + i] * sfq[i];
+    }
+    if (Ubar) {
+      probe_rank1(N, r, Z + (long)n * r, 0, NULL, sfp, Ubar);
+      probe_rank1(N, r, Z + (long)n * r, 0, NULL, sfq, Ubar + (long)r * N);
+    }
+    double *t = p0;
+    p0 = p1;
+    p1 = p2;
+    p2 = t;
+    t = q0;
+    q0 = q1;
+    q1 = q2;
+    q2 = t;
+  }
+  free(ip);
+  free(sp);
+  free(eta);
+  free(p0);
+  free(p1);
+  free(p2);
+  free(q0);
+  free(q1);
+  free(q2);
+  free(rp);
+  free(rq);
+  free(sfp);
+  free(sfq);
+  free(tmp);
+  return 0;
+}
