@@ -225,6 +225,38 @@ rtm_status fwi_gradient_exact(const rtm_plan *plan, const void *m, const double 
                               int32_t checkpoint_every, void *resid, void *grad, double *misfit,
                               void *work, size_t work_bytes, rtm_stream stream);
 
+/* Pseudo-acoustic TTI (3D plans).  The paper images a TTI model (Section
+ * "2007 BP TTI") without printing its equations; this library uses the
+ * coupled system
+ *   m p_tt = (1+2 eps) H0 p + sqrt(1+2 delta) Hz q
+ *   m q_tt = sqrt(1+2 delta) H0 p + Hz q
+ *   Hz = sum_a n_a^2 D_aa + sum_{a != b} n_a n_b D_a D_b,  H0 = L - Hz,
+ * n = (sin theta cos phi, sin theta sin phi, cos theta) in (x, y, z), D_a and
+ * D_aa 8th-order first and second differences, the damped leapfrog of the
+ * acoustic case on both fields; the adjoint is its exact transpose (the
+ * coefficients move inside the derivatives).  Sources inject into p and q,
+ * receivers record p.  The gradient is -sum_n (p_tt lam_p + q_tt lam_q), so
+ * both fields are compressed: Ubar / Vbar are [2][r*Npad] (p then q, each
+ * tile-major).  aniso: device [4][N] (eps, delta, theta, phi in radians) of
+ * the field dtype; delta <= eps keeps the system stable, and c_max in the
+ * plan must be the largest velocity times sqrt(1 + 2 eps).
+ *   rtm_tti_adjoint_probe: qadj[n] = Ps (lam_p + lam_q)^n (adjoint of q -> d).
+ *   fwi_gradient_tti: Vbar may be NULL on BF16 paths (fused imaging). */
+rtm_status rtm_tti_workspace_bytes(const rtm_plan *plan, size_t *bytes);
+rtm_status rtm_tti_forward_probe(const rtm_plan *plan, const void *m, const void *aniso,
+                                 const double *src_pos, const void *q, const double *rec_pos,
+                                 void *d_pred, const void *Z, rtm_dtype z_dtype, void *Ubar,
+                                 void *work, size_t work_bytes, rtm_stream stream);
+rtm_status rtm_tti_adjoint_probe(const rtm_plan *plan, const void *m, const void *aniso,
+                                 const double *rec_pos, const void *res, const double *src_pos,
+                                 void *qadj, const void *Z, rtm_dtype z_dtype, void *Vbar,
+                                 void *work, size_t work_bytes, rtm_stream stream);
+rtm_status fwi_gradient_tti(const rtm_plan *plan, const void *m, const void *aniso,
+                            const double *src_pos, const void *q, const double *rec_pos,
+                            const void *d_obs, const void *Z, rtm_dtype z_dtype, void *Ubar,
+                            void *Vbar, void *resid, void *grad, double *misfit, void *work,
+                            size_t work_bytes, rtm_stream stream);
+
 /* Batched shots (3D, F32 fields, BF16 / BF16X2 probes).  Each descriptor is
  * one shot's sub-domain window (its own nz, ny, nx, nb, c_ref, c_max, nsrc,
  * nrec); nt, dt, h, r, k_block and the probe dtype must agree.  One launch

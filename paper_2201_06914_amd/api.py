@@ -489,3 +489,90 @@ def rtm_dot(plan: Plan, a, b, work=None) -> torch.Tensor:
                                ctypes.c_void_p(work.data_ptr()), work.numel(),
                                _stream(a.device)), "rtm_dot")
     return out
+
+
+# ---------------------------------------------------------------------------
+# pseudo-acoustic TTI
+# ---------------------------------------------------------------------------
+def tti_workspace(plan: Plan, device="cuda") -> torch.Tensor:
+    n = ctypes.c_size_t()
+    _check(_lib.load().rtm_tti_workspace_bytes(plan.handle, ctypes.byref(n)),
+           "rtm_tti_workspace_bytes")
+    return torch.empty(int(n.value), dtype=torch.uint8, device=device)
+
+
+def _bars2(plan: Plan, dev):
+    return torch.empty((2, plan.Npad // 32, plan.spec.r, 32), dtype=plan.dtype, device=dev)
+
+
+def rtm_tti_forward_probe(plan: Plan, m, aniso, src_pos, q, rec_pos=None, Z=None,
+                          want_d: bool = True, work=None) -> dict:
+    """aniso: [4][N] (eps, delta, theta, phi).  Ubar: [2][...] (p then q)."""
+    s = plan.spec
+    dev = m.device
+    d = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev) if want_d else None
+    U = _bars2(plan, dev) if Z is not None else None
+    work = work if work is not None else tti_workspace(plan, dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos") if want_d else (None, None)
+    zp, zt = _z(plan, Z)
+    _check(_lib.load().rtm_tti_forward_probe(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), _dev(aniso, plan.dtype, 4 * plan.N, "aniso"),
+        spp, _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp,
+        _dev(d, plan.dtype, s.nt * s.nrec, "d"), zp, zt,
+        _dev(U, plan.dtype, 2 * s.r * plan.Npad, "Ubar"), ctypes.c_void_p(work.data_ptr()),
+        work.numel(), _stream(dev)), "rtm_tti_forward_probe")
+    out = {}
+    if d is not None:
+        out["d"] = d
+    if U is not None:
+        out["Ubar"] = U
+    return out
+
+
+def rtm_tti_adjoint_probe(plan: Plan, m, aniso, rec_pos, res, Z=None, src_pos=None,
+                          want_qadj=False, work=None) -> dict:
+    s = plan.spec
+    dev = m.device
+    V = _bars2(plan, dev) if Z is not None else None
+    qa = torch.empty((s.nt, s.nsrc), dtype=plan.dtype, device=dev) if want_qadj else None
+    work = work if work is not None else tti_workspace(plan, dev)
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos") if want_qadj else (None, None)
+    zp, zt = _z(plan, Z)
+    _check(_lib.load().rtm_tti_adjoint_probe(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), _dev(aniso, plan.dtype, 4 * plan.N, "aniso"),
+        rpp, _dev(res, plan.dtype, s.nt * s.nrec, "res"), spp,
+        _dev(qa, plan.dtype, s.nt * s.nsrc, "qadj"), zp, zt,
+        _dev(V, plan.dtype, 2 * s.r * plan.Npad, "Vbar"), ctypes.c_void_p(work.data_ptr()),
+        work.numel(), _stream(dev)), "rtm_tti_adjoint_probe")
+    out = {}
+    if V is not None:
+        out["Vbar"] = V
+    if qa is not None:
+        out["qadj"] = qa
+    return out
+
+
+def fwi_gradient_tti(plan: Plan, m, aniso, src_pos, q, rec_pos, d_obs, Z, fused: bool = False,
+                     work=None) -> dict:
+    s = plan.spec
+    dev = m.device
+    U = _bars2(plan, dev)
+    V = None if fused else _bars2(plan, dev)
+    res = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev)
+    g = torch.empty(plan.N, dtype=plan.dtype, device=dev)
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    work = work if work is not None else tti_workspace(plan, dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    zp, zt = _z(plan, Z)
+    _check(_lib.load().fwi_gradient_tti(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), _dev(aniso, plan.dtype, 4 * plan.N, "aniso"),
+        spp, _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp,
+        _dev(d_obs, plan.dtype, s.nt * s.nrec, "d_obs"), zp, zt,
+        _dev(U, plan.dtype, 2 * s.r * plan.Npad, "Ubar"),
+        _dev(V, plan.dtype, 2 * s.r * plan.Npad, "Vbar"), _dev(res, plan.dtype, s.nt * s.nrec, "resid"),
+        _dev(g, plan.dtype, plan.N, "grad"), _dev(J, torch.float64, 1, "misfit"),
+        ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(dev)), "fwi_gradient_tti")
+    return {"grad": g, "misfit": J, "Ubar": U, "Vbar": V, "resid": res}

@@ -91,6 +91,23 @@ template hipError_t launch_correlate<float>(float *, const float *, const float 
 template hipError_t launch_correlate<double>(double *, const double *, const double *, int64_t,
                                              hipStream_t);
 
+// y += x
+template <typename T>
+__global__ __launch_bounds__(256) void k_axpy(T *__restrict__ y, const T *__restrict__ x,
+                                              int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256)
+    y[i] += x[i];
+}
+template <typename T>
+hipError_t launch_axpy(T *y, const T *x, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_axpy<T>), dim3(grid_for(n)), dim3(256), 0, st, y, x, n);
+  return hipGetLastError();
+}
+template hipError_t launch_axpy<float>(float *, const float *, int64_t, hipStream_t);
+template hipError_t launch_axpy<double>(double *, const double *, int64_t, hipStream_t);
+
 // image[x] = scale * sum_i U[i][x] V[i][x]  (Eq. 3), summed in double.
 // U, V tile-major: (i, x) at ((x / 32) r + i) 32 + x % 32.
 template <typename T>

@@ -1329,3 +1329,257 @@ extern "C" rtm_status fwi_gradient_batched(rtm_batch *b, const rtm_shot_io *io, 
   HIP_TRY(hipGraphLaunch(b->gexec, st));
   return RTM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// pseudo-acoustic TTI sweeps
+// ---------------------------------------------------------------------------
+// Workspace beyond the acoustic plan's: a second ring (q), 5 coefficient
+// levels and 8 intermediate levels.  The acoustic ring holds p.
+static size_t tti_extra_bytes(const rtm_plan *P) {
+  return align256((size_t)(P->R + 5 + 8) * P->ld * P->esz);
+}
+
+extern "C" rtm_status rtm_tti_workspace_bytes(const rtm_plan *P, size_t *bytes) {
+  if (!P || !bytes) return fail(RTM_E_ARG, "plan and bytes must be non-NULL");
+  *bytes = P->total + tti_extra_bytes(P);
+  return RTM_OK;
+}
+
+struct TtiIO {
+  bool adjoint = false;
+  const void *m = nullptr, *aniso = nullptr;
+  const void *inj_vals = nullptr;  // forward: into p and q; adjoint: into lam_p
+  void *smp_out = nullptr;         // forward: Pr p; adjoint: Ps (lam_p + lam_q)
+  const void *Z = nullptr;
+  rtm_dtype zt = RTM_I8;
+  void *bar = nullptr;             // [2][r*Npad]: p then q
+  const void *fuse_U = nullptr;    // [2][r*Npad] forward compressed fields (fused imaging)
+  void *fuse_img = nullptr;
+  double fuse_scale = 0.0;
+};
+
+template <typename T>
+static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointTables<T> &inj,
+                                const PointTables<T> &smp, char *w, hipStream_t st) {
+  const rtm_desc &d = P->d;
+  const int64_t N = P->N, ld = P->ld, barn = (int64_t)d.r * P->Npad;
+  T *ringP = reinterpret_cast<T *>(w + P->ring.off);
+  T *ringQ = reinterpret_cast<T *>(w + P->total);
+  T *coef = ringQ + (int64_t)P->R * ld;
+  T *g = coef + 5 * ld;
+  auto lv = [&](T *ring, int j) { return ring + (int64_t)((j + 1) % P->R) * ld; };
+  StepArgs<T> a = step_args<T>(P, static_cast<const T *>(io.m));
+  // the coefficient levels and intermediates use stride ld (>= N)
+  HIP_TRY(launch_tti_coef<T>(static_cast<const T *>(io.aniso), N, coef, st));  // [5][N]
+  for (T *ring : {ringP, ringQ}) {
+    HIP_TRY(launch_fill<T>(lv(ring, -1), N, T(0), st));
+    HIP_TRY(launch_fill<T>(lv(ring, 0), N, T(0), st));
+  }
+  T *bar = static_cast<T *>(io.bar);
+  if (bar) HIP_TRY(launch_fill<T>(bar, 2 * barn, T(0), st));
+  const T *vals = static_cast<const T *>(io.inj_vals);
+  T *out = static_cast<T *>(io.smp_out);
+  int s0 = 0;
+  for (int s = 0; s < d.nt; ++s) {
+    const int n = io.adjoint ? d.nt - 1 - s : s;
+    T *pn = lv(ringP, s + 1), *qn = lv(ringQ, s + 1);
+    HIP_TRY(launch_tti_step<T>(a, d.h, io.adjoint, coef, lv(ringP, s), lv(ringP, s - 1),
+                               lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, st));
+    if (inj.ncell > 0 && vals) {
+      HIP_TRY(launch_inject<T>(a, inj, vals + (int64_t)n * inj.npts, pn, st));
+      if (!io.adjoint) HIP_TRY(launch_inject<T>(a, inj, vals + (int64_t)n * inj.npts, qn, st));
+    }
+    if (out && smp.npts > 0) {
+      if (!io.adjoint)
+        HIP_TRY(launch_sample<T>(smp, pn, out + (int64_t)n * smp.npts, st));
+      else
+        HIP_TRY(launch_sample_sum<T>(smp, pn, qn, out + (int64_t)n * smp.npts, st));
+    }
+    if ((bar || io.fuse_img) && (s + 1 - s0 == d.k_block || s == d.nt - 1)) {
+      for (int f = 0; f < 2; ++f) {
+        ProbeArgs<T> p{};
+        p.ring = f == 0 ? ringP : ringQ;
+        p.ld = ld;
+        p.R = P->R;
+        p.s0 = s0;
+        p.slot0 = s0 % P->R;
+        p.kb = s + 1 - s0;
+        p.zrow0 = io.adjoint ? d.nt - 1 - s0 : s0;
+        p.zdir = io.adjoint ? -1 : 1;
+        p.r = d.r;
+        p.N = N;
+        p.bar = bar ? bar + f * barn : nullptr;
+        p.inv_dt2 = (T)(1.0 / (d.dt * d.dt));
+        p.mode = io.adjoint ? PROBE_NEW : PROBE_UTT;
+        if constexpr (sizeof(T) == 4) {
+          if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
+            const float *Uf = io.fuse_img ? static_cast<const float *>(io.fuse_U) + f * barn : nullptr;
+            HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io.Z),
+                                      d.probe_dtype == RTM_BF16X2, Uf,
+                                      static_cast<float *>(io.fuse_img), (float)io.fuse_scale, st));
+            continue;
+          }
+        }
+        HIP_TRY(launch_probe_vec<T>(p, io.Z, io.zt == RTM_I8, st));
+      }
+      s0 = s + 1;
+    }
+  }
+  return RTM_OK;
+}
+
+static rtm_status check_tti(const rtm_plan *P, const void *m, const void *aniso, void *work,
+                            size_t work_bytes) {
+  rtm_status s = check_common(P, m, work, P ? P->total : 0);
+  if (s) return s;
+  if (P->d.ndim != 3) return fail(RTM_E_UNSUPPORTED, "TTI needs a 3D plan");
+  if (!aniso) return fail(RTM_E_ARG, "aniso (eps, delta, theta, phi) is required");
+  if (work_bytes < P->total + tti_extra_bytes(P))
+    return fail(RTM_E_WORKSPACE, "work has %zu bytes, TTI needs %zu", work_bytes,
+                P->total + tti_extra_bytes(P));
+  return RTM_OK;
+}
+
+template <typename T>
+static rtm_status tti_fwd_impl(const rtm_plan *P, const void *m, const void *aniso,
+                               const double *src_pos, const void *q, const double *rec_pos,
+                               void *d_pred, const void *Z, rtm_dtype zt, void *Ubar, void *work,
+                               hipStream_t st) {
+  PointTables<T> src_t, rec_t;
+  char *w = static_cast<char *>(work);
+  rtm_status s = upload_points<T>(P, w, st, src_pos, &src_t, d_pred ? rec_pos : nullptr, &rec_t);
+  if (s) return s;
+  TtiIO io;
+  io.m = m;
+  io.aniso = aniso;
+  io.inj_vals = q;
+  io.smp_out = d_pred;
+  io.Z = Z;
+  io.zt = zt;
+  io.bar = Ubar;
+  return run_tti_sweep<T>(P, io, src_t, rec_t, w, st);
+}
+
+extern "C" rtm_status rtm_tti_forward_probe(const rtm_plan *P, const void *m, const void *aniso,
+                                            const double *src_pos, const void *q,
+                                            const double *rec_pos, void *d_pred, const void *Z,
+                                            rtm_dtype zt, void *Ubar, void *work,
+                                            size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_tti(P, m, aniso, work, work_bytes);
+  if (s) return s;
+  if (P->d.nsrc > 0 && (!src_pos || !q)) return fail(RTM_E_ARG, "src_pos and q are required");
+  if (d_pred && P->d.nrec > 0 && !rec_pos) return fail(RTM_E_ARG, "rec_pos is required");
+  if ((s = check_probe(P, Z, zt, Ubar))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return tti_fwd_impl<double>(P, m, aniso, src_pos, q, rec_pos, d_pred, Z, zt, Ubar, work, st);
+  return tti_fwd_impl<float>(P, m, aniso, src_pos, q, rec_pos, d_pred, Z, zt, Ubar, work, st);
+}
+
+template <typename T>
+static rtm_status tti_adj_impl(const rtm_plan *P, const void *m, const void *aniso,
+                               const double *rec_pos, const void *res, const double *src_pos,
+                               void *qadj, const void *Z, rtm_dtype zt, void *Vbar, void *work,
+                               hipStream_t st) {
+  PointTables<T> src_t, rec_t;
+  char *w = static_cast<char *>(work);
+  rtm_status s = upload_points<T>(P, w, st, qadj ? src_pos : nullptr, &src_t, rec_pos, &rec_t);
+  if (s) return s;
+  TtiIO io;
+  io.adjoint = true;
+  io.m = m;
+  io.aniso = aniso;
+  io.inj_vals = res;
+  io.smp_out = qadj;
+  io.Z = Z;
+  io.zt = zt;
+  io.bar = Vbar;
+  return run_tti_sweep<T>(P, io, rec_t, src_t, w, st);
+}
+
+extern "C" rtm_status rtm_tti_adjoint_probe(const rtm_plan *P, const void *m, const void *aniso,
+                                            const double *rec_pos, const void *res,
+                                            const double *src_pos, void *qadj, const void *Z,
+                                            rtm_dtype zt, void *Vbar, void *work,
+                                            size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_tti(P, m, aniso, work, work_bytes);
+  if (s) return s;
+  if (P->d.nrec > 0 && (!rec_pos || !res)) return fail(RTM_E_ARG, "rec_pos and res are required");
+  if (qadj && P->d.nsrc > 0 && !src_pos) return fail(RTM_E_ARG, "src_pos is required with qadj");
+  if ((s = check_probe(P, Z, zt, Vbar))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return tti_adj_impl<double>(P, m, aniso, rec_pos, res, src_pos, qadj, Z, zt, Vbar, work, st);
+  return tti_adj_impl<float>(P, m, aniso, rec_pos, res, src_pos, qadj, Z, zt, Vbar, work, st);
+}
+
+template <typename T>
+static rtm_status tti_grad_impl(const rtm_plan *P, const void *m, const void *aniso,
+                                const double *src_pos, const void *q, const double *rec_pos,
+                                const void *d_obs, const void *Z, rtm_dtype zt, void *Ubar,
+                                void *Vbar, void *resid, void *grad, double *misfit, void *work,
+                                hipStream_t st) {
+  PointTables<T> src_t, rec_t;
+  char *w = static_cast<char *>(work);
+  rtm_status s = upload_points<T>(P, w, st, src_pos, &src_t, rec_pos, &rec_t);
+  if (s) return s;
+  TtiIO f;
+  f.m = m;
+  f.aniso = aniso;
+  f.inj_vals = q;
+  f.smp_out = resid;
+  f.Z = Z;
+  f.zt = zt;
+  f.bar = Ubar;
+  if ((s = run_tti_sweep<T>(P, f, src_t, rec_t, w, st))) return s;
+  double *part = reinterpret_cast<double *>(w + P->red.off);
+  HIP_TRY(launch_residual_misfit<T>(static_cast<const T *>(resid), static_cast<const T *>(d_obs),
+                                    static_cast<T *>(resid), (int64_t)P->d.nt * P->d.nrec, part,
+                                    misfit, st));
+  TtiIO b;
+  b.adjoint = true;
+  b.m = m;
+  b.aniso = aniso;
+  b.inj_vals = resid;
+  b.Z = Z;
+  b.zt = zt;
+  PointTables<T> none;
+  const int64_t barn = (int64_t)P->d.r * P->Npad;
+  if (!Vbar) {
+    HIP_TRY(launch_fill<T>(static_cast<T *>(grad), P->N, T(0), st));
+    b.fuse_U = Ubar;
+    b.fuse_img = grad;
+    b.fuse_scale = -1.0 / P->d.r;
+    return run_tti_sweep<T>(P, b, rec_t, none, w, st);
+  }
+  b.bar = Vbar;
+  if ((s = run_tti_sweep<T>(P, b, rec_t, none, w, st))) return s;
+  // grad = -(1/r) sum_i (Ubar_p Vbar_p + Ubar_q Vbar_q): two images summed
+  T *gq = reinterpret_cast<T *>(w + P->total) + (int64_t)(P->R + 5) * P->ld;  // scratch level
+  const T *U = static_cast<const T *>(Ubar), *V = static_cast<const T *>(Vbar);
+  HIP_TRY(launch_image<T>(U, V, P->N, P->d.r, -1.0 / P->d.r, static_cast<T *>(grad), st));
+  HIP_TRY(launch_image<T>(U + barn, V + barn, P->N, P->d.r, -1.0 / P->d.r, gq, st));
+  HIP_TRY(launch_axpy<T>(static_cast<T *>(grad), gq, P->N, st));
+  return RTM_OK;
+}
+
+extern "C" rtm_status fwi_gradient_tti(const rtm_plan *P, const void *m, const void *aniso,
+                                       const double *src_pos, const void *q,
+                                       const double *rec_pos, const void *d_obs, const void *Z,
+                                       rtm_dtype zt, void *Ubar, void *Vbar, void *resid,
+                                       void *grad, double *misfit, void *work, size_t work_bytes,
+                                       rtm_stream stream) {
+  rtm_status s = check_tti(P, m, aniso, work, work_bytes);
+  if (s) return s;
+  if (!src_pos || !q || !rec_pos || !d_obs || !Z || !Ubar || !resid || !grad || !misfit)
+    return fail(RTM_E_ARG, "fwi_gradient_tti needs every array except Vbar");
+  if (!Vbar && P->d.probe_dtype != RTM_BF16 && P->d.probe_dtype != RTM_BF16X2)
+    return fail(RTM_E_UNSUPPORTED, "fused imaging (Vbar = NULL) needs a BF16 probe path");
+  if ((s = check_probe(P, Z, zt, Ubar))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return tti_grad_impl<double>(P, m, aniso, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid,
+                                 grad, misfit, work, st);
+  return tti_grad_impl<float>(P, m, aniso, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid,
+                              grad, misfit, work, st);
+}

@@ -111,6 +111,19 @@ hipError_t launch_inject_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
 template <typename T>
 hipError_t launch_sample_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
                                  const BatchPoints<T> &pt, int s, int n, hipStream_t st);
+// TTI: per-cell coefficients [5][N] = (1 + 2 eps, sqrt(1 + 2 delta), n_z, n_y,
+// n_x) from aniso [4][N] = (eps, delta, theta, phi); one step of the coupled
+// system (adjoint = exact transpose) with intermediates g [8][N]; sampling of
+// p + q (adjoint of injecting into both fields)
+template <typename T>
+hipError_t launch_tti_coef(const T *aniso, int64_t N, T *coef, hipStream_t st);
+template <typename T>
+hipError_t launch_tti_step(const StepArgs<T> &a, double h, bool adjoint, const T *coef,
+                           const T *p, const T *pp, const T *q, const T *qp, T *pn, T *qn, T *g,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_sample_sum(const PointTables<T> &pt, const T *f1, const T *f2, T *out,
+                             hipStream_t st);
 // autotuning: hash pattern fill, count of bitwise-different elements (atomic
 // integer add into *count)
 template <typename T>
@@ -141,6 +154,8 @@ template <typename T>
 hipError_t launch_bar_to_rows(const T *bar, int64_t N, int r, T *rows, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
+template <typename T>
+hipError_t launch_axpy(T *y, const T *x, int64_t n, hipStream_t st);  // y += x
 template <typename T>
 hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
 template <typename T>

@@ -12,25 +12,9 @@
 //                     sits in LDS, double buffered, and the z neighbours in a
 //                     9-deep register queue per column.  Loads of plane z+1
 //                     are issued before plane z is computed.
-#include "rtm_internal.h"
+#include "step_common.h"
 
 namespace rtm {
-
-__device__ __forceinline__ int sponge_depth(int i, int n, int nb) {
-  const int a = nb - i;
-  const int b = i - (n - 1 - nb);
-  const int d = a > b ? a : b;
-  return d > 0 ? d : 0;
-}
-
-template <typename T>
-__device__ __forceinline__ T sponge_a(const StepArgs<T> &a, int z, int y, int x) {
-  if (a.nb <= 0) return T(0);
-  const int dz = sponge_depth(z, a.nz, a.nb);
-  const int dy = a.ny > 1 ? sponge_depth(y, a.ny, a.nb) : 0;
-  const int dx = sponge_depth(x, a.nx, a.nb);
-  return a.kd * T(dz * dz + dy * dy + dx * dx);
-}
 
 // c1 (p1 + m1) + c2 (p2 + m2) + c3 (p3 + m3) + c4 (p4 + m4), fixed order
 template <typename T>

@@ -1,0 +1,302 @@
+// Pseudo-acoustic TTI time step (coupled p, q fields) and its exact transpose.
+//
+//   m p_tt = c1 H0 p + c2 Hz q,   m q_tt = c2 H0 p + Hz q,
+//   Hz u = sum_a n_a^2 D_aa u + sum_{a != b} n_a n_b D_a (D_b u),  H0 = L - Hz,
+//   c1 = 1 + 2 eps, c2 = sqrt(1 + 2 delta), n = (sin th cos ph, sin th sin ph, cos th)
+//   as (x, y, z), D_a / D_aa 8th-order first / second differences, fields zero
+//   outside the grid.  The transpose moves coefficients inside the derivatives:
+//   lam_p: H0T (c1 lp + c2 lq),  lam_q: HzT (c2 lp + lq),
+//   HzT w = sum_a D_aa (n_a^2 w) + sum_{a != b} D_a D_b (n_a n_b w).
+// Both use the damped leapfrog of the acoustic step on each field.
+//
+// Kernels (one thread per cell; three passes per step):
+//   k_tti_coef     c1, c2, n_z, n_y, n_x from eps, delta, theta, phi (once)
+//   forward:  k_tti_grad   G_b = D_b p, K_b = D_b q (6 fields)
+//             k_tti_fwd    second differences, mixed terms D_a G_b, update
+//   adjoint:  k_tti_comb   w1 = c1 lp + c2 lq, w2 = c2 lp + lq
+//             k_tti_flux   F_a = sum_{b != a} D_b (n_a n_b w) for w1, w2 (6 fields)
+//             k_tti_adj    D_aa (n_a^2 w), D_a F_a, L w1, update
+#include "step_common.h"
+
+namespace rtm {
+
+template <typename T>
+struct TtiArgs {
+  StepArgs<T> a;            // grid, damping, second-difference weights, dt^2
+  T d1, d2, d3, d4;         // first-difference weights / h
+  T c0;                     // centre weight of one axis' second difference / h^2
+  const T *coef;            // [5][N]: c1, c2, n_z, n_y, n_x
+  const T *p, *pp, *q, *qp; // current and previous levels
+  T *pn, *qn;               // next levels
+  T *g;                     // [8][N] intermediates
+};
+
+template <typename T>
+__device__ __forceinline__ T tti_at(const T *u, const StepArgs<T> &a, int z, int y, int x) {
+  return (z >= 0 && z < a.nz && y >= 0 && y < a.ny && x >= 0 && x < a.nx)
+             ? u[((int64_t)z * a.ny + y) * a.nx + x]
+             : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void tti_cell(const StepArgs<T> &a, int64_t i, int &z, int &y, int &x) {
+  x = (int)(i % a.nx);
+  const int64_t zy = i / a.nx;
+  y = (int)(zy % a.ny);
+  z = (int)(zy / a.ny);
+}
+
+// D_axis u at (z, y, x); axis 0 = z, 1 = y, 2 = x
+template <typename T>
+__device__ __forceinline__ T d1_at(const TtiArgs<T> &t, const T *u, int axis, int z, int y,
+                                   int x) {
+  const int dz = axis == 0, dy = axis == 1, dx = axis == 2;
+  const StepArgs<T> &a = t.a;
+  T s = t.d1 * (tti_at(u, a, z + dz, y + dy, x + dx) - tti_at(u, a, z - dz, y - dy, x - dx));
+  s += t.d2 * (tti_at(u, a, z + 2 * dz, y + 2 * dy, x + 2 * dx) -
+               tti_at(u, a, z - 2 * dz, y - 2 * dy, x - 2 * dx));
+  s += t.d3 * (tti_at(u, a, z + 3 * dz, y + 3 * dy, x + 3 * dx) -
+               tti_at(u, a, z - 3 * dz, y - 3 * dy, x - 3 * dx));
+  s += t.d4 * (tti_at(u, a, z + 4 * dz, y + 4 * dy, x + 4 * dx) -
+               tti_at(u, a, z - 4 * dz, y - 4 * dy, x - 4 * dx));
+  return s;
+}
+
+// D_axis,axis of (f * u) at (z, y, x), f = NULL for plain u
+template <typename T>
+__device__ __forceinline__ T d2_at(const TtiArgs<T> &t, const T *u, const T *f, int axis, int z,
+                                   int y, int x) {
+  const int dz = axis == 0, dy = axis == 1, dx = axis == 2;
+  const StepArgs<T> &a = t.a;
+  auto v = [&](int k) -> T {
+    const int zz = z + k * dz, yy = y + k * dy, xx = x + k * dx;
+    const T uu = tti_at(u, a, zz, yy, xx);
+    if (!f) return uu;
+    const T ff = tti_at(f, a, zz, yy, xx);
+    return ff * ff * uu;
+  };
+  T s = t.c0 * v(0);
+  s += a.c1 * (v(1) + v(-1));
+  s += a.c2 * (v(2) + v(-2));
+  s += a.c3 * (v(3) + v(-3));
+  s += a.c4 * (v(4) + v(-4));
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tti_coef(const T *__restrict__ aniso, int64_t N,
+                                                  T *__restrict__ coef) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    const double eps = aniso[i], del = aniso[N + i], th = aniso[2 * N + i], ph = aniso[3 * N + i];
+    coef[i] = (T)(1.0 + 2.0 * eps);
+    coef[N + i] = (T)sqrt(1.0 + 2.0 * del);
+    coef[2 * N + i] = (T)cos(th);
+    coef[3 * N + i] = (T)(sin(th) * sin(ph));
+    coef[4 * N + i] = (T)(sin(th) * cos(ph));
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tti_grad(TtiArgs<T> t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= t.a.N) return;
+  int z, y, x;
+  tti_cell(t.a, i, z, y, x);
+  const int64_t N = t.a.N;
+  for (int b = 0; b < 3; ++b) {
+    t.g[b * N + i] = d1_at(t, t.p, b, z, y, x);
+    t.g[(3 + b) * N + i] = d1_at(t, t.q, b, z, y, x);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T damped_update(const StepArgs<T> &a, T u, T up, T m, T rhs, T damp) {
+  return (T(2) * m * u - (m - damp) * up + a.dt2 * rhs) / (m + damp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tti_fwd(TtiArgs<T> t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const StepArgs<T> &a = t.a;
+  if (i >= a.N) return;
+  int z, y, x;
+  tti_cell(a, i, z, y, x);
+  const int64_t N = a.N;
+  const T c1 = t.coef[i], c2 = t.coef[N + i];
+  const T n[3] = {t.coef[2 * N + i], t.coef[3 * N + i], t.coef[4 * N + i]};
+  T lp = T(0), hzp = T(0), hzq = T(0);
+  for (int ax = 0; ax < 3; ++ax) {
+    const T dp = d2_at(t, t.p, (const T *)nullptr, ax, z, y, x);
+    const T dq = d2_at(t, t.q, (const T *)nullptr, ax, z, y, x);
+    lp += dp;
+    hzp += n[ax] * n[ax] * dp;
+    hzq += n[ax] * n[ax] * dq;
+  }
+  for (int ax = 0; ax < 3; ++ax)
+    for (int b = 0; b < 3; ++b) {
+      if (b == ax) continue;
+      const T nn = n[ax] * n[b];
+      hzp += nn * d1_at(t, t.g + b * N, ax, z, y, x);
+      hzq += nn * d1_at(t, t.g + (3 + b) * N, ax, z, y, x);
+    }
+  const T h0p = lp - hzp;
+  const T damp = sponge_a(a, z, y, x);
+  const T m = a.m[i];
+  t.pn[i] = damped_update(a, t.p[i], t.pp[i], m, c1 * h0p + c2 * hzq, damp);
+  t.qn[i] = damped_update(a, t.q[i], t.qp[i], m, c2 * h0p + hzq, damp);
+}
+
+// adjoint: w1 = c1 lp + c2 lq into g[0], w2 = c2 lp + lq into g[1]
+template <typename T>
+__global__ __launch_bounds__(256) void k_tti_comb(TtiArgs<T> t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= t.a.N) return;
+  const int64_t N = t.a.N;
+  const T c1 = t.coef[i], c2 = t.coef[N + i];
+  t.g[i] = c1 * t.p[i] + c2 * t.q[i];
+  t.g[N + i] = c2 * t.p[i] + t.q[i];
+}
+
+// F_a = sum_{b != a} D_b (n_a n_b w) for w = w1 (g[0]) and w2 (g[1]) into g[2..7]
+template <typename T>
+__global__ __launch_bounds__(256) void k_tti_flux(TtiArgs<T> t, T *__restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const StepArgs<T> &a = t.a;
+  if (i >= a.N) return;
+  int z, y, x;
+  tti_cell(a, i, z, y, x);
+  const int64_t N = a.N;
+  const T *w1 = t.g, *w2 = t.g + N;
+  const T *nax[3] = {t.coef + 2 * N, t.coef + 3 * N, t.coef + 4 * N};
+  for (int ax = 0; ax < 3; ++ax) {
+    T f1 = T(0), f2 = T(0);
+    for (int b = 0; b < 3; ++b) {
+      if (b == ax) continue;
+      const int dz = b == 0, dy = b == 1, dx = b == 2;
+      T s1 = T(0), s2 = T(0);
+      for (int j = 4; j >= 1; --j) {
+        const T wj = j == 1 ? t.d1 : j == 2 ? t.d2 : j == 3 ? t.d3 : t.d4;
+        const int zp = z + j * dz, yp = y + j * dy, xp = x + j * dx;
+        const int zm = z - j * dz, ym = y - j * dy, xm = x - j * dx;
+        const T np_ = tti_at(nax[ax], a, zp, yp, xp) * tti_at(nax[b], a, zp, yp, xp);
+        const T nm_ = tti_at(nax[ax], a, zm, ym, xm) * tti_at(nax[b], a, zm, ym, xm);
+        s1 += wj * (np_ * tti_at(w1, a, zp, yp, xp) - nm_ * tti_at(w1, a, zm, ym, xm));
+        s2 += wj * (np_ * tti_at(w2, a, zp, yp, xp) - nm_ * tti_at(w2, a, zm, ym, xm));
+      }
+      f1 += s1;
+      f2 += s2;
+    }
+    F[ax * N + i] = f1;
+    F[(3 + ax) * N + i] = f2;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tti_adj(TtiArgs<T> t, const T *__restrict__ F) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const StepArgs<T> &a = t.a;
+  if (i >= a.N) return;
+  int z, y, x;
+  tti_cell(a, i, z, y, x);
+  const int64_t N = a.N;
+  const T *w1 = t.g, *w2 = t.g + N;
+  T lw1 = T(0), hz1 = T(0), hz2 = T(0);
+  for (int ax = 0; ax < 3; ++ax) {
+    const T *na = t.coef + (2 + ax) * N;
+    lw1 += d2_at(t, w1, (const T *)nullptr, ax, z, y, x);
+    hz1 += d2_at(t, w1, na, ax, z, y, x);
+    hz2 += d2_at(t, w2, na, ax, z, y, x);
+    hz1 += d1_at(t, F + ax * N, ax, z, y, x);
+    hz2 += d1_at(t, F + (3 + ax) * N, ax, z, y, x);
+  }
+  const T damp = sponge_a(a, z, y, x);
+  const T m = a.m[i];
+  t.pn[i] = damped_update(a, t.p[i], t.pp[i], m, lw1 - hz1, damp);
+  t.qn[i] = damped_update(a, t.q[i], t.qp[i], m, hz2, damp);
+}
+
+// out[n] = Pr (p + q): the adjoint of injecting into both fields
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample_sum(PointTables<T> pt, const T *__restrict__ f1,
+                                                    const T *__restrict__ f2, T *__restrict__ out) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= pt.npts) return;
+  T s = T(0);
+  for (int j = pt.soff[p]; j < pt.soff[p + 1]; ++j) s += pt.sw[j] * (f1[pt.sidx[j]] + f2[pt.sidx[j]]);
+  out[p] = s;
+}
+
+static unsigned cells_grid(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+hipError_t launch_tti_coef(const T *aniso, int64_t N, T *coef, hipStream_t st) {
+  int64_t b = (N + 255) / 256;
+  hipLaunchKernelGGL((k_tti_coef<T>), dim3((unsigned)(b < 8192 ? b : 8192)), dim3(256), 0, st,
+                     aniso, N, coef);
+  return hipGetLastError();
+}
+
+template <typename T>
+static TtiArgs<T> tti_args(const StepArgs<T> &a, T h, const T *coef, const T *p, const T *pp,
+                           const T *q, const T *qp, T *pn, T *qn, T *g) {
+  TtiArgs<T> t;
+  t.a = a;
+  t.d1 = (T)(4.0 / 5.0 / (double)h);
+  t.d2 = (T)(-1.0 / 5.0 / (double)h);
+  t.d3 = (T)(4.0 / 105.0 / (double)h);
+  t.d4 = (T)(-1.0 / 280.0 / (double)h);
+  t.c0 = (T)(-205.0 / 72.0 / ((double)h * (double)h));
+  t.coef = coef;
+  t.p = p;
+  t.pp = pp;
+  t.q = q;
+  t.qp = qp;
+  t.pn = pn;
+  t.qn = qn;
+  t.g = g;
+  return t;
+}
+
+template <typename T>
+hipError_t launch_tti_step(const StepArgs<T> &a, double h, bool adjoint, const T *coef,
+                           const T *p, const T *pp, const T *q, const T *qp, T *pn, T *qn, T *g,
+                           hipStream_t st) {
+  TtiArgs<T> t = tti_args<T>(a, (T)h, coef, p, pp, q, qp, pn, qn, g);
+  const unsigned nb = cells_grid(a.N);
+  if (!adjoint) {
+    hipLaunchKernelGGL((k_tti_grad<T>), dim3(nb), dim3(256), 0, st, t);
+    hipLaunchKernelGGL((k_tti_fwd<T>), dim3(nb), dim3(256), 0, st, t);
+  } else {
+    hipLaunchKernelGGL((k_tti_comb<T>), dim3(nb), dim3(256), 0, st, t);
+    T *F = g + 2 * a.N;
+    hipLaunchKernelGGL((k_tti_flux<T>), dim3(nb), dim3(256), 0, st, t, F);
+    hipLaunchKernelGGL((k_tti_adj<T>), dim3(nb), dim3(256), 0, st, t, (const T *)F);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sample_sum(const PointTables<T> &pt, const T *f1, const T *f2, T *out,
+                             hipStream_t st) {
+  if (pt.npts <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sample_sum<T>), dim3((pt.npts + 255) / 256), dim3(256), 0, st, pt, f1,
+                     f2, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_tti_coef<float>(const float *, int64_t, float *, hipStream_t);
+template hipError_t launch_tti_coef<double>(const double *, int64_t, double *, hipStream_t);
+template hipError_t launch_tti_step<float>(const StepArgs<float> &, double, bool, const float *,
+                                           const float *, const float *, const float *,
+                                           const float *, float *, float *, float *, hipStream_t);
+template hipError_t launch_tti_step<double>(const StepArgs<double> &, double, bool, const double *,
+                                            const double *, const double *, const double *,
+                                            const double *, double *, double *, double *,
+                                            hipStream_t);
+template hipError_t launch_sample_sum<float>(const PointTables<float> &, const float *,
+                                             const float *, float *, hipStream_t);
+template hipError_t launch_sample_sum<double>(const PointTables<double> &, const double *,
+                                              const double *, double *, hipStream_t);
+
+}  // namespace rtm

@@ -24,6 +24,7 @@ __all__ = [
     "smooth", "pad_edge", "two_layer_2d", "layered_3d", "salt_ellipsoid",
     "plane_receivers", "line_receivers", "Workload", "workload_c1",
     "workload_c2", "workload_small_3d", "workload_small_2d", "workload_batched",
+    "tti_parameters", "workload_tti",
 ]
 
 
@@ -272,3 +273,51 @@ def workload_batched(nt: int = 2000, r: int = 64, k_block: int = 32, nshots: int
                             4725.0, 1e-3, m, None, src, q, rec, rademacher(nt, r, 200 + s),
                             k_block))
     return out
+
+
+def tti_parameters(shape, seeds=(3, 4, 5, 6), sigma: float = 10.0, salt=None,
+                   dtype=np.float64) -> np.ndarray:
+    """[4][N] = (eps, delta, theta, phi): smoothed white noise mapped to
+    eps in [0, 0.3], delta in [0, 0.15] (then delta <= eps), tilt theta in
+    [0, 30 deg] and azimuth phi in [0, 360 deg) (radians); zero anisotropy
+    inside an optional salt mask."""
+    def field(seed, lo, hi):
+        w = smooth(np.random.default_rng(seed).standard_normal(shape), sigma)
+        w = (w - w.min()) / max(w.max() - w.min(), 1e-30)
+        return lo + (hi - lo) * w
+    eps = field(seeds[0], 0.0, 0.3)
+    dl = np.minimum(field(seeds[1], 0.0, 0.15), eps)
+    th = np.deg2rad(field(seeds[2], 0.0, 30.0))
+    ph = np.deg2rad(field(seeds[3], 0.0, 359.999))
+    if salt is not None:
+        eps[salt] = 0.0
+        dl[salt] = 0.0
+    return np.stack([eps.ravel(), dl.ravel(), th.ravel(), ph.ravel()]).astype(dtype)
+
+
+def workload_tti(shape=(300, 400, 400), nt: int = 2500, r: int = 64, sigma: float = 10.0,
+                 salt_centre=None, salt_semi=None, nb: int = 10, f0: float = 10.0,
+                 rec_stride: int = 1, dtype=np.float32):
+    """Layered TTI model: 10 layers 1.5-3.5 km/s, a 4.5 km/s salt ellipsoid
+    (centre (150, 200, 200), semi-axes (60, 120, 120) cells at full size,
+    scaled with the grid) with eps = delta = 0 inside, smooth eps / delta /
+    tilt / azimuth fields, source at the top centre, receiver plane at iz = 12,
+    r probes (seed 7).  Returns (Workload, aniso [4][N])."""
+    nz, ny, nx = shape
+    h, dt = 12.5, 1e-3
+    v = layered_3d(nz, ny, nx, 10, 1500.0, 3500.0, dtype=np.float64)
+    centre = salt_centre or (nz * 0.5, ny * 0.5, nx * 0.5)
+    semi = salt_semi or (nz * 0.2, ny * 0.3, nx * 0.3)
+    z, y, x = np.ogrid[:nz, :ny, :nx]
+    inside = (((z - centre[0]) / semi[0]) ** 2 + ((y - centre[1]) / semi[1]) ** 2
+              + ((x - centre[2]) / semi[2]) ** 2) <= 1.0
+    v[inside] = 4500.0
+    aniso = tti_parameters(shape, sigma=sigma, salt=inside, dtype=dtype)
+    m = (1.0 / v ** 2).astype(dtype).ravel()
+    vh_max = float(np.max(v.ravel() * np.sqrt(1.0 + 2.0 * aniso[0].astype(np.float64))))
+    src = np.array([[min(12.0, nz - 1.0), ny // 2, nx // 2]], dtype=np.float64)
+    rec = plane_receivers(min(12.0, nz - 1.0), ny, nx)[::rec_stride]
+    q = source_signature(nt, dt, f0, h, 3).astype(dtype)
+    wl = Workload(f"3d-tti-{nz}x{ny}x{nx}-nt{nt}-r{r}", 3, shape, h, dt, nt, nb, vh_max, 1e-3,
+                  m, None, src, q, rec, rademacher(nt, r, 7), 32)
+    return wl, aniso

@@ -1,0 +1,105 @@
+"""Pseudo-acoustic TTI on the GPU (through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import dev, host, rel, require_gpu, say
+from oracle import Grid
+
+pytestmark = pytest.mark.gpu
+
+import paper_2201_06914_amd as P  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _plan(wl, field, probe, nrec=None, k_block=16):
+    return P.Plan(P.PlanSpec(3, wl.shape, wl.h, wl.dt, wl.nt, wl.nb, wl.c_ref, wl.R, wl.c_ref,
+                             field, probe, wl.r, k_block, 1,
+                             wl.rec_pos.shape[0] if nrec is None else nrec))
+
+
+def _rows(plan, bar2):
+    return np.stack([host(P.rtm_bar_to_rows(plan, bar2[f])) for f in range(2)])
+
+
+def test_tti_f64_forward_adjoint_gradient_match_oracle():
+    wl, an = synth.workload_tti(shape=(18, 16, 20), nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
+                                rec_stride=7, dtype=np.float64)
+    g = Grid.of(wl)
+    say(f"case: TTI F64 {wl.shape} nt={wl.nt} r={wl.r}")
+    f = oracle.tti_forward(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos, Z=wl.Z)
+    plan = _plan(wl, "f64", "f64")
+    m, a, q, Z = (dev(wl.m, torch.float64), dev(an, torch.float64), dev(wl.q, torch.float64),
+                  dev(wl.Z, torch.int8))
+    out = P.rtm_tti_forward_probe(plan, m, a, wl.src_pos, q, wl.rec_pos, Z=Z)
+    torch.cuda.synchronize()
+    e_d, e_u = rel(host(out["d"]), f["d"]), rel(_rows(plan, out["Ubar"]), f["bar"])
+    rng = np.random.default_rng(3)
+    res = rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))
+    ad = oracle.tti_adjoint(g, wl.m, an, wl.rec_pos, res, src_pos=wl.src_pos, Z=wl.Z)
+    adj = P.rtm_tti_adjoint_probe(plan, m, a, wl.rec_pos, dev(res, torch.float64), Z=Z,
+                                  src_pos=wl.src_pos, want_qadj=True)
+    torch.cuda.synchronize()
+    e_v, e_qa = rel(_rows(plan, adj["Vbar"]), ad["bar"]), rel(host(adj["qadj"]), ad["qadj"])
+    d_obs = oracle.tti_forward(g, wl.m * 1.03, an, wl.src_pos, wl.q, wl.rec_pos)["d"]
+    J, gp, _, _ = oracle.tti_probed_gradient(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos, d_obs,
+                                             wl.Z)
+    gr = P.fwi_gradient_tti(plan, m, a, wl.src_pos, q, wl.rec_pos, dev(d_obs, torch.float64), Z)
+    torch.cuda.synchronize()
+    e_g = rel(host(gr["grad"]), gp)
+    e_J = abs(float(gr["misfit"].item()) - J) / J
+    say(f"  d {e_d:.2e} Ubar {e_u:.2e} Vbar {e_v:.2e} qadj {e_qa:.2e} grad {e_g:.2e} J {e_J:.2e}")
+    assert max(e_d, e_u, e_v, e_qa, e_g) < 1e-10 and e_J < 1e-12
+
+
+def test_tti_gpu_dot_test_and_isotropic_limit():
+    wl, an = synth.workload_tti(shape=(20, 18, 22), nt=60, r=4, sigma=2.0, nb=4, f0=15.0,
+                                rec_stride=9, dtype=np.float64)
+    plan = _plan(wl, "f64", "f64")
+    rng = np.random.default_rng(4)
+    m, a = dev(wl.m, torch.float64), dev(an, torch.float64)
+    qx = dev(rng.standard_normal((wl.nt, 1)), torch.float64)
+    y = dev(rng.standard_normal((wl.nt, wl.rec_pos.shape[0])), torch.float64)
+    d = P.rtm_tti_forward_probe(plan, m, a, wl.src_pos, qx, wl.rec_pos)["d"]
+    qa = P.rtm_tti_adjoint_probe(plan, m, a, wl.rec_pos, y, src_pos=wl.src_pos,
+                                 want_qadj=True)["qadj"]
+    l, r_ = P.rtm_dot(plan, d.reshape(-1), y.reshape(-1)).item(), \
+        P.rtm_dot(plan, qx.reshape(-1), qa.reshape(-1)).item()
+    say(f"  TTI dot test: rel {abs(l - r_) / abs(l):.2e}")
+    assert abs(l - r_) <= 1e-12 * abs(l)
+    iso = an.copy()
+    iso[0] = 0.0
+    iso[1] = 0.0
+    d_tti = P.rtm_tti_forward_probe(plan, m, dev(iso, torch.float64), wl.src_pos, qx,
+                                    wl.rec_pos)["d"]
+    d_ac = P.rtm_forward_probe(plan, m, wl.src_pos, qx, wl.rec_pos)["d"]
+    torch.cuda.synchronize()
+    e = rel(host(d_tti), host(d_ac))
+    say(f"  isotropic TTI vs acoustic: {e:.2e}")
+    assert e < 1e-12
+
+
+def test_tti_f32_bf16x2_fused_gradient():
+    wl, an = synth.workload_tti(shape=(30, 26, 36), nt=80, r=16, sigma=3.0, nb=5, f0=12.0,
+                                rec_stride=3)
+    g = Grid.of(wl)
+    d_obs = np.zeros((wl.nt, wl.rec_pos.shape[0]), dtype=np.float32)
+    J, gp, _, _ = oracle.tti_probed_gradient(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos, d_obs,
+                                             wl.Z)
+    plan = _plan(wl, "f32", "bf16x2")
+    args = (plan, dev(wl.m, torch.float32), dev(an, torch.float32), wl.src_pos,
+            dev(wl.q, torch.float32), wl.rec_pos, dev(d_obs, torch.float32),
+            dev(wl.Z, torch.int8))
+    fu = P.fwi_gradient_tti(*args, fused=True)
+    un = P.fwi_gradient_tti(*args)
+    torch.cuda.synchronize()
+    e_f, e_u = rel(host(fu["grad"]), gp), rel(host(fu["grad"]), host(un["grad"]))
+    e_J = abs(float(fu["misfit"].item()) - J) / J
+    say(f"  TTI f32/bf16x2 fused: vs oracle {e_f:.2e}, vs unfused {e_u:.2e}, misfit {e_J:.2e}")
+    assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
