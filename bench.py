@@ -78,6 +78,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 16-shot batched workload section")
     ap.add_argument("--batched-nt", type=int, default=2000)
+    ap.add_argument("--no-rsweep", action="store_true",
+                    help="skip the 300^3 four-shot probe-count sweep against the exact gradient")
+    ap.add_argument("--rsweep-n", type=int, default=300)
+    ap.add_argument("--rsweep-nt", type=int, default=2000)
     ap.add_argument("--cpu-planes", type=int, default=24)
     ap.add_argument("--cpu-nt", type=int, default=80)
     return ap.parse_args()
@@ -168,6 +172,104 @@ def bench_batched(nt: int, variant: int):
             "ms_one_shot_at_a_time": round(t_single, 1),
             "speedup_vs_one_shot_at_a_time": round(t_single / t_graph, 3),
             "graph_equals_eager": bool(same), "stencil_variant": variant}
+
+
+def bench_rsweep(n: int, nt: int, variant: int):
+    """300^3 salt model, 4 shots, nt steps: the probed FWI gradient (4 shots
+    batched, BF16X2, fused imaging) for r = 16, 32, 64, 128 against the exact
+    FP32 gradient with uniform checkpointing, plus a central finite difference
+    of the misfit along a smooth direction.  d_obs is modelled from the true
+    model; the gradient is taken at the smoothed model."""
+    import numpy as np
+    import torch
+
+    import paper_2201_06914_amd as P
+    import synth
+    h, dt, nb = 12.5, 1e-3, 10
+    m_true, m0 = synth.model_salt_300(n)
+    srcs, rec = synth.shots_salt_300(n)
+    q = torch.from_numpy(synth.source_signature(nt, dt, 10.0, h, 3).astype(np.float32)).cuda()
+    mt, mb = torch.from_numpy(m_true).cuda(), torch.from_numpy(m0).cuda()
+    N = n ** 3
+
+    def spec(r):
+        return P.PlanSpec(3, (n, n, n), h, dt, nt, nb, 4500.0, 1e-3, 4500.0, "f32", "bf16x2", r,
+                          32, 1, rec.shape[0])
+    # observed data (untimed setup)
+    p_obs = P.Plan(spec(16))
+    dobs = [P.rtm_forward_probe(p_obs, mt, s, q, rec)["d"] for s in srcs]
+    del mt
+    torch.cuda.empty_cache()
+    print("rsweep: observed data modelled", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t) * 1e3
+    # exact gradient, 4 shots
+    pe = P.Plan(spec(16))
+    ewb = P.exact_workspace_bytes(pe)
+    ework = torch.empty(ewb, dtype=torch.uint8, device="cuda")
+
+    def exact_all():
+        g = torch.zeros(N, dtype=torch.float64, device="cuda")
+        J = 0.0
+        for s, d in zip(srcs, dobs):
+            o = P.fwi_gradient_exact(pe, mb, s, q, rec, d, work=ework)
+            g += o["grad"].double()
+            J += float(o["misfit"].item())
+        return g, J
+    (ge, Je), t_exact = timed(exact_all)
+    del ework
+    torch.cuda.empty_cache()
+    print("rsweep: exact done", file=sys.stderr, flush=True)
+    # finite difference along a smooth direction (FP64 misfits)
+    rng = np.random.default_rng(400)
+    dm = synth.smooth(rng.standard_normal((n, n, n)).astype(np.float32), 8.0).ravel()
+    dm = torch.from_numpy((dm / np.abs(dm).max() * 0.01 * m0).astype(np.float32)).cuda()
+
+    def misfit_at(mm):
+        J = 0.0
+        for s, d in zip(srcs, dobs):
+            dp = P.rtm_forward_probe(p_obs, mm, s, q, rec)["d"]
+            J += 0.5 * float(((dp.double() - d.double()) ** 2).sum())
+        return J
+    eps = 1.0
+    fd = (misfit_at(mb + eps * dm) - misfit_at(mb - eps * dm)) / (2 * eps)
+    lin_exact = float((ge * dm.double()).sum())
+    rows = []
+    for r in (16, 32, 64, 128):
+        B = P.Batch([spec(r)] * 4)
+        shots = [dict(m=mb, src_pos=s, q=q, rec_pos=rec, d_obs=d,
+                      Z=torch.from_numpy(synth.rademacher(nt, r, 300 + 10 * i + r)).cuda())
+                 for i, (s, d) in enumerate(zip(srcs, dobs))]
+        outs = B.outputs()
+        J = torch.empty(4, dtype=torch.float64, device="cuda")
+        work = torch.empty(B.workspace_bytes, dtype=torch.uint8, device="cuda")
+        P.set_stencil_variant(variant)
+        B.fwi_gradient(shots, outs=outs, misfit=J, use_graph=True, work=work)   # capture
+        _, t_pr = timed(lambda: B.fwi_gradient(shots, outs=outs, misfit=J, use_graph=True,
+                                                 work=work))
+        gp = sum(o["grad"].double() for o in outs)
+        err = float(torch.linalg.vector_norm(gp - ge) / torch.linalg.vector_norm(ge))
+        cos = float((gp * ge).sum() / (torch.linalg.vector_norm(gp) * torch.linalg.vector_norm(ge)))
+        rows.append({"r": r, "ms": round(t_pr, 1), "speedup_vs_exact": round(t_exact / t_pr, 3),
+                     "grad_rel_err": round(err, 4), "cosine": round(cos, 4),
+                     "fd_rel_diff": round(abs(float((gp * dm.double()).sum()) - fd) / abs(fd), 4),
+                     "memory_gb": round((B.workspace_bytes + sum(o["Ubar"].numel() * 4
+                                                                  for o in outs)) / 1e9, 2)})
+        del B, outs, work, shots
+        torch.cuda.empty_cache()
+        print(f"rsweep: r={r} done", file=sys.stderr, flush=True)
+    return {"workload": f"{n}^3 salt model, 4 shots, nt={nt}, h=12.5 m, 10 Hz, gradient at the "
+                        f"smoothed model, d_obs modelled from the true model",
+            "exact_ms": round(t_exact, 1),
+            "exact_memory_gb": round(ewb / 1e9, 2),
+            "full_history_gb_per_shot": round(nt * N * 4 / 1e9, 1),
+            "fd_vs_exact_rel_diff": round(abs(lin_exact - fd) / abs(fd), 5),
+            "misfit": Je, "probed": rows}
 
 
 def main():
@@ -347,7 +449,19 @@ def main():
         if "out" in locals():
             del out
         torch.cuda.empty_cache()
-        rec_line["batched"] = bench_batched(a.batched_nt, tune["best"] if tune["best"] >= 1 else 7)
+        try:
+            rec_line["batched"] = bench_batched(a.batched_nt,
+                                                tune["best"] if tune["best"] >= 1 else 7)
+        except Exception as e:  # a failing section must not lose the headline line
+            rec_line["batched"] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
+    if not a.no_rsweep:
+        torch.cuda.empty_cache()
+        try:
+            rec_line["rsweep"] = bench_rsweep(a.rsweep_n, a.rsweep_nt,
+                                              tune["best"] if tune["best"] >= 1 else 7)
+        except Exception as e:
+            rec_line["rsweep"] = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         torch.cuda.empty_cache()

@@ -24,7 +24,7 @@ __all__ = [
     "smooth", "pad_edge", "two_layer_2d", "layered_3d", "salt_ellipsoid",
     "plane_receivers", "line_receivers", "Workload", "workload_c1",
     "workload_c2", "workload_small_3d", "workload_small_2d", "workload_batched",
-    "tti_parameters", "workload_tti",
+    "tti_parameters", "workload_tti", "model_salt_300",
 ]
 
 
@@ -321,3 +321,24 @@ def workload_tti(shape=(300, 400, 400), nt: int = 2500, r: int = 64, sigma: floa
     wl = Workload(f"3d-tti-{nz}x{ny}x{nx}-nt{nt}-r{r}", 3, shape, h, dt, nt, nb, vh_max, 1e-3,
                   m, None, src, q, rec, rademacher(nt, r, 7), 32)
     return wl, aniso
+
+
+def model_salt_300(n: int = 300, sigma: float = 5.0):
+    """300^3 salt case (h = 12.5 m): 10 layers 1.5-3.5 km/s and a 4.5 km/s salt
+    ellipsoid at (170, 150, 150) with semi-axes (40, 80, 80) cells (scaled for
+    other n).  Returns (m_true, m0) as float32 [N], m0 from the velocity
+    smoothed with sigma = 5 cells."""
+    f = n / 300.0
+    v = layered_3d(n, n, n, 10, 1500.0, 3500.0, dtype=np.float64)
+    v = salt_ellipsoid(v, (170 * f, 150 * f, 150 * f), (40 * f, 80 * f, 80 * f), 4500.0)
+    m_true = (1.0 / v ** 2).astype(np.float32).ravel()
+    m0 = (1.0 / smooth(v, sigma) ** 2).astype(np.float32).ravel()
+    return m_true, m0
+
+
+def shots_salt_300(n: int = 300):
+    """Four sources at (12, {75, 225}, {75, 225}) (scaled for other n) and the
+    full receiver plane at iz = 12."""
+    f = n / 300.0
+    src = [np.array([[12.0, y * f, x * f]]) for y in (75, 225) for x in (75, 225)]
+    return src, plane_receivers(12.0, n, n)
