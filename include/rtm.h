@@ -220,6 +220,11 @@ rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_p
  * misfit device double [1] as in fwi_gradient. */
 rtm_status rtm_exact_workspace_bytes(const rtm_plan *plan, int32_t checkpoint_every,
                                      size_t *bytes);
+/* Tuning hook, process wide: 1 (default) lets fwi_gradient_exact fold the
+ * u_tt store and the correlation into the stencil (3D F32 tiled grids), 0
+ * runs them as separate passes.  Results agree to rounding at the injected
+ * cells. */
+void rtm_set_exact_fused(int32_t on);
 rtm_status fwi_gradient_exact(const rtm_plan *plan, const void *m, const double *src_pos,
                               const void *q, const double *rec_pos, const void *d_obs,
                               int32_t checkpoint_every, void *resid, void *grad, double *misfit,

@@ -13,4 +13,5 @@ from .api import (Plan, PlanSpec, RtmError, bar_index, cfl_bound, fwi_gradient, 
                   profile_enable, profile_read, rtm_bar_to_rows,
                   fwi_gradient_exact, exact_workspace_bytes,
                   autotune_stencil, set_stencil_blocks, Batch,
-                  rtm_tti_forward_probe, rtm_tti_adjoint_probe, fwi_gradient_tti)
+                  rtm_tti_forward_probe, rtm_tti_adjoint_probe, fwi_gradient_tti,
+                  set_exact_fused)

@@ -455,6 +455,10 @@ def fwi_gradient_exact(plan: Plan, m, src_pos, q, rec_pos, d_obs, checkpoint_eve
     return {"grad": g, "misfit": J, "resid": res, "workspace_bytes": int(n.value)}
 
 
+def set_exact_fused(on: bool) -> None:
+    _lib.load().rtm_set_exact_fused(1 if on else 0)
+
+
 def exact_workspace_bytes(plan: Plan, checkpoint_every: int = 0) -> int:
     n = ctypes.c_size_t()
     _check(_lib.load().rtm_exact_workspace_bytes(plan.handle, int(checkpoint_every),

@@ -32,6 +32,7 @@ using namespace rtm;
 static thread_local std::string g_last_error;
 static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled variant id
 static int g_stencil_blocks = 1024; // tiled stencil: split z until this many workgroups
+static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
@@ -157,6 +158,8 @@ extern "C" const char *rtm_last_error(void) { return g_last_error.c_str(); }
 extern "C" void rtm_set_stencil_variant(int v) {
   g_stencil_variant = (v >= -1 && v <= kStencilVariants) ? v : -1;
 }
+
+extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
   g_stencil_blocks = blocks > 0 ? blocks : 1024;
@@ -838,6 +841,9 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
   HIP_TRY(launch_fill<T>(lvA(-1), N, T(0), st));
   HIP_TRY(launch_fill<T>(lvA(0), N, T(0), st));
   const T inv_dt2 = (T)(1.0 / (d.dt * d.dt));
+  // fuse the u_tt store and the correlation into the stencil when a tiled
+  // kernel serves the grid (3D F32); else separate passes
+  const bool fused = g_exact_fused && ndim == 3 && sizeof(T) == 4 && variant >= kStencilTiled;
   for (int j = ncp - 1; j >= 0; --j) {
     const int n_lo = j * c, n_hi = std::min(nt, (j + 1) * c);
     HIP_TRY(launch_copy<T>(lvF(n_lo), CP + (int64_t)(2 * j) * ld, N, st));
@@ -847,21 +853,41 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
       fa.cur = lvF(n);
       fa.prev = lvF(n - 1);
       fa.next = lvF(n + 1);
-      HIP_TRY(launch_stencil<T>(ndim, fa, variant, g_stencil_blocks, st));
-      if (src_t.ncell > 0)
-        HIP_TRY(launch_inject<T>(fa, src_t, q + (int64_t)n * src_t.npts, fa.next, st));
-      HIP_TRY(launch_second_diff<T>(fa.next, fa.cur, fa.prev, inv_dt2, N,
-                                    S + (int64_t)(n - n_lo) * ld, st));
+      EpiArgs<T> e;
+      e.d2 = S + (int64_t)(n - n_lo) * ld;
+      e.inv_dt2 = inv_dt2;
+      if (fused && launch_stencil_epi<T>(ndim, fa, variant, g_stencil_blocks, EPI_D2, e, st) ==
+                       hipSuccess) {
+        // u_tt written by the stencil's epilogue; the injection adds its share
+        if (src_t.ncell > 0)
+          HIP_TRY(launch_inject_epi<T>(fa, src_t, q + (int64_t)n * src_t.npts, fa.next, EPI_D2,
+                                       e, st));
+      } else {
+        HIP_TRY(launch_stencil<T>(ndim, fa, variant, g_stencil_blocks, st));
+        if (src_t.ncell > 0)
+          HIP_TRY(launch_inject<T>(fa, src_t, q + (int64_t)n * src_t.npts, fa.next, st));
+        HIP_TRY(launch_second_diff<T>(fa.next, fa.cur, fa.prev, inv_dt2, N, e.d2, st));
+      }
     }
     for (int n = n_hi - 1; n >= n_lo; --n) {
       const int sa = nt - 1 - n;  // adjoint sweep step: lam^n is level sa + 1
       a.cur = lvA(sa);
       a.prev = lvA(sa - 1);
       a.next = lvA(sa + 1);
-      HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
-      if (rec_t.ncell > 0)
-        HIP_TRY(launch_inject<T>(a, rec_t, resid + (int64_t)n * rec_t.npts, a.next, st));
-      HIP_TRY(launch_correlate<T>(grad, S + (int64_t)(n - n_lo) * ld, a.next, N, st));
+      EpiArgs<T> e;
+      e.s = S + (int64_t)(n - n_lo) * ld;
+      e.g = grad;
+      if (fused && launch_stencil_epi<T>(ndim, a, variant, g_stencil_blocks, EPI_CORR, e, st) ==
+                       hipSuccess) {
+        if (rec_t.ncell > 0)
+          HIP_TRY(launch_inject_epi<T>(a, rec_t, resid + (int64_t)n * rec_t.npts, a.next,
+                                       EPI_CORR, e, st));
+      } else {
+        HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
+        if (rec_t.ncell > 0)
+          HIP_TRY(launch_inject<T>(a, rec_t, resid + (int64_t)n * rec_t.npts, a.next, st));
+        HIP_TRY(launch_correlate<T>(grad, e.s, a.next, N, st));
+      }
     }
   }
   return RTM_OK;

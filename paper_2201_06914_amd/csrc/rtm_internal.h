@@ -39,6 +39,16 @@ struct ShotStep {
   int R;
 };
 
+// Cell-local epilogue of the exact comparator's stencil steps.
+enum { EPI_NONE = 0, EPI_D2 = 1, EPI_CORR = 2 };
+template <typename T>
+struct EpiArgs {
+  T *d2 = nullptr;         // EPI_D2: (next - 2 cur + prev) * inv_dt2
+  const T *s = nullptr;    // EPI_CORR: g -= s * next
+  T *g = nullptr;
+  T inv_dt2 = T(0);
+};
+
 // Point tables in CSR form (device pointers into the workspace).
 template <typename T>
 struct PointTables {
@@ -100,6 +110,14 @@ struct ProbeArgs {
 template <typename T>
 hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
                           hipStream_t st);
+// exact comparator: stencil step with a fused epilogue (hipErrorInvalidValue
+// when no tiled kernel serves the grid), and the matching injection
+template <typename T>
+hipError_t launch_stencil_epi(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
+                              int epi, const EpiArgs<T> &e, hipStream_t st);
+template <typename T>
+hipError_t launch_inject_epi(const StepArgs<T> &a, const PointTables<T> &pt, const T *vals,
+                             T *field, int epi, const EpiArgs<T> &e, hipStream_t st);
 // batched sweep step (all shots, one launch each): stencil over the tile
 // table, then injection / sampling of level s+1 for time index n
 template <typename T>

@@ -81,9 +81,13 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
   else *p = v;
 }
 
-// One column tile (bx, by) over planes [z0, z1) of one level.
-template <typename T, int TX, int TYT, int RY, bool NT>
-__device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by, int z0, int z1) {
+// One column tile (bx, by) over planes [z0, z1) of one level.  EPI adds a
+// cell-local epilogue for the exact comparator: EPI_D2 writes the second time
+// difference of the step, EPI_CORR subtracts (stored u_tt) x (new level) from
+// a gradient.
+template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE>
+__device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by, int z0, int z1,
+                                           const EpiArgs<T> &e = EpiArgs<T>{}) {
   constexpr int NTH = TX * TYT;
   constexpr int TY = TYT * RY;
   constexpr int LX = TX + 8;
@@ -201,7 +205,10 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
       const T lap = ((a.cc * c + lz) + lyv) + lxv;
       if (in[j]) {
         const int64_t o = (int64_t)z * sp + (int64_t)yr[j] * a.nx + x;
-        st_stream<T, NT>(a.next + o, cell_update(a, c, pvc[j], mmc[j], lap, sponge_a(a, z, yr[j], x)));
+        const T nv = cell_update(a, c, pvc[j], mmc[j], lap, sponge_a(a, z, yr[j], x));
+        st_stream<T, NT>(a.next + o, nv);
+        if constexpr (EPI == EPI_D2) st_stream<T, NT>(e.d2 + o, (nv - T(2) * c + pvc[j]) * e.inv_dt2);
+        if constexpr (EPI == EPI_CORR) e.g[o] -= ld_stream<T, NT>(e.s + o) * nv;
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) q[j][k] = q[j][k + 1];
@@ -209,9 +216,10 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
   }
 }
 
-template <typename T, int TX, int TYT, int RY, bool NT>
+template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE>
 __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int ntx, int nty,
-                                                             int nzc, int zchunk) {
+                                                             int nzc, int zchunk,
+                                                             EpiArgs<T> e = EpiArgs<T>{}) {
   // XCD-aware order: consecutive hardware block ids go round-robin over the 8
   // XCDs; give each XCD a contiguous run of tiles so halo re-reads hit its L2.
   const int nblk = ntx * nty * nzc;
@@ -221,7 +229,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
   const int by = (b / ntx) % nty;
   const int bz = b / (ntx * nty);
   const int z0 = bz * zchunk;
-  tiled_body<T, TX, TYT, RY, NT>(a, bx, by, z0, min(z0 + zchunk, a.nz));
+  tiled_body<T, TX, TYT, RY, NT, EPI>(a, bx, by, z0, min(z0 + zchunk, a.nz), e);
 }
 
 // Several shots (independent grids, one ring each) in one launch: entry e of
@@ -242,8 +250,9 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_batched(const ShotStep<T>
   tiled_body<T, TX, TYT, RY, NT>(a, t.y & 0xffff, t.y >> 16, t.z, t.w);
 }
 
-template <typename T, int TX, int TYT, int RY, bool NT>
-static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st) {
+template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE>
+static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st,
+                         const EpiArgs<T> &e = EpiArgs<T>{}) {
   constexpr int TY = TYT * RY;
   const int ntx = (a.nx + TX - 1) / TX;
   const int nty = (a.ny + TY - 1) / TY;
@@ -252,8 +261,8 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
   while ((int64_t)ntx * nty * nzc < target_blocks && a.nz / (nzc * 2) >= 16) nzc *= 2;
   const int zchunk = (a.nz + nzc - 1) / nzc;
   nzc = (a.nz + zchunk - 1) / zchunk;
-  hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT>), dim3(ntx * nty * nzc),
-                     dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk);
+  hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT, EPI>), dim3(ntx * nty * nzc),
+                     dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk, e);
 }
 
 // tiled variants: id -> (TX, threads in y, rows per thread, non-temporal)
@@ -290,6 +299,71 @@ hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int targe
 
 template hipError_t launch_stencil<float>(int, const StepArgs<float> &, int, int, hipStream_t);
 template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, int, hipStream_t);
+
+// Stencil step with an exact-comparator epilogue (3D F32, tiled variants 1
+// and 7; other variants use variant 7).  Returns hipErrorInvalidValue for
+// grids the tiled kernel does not serve, so the caller falls back to the
+// separate kernels.
+template <typename T>
+hipError_t launch_stencil_epi(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
+                              int epi, const EpiArgs<T> &e, hipStream_t st) {
+  if (ndim != 3 || sizeof(T) != 4 || variant < kStencilTiled) return hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 4) {
+    const bool nt = variant != 1;
+    if (epi == EPI_D2) {
+      if (nt) launch_tiled<T, 64, 4, 4, true, EPI_D2>(a, target_blocks, st, e);
+      else launch_tiled<T, 64, 4, 4, false, EPI_D2>(a, target_blocks, st, e);
+    } else if (epi == EPI_CORR) {
+      if (nt) launch_tiled<T, 64, 4, 4, true, EPI_CORR>(a, target_blocks, st, e);
+      else launch_tiled<T, 64, 4, 4, false, EPI_CORR>(a, target_blocks, st, e);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_stencil_epi<float>(int, const StepArgs<float> &, int, int, int,
+                                              const EpiArgs<float> &, hipStream_t);
+template hipError_t launch_stencil_epi<double>(int, const StepArgs<double> &, int, int, int,
+                                               const EpiArgs<double> &, hipStream_t);
+
+// Injection whose increment d = dt^2 acc / (m + a) also updates an
+// exact-comparator epilogue output: EPI_D2 adds d / dt^2 to the stored u_tt,
+// EPI_CORR subtracts s * d from the gradient.
+template <typename T>
+__global__ __launch_bounds__(256) void k_inject_epi(StepArgs<T> a, PointTables<T> pt,
+                                                    const T *__restrict__ vals, T *field, int epi,
+                                                    EpiArgs<T> e) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= pt.ncell) return;
+  T acc = T(0);
+  for (int j = pt.ioff[c]; j < pt.ioff[c + 1]; ++j) acc += pt.iw[j] * vals[pt.ipt[j]];
+  const int64_t i = pt.icell[c];
+  const int x = (int)(i % a.nx);
+  const int64_t zy = i / a.nx;
+  const int y = (int)(zy % a.ny);
+  const int z = (int)(zy / a.ny);
+  const T d = a.dt2 * acc / (a.m[i] + sponge_a(a, z, y, x));
+  field[i] += d;
+  if (epi == EPI_D2) e.d2[i] += d * e.inv_dt2;
+  if (epi == EPI_CORR) e.g[i] -= e.s[i] * d;
+}
+
+template <typename T>
+hipError_t launch_inject_epi(const StepArgs<T> &a, const PointTables<T> &pt, const T *vals,
+                             T *field, int epi, const EpiArgs<T> &e, hipStream_t st) {
+  if (pt.ncell <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_inject_epi<T>), dim3((pt.ncell + 255) / 256), dim3(256), 0, st, a, pt,
+                     vals, field, epi, e);
+  return hipGetLastError();
+}
+template hipError_t launch_inject_epi<float>(const StepArgs<float> &, const PointTables<float> &,
+                                             const float *, float *, int, const EpiArgs<float> &,
+                                             hipStream_t);
+template hipError_t launch_inject_epi<double>(const StepArgs<double> &,
+                                              const PointTables<double> &, const double *,
+                                              double *, int, const EpiArgs<double> &,
+                                              hipStream_t);
 
 // ---------------------------------------------------------------------------
 // autotuning helpers: a deterministic test pattern and a bitwise comparison

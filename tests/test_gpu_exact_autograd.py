@@ -61,6 +61,37 @@ def test_exact_gradient_f32_3d():
     assert e < 1e-4
 
 
+@pytest.mark.parametrize("variant", [1, 7])
+def test_exact_fused_epilogue_equals_separate_passes(variant):
+    """The u_tt store and the correlation folded into the tiled stencil (with
+    the injected increments corrected at source and receiver cells) agree with
+    the separate second-difference and correlation passes to FP32 rounding,
+    and with the oracle."""
+    wl = synth.workload_small_3d(shape=(30, 26, 44), nt=90, nb=5)
+    g = Grid.of(wl)
+    rng = np.random.default_rng(3)
+    d_obs = (0.1 * rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))).astype(np.float32)
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2")
+    args = (plan, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32), wl.rec_pos,
+            dev(d_obs, torch.float32))
+    P.set_stencil_variant(variant)
+    try:
+        P.set_exact_fused(False)
+        sep = P.fwi_gradient_exact(*args, checkpoint_every=11)
+        P.set_exact_fused(True)
+        fus = P.fwi_gradient_exact(*args, checkpoint_every=11)
+        torch.cuda.synchronize()
+    finally:
+        P.set_exact_fused(True)
+        P.set_stencil_variant(-1)
+    e = rel(host(fus["grad"]), host(sep["grad"]))
+    J, ge = oracle.exact_gradient(g, wl.m, wl.src_pos, wl.q, wl.rec_pos, d_obs)
+    eo = rel(host(fus["grad"]), ge)
+    say(f"  exact fused vs separate (variant {variant}): {e:.2e}, vs oracle {eo:.2e}")
+    assert e < 2e-6 and eo < 1e-4
+    assert torch.equal(fus["resid"], sep["resid"])
+
+
 def test_probed_with_orthogonal_probes_equals_exact_on_gpu():
     """Both GPU gradients, Hadamard probes with r = nt: identical up to FP32 /
     BF16X2 rounding."""
