@@ -82,6 +82,9 @@ def parse():
                     help="skip the 300^3 four-shot probe-count sweep against the exact gradient")
     ap.add_argument("--rsweep-n", type=int, default=300)
     ap.add_argument("--rsweep-nt", type=int, default=2000)
+    ap.add_argument("--no-tti", action="store_true",
+                    help="skip the 300x400x400 TTI gradient section")
+    ap.add_argument("--tti-nt", type=int, default=2500)
     ap.add_argument("--cpu-planes", type=int, default=24)
     ap.add_argument("--cpu-nt", type=int, default=80)
     return ap.parse_args()
@@ -270,6 +273,58 @@ def bench_rsweep(n: int, nt: int, variant: int):
             "full_history_gb_per_shot": round(nt * N * 4 / 1e9, 1),
             "fd_vs_exact_rel_diff": round(abs(lin_exact - fd) / abs(fd), 5),
             "misfit": Je, "probed": rows}
+
+
+def bench_tti(shape, nt: int, r: int, stride: int):
+    """Pseudo-acoustic TTI gradient, one shot: layered model with a salt
+    ellipsoid, smooth eps / delta / tilt / azimuth fields, r probes on both
+    fields (p, q), BF16X2 probe GEMM with fused imaging.  The TTI step (all of
+    its kernels) is timed with HIP events on every stride-th step."""
+    import numpy as np
+    import torch
+
+    import paper_2201_06914_amd as P
+    import synth
+    wl, an = synth.workload_tti(shape=shape, nt=nt, r=r)
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", c_max=wl.c_ref)
+    m = torch.from_numpy(wl.m).cuda()
+    aniso = torch.from_numpy(an).cuda()
+    del an
+    q = torch.from_numpy(wl.q).cuda()
+    Z = torch.from_numpy(wl.Z).cuda()
+    d_obs = torch.zeros((nt, wl.rec_pos.shape[0]), device="cuda")
+    from paper_2201_06914_amd.api import tti_workspace
+    work = tti_workspace(plan, "cuda")
+    print("tti: inputs resident", file=sys.stderr, flush=True)
+    P.profile_enable(stride)
+    from paper_2201_06914_amd.api import KERNEL_KINDS
+    for k in KERNEL_KINDS:
+        P.profile_read(k)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = P.fwi_gradient_tti(plan, m, aniso, wl.src_pos, q, wl.rec_pos, d_obs, Z, fused=True,
+                             work=work)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3
+    step_ms, cnt = P.profile_read("tti_step")
+    P.profile_enable(0)
+    N = int(np.prod(shape))
+    avg_us = step_ms / max(cnt, 1) * 1e3
+    # algorithmic bytes of one step per cell: read p, q, their previous
+    # levels, m and the five coefficients; write the two new levels (FP32)
+    bpc = 12 * 4
+    gbs = bpc * N / (avg_us * 1e-6) / 1e9
+    finite = bool(torch.isfinite(out["grad"]).all().item())
+    print("tti: gradient done", file=sys.stderr, flush=True)
+    return {"workload": f"TTI {shape[0]}x{shape[1]}x{shape[2]}, nt={nt}, r={r} on p and q, "
+                        f"k=32, bf16x2, fused imaging, one shot",
+            "value": round(2.0 * N * nt / (ms * 1e-3) / 1e9, 2), "unit": "Gcell-updates/s",
+            "ms_per_gradient": round(ms, 1),
+            "step_avg_us": round(avg_us, 1), "step_count_timed": cnt,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                         "bytes_per_cell": bpc},
+            "misfit": float(out["misfit"].item()), "grad_finite": finite}
 
 
 def main():
@@ -462,6 +517,13 @@ def main():
                                               tune["best"] if tune["best"] >= 1 else 7)
         except Exception as e:
             rec_line["rsweep"] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
+    if not a.no_tti:
+        torch.cuda.empty_cache()
+        try:
+            rec_line["tti"] = bench_tti((300, 400, 400), a.tti_nt, 64, a.prof_stride)
+        except Exception as e:
+            rec_line["tti"] = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         torch.cuda.empty_cache()

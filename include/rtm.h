@@ -141,10 +141,12 @@ rtm_status rtm_autotune_stencil(const rtm_plan *plan, const void *m, void *work,
                                 int64_t *mismatch, rtm_stream stream);
 /* Kernel timing, process wide and off by default.  With stride > 0 the
  * sweeps record HIP events on their own stream around every stride-th
- * stencil launch and around every probe-GEMM and image launch (0 turns it
- * off).  rtm_profile_read(kind, ...) waits for the recorded events of one
- * kind (0 stencil, 1 forward probe GEMM, 2 image, 3 adjoint probe GEMM),
- * returns their summed duration in ms and their count, and forgets them. */
+ * stencil launch (every stride-th TTI step, all of its kernels) and around
+ * every probe-GEMM and image launch (0 turns it off).
+ * rtm_profile_read(kind, ...) waits for the recorded events of one kind
+ * (0 stencil, 1 forward probe GEMM, 2 image, 3 adjoint probe GEMM, 4 TTI
+ * step), returns their summed duration in ms and their count, and forgets
+ * them. */
 void rtm_profile_enable(int32_t stride);
 rtm_status rtm_profile_read(int32_t kind, double *total_ms, int64_t *count);
 /* Message of the last HIP failure seen by this thread (empty if none). */

@@ -258,7 +258,7 @@ def autotune_stencil(plan: Plan, m, work=None, steps: int = 20, apply: bool = Tr
     return res
 
 
-KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2, "probe_adj": 3}
+KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2, "probe_adj": 3, "tti_step": 4}
 
 
 def profile_enable(stride: int) -> None:

@@ -36,7 +36,7 @@ static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
-enum { KT_STENCIL = 0, KT_PROBE = 1, KT_IMAGE = 2, KT_PROBE_ADJ = 3, KT_N = 4 };
+enum { KT_STENCIL = 0, KT_PROBE = 1, KT_IMAGE = 2, KT_PROBE_ADJ = 3, KT_TTI = 4, KT_N = 5 };
 struct TimedLaunch {
   int kind;
   hipEvent_t a, b;
@@ -47,7 +47,7 @@ static std::vector<TimedLaunch> g_prof;
 static void prof_begin(int kind, int step, hipStream_t st, TimedLaunch *t) {
   t->kind = -1;
   if (g_prof_stride <= 0) return;
-  if (kind == KT_STENCIL && step % g_prof_stride) return;
+  if ((kind == KT_STENCIL || kind == KT_TTI) && step % g_prof_stride) return;
   if (hipEventCreate(&t->a) != hipSuccess) return;
   if (hipEventCreate(&t->b) != hipSuccess) {
     (void)hipEventDestroy(t->a);
@@ -1409,8 +1409,11 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
   for (int s = 0; s < d.nt; ++s) {
     const int n = io.adjoint ? d.nt - 1 - s : s;
     T *pn = lv(ringP, s + 1), *qn = lv(ringQ, s + 1);
+    TimedLaunch tl;
+    prof_begin(KT_TTI, s, st, &tl);
     HIP_TRY(launch_tti_step<T>(a, d.h, io.adjoint, coef, lv(ringP, s), lv(ringP, s - 1),
                                lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, st));
+    prof_end(st, &tl);
     if (inj.ncell > 0 && vals) {
       HIP_TRY(launch_inject<T>(a, inj, vals + (int64_t)n * inj.npts, pn, st));
       if (!io.adjoint) HIP_TRY(launch_inject<T>(a, inj, vals + (int64_t)n * inj.npts, qn, st));

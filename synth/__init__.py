@@ -281,18 +281,27 @@ def tti_parameters(shape, seeds=(3, 4, 5, 6), sigma: float = 10.0, salt=None,
     eps in [0, 0.3], delta in [0, 0.15] (then delta <= eps), tilt theta in
     [0, 30 deg] and azimuth phi in [0, 360 deg) (radians); zero anisotropy
     inside an optional salt mask."""
-    def field(seed, lo, hi):
+    from concurrent.futures import ThreadPoolExecutor
+
+    def field(args):
+        seed, lo, hi = args
         w = smooth(np.random.default_rng(seed).standard_normal(shape), sigma)
         w = (w - w.min()) / max(w.max() - w.min(), 1e-30)
         return lo + (hi - lo) * w
-    eps = field(seeds[0], 0.0, 0.3)
-    dl = np.minimum(field(seeds[1], 0.0, 0.15), eps)
-    th = np.deg2rad(field(seeds[2], 0.0, 30.0))
-    ph = np.deg2rad(field(seeds[3], 0.0, 359.999))
+    # the four fields are independent; the filter releases the GIL
+    with ThreadPoolExecutor(4) as ex:
+        eps, dl, th, ph = ex.map(field, [(seeds[0], 0.0, 0.3), (seeds[1], 0.0, 0.15),
+                                         (seeds[2], 0.0, 30.0), (seeds[3], 0.0, 359.999)])
+    dl = np.minimum(dl, eps)
+    th = np.deg2rad(th)
+    ph = np.deg2rad(ph)
     if salt is not None:
         eps[salt] = 0.0
         dl[salt] = 0.0
-    return np.stack([eps.ravel(), dl.ravel(), th.ravel(), ph.ravel()]).astype(dtype)
+    out = np.empty((4, eps.size), dtype=dtype)
+    for i, f in enumerate((eps, dl, th, ph)):
+        out[i] = f.ravel()
+    return out
 
 
 def workload_tti(shape=(300, 400, 400), nt: int = 2500, r: int = 64, sigma: float = 10.0,
