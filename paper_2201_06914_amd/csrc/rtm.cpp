@@ -1395,6 +1395,8 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
   T *g = coef + 5 * ld;
   auto lv = [&](T *ring, int j) { return ring + (int64_t)((j + 1) % P->R) * ld; };
   StepArgs<T> a = step_args<T>(P, static_cast<const T *>(io.m));
+  // tiled TTI kernels unless the simple stencil is forced
+  const bool tiled = g_stencil_variant != kStencilSimple;
   // the coefficient levels and intermediates use stride ld (>= N)
   HIP_TRY(launch_tti_coef<T>(static_cast<const T *>(io.aniso), N, coef, st));  // [5][N]
   for (T *ring : {ringP, ringQ}) {
@@ -1412,7 +1414,8 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
     TimedLaunch tl;
     prof_begin(KT_TTI, s, st, &tl);
     HIP_TRY(launch_tti_step<T>(a, d.h, io.adjoint, coef, lv(ringP, s), lv(ringP, s - 1),
-                               lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, st));
+                               lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, tiled,
+                               g_stencil_blocks, st));
     prof_end(st, &tl);
     if (inj.ncell > 0 && vals) {
       HIP_TRY(launch_inject<T>(a, inj, vals + (int64_t)n * inj.npts, pn, st));

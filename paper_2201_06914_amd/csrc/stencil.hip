@@ -140,6 +140,7 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
 
   T q[RY][9];
   T front[RY], pv[RY], mm[RY], hyv[NHY], hxv[NHX];
+  T es[RY], eg[RY];  // EPI_CORR operands, fetched with the plane they belong to
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
 #pragma unroll
@@ -148,6 +149,10 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
     const int64_t o = (int64_t)z0 * sp + (int64_t)yr[j] * a.nx + x;
     pv[j] = in[j] ? ld_stream<T, NT>(a.prev + o) : T(0);
     mm[j] = in[j] ? ld_stream<T, NT>(a.m + o) : T(1);
+    if constexpr (EPI == EPI_CORR) {
+      es[j] = in[j] ? ld_stream<T, NT>(e.s + o) : T(0);
+      eg[j] = in[j] ? e.g[o] : T(0);
+    }
   }
 #pragma unroll
   for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z0, hyg[k], x) : T(0);
@@ -155,12 +160,16 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
   for (int k = 0; k < NHX; ++k) hxv[k] = hxon[k] ? ldu(z0, y0 - 4 + hxr[k], x0 - 4 + hxc[k]) : T(0);
 
   for (int z = z0; z < z1; ++z) {
-    T pvc[RY], mmc[RY], hyc[NHY], hxcv[NHX];
+    T pvc[RY], mmc[RY], hyc[NHY], hxcv[NHX], esc[RY], egc[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
       q[j][8] = front[j];
       pvc[j] = pv[j];
       mmc[j] = mm[j];
+      if constexpr (EPI == EPI_CORR) {
+        esc[j] = es[j];
+        egc[j] = eg[j];
+      }
     }
 #pragma unroll
     for (int k = 0; k < NHY; ++k) hyc[k] = hyv[k];
@@ -174,6 +183,10 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
         const int64_t o = (int64_t)(z + 1) * sp + (int64_t)yr[j] * a.nx + x;
         pv[j] = in[j] ? ld_stream<T, NT>(a.prev + o) : T(0);
         mm[j] = in[j] ? ld_stream<T, NT>(a.m + o) : T(1);
+        if constexpr (EPI == EPI_CORR) {
+          es[j] = in[j] ? ld_stream<T, NT>(e.s + o) : T(0);
+          eg[j] = in[j] ? e.g[o] : T(0);
+        }
       }
 #pragma unroll
       for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z + 1, hyg[k], x) : T(0);
@@ -208,7 +221,7 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
         const T nv = cell_update(a, c, pvc[j], mmc[j], lap, sponge_a(a, z, yr[j], x));
         st_stream<T, NT>(a.next + o, nv);
         if constexpr (EPI == EPI_D2) st_stream<T, NT>(e.d2 + o, (nv - T(2) * c + pvc[j]) * e.inv_dt2);
-        if constexpr (EPI == EPI_CORR) e.g[o] -= ld_stream<T, NT>(e.s + o) * nv;
+        if constexpr (EPI == EPI_CORR) e.g[o] = egc[j] - esc[j] * nv;
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) q[j][k] = q[j][k + 1];

@@ -16,20 +16,9 @@
 //   adjoint:  k_tti_comb   w1 = c1 lp + c2 lq, w2 = c2 lp + lq
 //             k_tti_flux   F_a = sum_{b != a} D_b (n_a n_b w) for w1, w2 (6 fields)
 //             k_tti_adj    D_aa (n_a^2 w), D_a F_a, L w1, update
-#include "step_common.h"
+#include "tti_common.h"
 
 namespace rtm {
-
-template <typename T>
-struct TtiArgs {
-  StepArgs<T> a;            // grid, damping, second-difference weights, dt^2
-  T d1, d2, d3, d4;         // first-difference weights / h
-  T c0;                     // centre weight of one axis' second difference / h^2
-  const T *coef;            // [5][N]: c1, c2, n_z, n_y, n_x
-  const T *p, *pp, *q, *qp; // current and previous levels
-  T *pn, *qn;               // next levels
-  T *g;                     // [8][N] intermediates
-};
 
 template <typename T>
 __device__ __forceinline__ T tti_at(const T *u, const StepArgs<T> &a, int z, int y, int x) {
@@ -237,32 +226,13 @@ hipError_t launch_tti_coef(const T *aniso, int64_t N, T *coef, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T>
-static TtiArgs<T> tti_args(const StepArgs<T> &a, T h, const T *coef, const T *p, const T *pp,
-                           const T *q, const T *qp, T *pn, T *qn, T *g) {
-  TtiArgs<T> t;
-  t.a = a;
-  t.d1 = (T)(4.0 / 5.0 / (double)h);
-  t.d2 = (T)(-1.0 / 5.0 / (double)h);
-  t.d3 = (T)(4.0 / 105.0 / (double)h);
-  t.d4 = (T)(-1.0 / 280.0 / (double)h);
-  t.c0 = (T)(-205.0 / 72.0 / ((double)h * (double)h));
-  t.coef = coef;
-  t.p = p;
-  t.pp = pp;
-  t.q = q;
-  t.qp = qp;
-  t.pn = pn;
-  t.qn = qn;
-  t.g = g;
-  return t;
-}
 
 template <typename T>
 hipError_t launch_tti_step(const StepArgs<T> &a, double h, bool adjoint, const T *coef,
                            const T *p, const T *pp, const T *q, const T *qp, T *pn, T *qn, T *g,
-                           hipStream_t st) {
+                           bool tiled, int target_blocks, hipStream_t st) {
   TtiArgs<T> t = tti_args<T>(a, (T)h, coef, p, pp, q, qp, pn, qn, g);
+  if (tiled) return launch_tti_step_tiled<T>(t, adjoint, target_blocks, st);
   const unsigned nb = cells_grid(a.N);
   if (!adjoint) {
     hipLaunchKernelGGL((k_tti_grad<T>), dim3(nb), dim3(256), 0, st, t);
@@ -289,11 +259,12 @@ template hipError_t launch_tti_coef<float>(const float *, int64_t, float *, hipS
 template hipError_t launch_tti_coef<double>(const double *, int64_t, double *, hipStream_t);
 template hipError_t launch_tti_step<float>(const StepArgs<float> &, double, bool, const float *,
                                            const float *, const float *, const float *,
-                                           const float *, float *, float *, float *, hipStream_t);
+                                           const float *, float *, float *, float *, bool, int,
+                                           hipStream_t);
 template hipError_t launch_tti_step<double>(const StepArgs<double> &, double, bool, const double *,
                                             const double *, const double *, const double *,
-                                            const double *, double *, double *, double *,
-                                            hipStream_t);
+                                            const double *, double *, double *, double *, bool,
+                                            int, hipStream_t);
 template hipError_t launch_sample_sum<float>(const PointTables<float> &, const float *,
                                              const float *, float *, hipStream_t);
 template hipError_t launch_sample_sum<double>(const PointTables<double> &, const double *,

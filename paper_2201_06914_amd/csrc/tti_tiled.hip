@@ -1,0 +1,508 @@
+// Tiled pseudo-acoustic TTI step: the operator of tti.hip (same symbols),
+// restructured so that every pass streams its fields once from HBM.
+//
+// The mixed terms use the identity D_a D_b = D_b D_a, exact for first
+// differences on a box with the field taken as zero outside it (the two
+// nested zero-extensions cut the same cells), so each unordered pair {a, b} is
+// evaluated once with a factor 2:
+//   Hz u  = sum_a n_a^2 D_aa u + 2 [n_x n_y D_x (D_y u) + n_x n_z D_z (D_x u)
+//                                   + n_y n_z D_z (D_y u)]
+//   HzT w = sum_a D_aa (n_a^2 w) + 2 [D_x E_xy + D_z E_xz],
+//           E_xy = D_y (n_x n_y w),  E_xz = D_x (n_x n_z w) + D_y (n_y n_z w).
+// Each sweep step is two launches over the same tile geometry:
+//   forward  k_tti_fprep  in-plane: G = (D_x p, D_y p, D_x q, D_y q)
+//            k_tti_fmarch z-march: D_zz and D_z G from register queues, D_xx,
+//                         D_yy and D_x (D_y .) from the LDS plane, update
+//   adjoint  k_tti_aprep  in-plane: w1 = c1 lp + c2 lq, w2 = c2 lp + lq,
+//                         E_xz and E_xy of w1 and w2
+//            k_tti_amarch z-march: D_zz (n_z^2 w) and D_z E_xz from queues,
+//                         D_xx, D_yy, D_x E_xy from LDS, update
+// A workgroup owns a 64 x 8 column tile (one thread per column) and marches a
+// z-chunk; the current plane sits in LDS with a 4-cell halo along x and y
+// (double buffered, one barrier per plane) and the next plane's loads are in
+// flight while the current one is computed.  Intermediates live in the
+// plan's scratch slots g[k] (stride N).
+#include "tti_common.h"
+
+namespace rtm {
+
+namespace {
+
+constexpr int TX = 64;
+constexpr int TY = 8;
+constexpr int NTHR = TX * TY;  // 512
+constexpr int LX = TX + 8;
+constexpr int LY = TY + 8;
+constexpr int PL = LY * LX;     // one LDS plane
+
+template <typename T>
+struct TtiTile {
+  int tx, ty, x, y, lc;  // own column, its LDS offset
+  bool in;
+  int hyg, hyl;          // y-halo cell: global row, LDS offset (column x)
+  bool hyon;
+  int hxg_y, hxg_x, hxl;  // x-halo cell (threads < 64)
+  bool hxon;
+};
+
+template <typename T>
+__device__ __forceinline__ TtiTile<T> tile_of(const StepArgs<T> &a, int bx, int by) {
+  TtiTile<T> t;
+  const int tid = threadIdx.x;
+  t.tx = tid % TX;
+  t.ty = tid / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  t.x = x0 + t.tx;
+  t.y = y0 + t.ty;
+  t.in = t.x < a.nx && t.y < a.ny;
+  t.lc = (t.ty + 4) * LX + t.tx + 4;
+  // 8 halo rows x 64 columns: one per thread
+  const int hr = t.ty < 4 ? t.ty : TY + t.ty;
+  t.hyg = y0 - 4 + hr;
+  t.hyl = hr * LX + t.tx + 4;
+  t.hyon = t.x < a.nx && t.hyg >= 0 && t.hyg < a.ny;
+  // 8 halo columns x 8 rows: threads 0..63
+  const int r = tid / 8, c = tid % 8;
+  const int lcx = c < 4 ? c : TX + c;
+  t.hxg_y = y0 + r;
+  t.hxg_x = x0 - 4 + lcx;
+  t.hxl = (4 + r) * LX + lcx;
+  t.hxon = tid < 64 && t.hxg_y < a.ny && t.hxg_x >= 0 && t.hxg_x < a.nx;
+  return t;
+}
+
+template <typename T>
+__device__ __forceinline__ int64_t cidx(const StepArgs<T> &a, int z, int y, int x) {
+  return ((int64_t)z * a.ny + y) * a.nx + x;
+}
+
+// field value at (z, y, x) of a column known to lie inside the x-y range; zero
+// for planes outside the grid
+template <typename T>
+__device__ __forceinline__ T ldz(const T *f, const StepArgs<T> &a, bool on, int z, int y, int x) {
+  return (on && z >= 0 && z < a.nz) ? f[cidx(a, z, y, x)] : T(0);
+}
+
+// first difference from a 9-value window centred at w[4] (w[4] unused)
+template <typename T>
+__device__ __forceinline__ T d1q(const TtiArgs<T> &t, const T *w) {
+  T s = t.d1 * (w[5] - w[3]);
+  s += t.d2 * (w[6] - w[2]);
+  s += t.d3 * (w[7] - w[1]);
+  s += t.d4 * (w[8] - w[0]);
+  return s;
+}
+// first difference along an LDS row / column (stride st) centred at c
+template <typename T>
+__device__ __forceinline__ T d1l(const TtiArgs<T> &t, const T *c, int st) {
+  T s = t.d1 * (c[st] - c[-st]);
+  s += t.d2 * (c[2 * st] - c[-2 * st]);
+  s += t.d3 * (c[3 * st] - c[-3 * st]);
+  s += t.d4 * (c[4 * st] - c[-4 * st]);
+  return s;
+}
+// second difference (centre included)
+template <typename T>
+__device__ __forceinline__ T d2q(const TtiArgs<T> &t, const T *w) {
+  T s = t.c0 * w[4];
+  s += t.a.c1 * (w[5] + w[3]);
+  s += t.a.c2 * (w[6] + w[2]);
+  s += t.a.c3 * (w[7] + w[1]);
+  s += t.a.c4 * (w[8] + w[0]);
+  return s;
+}
+template <typename T>
+__device__ __forceinline__ T d2l(const TtiArgs<T> &t, const T *c, int st) {
+  T s = t.c0 * c[0];
+  s += t.a.c1 * (c[st] + c[-st]);
+  s += t.a.c2 * (c[2 * st] + c[-2 * st]);
+  s += t.a.c3 * (c[3 * st] + c[-3 * st]);
+  s += t.a.c4 * (c[4 * st] + c[-4 * st]);
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T tti_update(const StepArgs<T> &a, T u, T up, T m, T rhs, T damp) {
+  return (T(2) * m * u - (m - damp) * up + a.dt2 * rhs) / (m + damp);
+}
+
+// block -> (tile, z-chunk), XCD-aware as in the acoustic kernel
+__device__ __forceinline__ void block_of(int ntx, int nty, int nzc, int zchunk, int nz, int &bx,
+                                         int &by, int &z0, int &z1) {
+  const int nblk = ntx * nty * nzc;
+  int b = blockIdx.x;
+  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  bx = b % ntx;
+  by = (b / ntx) % nty;
+  z0 = (b / (ntx * nty)) * zchunk;
+  z1 = min(z0 + zchunk, nz);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// forward, in-plane: g0 = D_x p, g1 = D_y p, g2 = D_x q, g3 = D_y q
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_tti_fprep(TtiArgs<T> t, int ntx, int nty, int nzc,
+                                                    int zchunk) {
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<T> g = tile_of(a, bx, by);
+  __shared__ T L[2][2][PL];  // [buffer][p, q]
+  const int64_t N = a.N;
+  T cp, cq, yp, yq, xp, xq;
+  auto fetch = [&](int z) {
+    cp = ldz(t.p, a, g.in, z, g.y, g.x);
+    cq = ldz(t.q, a, g.in, z, g.y, g.x);
+    yp = ldz(t.p, a, g.hyon, z, g.hyg, g.x);
+    yq = ldz(t.q, a, g.hyon, z, g.hyg, g.x);
+    xp = ldz(t.p, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    xq = ldz(t.q, a, g.hxon, z, g.hxg_y, g.hxg_x);
+  };
+  fetch(z0);
+  for (int z = z0; z < z1; ++z) {
+    T *Lp = L[z & 1][0], *Lq = L[z & 1][1];
+    Lp[g.lc] = cp;
+    Lq[g.lc] = cq;
+    Lp[g.hyl] = yp;
+    Lq[g.hyl] = yq;
+    if (threadIdx.x < 64) {
+      Lp[g.hxl] = xp;
+      Lq[g.hxl] = xq;
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    if (g.in) {
+      const int64_t o = cidx(a, z, g.y, g.x);
+      t.g[o] = d1l(t, Lp + g.lc, 1);
+      t.g[N + o] = d1l(t, Lp + g.lc, LX);
+      t.g[2 * N + o] = d1l(t, Lq + g.lc, 1);
+      t.g[3 * N + o] = d1l(t, Lq + g.lc, LX);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward, z-march
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int nty, int nzc,
+                                                     int zchunk) {
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<T> g = tile_of(a, bx, by);
+  __shared__ T L[2][4][PL];  // [buffer][p, q, D_y p, D_y q]
+  const int64_t N = a.N;
+  const T *Gxp = t.g, *Gyp = t.g + N, *Gxq = t.g + 2 * N, *Gyq = t.g + 3 * N;
+  // z queues of the own column: p, q, D_x p, D_y p, D_x q, D_y q
+  T Qp[9], Qq[9], Qxp[9], Qyp[9], Qxq[9], Qyq[9];
+  T f[6];  // queue fronts (plane z + 4)
+  for (int k = 0; k < 8; ++k) {
+    const int zz = z0 - 4 + k;
+    Qp[k] = ldz(t.p, a, g.in, zz, g.y, g.x);
+    Qq[k] = ldz(t.q, a, g.in, zz, g.y, g.x);
+    Qxp[k] = ldz(Gxp, a, g.in, zz, g.y, g.x);
+    Qyp[k] = ldz(Gyp, a, g.in, zz, g.y, g.x);
+    Qxq[k] = ldz(Gxq, a, g.in, zz, g.y, g.x);
+    Qyq[k] = ldz(Gyq, a, g.in, zz, g.y, g.x);
+  }
+  // plane values: previous levels, m, coefficients; halos of p, q, D_y p, D_y q
+  T pp, qp, mm, c1, c2, nz, ny, nx, yp, yq, xp, xq, xgp, xgq;
+  auto fetch = [&](int z) {
+    const int zf = z + 4;
+    f[0] = ldz(t.p, a, g.in, zf, g.y, g.x);
+    f[1] = ldz(t.q, a, g.in, zf, g.y, g.x);
+    f[2] = ldz(Gxp, a, g.in, zf, g.y, g.x);
+    f[3] = ldz(Gyp, a, g.in, zf, g.y, g.x);
+    f[4] = ldz(Gxq, a, g.in, zf, g.y, g.x);
+    f[5] = ldz(Gyq, a, g.in, zf, g.y, g.x);
+    pp = ldz(t.pp, a, g.in, z, g.y, g.x);
+    qp = ldz(t.qp, a, g.in, z, g.y, g.x);
+    mm = ldz(a.m, a, g.in, z, g.y, g.x);
+    c1 = ldz(t.coef, a, g.in, z, g.y, g.x);
+    c2 = ldz(t.coef + N, a, g.in, z, g.y, g.x);
+    nz = ldz(t.coef + 2 * N, a, g.in, z, g.y, g.x);
+    ny = ldz(t.coef + 3 * N, a, g.in, z, g.y, g.x);
+    nx = ldz(t.coef + 4 * N, a, g.in, z, g.y, g.x);
+    yp = ldz(t.p, a, g.hyon, z, g.hyg, g.x);
+    yq = ldz(t.q, a, g.hyon, z, g.hyg, g.x);
+    xp = ldz(t.p, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    xq = ldz(t.q, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    xgp = ldz(Gyp, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    xgq = ldz(Gyq, a, g.hxon, z, g.hxg_y, g.hxg_x);
+  };
+  fetch(z0);
+  for (int z = z0; z < z1; ++z) {
+    Qp[8] = f[0];
+    Qq[8] = f[1];
+    Qxp[8] = f[2];
+    Qyp[8] = f[3];
+    Qxq[8] = f[4];
+    Qyq[8] = f[5];
+    const T cpp = pp, cqp = qp, cm = mm, cc1 = c1, cc2 = c2, cnz = nz, cny = ny, cnx = nx;
+    T *Lp = L[z & 1][0], *Lq = L[z & 1][1], *Lyp = L[z & 1][2], *Lyq = L[z & 1][3];
+    Lp[g.lc] = Qp[4];
+    Lq[g.lc] = Qq[4];
+    Lyp[g.lc] = Qyp[4];
+    Lyq[g.lc] = Qyq[4];
+    Lp[g.hyl] = yp;
+    Lq[g.hyl] = yq;
+    if (threadIdx.x < 64) {
+      Lp[g.hxl] = xp;
+      Lq[g.hxl] = xq;
+      Lyp[g.hxl] = xgp;
+      Lyq[g.hxl] = xgq;
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    if (g.in) {
+      const T pzz = d2q(t, Qp), qzz = d2q(t, Qq);
+      const T pxx = d2l(t, Lp + g.lc, 1), qxx = d2l(t, Lq + g.lc, 1);
+      const T pyy = d2l(t, Lp + g.lc, LX), qyy = d2l(t, Lq + g.lc, LX);
+      const T pxy = d1l(t, Lyp + g.lc, 1), qxy = d1l(t, Lyq + g.lc, 1);
+      const T pxz = d1q(t, Qxp), qxz = d1q(t, Qxq);
+      const T pyz = d1q(t, Qyp), qyz = d1q(t, Qyq);
+      const T lp = (pzz + pyy) + pxx;
+      const T mix_p = (cnx * cny) * pxy + (cnx * cnz) * pxz + (cny * cnz) * pyz;
+      const T mix_q = (cnx * cny) * qxy + (cnx * cnz) * qxz + (cny * cnz) * qyz;
+      const T hzp = ((cnz * cnz) * pzz + (cny * cny) * pyy + (cnx * cnx) * pxx) + T(2) * mix_p;
+      const T hzq = ((cnz * cnz) * qzz + (cny * cny) * qyy + (cnx * cnx) * qxx) + T(2) * mix_q;
+      const T h0p = lp - hzp;
+      const T damp = sponge_a(a, z, g.y, g.x);
+      const int64_t o = cidx(a, z, g.y, g.x);
+      t.pn[o] = tti_update(a, Qp[4], cpp, cm, cc1 * h0p + cc2 * hzq, damp);
+      t.qn[o] = tti_update(a, Qq[4], cqp, cm, cc2 * h0p + hzq, damp);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      Qp[k] = Qp[k + 1];
+      Qq[k] = Qq[k + 1];
+      Qxp[k] = Qxp[k + 1];
+      Qyp[k] = Qyp[k + 1];
+      Qxq[k] = Qxq[k + 1];
+      Qyq[k] = Qyq[k + 1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint, in-plane: g0 = w1, g1 = w2, g2 = E_xz(w1), g3 = E_xz(w2),
+// g4 = E_xy(w1), g5 = E_xy(w2)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_tti_aprep(TtiArgs<T> t, int ntx, int nty, int nzc,
+                                                    int zchunk) {
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<T> g = tile_of(a, bx, by);
+  // [buffer][X1, X2, Y1, Y2, XY1, XY2]: X = n_x n_z w (x taps), Y = n_y n_z w and
+  // XY = n_x n_y w (y taps)
+  __shared__ T L[2][6][PL];
+  const int64_t N = a.N;
+  const T *c1f = t.coef, *c2f = t.coef + N, *nzf = t.coef + 2 * N, *nyf = t.coef + 3 * N,
+          *nxf = t.coef + 4 * N;
+  struct Cell {
+    T lp, lq, c1, c2, nz, ny, nx;
+  };
+  auto load = [&](bool on, int z, int y, int x) {
+    Cell c;
+    c.lp = ldz(t.p, a, on, z, y, x);
+    c.lq = ldz(t.q, a, on, z, y, x);
+    c.c1 = ldz(c1f, a, on, z, y, x);
+    c.c2 = ldz(c2f, a, on, z, y, x);
+    c.nz = ldz(nzf, a, on, z, y, x);
+    c.ny = ldz(nyf, a, on, z, y, x);
+    c.nx = ldz(nxf, a, on, z, y, x);
+    return c;
+  };
+  Cell cc, cy, cx;
+  auto fetch = [&](int z) {
+    cc = load(g.in, z, g.y, g.x);
+    cy = load(g.hyon, z, g.hyg, g.x);
+    cx = load(g.hxon, z, g.hxg_y, g.hxg_x);
+  };
+  fetch(z0);
+  for (int z = z0; z < z1; ++z) {
+    T(*B)[PL] = L[z & 1];
+    const T w1 = cc.c1 * cc.lp + cc.c2 * cc.lq;
+    const T w2 = cc.c2 * cc.lp + cc.lq;
+    B[0][g.lc] = (cc.nx * cc.nz) * w1;
+    B[1][g.lc] = (cc.nx * cc.nz) * w2;
+    B[2][g.lc] = (cc.ny * cc.nz) * w1;
+    B[3][g.lc] = (cc.ny * cc.nz) * w2;
+    B[4][g.lc] = (cc.nx * cc.ny) * w1;
+    B[5][g.lc] = (cc.nx * cc.ny) * w2;
+    {
+      const T v1 = cy.c1 * cy.lp + cy.c2 * cy.lq, v2 = cy.c2 * cy.lp + cy.lq;
+      B[2][g.hyl] = (cy.ny * cy.nz) * v1;
+      B[3][g.hyl] = (cy.ny * cy.nz) * v2;
+      B[4][g.hyl] = (cy.nx * cy.ny) * v1;
+      B[5][g.hyl] = (cy.nx * cy.ny) * v2;
+    }
+    if (threadIdx.x < 64) {
+      const T v1 = cx.c1 * cx.lp + cx.c2 * cx.lq, v2 = cx.c2 * cx.lp + cx.lq;
+      B[0][g.hxl] = (cx.nx * cx.nz) * v1;
+      B[1][g.hxl] = (cx.nx * cx.nz) * v2;
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    if (g.in) {
+      const int64_t o = cidx(a, z, g.y, g.x);
+      t.g[o] = w1;
+      t.g[N + o] = w2;
+      t.g[2 * N + o] = d1l(t, B[0] + g.lc, 1) + d1l(t, B[2] + g.lc, LX);
+      t.g[3 * N + o] = d1l(t, B[1] + g.lc, 1) + d1l(t, B[3] + g.lc, LX);
+      t.g[4 * N + o] = d1l(t, B[4] + g.lc, LX);
+      t.g[5 * N + o] = d1l(t, B[5] + g.lc, LX);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint, z-march:
+//   rhs_p = L w1 - HzT w1,  rhs_q = HzT w2
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int nty, int nzc,
+                                                     int zchunk) {
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<T> g = tile_of(a, bx, by);
+  // [buffer][w1, n_x^2 w1, n_y^2 w1, n_x^2 w2, n_y^2 w2, E_xy(w1), E_xy(w2)]
+  __shared__ T L[2][7][PL];
+  const int64_t N = a.N;
+  const T *nzf = t.coef + 2 * N, *nyf = t.coef + 3 * N, *nxf = t.coef + 4 * N;
+  const T *W1 = t.g, *W2 = t.g + N, *Exz1 = t.g + 2 * N, *Exz2 = t.g + 3 * N,
+          *Exy1 = t.g + 4 * N, *Exy2 = t.g + 5 * N;
+  // z queues of the own column: w1, n_z^2 w1, n_z^2 w2, E_xz(w1), E_xz(w2)
+  T Qw[9], Qz1[9], Qz2[9], Qe1[9], Qe2[9];
+  T f[5];
+  auto front = [&](int zz, T *o5) {
+    const T w1 = ldz(W1, a, g.in, zz, g.y, g.x);
+    const T w2 = ldz(W2, a, g.in, zz, g.y, g.x);
+    const T n = ldz(nzf, a, g.in, zz, g.y, g.x);
+    o5[0] = w1;
+    o5[1] = (n * n) * w1;
+    o5[2] = (n * n) * w2;
+    o5[3] = ldz(Exz1, a, g.in, zz, g.y, g.x);
+    o5[4] = ldz(Exz2, a, g.in, zz, g.y, g.x);
+  };
+  for (int k = 0; k < 8; ++k) {
+    T v[5];
+    front(z0 - 4 + k, v);
+    Qw[k] = v[0];
+    Qz1[k] = v[1];
+    Qz2[k] = v[2];
+    Qe1[k] = v[3];
+    Qe2[k] = v[4];
+  }
+  // plane values of the own cell and the halo cells
+  T lp, lq, lpp, lqp, mm, w2c, nxc, nyc, e1c, e2c;
+  T hy_w1, hy_w2, hy_ny;                      // y-halo
+  T hx_w1, hx_w2, hx_nx, hx_e1, hx_e2;        // x-halo
+  auto fetch = [&](int z) {
+    front(z + 4, f);
+    lp = ldz(t.p, a, g.in, z, g.y, g.x);
+    lq = ldz(t.q, a, g.in, z, g.y, g.x);
+    lpp = ldz(t.pp, a, g.in, z, g.y, g.x);
+    lqp = ldz(t.qp, a, g.in, z, g.y, g.x);
+    mm = ldz(a.m, a, g.in, z, g.y, g.x);
+    w2c = ldz(W2, a, g.in, z, g.y, g.x);
+    nxc = ldz(nxf, a, g.in, z, g.y, g.x);
+    nyc = ldz(nyf, a, g.in, z, g.y, g.x);
+    e1c = ldz(Exy1, a, g.in, z, g.y, g.x);
+    e2c = ldz(Exy2, a, g.in, z, g.y, g.x);
+    hy_w1 = ldz(W1, a, g.hyon, z, g.hyg, g.x);
+    hy_w2 = ldz(W2, a, g.hyon, z, g.hyg, g.x);
+    hy_ny = ldz(nyf, a, g.hyon, z, g.hyg, g.x);
+    hx_w1 = ldz(W1, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    hx_w2 = ldz(W2, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    hx_nx = ldz(nxf, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    hx_e1 = ldz(Exy1, a, g.hxon, z, g.hxg_y, g.hxg_x);
+    hx_e2 = ldz(Exy2, a, g.hxon, z, g.hxg_y, g.hxg_x);
+  };
+  fetch(z0);
+  for (int z = z0; z < z1; ++z) {
+    Qw[8] = f[0];
+    Qz1[8] = f[1];
+    Qz2[8] = f[2];
+    Qe1[8] = f[3];
+    Qe2[8] = f[4];
+    const T clp = lp, clq = lq, clpp = lpp, clqp = lqp, cm = mm;
+    T(*B)[PL] = L[z & 1];
+    {
+      const T w1 = Qw[4];
+      B[0][g.lc] = w1;
+      B[1][g.lc] = (nxc * nxc) * w1;
+      B[2][g.lc] = (nyc * nyc) * w1;
+      B[3][g.lc] = (nxc * nxc) * w2c;
+      B[4][g.lc] = (nyc * nyc) * w2c;
+      B[5][g.lc] = e1c;
+      B[6][g.lc] = e2c;
+    }
+    B[0][g.hyl] = hy_w1;
+    B[2][g.hyl] = (hy_ny * hy_ny) * hy_w1;
+    B[4][g.hyl] = (hy_ny * hy_ny) * hy_w2;
+    if (threadIdx.x < 64) {
+      B[0][g.hxl] = hx_w1;
+      B[1][g.hxl] = (hx_nx * hx_nx) * hx_w1;
+      B[3][g.hxl] = (hx_nx * hx_nx) * hx_w2;
+      B[5][g.hxl] = hx_e1;
+      B[6][g.hxl] = hx_e2;
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    if (g.in) {
+      const T lw1 = (d2q(t, Qw) + d2l(t, B[0] + g.lc, LX)) + d2l(t, B[0] + g.lc, 1);
+      const T hz1 = ((d2q(t, Qz1) + d2l(t, B[2] + g.lc, LX)) + d2l(t, B[1] + g.lc, 1)) +
+                    T(2) * (d1l(t, B[5] + g.lc, 1) + d1q(t, Qe1));
+      const T hz2 = ((d2q(t, Qz2) + d2l(t, B[4] + g.lc, LX)) + d2l(t, B[3] + g.lc, 1)) +
+                    T(2) * (d1l(t, B[6] + g.lc, 1) + d1q(t, Qe2));
+      const T damp = sponge_a(a, z, g.y, g.x);
+      const int64_t o = cidx(a, z, g.y, g.x);
+      t.pn[o] = tti_update(a, clp, clpp, cm, lw1 - hz1, damp);
+      t.qn[o] = tti_update(a, clq, clqp, cm, hz2, damp);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      Qw[k] = Qw[k + 1];
+      Qz1[k] = Qz1[k + 1];
+      Qz2[k] = Qz2[k + 1];
+      Qe1[k] = Qe1[k + 1];
+      Qe2[k] = Qe2[k + 1];
+    }
+  }
+}
+
+// one TTI step with the tiled kernels; g needs 4 (forward) / 6 (adjoint) slots
+// of N
+template <typename T>
+hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
+                                 hipStream_t st) {
+  const StepArgs<T> &a = t.a;
+  const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
+  int nzc = 1;
+  while (ntx * nty * nzc < target_blocks && a.nz / (nzc * 2) >= 16) nzc *= 2;
+  const int zchunk = (a.nz + nzc - 1) / nzc;
+  nzc = (a.nz + zchunk - 1) / zchunk;
+  const dim3 grid(ntx * nty * nzc), blk(NTHR);
+  if (!adjoint) {
+    hipLaunchKernelGGL((k_tti_fprep<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_fmarch<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+  } else {
+    hipLaunchKernelGGL((k_tti_aprep<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_amarch<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_tti_step_tiled<float>(const TtiArgs<float> &, bool, int, hipStream_t);
+template hipError_t launch_tti_step_tiled<double>(const TtiArgs<double> &, bool, int,
+                                                  hipStream_t);
+
+}  // namespace rtm

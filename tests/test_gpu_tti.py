@@ -28,11 +28,23 @@ def _rows(plan, bar2):
     return np.stack([host(P.rtm_bar_to_rows(plan, bar2[f])) for f in range(2)])
 
 
-def test_tti_f64_forward_adjoint_gradient_match_oracle():
-    wl, an = synth.workload_tti(shape=(18, 16, 20), nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
+@pytest.fixture
+def variant(request):
+    """Stencil variant for the test's duration: -1 lets the library pick (the
+    tiled TTI kernels), 0 forces the one-thread-per-cell kernels."""
+    P.set_stencil_variant(request.param)
+    yield request.param
+    P.set_stencil_variant(-1)
+
+
+@pytest.mark.parametrize("variant,shape", [(-1, (18, 16, 20)), (0, (18, 16, 20)),
+                                           (-1, (40, 21, 70))], indirect=["variant"])
+def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
+    """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels."""
+    wl, an = synth.workload_tti(shape=shape, nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
                                 rec_stride=7, dtype=np.float64)
     g = Grid.of(wl)
-    say(f"case: TTI F64 {wl.shape} nt={wl.nt} r={wl.r}")
+    say(f"case: TTI F64 {wl.shape} nt={wl.nt} r={wl.r} variant {variant}")
     f = oracle.tti_forward(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos, Z=wl.Z)
     plan = _plan(wl, "f64", "f64")
     m, a, q, Z = (dev(wl.m, torch.float64), dev(an, torch.float64), dev(wl.q, torch.float64),
@@ -103,3 +115,31 @@ def test_tti_f32_bf16x2_fused_gradient():
     e_J = abs(float(fu["misfit"].item()) - J) / J
     say(f"  TTI f32/bf16x2 fused: vs oracle {e_f:.2e}, vs unfused {e_u:.2e}, misfit {e_J:.2e}")
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
+
+
+def test_tti_f32_tiled_equals_simple_kernels():
+    """The tiled TTI step (mixed terms once per unordered pair, intermediates
+    staged per plane) against the one-thread-per-cell step on the same FP32
+    inputs: equal to FP32 rounding for the data, the compressed fields and the
+    gradient.  The fields themselves agree to ~1e-8; u_tt is a second time
+    difference of FP32 levels (about three digits cancel), so Ubar and the
+    gradient carry ~2e-5 and the bar is 5e-5, as for the acoustic FP32 Ubar."""
+    wl, an = synth.workload_tti(shape=(44, 27, 75), nt=70, r=32, sigma=3.0, nb=5, f0=12.0,
+                                rec_stride=4)
+    rng = np.random.default_rng(9)
+    d_obs = (0.05 * rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))).astype(np.float32)
+    plan = _plan(wl, "f32", "bf16x2", k_block=32)
+    args = (plan, dev(wl.m, torch.float32), dev(an, torch.float32), wl.src_pos,
+            dev(wl.q, torch.float32), wl.rec_pos, dev(d_obs, torch.float32),
+            dev(wl.Z, torch.int8))
+    out = {}
+    for v in (0, -1):
+        P.set_stencil_variant(v)
+        try:
+            out[v] = P.fwi_gradient_tti(*args, fused=False)
+            torch.cuda.synchronize()
+        finally:
+            P.set_stencil_variant(-1)
+    e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
+    say("  TTI tiled vs simple (f32): " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    assert e["resid"] < 1e-6 and max(e.values()) < 5e-5
