@@ -19,7 +19,7 @@ EXPORTS = (
     "rtm_adjoint_image", "rtm_set_stencil_blocks", "rtm_autotune_stencil",
     "rtm_batch_create", "rtm_batch_destroy", "rtm_batch_workspace_bytes", "fwi_gradient_batched",
     "rtm_tti_workspace_bytes", "rtm_tti_forward_probe", "rtm_tti_adjoint_probe",
-    "fwi_gradient_tti", "rtm_set_exact_fused",
+    "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape",
 )
 
 
@@ -107,6 +107,8 @@ def load() -> ctypes.CDLL:
     L.fwi_gradient_batched.restype = ctypes.c_int
     L.rtm_set_exact_fused.argtypes = [i32]
     L.rtm_set_exact_fused.restype = None
+    L.rtm_set_tti_shape.argtypes = [i32]
+    L.rtm_set_tti_shape.restype = None
     L.rtm_tti_workspace_bytes.argtypes = [_vp, ctypes.POINTER(sz)]
     L.rtm_tti_workspace_bytes.restype = ctypes.c_int
     L.rtm_tti_forward_probe.argtypes = [_vp, _vp, _vp, _dp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp,

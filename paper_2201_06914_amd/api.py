@@ -459,6 +459,10 @@ def set_exact_fused(on: bool) -> None:
     _lib.load().rtm_set_exact_fused(1 if on else 0)
 
 
+def set_tti_shape(shape: int) -> None:
+    _lib.load().rtm_set_tti_shape(int(shape))
+
+
 def exact_workspace_bytes(plan: Plan, checkpoint_every: int = 0) -> int:
     n = ctypes.c_size_t()
     _check(_lib.load().rtm_exact_workspace_bytes(plan.handle, int(checkpoint_every),

@@ -33,6 +33,7 @@ static thread_local std::string g_last_error;
 static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled variant id
 static int g_stencil_blocks = 1024; // tiled stencil: split z until this many workgroups
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
+static int g_tti_shape = 1;         // tiled TTI tile shape (1..3)
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
@@ -160,6 +161,8 @@ extern "C" void rtm_set_stencil_variant(int v) {
 }
 
 extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
+
+extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 3) ? shape : 1; }
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
   g_stencil_blocks = blocks > 0 ? blocks : 1024;
@@ -1395,8 +1398,10 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
   T *g = coef + 5 * ld;
   auto lv = [&](T *ring, int j) { return ring + (int64_t)((j + 1) % P->R) * ld; };
   StepArgs<T> a = step_args<T>(P, static_cast<const T *>(io.m));
-  // tiled TTI kernels unless the simple stencil is forced
-  const bool tiled = g_stencil_variant != kStencilSimple;
+  // tiled TTI kernels (32-bit offsets: fields below 4 GiB) unless the simple
+  // stencil is forced
+  const int shape = (g_stencil_variant == kStencilSimple || ld * (int64_t)sizeof(T) >= (1LL << 32))
+                        ? 0 : g_tti_shape;
   // the coefficient levels and intermediates use stride ld (>= N)
   HIP_TRY(launch_tti_coef<T>(static_cast<const T *>(io.aniso), N, coef, st));  // [5][N]
   for (T *ring : {ringP, ringQ}) {
@@ -1414,7 +1419,7 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
     TimedLaunch tl;
     prof_begin(KT_TTI, s, st, &tl);
     HIP_TRY(launch_tti_step<T>(a, d.h, io.adjoint, coef, lv(ringP, s), lv(ringP, s - 1),
-                               lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, tiled,
+                               lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, shape,
                                g_stencil_blocks, st));
     prof_end(st, &tl);
     if (inj.ncell > 0 && vals) {

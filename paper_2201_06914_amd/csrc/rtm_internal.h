@@ -135,12 +135,12 @@ hipError_t launch_sample_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
 // p + q (adjoint of injecting into both fields)
 template <typename T>
 hipError_t launch_tti_coef(const T *aniso, int64_t N, T *coef, hipStream_t st);
-// (tiled: 64 x 8 column tiles marching z-chunks, split until target_blocks
-// workgroups; else one thread per cell)
+// (shape 0: one thread per cell; 1..3: column tiles marching z-chunks, split
+// until target_blocks workgroups)
 template <typename T>
 hipError_t launch_tti_step(const StepArgs<T> &a, double h, bool adjoint, const T *coef,
                            const T *p, const T *pp, const T *q, const T *qp, T *pn, T *qn, T *g,
-                           bool tiled, int target_blocks, hipStream_t st);
+                           int shape, int target_blocks, hipStream_t st);
 template <typename T>
 hipError_t launch_sample_sum(const PointTables<T> &pt, const T *f1, const T *f2, T *out,
                              hipStream_t st);

@@ -230,9 +230,9 @@ hipError_t launch_tti_coef(const T *aniso, int64_t N, T *coef, hipStream_t st) {
 template <typename T>
 hipError_t launch_tti_step(const StepArgs<T> &a, double h, bool adjoint, const T *coef,
                            const T *p, const T *pp, const T *q, const T *qp, T *pn, T *qn, T *g,
-                           bool tiled, int target_blocks, hipStream_t st) {
+                           int shape, int target_blocks, hipStream_t st) {
   TtiArgs<T> t = tti_args<T>(a, (T)h, coef, p, pp, q, qp, pn, qn, g);
-  if (tiled) return launch_tti_step_tiled<T>(t, adjoint, target_blocks, st);
+  if (shape > 0) return launch_tti_step_tiled<T>(t, adjoint, shape, target_blocks, st);
   const unsigned nb = cells_grid(a.N);
   if (!adjoint) {
     hipLaunchKernelGGL((k_tti_grad<T>), dim3(nb), dim3(256), 0, st, t);
@@ -259,11 +259,11 @@ template hipError_t launch_tti_coef<float>(const float *, int64_t, float *, hipS
 template hipError_t launch_tti_coef<double>(const double *, int64_t, double *, hipStream_t);
 template hipError_t launch_tti_step<float>(const StepArgs<float> &, double, bool, const float *,
                                            const float *, const float *, const float *,
-                                           const float *, float *, float *, float *, bool, int,
+                                           const float *, float *, float *, float *, int, int,
                                            hipStream_t);
 template hipError_t launch_tti_step<double>(const StepArgs<double> &, double, bool, const double *,
                                             const double *, const double *, const double *,
-                                            const double *, double *, double *, double *, bool,
+                                            const double *, double *, double *, double *, int,
                                             int, hipStream_t);
 template hipError_t launch_sample_sum<float>(const PointTables<float> &, const float *,
                                              const float *, float *, hipStream_t);

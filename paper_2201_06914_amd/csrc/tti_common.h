@@ -36,9 +36,10 @@ inline TtiArgs<T> tti_args(const StepArgs<T> &a, T h, const T *coef, const T *p,
   return t;
 }
 
-// one step with the tiled kernels (tti_tiled.hip); g needs 6 slots of N
+// one step with the tiled kernels (tti_tiled.hip), tile shape 1..3; g needs 6
+// slots of N
 template <typename T>
-hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
+hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st);
 
 }  // namespace rtm

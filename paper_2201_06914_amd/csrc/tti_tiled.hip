@@ -29,58 +29,77 @@ namespace rtm {
 namespace {
 
 constexpr int TX = 64;
-constexpr int TY = 8;
-constexpr int NTHR = TX * TY;  // 512
-constexpr int LX = TX + 8;
-constexpr int LY = TY + 8;
-constexpr int PL = LY * LX;     // one LDS plane
 
-template <typename T>
+// Tile geometry: 64 x TY columns, one thread each; LDS planes of (TY + 8) x 72
+// cells hold the tile with a 4-cell halo along x and y (no corners).
+template <int TY>
+struct Geo {
+  static constexpr int NTHR = TX * TY;
+  static constexpr int LX = TX + 8;
+  static constexpr int LY = TY + 8;
+  static constexpr int PL = LY * LX;  // one LDS plane
+  static constexpr int NHY = 8 / TY;  // y-halo cells per thread (8 rows x 64)
+  static constexpr int NHX = 8 * TY;  // x-halo cells (8 columns x TY rows), one per thread
+};
+
+template <int TY>
 struct TtiTile {
-  int tx, ty, x, y, lc;  // own column, its LDS offset
+  using G = Geo<TY>;
+  int x, y, lc;  // own column and its LDS offset
   bool in;
-  int hyg, hyl;          // y-halo cell: global row, LDS offset (column x)
-  bool hyon;
-  int hxg_y, hxg_x, hxl;  // x-halo cell (threads < 64)
+  int hyg[G::NHY], hyl[G::NHY];  // y-halo cells (column x): global row, LDS offset
+  bool hyon[G::NHY];
+  int hxg_y, hxg_x, hxl;  // x-halo cell (threads < NHX)
   bool hxon;
 };
 
-template <typename T>
-__device__ __forceinline__ TtiTile<T> tile_of(const StepArgs<T> &a, int bx, int by) {
-  TtiTile<T> t;
+template <int TY, typename T>
+__device__ __forceinline__ TtiTile<TY> tile_of(const StepArgs<T> &a, int bx, int by) {
+  using G = Geo<TY>;
+  TtiTile<TY> t;
   const int tid = threadIdx.x;
-  t.tx = tid % TX;
-  t.ty = tid / TX;
+  const int tx = tid % TX, ty = tid / TX;
   const int x0 = bx * TX, y0 = by * TY;
-  t.x = x0 + t.tx;
-  t.y = y0 + t.ty;
+  t.x = x0 + tx;
+  t.y = y0 + ty;
   t.in = t.x < a.nx && t.y < a.ny;
-  t.lc = (t.ty + 4) * LX + t.tx + 4;
-  // 8 halo rows x 64 columns: one per thread
-  const int hr = t.ty < 4 ? t.ty : TY + t.ty;
-  t.hyg = y0 - 4 + hr;
-  t.hyl = hr * LX + t.tx + 4;
-  t.hyon = t.x < a.nx && t.hyg >= 0 && t.hyg < a.ny;
-  // 8 halo columns x 8 rows: threads 0..63
+  t.lc = (ty + 4) * G::LX + tx + 4;
+#pragma unroll
+  for (int k = 0; k < G::NHY; ++k) {
+    const int h = ty + TY * k;                 // 0..7
+    const int hr = h < 4 ? h : TY + h;         // LDS rows 0..3, TY+4..TY+7
+    t.hyg[k] = y0 - 4 + hr;
+    t.hyl[k] = hr * G::LX + tx + 4;
+    t.hyon[k] = t.x < a.nx && t.hyg[k] >= 0 && t.hyg[k] < a.ny;
+  }
   const int r = tid / 8, c = tid % 8;
   const int lcx = c < 4 ? c : TX + c;
   t.hxg_y = y0 + r;
   t.hxg_x = x0 - 4 + lcx;
-  t.hxl = (4 + r) * LX + lcx;
-  t.hxon = tid < 64 && t.hxg_y < a.ny && t.hxg_x >= 0 && t.hxg_x < a.nx;
+  t.hxl = (4 + r) * G::LX + lcx;
+  t.hxon = tid < G::NHX && t.hxg_y < a.ny && t.hxg_x >= 0 && t.hxg_x < a.nx;
   return t;
 }
 
 template <typename T>
-__device__ __forceinline__ int64_t cidx(const StepArgs<T> &a, int z, int y, int x) {
-  return ((int64_t)z * a.ny + y) * a.nx + x;
+__device__ __forceinline__ uint32_t cidx(const StepArgs<T> &a, int z, int y, int x) {
+  return (((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x) *
+         (uint32_t)sizeof(T);
+}
+template <typename T>
+__device__ __forceinline__ T ldo(const T *f, uint32_t o) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(f) + o);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *f, uint32_t o, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(f) + o) = v;
 }
 
 // field value at (z, y, x) of a column known to lie inside the x-y range; zero
 // for planes outside the grid
 template <typename T>
 __device__ __forceinline__ T ldz(const T *f, const StepArgs<T> &a, bool on, int z, int y, int x) {
-  return (on && z >= 0 && z < a.nz) ? f[cidx(a, z, y, x)] : T(0);
+  return (on && z >= 0 && z < a.nz) ? ldo(f, cidx(a, z, y, x)) : T(0);
 }
 
 // first difference from a 9-value window centred at w[4] (w[4] unused)
@@ -143,21 +162,25 @@ __device__ __forceinline__ void block_of(int ntx, int nty, int nzc, int zchunk, 
 // ---------------------------------------------------------------------------
 // forward, in-plane: g0 = D_x p, g1 = D_y p, g2 = D_x q, g3 = D_y q
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(NTHR) void k_tti_fprep(TtiArgs<T> t, int ntx, int nty, int nzc,
-                                                    int zchunk) {
+template <typename T, int TY, int MINW>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_fprep(TtiArgs<T> t, int ntx, int nty,
+                                                            int nzc, int zchunk) {
+  using G = Geo<TY>;
   const StepArgs<T> &a = t.a;
   int bx, by, z0, z1;
   block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
-  const TtiTile<T> g = tile_of(a, bx, by);
-  __shared__ T L[2][2][PL];  // [buffer][p, q]
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
+  __shared__ T L[2][2][G::PL];  // [buffer][p, q]
   const int64_t N = a.N;
-  T cp, cq, yp, yq, xp, xq;
+  T cp, cq, yp[G::NHY], yq[G::NHY], xp, xq;
   auto fetch = [&](int z) {
     cp = ldz(t.p, a, g.in, z, g.y, g.x);
     cq = ldz(t.q, a, g.in, z, g.y, g.x);
-    yp = ldz(t.p, a, g.hyon, z, g.hyg, g.x);
-    yq = ldz(t.q, a, g.hyon, z, g.hyg, g.x);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      yp[k] = ldz(t.p, a, g.hyon[k], z, g.hyg[k], g.x);
+      yq[k] = ldz(t.q, a, g.hyon[k], z, g.hyg[k], g.x);
+    }
     xp = ldz(t.p, a, g.hxon, z, g.hxg_y, g.hxg_x);
     xq = ldz(t.q, a, g.hxon, z, g.hxg_y, g.hxg_x);
   };
@@ -166,20 +189,23 @@ __global__ __launch_bounds__(NTHR) void k_tti_fprep(TtiArgs<T> t, int ntx, int n
     T *Lp = L[z & 1][0], *Lq = L[z & 1][1];
     Lp[g.lc] = cp;
     Lq[g.lc] = cq;
-    Lp[g.hyl] = yp;
-    Lq[g.hyl] = yq;
-    if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      Lp[g.hyl[k]] = yp[k];
+      Lq[g.hyl[k]] = yq[k];
+    }
+    if (threadIdx.x < G::NHX) {
       Lp[g.hxl] = xp;
       Lq[g.hxl] = xq;
     }
     if (z + 1 < z1) fetch(z + 1);
     __syncthreads();
     if (g.in) {
-      const int64_t o = cidx(a, z, g.y, g.x);
-      t.g[o] = d1l(t, Lp + g.lc, 1);
-      t.g[N + o] = d1l(t, Lp + g.lc, LX);
-      t.g[2 * N + o] = d1l(t, Lq + g.lc, 1);
-      t.g[3 * N + o] = d1l(t, Lq + g.lc, LX);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      sto(t.g, o, d1l(t, Lp + g.lc, 1));
+      sto(t.g + N, o, d1l(t, Lp + g.lc, G::LX));
+      sto(t.g + 2 * N, o, d1l(t, Lq + g.lc, 1));
+      sto(t.g + 3 * N, o, d1l(t, Lq + g.lc, G::LX));
     }
   }
 }
@@ -187,14 +213,15 @@ __global__ __launch_bounds__(NTHR) void k_tti_fprep(TtiArgs<T> t, int ntx, int n
 // ---------------------------------------------------------------------------
 // forward, z-march
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int nty, int nzc,
-                                                     int zchunk) {
+template <typename T, int TY, int MINW>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_fmarch(TtiArgs<T> t, int ntx, int nty,
+                                                             int nzc, int zchunk) {
+  using G = Geo<TY>;
   const StepArgs<T> &a = t.a;
   int bx, by, z0, z1;
   block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
-  const TtiTile<T> g = tile_of(a, bx, by);
-  __shared__ T L[2][4][PL];  // [buffer][p, q, D_y p, D_y q]
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
+  __shared__ T L[2][4][G::PL];  // [buffer][p, q, D_y p, D_y q]
   const int64_t N = a.N;
   const T *Gxp = t.g, *Gyp = t.g + N, *Gxq = t.g + 2 * N, *Gyq = t.g + 3 * N;
   // z queues of the own column: p, q, D_x p, D_y p, D_x q, D_y q
@@ -210,7 +237,7 @@ __global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int 
     Qyq[k] = ldz(Gyq, a, g.in, zz, g.y, g.x);
   }
   // plane values: previous levels, m, coefficients; halos of p, q, D_y p, D_y q
-  T pp, qp, mm, c1, c2, nz, ny, nx, yp, yq, xp, xq, xgp, xgq;
+  T pp, qp, mm, c1, c2, nz, ny, nx, yp[G::NHY], yq[G::NHY], xp, xq, xgp, xgq;
   auto fetch = [&](int z) {
     const int zf = z + 4;
     f[0] = ldz(t.p, a, g.in, zf, g.y, g.x);
@@ -227,8 +254,11 @@ __global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int 
     nz = ldz(t.coef + 2 * N, a, g.in, z, g.y, g.x);
     ny = ldz(t.coef + 3 * N, a, g.in, z, g.y, g.x);
     nx = ldz(t.coef + 4 * N, a, g.in, z, g.y, g.x);
-    yp = ldz(t.p, a, g.hyon, z, g.hyg, g.x);
-    yq = ldz(t.q, a, g.hyon, z, g.hyg, g.x);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      yp[k] = ldz(t.p, a, g.hyon[k], z, g.hyg[k], g.x);
+      yq[k] = ldz(t.q, a, g.hyon[k], z, g.hyg[k], g.x);
+    }
     xp = ldz(t.p, a, g.hxon, z, g.hxg_y, g.hxg_x);
     xq = ldz(t.q, a, g.hxon, z, g.hxg_y, g.hxg_x);
     xgp = ldz(Gyp, a, g.hxon, z, g.hxg_y, g.hxg_x);
@@ -248,9 +278,12 @@ __global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int 
     Lq[g.lc] = Qq[4];
     Lyp[g.lc] = Qyp[4];
     Lyq[g.lc] = Qyq[4];
-    Lp[g.hyl] = yp;
-    Lq[g.hyl] = yq;
-    if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      Lp[g.hyl[k]] = yp[k];
+      Lq[g.hyl[k]] = yq[k];
+    }
+    if (threadIdx.x < G::NHX) {
       Lp[g.hxl] = xp;
       Lq[g.hxl] = xq;
       Lyp[g.hxl] = xgp;
@@ -261,7 +294,7 @@ __global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int 
     if (g.in) {
       const T pzz = d2q(t, Qp), qzz = d2q(t, Qq);
       const T pxx = d2l(t, Lp + g.lc, 1), qxx = d2l(t, Lq + g.lc, 1);
-      const T pyy = d2l(t, Lp + g.lc, LX), qyy = d2l(t, Lq + g.lc, LX);
+      const T pyy = d2l(t, Lp + g.lc, G::LX), qyy = d2l(t, Lq + g.lc, G::LX);
       const T pxy = d1l(t, Lyp + g.lc, 1), qxy = d1l(t, Lyq + g.lc, 1);
       const T pxz = d1q(t, Qxp), qxz = d1q(t, Qxq);
       const T pyz = d1q(t, Qyp), qyz = d1q(t, Qyq);
@@ -272,9 +305,9 @@ __global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int 
       const T hzq = ((cnz * cnz) * qzz + (cny * cny) * qyy + (cnx * cnx) * qxx) + T(2) * mix_q;
       const T h0p = lp - hzp;
       const T damp = sponge_a(a, z, g.y, g.x);
-      const int64_t o = cidx(a, z, g.y, g.x);
-      t.pn[o] = tti_update(a, Qp[4], cpp, cm, cc1 * h0p + cc2 * hzq, damp);
-      t.qn[o] = tti_update(a, Qq[4], cqp, cm, cc2 * h0p + hzq, damp);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      sto(t.pn, o, tti_update(a, Qp[4], cpp, cm, cc1 * h0p + cc2 * hzq, damp));
+      sto(t.qn, o, tti_update(a, Qq[4], cqp, cm, cc2 * h0p + hzq, damp));
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -292,16 +325,17 @@ __global__ __launch_bounds__(NTHR) void k_tti_fmarch(TtiArgs<T> t, int ntx, int 
 // adjoint, in-plane: g0 = w1, g1 = w2, g2 = E_xz(w1), g3 = E_xz(w2),
 // g4 = E_xy(w1), g5 = E_xy(w2)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(NTHR) void k_tti_aprep(TtiArgs<T> t, int ntx, int nty, int nzc,
-                                                    int zchunk) {
+template <typename T, int TY, int MINW>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_aprep(TtiArgs<T> t, int ntx, int nty,
+                                                            int nzc, int zchunk) {
+  using G = Geo<TY>;
   const StepArgs<T> &a = t.a;
   int bx, by, z0, z1;
   block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
-  const TtiTile<T> g = tile_of(a, bx, by);
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
   // [buffer][X1, X2, Y1, Y2, XY1, XY2]: X = n_x n_z w (x taps), Y = n_y n_z w and
   // XY = n_x n_y w (y taps)
-  __shared__ T L[2][6][PL];
+  __shared__ T L[2][6][G::PL];
   const int64_t N = a.N;
   const T *c1f = t.coef, *c2f = t.coef + N, *nzf = t.coef + 2 * N, *nyf = t.coef + 3 * N,
           *nxf = t.coef + 4 * N;
@@ -319,15 +353,16 @@ __global__ __launch_bounds__(NTHR) void k_tti_aprep(TtiArgs<T> t, int ntx, int n
     c.nx = ldz(nxf, a, on, z, y, x);
     return c;
   };
-  Cell cc, cy, cx;
+  Cell cc, cy[G::NHY], cx;
   auto fetch = [&](int z) {
     cc = load(g.in, z, g.y, g.x);
-    cy = load(g.hyon, z, g.hyg, g.x);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) cy[k] = load(g.hyon[k], z, g.hyg[k], g.x);
     cx = load(g.hxon, z, g.hxg_y, g.hxg_x);
   };
   fetch(z0);
   for (int z = z0; z < z1; ++z) {
-    T(*B)[PL] = L[z & 1];
+    T(*B)[G::PL] = L[z & 1];
     const T w1 = cc.c1 * cc.lp + cc.c2 * cc.lq;
     const T w2 = cc.c2 * cc.lp + cc.lq;
     B[0][g.lc] = (cc.nx * cc.nz) * w1;
@@ -336,14 +371,16 @@ __global__ __launch_bounds__(NTHR) void k_tti_aprep(TtiArgs<T> t, int ntx, int n
     B[3][g.lc] = (cc.ny * cc.nz) * w2;
     B[4][g.lc] = (cc.nx * cc.ny) * w1;
     B[5][g.lc] = (cc.nx * cc.ny) * w2;
-    {
-      const T v1 = cy.c1 * cy.lp + cy.c2 * cy.lq, v2 = cy.c2 * cy.lp + cy.lq;
-      B[2][g.hyl] = (cy.ny * cy.nz) * v1;
-      B[3][g.hyl] = (cy.ny * cy.nz) * v2;
-      B[4][g.hyl] = (cy.nx * cy.ny) * v1;
-      B[5][g.hyl] = (cy.nx * cy.ny) * v2;
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      const Cell &h = cy[k];
+      const T v1 = h.c1 * h.lp + h.c2 * h.lq, v2 = h.c2 * h.lp + h.lq;
+      B[2][g.hyl[k]] = (h.ny * h.nz) * v1;
+      B[3][g.hyl[k]] = (h.ny * h.nz) * v2;
+      B[4][g.hyl[k]] = (h.nx * h.ny) * v1;
+      B[5][g.hyl[k]] = (h.nx * h.ny) * v2;
     }
-    if (threadIdx.x < 64) {
+    if (threadIdx.x < G::NHX) {
       const T v1 = cx.c1 * cx.lp + cx.c2 * cx.lq, v2 = cx.c2 * cx.lp + cx.lq;
       B[0][g.hxl] = (cx.nx * cx.nz) * v1;
       B[1][g.hxl] = (cx.nx * cx.nz) * v2;
@@ -351,13 +388,13 @@ __global__ __launch_bounds__(NTHR) void k_tti_aprep(TtiArgs<T> t, int ntx, int n
     if (z + 1 < z1) fetch(z + 1);
     __syncthreads();
     if (g.in) {
-      const int64_t o = cidx(a, z, g.y, g.x);
-      t.g[o] = w1;
-      t.g[N + o] = w2;
-      t.g[2 * N + o] = d1l(t, B[0] + g.lc, 1) + d1l(t, B[2] + g.lc, LX);
-      t.g[3 * N + o] = d1l(t, B[1] + g.lc, 1) + d1l(t, B[3] + g.lc, LX);
-      t.g[4 * N + o] = d1l(t, B[4] + g.lc, LX);
-      t.g[5 * N + o] = d1l(t, B[5] + g.lc, LX);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      sto(t.g, o, w1);
+      sto(t.g + N, o, w2);
+      sto(t.g + 2 * N, o, d1l(t, B[0] + g.lc, 1) + d1l(t, B[2] + g.lc, G::LX));
+      sto(t.g + 3 * N, o, d1l(t, B[1] + g.lc, 1) + d1l(t, B[3] + g.lc, G::LX));
+      sto(t.g + 4 * N, o, d1l(t, B[4] + g.lc, G::LX));
+      sto(t.g + 5 * N, o, d1l(t, B[5] + g.lc, G::LX));
     }
   }
 }
@@ -366,15 +403,16 @@ __global__ __launch_bounds__(NTHR) void k_tti_aprep(TtiArgs<T> t, int ntx, int n
 // adjoint, z-march:
 //   rhs_p = L w1 - HzT w1,  rhs_q = HzT w2
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int nty, int nzc,
-                                                     int zchunk) {
+template <typename T, int TY, int MINW>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_amarch(TtiArgs<T> t, int ntx, int nty,
+                                                             int nzc, int zchunk) {
+  using G = Geo<TY>;
   const StepArgs<T> &a = t.a;
   int bx, by, z0, z1;
   block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
-  const TtiTile<T> g = tile_of(a, bx, by);
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
   // [buffer][w1, n_x^2 w1, n_y^2 w1, n_x^2 w2, n_y^2 w2, E_xy(w1), E_xy(w2)]
-  __shared__ T L[2][7][PL];
+  __shared__ T L[2][7][G::PL];
   const int64_t N = a.N;
   const T *nzf = t.coef + 2 * N, *nyf = t.coef + 3 * N, *nxf = t.coef + 4 * N;
   const T *W1 = t.g, *W2 = t.g + N, *Exz1 = t.g + 2 * N, *Exz2 = t.g + 3 * N,
@@ -403,7 +441,7 @@ __global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int 
   }
   // plane values of the own cell and the halo cells
   T lp, lq, lpp, lqp, mm, w2c, nxc, nyc, e1c, e2c;
-  T hy_w1, hy_w2, hy_ny;                      // y-halo
+  T hy_w1[G::NHY], hy_w2[G::NHY], hy_ny[G::NHY];  // y-halo
   T hx_w1, hx_w2, hx_nx, hx_e1, hx_e2;        // x-halo
   auto fetch = [&](int z) {
     front(z + 4, f);
@@ -417,9 +455,12 @@ __global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int 
     nyc = ldz(nyf, a, g.in, z, g.y, g.x);
     e1c = ldz(Exy1, a, g.in, z, g.y, g.x);
     e2c = ldz(Exy2, a, g.in, z, g.y, g.x);
-    hy_w1 = ldz(W1, a, g.hyon, z, g.hyg, g.x);
-    hy_w2 = ldz(W2, a, g.hyon, z, g.hyg, g.x);
-    hy_ny = ldz(nyf, a, g.hyon, z, g.hyg, g.x);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      hy_w1[k] = ldz(W1, a, g.hyon[k], z, g.hyg[k], g.x);
+      hy_w2[k] = ldz(W2, a, g.hyon[k], z, g.hyg[k], g.x);
+      hy_ny[k] = ldz(nyf, a, g.hyon[k], z, g.hyg[k], g.x);
+    }
     hx_w1 = ldz(W1, a, g.hxon, z, g.hxg_y, g.hxg_x);
     hx_w2 = ldz(W2, a, g.hxon, z, g.hxg_y, g.hxg_x);
     hx_nx = ldz(nxf, a, g.hxon, z, g.hxg_y, g.hxg_x);
@@ -434,7 +475,7 @@ __global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int 
     Qe1[8] = f[3];
     Qe2[8] = f[4];
     const T clp = lp, clq = lq, clpp = lpp, clqp = lqp, cm = mm;
-    T(*B)[PL] = L[z & 1];
+    T(*B)[G::PL] = L[z & 1];
     {
       const T w1 = Qw[4];
       B[0][g.lc] = w1;
@@ -445,10 +486,13 @@ __global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int 
       B[5][g.lc] = e1c;
       B[6][g.lc] = e2c;
     }
-    B[0][g.hyl] = hy_w1;
-    B[2][g.hyl] = (hy_ny * hy_ny) * hy_w1;
-    B[4][g.hyl] = (hy_ny * hy_ny) * hy_w2;
-    if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      B[0][g.hyl[k]] = hy_w1[k];
+      B[2][g.hyl[k]] = (hy_ny[k] * hy_ny[k]) * hy_w1[k];
+      B[4][g.hyl[k]] = (hy_ny[k] * hy_ny[k]) * hy_w2[k];
+    }
+    if (threadIdx.x < G::NHX) {
       B[0][g.hxl] = hx_w1;
       B[1][g.hxl] = (hx_nx * hx_nx) * hx_w1;
       B[3][g.hxl] = (hx_nx * hx_nx) * hx_w2;
@@ -458,15 +502,15 @@ __global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int 
     if (z + 1 < z1) fetch(z + 1);
     __syncthreads();
     if (g.in) {
-      const T lw1 = (d2q(t, Qw) + d2l(t, B[0] + g.lc, LX)) + d2l(t, B[0] + g.lc, 1);
-      const T hz1 = ((d2q(t, Qz1) + d2l(t, B[2] + g.lc, LX)) + d2l(t, B[1] + g.lc, 1)) +
+      const T lw1 = (d2q(t, Qw) + d2l(t, B[0] + g.lc, G::LX)) + d2l(t, B[0] + g.lc, 1);
+      const T hz1 = ((d2q(t, Qz1) + d2l(t, B[2] + g.lc, G::LX)) + d2l(t, B[1] + g.lc, 1)) +
                     T(2) * (d1l(t, B[5] + g.lc, 1) + d1q(t, Qe1));
-      const T hz2 = ((d2q(t, Qz2) + d2l(t, B[4] + g.lc, LX)) + d2l(t, B[3] + g.lc, 1)) +
+      const T hz2 = ((d2q(t, Qz2) + d2l(t, B[4] + g.lc, G::LX)) + d2l(t, B[3] + g.lc, 1)) +
                     T(2) * (d1l(t, B[6] + g.lc, 1) + d1q(t, Qe2));
       const T damp = sponge_a(a, z, g.y, g.x);
-      const int64_t o = cidx(a, z, g.y, g.x);
-      t.pn[o] = tti_update(a, clp, clpp, cm, lw1 - hz1, damp);
-      t.qn[o] = tti_update(a, clq, clqp, cm, hz2, damp);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      sto(t.pn, o, tti_update(a, clp, clpp, cm, lw1 - hz1, damp));
+      sto(t.qn, o, tti_update(a, clq, clqp, cm, hz2, damp));
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -481,8 +525,8 @@ __global__ __launch_bounds__(NTHR) void k_tti_amarch(TtiArgs<T> t, int ntx, int 
 
 // one TTI step with the tiled kernels; g needs 4 (forward) / 6 (adjoint) slots
 // of N
-template <typename T>
-hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
+template <typename T, int TY, int MINW>
+static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
   const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
@@ -490,19 +534,32 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
   while (ntx * nty * nzc < target_blocks && a.nz / (nzc * 2) >= 16) nzc *= 2;
   const int zchunk = (a.nz + nzc - 1) / nzc;
   nzc = (a.nz + zchunk - 1) / zchunk;
-  const dim3 grid(ntx * nty * nzc), blk(NTHR);
+  const dim3 grid(ntx * nty * nzc), blk(TX * TY);
   if (!adjoint) {
-    hipLaunchKernelGGL((k_tti_fprep<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
-    hipLaunchKernelGGL((k_tti_fmarch<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_fprep<T, TY, 1>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_fmarch<T, TY, MINW>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
   } else {
-    hipLaunchKernelGGL((k_tti_aprep<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
-    hipLaunchKernelGGL((k_tti_amarch<T>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_aprep<T, TY, 1>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_amarch<T, TY, MINW>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
   }
   return hipGetLastError();
 }
 
-template hipError_t launch_tti_step_tiled<float>(const TtiArgs<float> &, bool, int, hipStream_t);
-template hipError_t launch_tti_step_tiled<double>(const TtiArgs<double> &, bool, int,
+// tile shapes: 1 = 64 x 8 (512 threads), 2 = 64 x 8 held to 128 VGPRs (two
+// workgroups per CU), 3 = 64 x 4 (256 threads)
+template <typename T>
+hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
+                                 hipStream_t st) {
+  switch (shape) {
+    case 2: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
+    case 3: return tti_step_tiled<T, 4, 1>(t, adjoint, target_blocks, st);
+    default: return tti_step_tiled<T, 8, 1>(t, adjoint, target_blocks, st);
+  }
+}
+
+template hipError_t launch_tti_step_tiled<float>(const TtiArgs<float> &, bool, int, int,
+                                                 hipStream_t);
+template hipError_t launch_tti_step_tiled<double>(const TtiArgs<double> &, bool, int, int,
                                                   hipStream_t);
 
 }  // namespace rtm

@@ -30,17 +30,23 @@ def _rows(plan, bar2):
 
 @pytest.fixture
 def variant(request):
-    """Stencil variant for the test's duration: -1 lets the library pick (the
-    tiled TTI kernels), 0 forces the one-thread-per-cell kernels."""
-    P.set_stencil_variant(request.param)
+    """(stencil variant, TTI tile shape) for the test's duration: variant -1
+    lets the library pick (the tiled TTI kernels, in the given tile shape), 0
+    forces the one-thread-per-cell kernels."""
+    v, sh = request.param
+    P.set_stencil_variant(v)
+    P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
+    P.set_tti_shape(1)
 
 
-@pytest.mark.parametrize("variant,shape", [(-1, (18, 16, 20)), (0, (18, 16, 20)),
-                                           (-1, (40, 21, 70))], indirect=["variant"])
+@pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
+                                           ((-1, 1), (40, 21, 70)), ((-1, 2), (40, 21, 70)),
+                                           ((-1, 3), (40, 21, 70))], indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
-    """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels."""
+    """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
+    (64 x 8 and 64 x 4 columns)."""
     wl, an = synth.workload_tti(shape=shape, nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
                                 rec_stride=7, dtype=np.float64)
     g = Grid.of(wl)
