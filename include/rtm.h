@@ -227,11 +227,11 @@ rtm_status rtm_exact_workspace_bytes(const rtm_plan *plan, int32_t checkpoint_ev
  * runs them as separate passes.  Results agree to rounding at the injected
  * cells. */
 void rtm_set_exact_fused(int32_t on);
-/* Tuning hook, process wide: tile shape of the tiled TTI step kernels,
- * 1 (default) 64 x 8 columns, 2 the same held to 128 VGPRs (two workgroups per
- * CU), 3 64 x 4 columns; other values select 1.  rtm_set_stencil_variant(0)
- * forces the one-thread-per-cell TTI kernels instead.  Results agree to
- * rounding. */
+/* Tuning hook, process wide: tile shape of the tiled TTI step kernels, as
+ * rows of 64 columns for the in-plane pass / the z-marching pass: 1 = 8 / 8,
+ * 2 = 4 / 4, 3 = 8 / 4 (default); other values select 3.
+ * rtm_set_stencil_variant(0) forces the one-thread-per-cell TTI kernels
+ * instead.  Results agree to rounding. */
 void rtm_set_tti_shape(int32_t shape);
 rtm_status fwi_gradient_exact(const rtm_plan *plan, const void *m, const double *src_pos,
                               const void *q, const double *rec_pos, const void *d_obs,

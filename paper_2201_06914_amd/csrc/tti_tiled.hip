@@ -523,37 +523,55 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_amarch(TtiArgs<T> t, int n
   }
 }
 
-// one TTI step with the tiled kernels; g needs 4 (forward) / 6 (adjoint) slots
-// of N
-template <typename T, int TY, int MINW>
+// grid of one tiled launch: (64 x ty) column tiles, z split in chunks until
+// target_blocks workgroups (chunks of at least 16 planes)
+struct TtiGrid {
+  int ntx, nty, nzc, zchunk;
+};
+static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
+  TtiGrid g;
+  g.ntx = (nx + TX - 1) / TX;
+  g.nty = (ny + ty - 1) / ty;
+  int nzc = 1;
+  while (g.ntx * g.nty * nzc < target_blocks && nz / (nzc * 2) >= 16) nzc *= 2;
+  g.zchunk = (nz + nzc - 1) / nzc;
+  g.nzc = (nz + g.zchunk - 1) / g.zchunk;
+  return g;
+}
+
+// one TTI step with the tiled kernels (prep with TYP rows, march with TYM
+// rows); g needs 4 (forward) / 6 (adjoint) slots of N
+template <typename T, int TYP, int TYM>
 static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
-  const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
-  int nzc = 1;
-  while (ntx * nty * nzc < target_blocks && a.nz / (nzc * 2) >= 16) nzc *= 2;
-  const int zchunk = (a.nz + nzc - 1) / nzc;
-  nzc = (a.nz + zchunk - 1) / zchunk;
-  const dim3 grid(ntx * nty * nzc), blk(TX * TY);
+  const TtiGrid gp = tti_grid(a.nz, a.ny, a.nx, TYP, target_blocks);
+  const TtiGrid gm = tti_grid(a.nz, a.ny, a.nx, TYM, target_blocks);
+  const dim3 bp(TX * TYP), bm(TX * TYM);
+  const dim3 np(gp.ntx * gp.nty * gp.nzc), nm(gm.ntx * gm.nty * gm.nzc);
   if (!adjoint) {
-    hipLaunchKernelGGL((k_tti_fprep<T, TY, 1>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
-    hipLaunchKernelGGL((k_tti_fmarch<T, TY, MINW>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_fprep<T, TYP, 1>), np, bp, 0, st, t, gp.ntx, gp.nty, gp.nzc,
+                       gp.zchunk);
+    hipLaunchKernelGGL((k_tti_fmarch<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
+                       gm.zchunk);
   } else {
-    hipLaunchKernelGGL((k_tti_aprep<T, TY, 1>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
-    hipLaunchKernelGGL((k_tti_amarch<T, TY, MINW>), grid, blk, 0, st, t, ntx, nty, nzc, zchunk);
+    hipLaunchKernelGGL((k_tti_aprep<T, TYP, 1>), np, bp, 0, st, t, gp.ntx, gp.nty, gp.nzc,
+                       gp.zchunk);
+    hipLaunchKernelGGL((k_tti_amarch<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
+                       gm.zchunk);
   }
   return hipGetLastError();
 }
 
-// tile shapes: 1 = 64 x 8 (512 threads), 2 = 64 x 8 held to 128 VGPRs (two
-// workgroups per CU), 3 = 64 x 4 (256 threads)
+// tile shapes (prep / march rows of 64 columns): 1 = 8 / 8, 2 = 4 / 4,
+// 3 = 8 / 4 (default)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
   switch (shape) {
-    case 2: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
-    case 3: return tti_step_tiled<T, 4, 1>(t, adjoint, target_blocks, st);
-    default: return tti_step_tiled<T, 8, 1>(t, adjoint, target_blocks, st);
+    case 1: return tti_step_tiled<T, 8, 8>(t, adjoint, target_blocks, st);
+    case 2: return tti_step_tiled<T, 4, 4>(t, adjoint, target_blocks, st);
+    default: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
   }
 }
 

@@ -38,7 +38,7 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(1)
+    P.set_tti_shape(3)
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
@@ -46,7 +46,7 @@ def variant(request):
                                            ((-1, 3), (40, 21, 70))], indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
-    (64 x 8 and 64 x 4 columns)."""
+    (tile shapes 1..3: 64 x 8 and 64 x 4 columns)."""
     wl, an = synth.workload_tti(shape=shape, nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
                                 rec_stride=7, dtype=np.float64)
     g = Grid.of(wl)
