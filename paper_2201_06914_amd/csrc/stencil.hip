@@ -269,9 +269,11 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
   constexpr int TY = TYT * RY;
   const int ntx = (a.nx + TX - 1) / TX;
   const int nty = (a.ny + TY - 1) / TY;
-  // split z so that the launch has at least target_blocks workgroups
+  // split z so that the launch has at least target_blocks workgroups of 256
+  // threads' worth (fewer, larger workgroups for the 512 / 1024 thread shapes)
+  const int64_t want = (int64_t)target_blocks * 256 / (TX * TYT);
   int nzc = 1;
-  while ((int64_t)ntx * nty * nzc < target_blocks && a.nz / (nzc * 2) >= 16) nzc *= 2;
+  while ((int64_t)ntx * nty * nzc < want && a.nz / (nzc * 2) >= 16) nzc *= 2;
   const int zchunk = (a.nz + nzc - 1) / nzc;
   nzc = (a.nz + zchunk - 1) / zchunk;
   hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT, EPI>), dim3(ntx * nty * nzc),
@@ -282,6 +284,9 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
 //   1: 64 x 16 (4 x 4)    2: 64 x 32 (4 x 8)    3: 64 x 16 (8 x 2, 512 thr)
 //   4: 64 x 16 (2 x 8, 128 thr)    5: 32 x 32 (8 x 4)    6: 128 x 8 (2 x 4)
 //   7: as 1, non-temporal          8: as 2, non-temporal
+//   9: 64 x 32 (8 x 4, 512 thr), non-temporal
+//  10: 64 x 32 (16 x 2, 1024 thr), non-temporal
+//  11: as 3, non-temporal
 template <typename T>
 hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
                           hipStream_t st) {
@@ -295,6 +300,9 @@ hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int targe
         case 6: launch_tiled<T, 128, 2, 4, false>(a, target_blocks, st); break;
         case 7: launch_tiled<T, 64, 4, 4, true>(a, target_blocks, st); break;
         case 8: launch_tiled<T, 64, 4, 8, true>(a, target_blocks, st); break;
+        case 9: launch_tiled<T, 64, 8, 4, true>(a, target_blocks, st); break;
+        case 10: launch_tiled<T, 64, 16, 2, true>(a, target_blocks, st); break;
+        case 11: launch_tiled<T, 64, 8, 2, true>(a, target_blocks, st); break;
         default: launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st); break;
       }
     } else {
@@ -481,7 +489,14 @@ hipError_t launch_stencil_batched(const ShotStep<T> *shots, const int4 *tiles, i
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 8, 2, false>), dim3(ntiles), dim3(512), 0,
                            st, shots, tiles, ntiles, s);
         break;
+      case 11:
+        hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 8, 2, true>), dim3(ntiles), dim3(512), 0,
+                           st, shots, tiles, ntiles, s);
+        break;
       case 7:
+      case 8:
+      case 9:
+      case 10:  // 64 x 32 variants run the 64 x 16 tile table with the variant 7 kernel
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, true>), dim3(ntiles), dim3(256), 0,
                            st, shots, tiles, ntiles, s);
         break;
