@@ -121,23 +121,24 @@ double rtm_cfl_bound(int32_t ndim);
 const char *rtm_status_str(rtm_status s);
 /* Tuning hooks, process wide: stencil kernel of the sweeps.  -1 automatic
  * (LDS-tiled 64 x 16 for F32 3D grids, else one thread per cell), 0 one
- * thread per cell, 1..11 LDS-tiled z-marching variants (3D; x-width x y-rows):
+ * thread per cell, 1..13 LDS-tiled z-marching variants (3D; x-width x y-rows):
  * 1: 64x16, 2: 64x32, 3: 64x16 with 512 threads, 4: 64x16 with 128 threads,
  * 5: 32x32, 6: 128x8, 7: as 1 and 8: as 2 with non-temporal streaming loads
  * and stores, 9: 64x32 with 512 threads, 10: 64x32 with 1024 threads,
- * 11: as 3 (all three non-temporal).  Every choice gives bitwise-identical
- * levels.  Batched shots run the 64x16 variants 3, 11 or 7 (variants 8..10
- * select 7, the others 1).
+ * 11: as 3 (all three non-temporal), 12: as 7 and 13: as 9 with the x/y halo
+ * of a plane loaded four planes ahead, with the column fronts.  Every choice
+ * gives bitwise-identical levels.  Batched shots run the 64x16 variants 3,
+ * 11, 7 or 12 (8..10 select 7, 13 selects 12, the others 1).
  * rtm_set_stencil_blocks: the tiled kernels split z until a launch has at
  * least this many workgroups of 256 threads' worth (default 1024; a 512
  * thread shape aims at half as many). */
 void rtm_set_stencil_variant(int variant);
 void rtm_set_stencil_blocks(int32_t blocks);
 /* Autotuner and race check for the stencil: runs one step of every variant
- * (0..11 in 3D, 0 in 2D) from the same pattern levels in the ring of `work`,
+ * (0..13 in 3D, 0 in 2D) from the same pattern levels in the ring of `work`,
  * counts elements that differ bitwise from variant 0 (mismatch[v]), times
  * `steps` launches of each (us[v], microseconds per launch; us and mismatch
- * may be NULL or hold 12 entries) and returns in *best the fastest variant
+ * may be NULL or hold 14 entries) and returns in *best the fastest variant
  * with no mismatch.  It does not change the current variant.  Needs
  * k_block >= 2; synchronises `stream`. */
 rtm_status rtm_autotune_stencil(const rtm_plan *plan, const void *m, void *work,

@@ -207,7 +207,7 @@ def set_stencil_variant(v: int) -> None:
     _lib.load().rtm_set_stencil_variant(int(v))
 
 
-N_STENCIL_VARIANTS = 12
+N_STENCIL_VARIANTS = 14
 
 
 def set_stencil_blocks(blocks: int) -> None:

@@ -196,6 +196,6 @@ constexpr int kReduceBlocks = 1024;  // partial sums of the two-pass reductions
 // give bitwise-identical levels.
 constexpr int kStencilSimple = 0;
 constexpr int kStencilTiled = 1;     // first LDS-tiled variant
-constexpr int kStencilVariants = 11;  // last variant id
+constexpr int kStencilVariants = 13;  // last variant id
 
 }  // namespace rtm

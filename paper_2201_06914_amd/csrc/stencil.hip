@@ -85,7 +85,11 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
 // cell-local epilogue for the exact comparator: EPI_D2 writes the second time
 // difference of the step, EPI_CORR subtracts (stored u_tt) x (new level) from
 // a gradient.
-template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE>
+// EH (early halo): the x/y halo of plane z is loaded together with the
+// column fronts of plane z (four planes ahead of its use) and held in a short
+// register queue, so that a tile's halo loads and its neighbours' interior
+// loads of the same plane are issued close together in time (L2 reuse).
+template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE, bool EH = false>
 __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by, int z0, int z1,
                                            const EpiArgs<T> &e = EpiArgs<T>{}) {
   constexpr int NTH = TX * TYT;
@@ -154,10 +158,22 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
       eg[j] = in[j] ? e.g[o] : T(0);
     }
   }
+  // halo of one plane into hy / hx
+  auto ldhalo = [&](int zz, T *hy, T *hx) {
 #pragma unroll
-  for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z0, hyg[k], x) : T(0);
+    for (int k = 0; k < NHY; ++k) hy[k] = hyon[k] ? ldu(zz, hyg[k], x) : T(0);
 #pragma unroll
-  for (int k = 0; k < NHX; ++k) hxv[k] = hxon[k] ? ldu(z0, y0 - 4 + hxr[k], x0 - 4 + hxc[k]) : T(0);
+    for (int k = 0; k < NHX; ++k) hx[k] = hxon[k] ? ldu(zz, y0 - 4 + hxr[k], x0 - 4 + hxc[k]) : T(0);
+  };
+  constexpr int HQ = EH ? 4 : 1;  // early halo: planes z+1..z+4 queued, z+5 in flight
+  T hqy[HQ][NHY], hqx[HQ][NHX];
+  if constexpr (EH) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) ldhalo(z0 + d, hqy[d], hqx[d]);
+    ldhalo(z0 + 4, hyv, hxv);
+  } else {
+    ldhalo(z0, hyv, hxv);
+  }
 
   for (int z = z0; z < z1; ++z) {
     T pvc[RY], mmc[RY], hyc[NHY], hxcv[NHX], esc[RY], egc[RY];
@@ -171,10 +187,28 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
         egc[j] = eg[j];
       }
     }
+    if constexpr (EH) {
 #pragma unroll
-    for (int k = 0; k < NHY; ++k) hyc[k] = hyv[k];
+      for (int k = 0; k < NHY; ++k) hyc[k] = hqy[0][k];
 #pragma unroll
-    for (int k = 0; k < NHX; ++k) hxcv[k] = hxv[k];
+      for (int k = 0; k < NHX; ++k) hxcv[k] = hqx[0][k];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int k = 0; k < NHY; ++k) hqy[d][k] = hqy[d + 1][k];
+#pragma unroll
+        for (int k = 0; k < NHX; ++k) hqx[d][k] = hqx[d + 1][k];
+      }
+#pragma unroll
+      for (int k = 0; k < NHY; ++k) hqy[3][k] = hyv[k];
+#pragma unroll
+      for (int k = 0; k < NHX; ++k) hqx[3][k] = hxv[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < NHY; ++k) hyc[k] = hyv[k];
+#pragma unroll
+      for (int k = 0; k < NHX; ++k) hxcv[k] = hxv[k];
+    }
     // prefetch plane z+1
     if (z + 1 < z1) {
 #pragma unroll
@@ -188,11 +222,7 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
           eg[j] = in[j] ? e.g[o] : T(0);
         }
       }
-#pragma unroll
-      for (int k = 0; k < NHY; ++k) hyv[k] = hyon[k] ? ldu(z + 1, hyg[k], x) : T(0);
-#pragma unroll
-      for (int k = 0; k < NHX; ++k)
-        hxv[k] = hxon[k] ? ldu(z + 1, y0 - 4 + hxr[k], x0 - 4 + hxc[k]) : T(0);
+      ldhalo(EH ? z + 5 : z + 1, hyv, hxv);
     }
     T *L = lds[z & 1];
 #pragma unroll
@@ -229,7 +259,7 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
   }
 }
 
-template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE>
+template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE, bool EH = false>
 __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int ntx, int nty,
                                                              int nzc, int zchunk,
                                                              EpiArgs<T> e = EpiArgs<T>{}) {
@@ -242,13 +272,13 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
   const int by = (b / ntx) % nty;
   const int bz = b / (ntx * nty);
   const int z0 = bz * zchunk;
-  tiled_body<T, TX, TYT, RY, NT, EPI>(a, bx, by, z0, min(z0 + zchunk, a.nz), e);
+  tiled_body<T, TX, TYT, RY, NT, EPI, EH>(a, bx, by, z0, min(z0 + zchunk, a.nz), e);
 }
 
 // Several shots (independent grids, one ring each) in one launch: entry e of
 // the tile table names the shot and the tile; the shot's step arguments come
 // from a device table (level pointers rebuilt from the step index s).
-template <typename T, int TX, int TYT, int RY, bool NT>
+template <typename T, int TX, int TYT, int RY, bool NT, bool EH = false>
 __global__ __launch_bounds__(TX *TYT) void k_stencil3d_batched(const ShotStep<T> *__restrict__ shots,
                                                                const int4 *__restrict__ tiles,
                                                                int ntiles, int s) {
@@ -260,10 +290,10 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_batched(const ShotStep<T>
   a.cur = sh.ring + (int64_t)(((s + 1) % sh.R)) * sh.ld;
   a.prev = sh.ring + (int64_t)(((s + sh.R) % sh.R)) * sh.ld;
   a.next = sh.ring + (int64_t)(((s + 2) % sh.R)) * sh.ld;
-  tiled_body<T, TX, TYT, RY, NT>(a, t.y & 0xffff, t.y >> 16, t.z, t.w);
+  tiled_body<T, TX, TYT, RY, NT, EPI_NONE, EH>(a, t.y & 0xffff, t.y >> 16, t.z, t.w);
 }
 
-template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE>
+template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE, bool EH = false>
 static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st,
                          const EpiArgs<T> &e = EpiArgs<T>{}) {
   constexpr int TY = TYT * RY;
@@ -276,7 +306,7 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
   while ((int64_t)ntx * nty * nzc < want && a.nz / (nzc * 2) >= 16) nzc *= 2;
   const int zchunk = (a.nz + nzc - 1) / nzc;
   nzc = (a.nz + zchunk - 1) / zchunk;
-  hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT, EPI>), dim3(ntx * nty * nzc),
+  hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT, EPI, EH>), dim3(ntx * nty * nzc),
                      dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk, e);
 }
 
@@ -287,6 +317,7 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
 //   9: 64 x 32 (8 x 4, 512 thr), non-temporal
 //  10: 64 x 32 (16 x 2, 1024 thr), non-temporal
 //  11: as 3, non-temporal
+//  12: as 7 and 13: as 9, with early halo loads
 template <typename T>
 hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
                           hipStream_t st) {
@@ -303,6 +334,8 @@ hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int targe
         case 9: launch_tiled<T, 64, 8, 4, true>(a, target_blocks, st); break;
         case 10: launch_tiled<T, 64, 16, 2, true>(a, target_blocks, st); break;
         case 11: launch_tiled<T, 64, 8, 2, true>(a, target_blocks, st); break;
+        case 12: launch_tiled<T, 64, 4, 4, true, EPI_NONE, true>(a, target_blocks, st); break;
+        case 13: launch_tiled<T, 64, 8, 4, true, EPI_NONE, true>(a, target_blocks, st); break;
         default: launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st); break;
       }
     } else {
@@ -492,6 +525,11 @@ hipError_t launch_stencil_batched(const ShotStep<T> *shots, const int4 *tiles, i
       case 11:
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 8, 2, true>), dim3(ntiles), dim3(512), 0,
                            st, shots, tiles, ntiles, s);
+        break;
+      case 12:
+      case 13:
+        hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, true, true>), dim3(ntiles),
+                           dim3(256), 0, st, shots, tiles, ntiles, s);
         break;
       case 7:
       case 8:
