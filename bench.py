@@ -27,10 +27,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(grid, r, k):
+def measured_traffic(part: str, grid, r, k):
     """HBM bytes per dispatch measured with rocprofv3 --pmc (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy of known size) for this workload, if the
-    kernel sources are unchanged since the counters were taken; else None."""
+    WRITE_SIZE, scaled by a plain copy of known size) for one workload
+    ("acoustic" or "tti"), keyed by kernel, if the kernel sources are unchanged
+    since the counters were taken and the workload matches; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
@@ -38,23 +39,14 @@ def measured_traffic(grid, r, k):
     with open(path) as f:
         rec = json.load(f)
     h = hashlib.sha256()
-    for name in ("stencil.hip", "probe.hip", "misc.hip"):
+    for name in ("stencil.hip", "probe.hip", "misc.hip", "tti.hip", "tti_tiled.hip"):
         with open(os.path.join(ROOT, "paper_2201_06914_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    if rec.get("source_hash") != h.hexdigest()[:16] or rec.get("grid") != list(grid) \
-            or rec.get("r") != r or rec.get("k") != k:
+    w = rec.get(part)
+    if rec.get("source_hash") != h.hexdigest()[:16] or not w or w.get("grid") != list(grid) \
+            or w.get("r") != r or w.get("k") != k:
         return None
-    kk = rec["kernels"]
-    st = kk.get("k_stencil3d_tiled")
-    fw = kk.get("k_probe_mfma_fast<2, true, 1, false, 4>")
-    ad = kk.get("k_probe_mfma_fast<2, true, 2, true, 2>")
-    out = {}
-    if st:
-        out["stencil"] = st["read_bytes"] + st["write_bytes"]
-    if fw and ad:
-        out["probe"] = 0.5 * (fw["read_bytes"] + fw["write_bytes"] + ad["read_bytes"]
-                              + ad["write_bytes"])
-    return out
+    return {key: v["read_bytes"] + v["write_bytes"] for key, v in w["kernels"].items()}
 
 
 def parse():
@@ -316,13 +308,16 @@ def bench_tti(shape, nt: int, r: int, stride: int):
     gbs = bpc * N / (avg_us * 1e-6) / 1e9
     finite = bool(torch.isfinite(out["grad"]).all().item())
     print("tti: gradient done", file=sys.stderr, flush=True)
+    tr = measured_traffic("tti", shape, r, 32)
+    traffic = (round(0.5 * (tr["tti_fprep"] + tr["tti_fmarch"] + tr["tti_aprep"]
+                            + tr["tti_amarch"])) if tr else None)
     return {"workload": f"TTI {shape[0]}x{shape[1]}x{shape[2]}, nt={nt}, r={r} on p and q, "
                         f"k=32, bf16x2, fused imaging, one shot",
             "value": round(2.0 * N * nt / (ms * 1e-3) / 1e9, 2), "unit": "Gcell-updates/s",
             "ms_per_gradient": round(ms, 1),
             "step_avg_us": round(avg_us, 1), "step_count_timed": cnt,
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
-                         "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                         "unit": "GB/s", "frac": round(gbs / 8000.0, 4), "traffic": traffic,
                          "bytes_per_cell": bpc},
             "misfit": float(out["misfit"].item()), "grad_finite": finite}
 
@@ -476,10 +471,10 @@ def main():
              "mfma_tflops": round((2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 *
                                   math.ceil(k / 16) * N * 2 * nblk * a.steps /
                                   (pr_ms * 1e-3) / 1e12, 2) if pr_n else None}
-    tr = measured_traffic((384, 512, 512), r, k) if fused else None
+    tr = measured_traffic("acoustic", (384, 512, 512), r, k) if fused else None
     if tr:
-        stencil["traffic"] = round(tr.get("stencil", 0.0))
-        probe["traffic"] = round(tr.get("probe", 0.0))
+        stencil["traffic"] = round(tr["stencil"])
+        probe["traffic"] = round(0.5 * (tr["probe_fwd"] + tr["probe_adj"]))
     dominant, other = (probe, stencil) if pr_tot > st_tot else (stencil, probe)
     path_bytes = 2 * nt * st_bytes + pr_bytes_step
     rec_line = {
