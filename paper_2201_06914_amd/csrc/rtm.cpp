@@ -1087,6 +1087,10 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
       rtm_batch_destroy(b);
       return fail(RTM_E_SHAPE, "shot %d: too many tiles", i);
     }
+    if (b->P[i]->N * 4 >= (int64_t(1) << 32)) {  // tiled kernels use 32-bit offsets
+      rtm_batch_destroy(b);
+      return fail(RTM_E_SHAPE, "shot %d: a window of 4 GiB or more per level", i);
+    }
     for (int z0 = 0; z0 < d.nz; z0 += zc)
       for (int by = 0; by < nty; ++by)
         for (int bx = 0; bx < ntx; ++bx)

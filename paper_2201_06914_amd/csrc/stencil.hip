@@ -27,9 +27,25 @@ __device__ __forceinline__ T axis_sum(const StepArgs<T> &a, T p1, T m1, T p2, T 
   return s;
 }
 
+// n / d; for FP32 a hardware reciprocal refined by one Newton step and one
+// residual correction (Markstein's scheme), within an ulp of the IEEE
+// quotient for the normal, well-scaled operands of the update (slowness
+// squared plus damping), in fewer instructions than the IEEE sequence
+template <typename T>
+__device__ __forceinline__ T quot(T n, T d) {
+  return n / d;
+}
+template <>
+__device__ __forceinline__ float quot<float>(float n, float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  r = __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
+  const float q = n * r;
+  return __builtin_fmaf(__builtin_fmaf(-d, q, n), r, q);
+}
+
 template <typename T>
 __device__ __forceinline__ T cell_update(const StepArgs<T> &a, T u, T up, T m, T lap, T damp) {
-  return (T(2) * m * u - (m - damp) * up + a.dt2 * lap) / (m + damp);
+  return quot(T(2) * m * u - (m - damp) * up + a.dt2 * lap, m + damp);
 }
 
 // ---------------------------------------------------------------------------
@@ -80,6 +96,16 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
+// element at a 32-bit byte offset from a base held in scalar registers (the
+// tiled kernels run on levels below 4 GiB)
+template <typename T>
+__device__ __forceinline__ T *at(T *p, uint32_t off) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(p) + off);
+}
+template <typename T>
+__device__ __forceinline__ const T *at(const T *p, uint32_t off) {
+  return reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + off);
+}
 
 // One column tile (bx, by) over planes [z0, z1) of one level.  EPI adds a
 // cell-local epilogue for the exact comparator: EPI_D2 writes the second time
@@ -105,8 +131,11 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
   const int ty = tid / TX;
   const int x0 = bx * TX, y0 = by * TY;
   const int x = x0 + tx;
-  const int64_t sp = (int64_t)a.ny * a.nx;
+  const uint32_t sp = (uint32_t)a.ny * (uint32_t)a.nx;
   const T *__restrict__ u = a.cur;
+  auto off = [&](int zz, int yy, int xx) -> uint32_t {
+    return ((uint32_t)zz * sp + (uint32_t)yy * (uint32_t)a.nx + (uint32_t)xx) * (uint32_t)sizeof(T);
+  };
 
   int yr[RY];
   bool in[RY];
@@ -117,7 +146,7 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
   }
   auto ldu = [&](int zz, int yy, int xx) -> T {
     return (zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny && xx >= 0 && xx < a.nx)
-               ? u[(int64_t)zz * sp + (int64_t)yy * a.nx + xx]
+               ? *at(u, off(zz, yy, xx))
                : T(0);
   };
   // halo bookkeeping: y-halo rows hy = ty + TYT*k (LDS rows 0..3 and TY+4..TY+7),
@@ -150,12 +179,12 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
 #pragma unroll
     for (int k = 0; k < 8; ++k) q[j][k] = ldu(z0 - 4 + k, yr[j], x);
     front[j] = ldu(z0 + 4, yr[j], x);
-    const int64_t o = (int64_t)z0 * sp + (int64_t)yr[j] * a.nx + x;
-    pv[j] = in[j] ? ld_stream<T, NT>(a.prev + o) : T(0);
-    mm[j] = in[j] ? ld_stream<T, NT>(a.m + o) : T(1);
+    const uint32_t o = off(z0, yr[j], x);
+    pv[j] = in[j] ? ld_stream<T, NT>(at(a.prev, o)) : T(0);
+    mm[j] = in[j] ? ld_stream<T, NT>(at(a.m, o)) : T(1);
     if constexpr (EPI == EPI_CORR) {
-      es[j] = in[j] ? ld_stream<T, NT>(e.s + o) : T(0);
-      eg[j] = in[j] ? e.g[o] : T(0);
+      es[j] = in[j] ? ld_stream<T, NT>(at(e.s, o)) : T(0);
+      eg[j] = in[j] ? *at(e.g, o) : T(0);
     }
   }
   // halo of one plane into hy / hx
@@ -214,12 +243,12 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
         front[j] = ldu(z + 5, yr[j], x);
-        const int64_t o = (int64_t)(z + 1) * sp + (int64_t)yr[j] * a.nx + x;
-        pv[j] = in[j] ? ld_stream<T, NT>(a.prev + o) : T(0);
-        mm[j] = in[j] ? ld_stream<T, NT>(a.m + o) : T(1);
+        const uint32_t o = off(z + 1, yr[j], x);
+        pv[j] = in[j] ? ld_stream<T, NT>(at(a.prev, o)) : T(0);
+        mm[j] = in[j] ? ld_stream<T, NT>(at(a.m, o)) : T(1);
         if constexpr (EPI == EPI_CORR) {
-          es[j] = in[j] ? ld_stream<T, NT>(e.s + o) : T(0);
-          eg[j] = in[j] ? e.g[o] : T(0);
+          es[j] = in[j] ? ld_stream<T, NT>(at(e.s, o)) : T(0);
+          eg[j] = in[j] ? *at(e.g, o) : T(0);
         }
       }
       ldhalo(EH ? z + 5 : z + 1, hyv, hxv);
@@ -247,11 +276,12 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
                              row[-4]);
       const T lap = ((a.cc * c + lz) + lyv) + lxv;
       if (in[j]) {
-        const int64_t o = (int64_t)z * sp + (int64_t)yr[j] * a.nx + x;
+        const uint32_t o = off(z, yr[j], x);
         const T nv = cell_update(a, c, pvc[j], mmc[j], lap, sponge_a(a, z, yr[j], x));
-        st_stream<T, NT>(a.next + o, nv);
-        if constexpr (EPI == EPI_D2) st_stream<T, NT>(e.d2 + o, (nv - T(2) * c + pvc[j]) * e.inv_dt2);
-        if constexpr (EPI == EPI_CORR) e.g[o] = egc[j] - esc[j] * nv;
+        st_stream<T, NT>(at(a.next, o), nv);
+        if constexpr (EPI == EPI_D2)
+          st_stream<T, NT>(at(e.d2, o), (nv - T(2) * c + pvc[j]) * e.inv_dt2);
+        if constexpr (EPI == EPI_CORR) *at(e.g, o) = egc[j] - esc[j] * nv;
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) q[j][k] = q[j][k + 1];
@@ -321,7 +351,9 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
 template <typename T>
 hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
                           hipStream_t st) {
-  if (ndim == 3 && variant >= kStencilTiled && variant <= kStencilVariants) {
+  // the tiled kernels address a level with 32-bit byte offsets
+  const bool fits = a.N * (int64_t)sizeof(T) < (int64_t(1) << 32);
+  if (ndim == 3 && fits && variant >= kStencilTiled && variant <= kStencilVariants) {
     if constexpr (sizeof(T) == 4) {
       switch (variant) {
         case 2: launch_tiled<T, 64, 4, 8, false>(a, target_blocks, st); break;
@@ -361,7 +393,9 @@ template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, i
 template <typename T>
 hipError_t launch_stencil_epi(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
                               int epi, const EpiArgs<T> &e, hipStream_t st) {
-  if (ndim != 3 || sizeof(T) != 4 || variant < kStencilTiled) return hipErrorInvalidValue;
+  if (ndim != 3 || sizeof(T) != 4 || variant < kStencilTiled ||
+      a.N * (int64_t)sizeof(T) >= (int64_t(1) << 32))
+    return hipErrorInvalidValue;
   if constexpr (sizeof(T) == 4) {
     const bool nt = variant != 1;
     if (epi == EPI_D2) {
