@@ -253,15 +253,17 @@ def bench_rsweep(n: int, nt: int, variant: int):
         rows.append({"r": r, "ms": round(t_pr, 1), "speedup_vs_exact": round(t_exact / t_pr, 3),
                      "grad_rel_err": round(err, 4), "cosine": round(cos, 4),
                      "fd_rel_diff": round(abs(float((gp * dm.double()).sum()) - fd) / abs(fd), 4),
-                     "memory_gb": round((B.workspace_bytes + sum(o["Ubar"].numel() * 4
-                                                                  for o in outs)) / 1e9, 2)})
+                     "memory_gb_4_shots": round((B.workspace_bytes + sum(o["Ubar"].numel() * 4
+                                                                          for o in outs)) / 1e9, 2),
+                     "memory_gb_per_shot": round((B.workspace_bytes + sum(o["Ubar"].numel() * 4
+                                                                          for o in outs)) / 4e9, 2)})
         del B, outs, work, shots
         torch.cuda.empty_cache()
         print(f"rsweep: r={r} done", file=sys.stderr, flush=True)
     return {"workload": f"{n}^3 salt model, 4 shots, nt={nt}, h=12.5 m, 10 Hz, gradient at the "
                         f"smoothed model, d_obs modelled from the true model",
             "exact_ms": round(t_exact, 1),
-            "exact_memory_gb": round(ewb / 1e9, 2),
+            "exact_memory_gb_per_shot": round(ewb / 1e9, 2),
             "full_history_gb_per_shot": round(nt * N * 4 / 1e9, 1),
             "fd_vs_exact_rel_diff": round(abs(lin_exact - fd) / abs(fd), 5),
             "misfit": Je, "probed": rows}
