@@ -51,6 +51,8 @@ struct TtiTile {
   bool hyon[G::NHY];
   int hxg_y, hxg_x, hxl;  // x-halo cell (threads < NHX)
   bool hxon;
+  int cng_y, cng_x, cnl;  // corner cell (threads NHX .. NHX + 63; 4 corners of 4 x 4)
+  bool cnon;
 };
 
 template <int TY, typename T>
@@ -78,6 +80,13 @@ __device__ __forceinline__ TtiTile<TY> tile_of(const StepArgs<T> &a, int bx, int
   t.hxg_x = x0 - 4 + lcx;
   t.hxl = (4 + r) * G::LX + lcx;
   t.hxon = tid < G::NHX && t.hxg_y < a.ny && t.hxg_x >= 0 && t.hxg_x < a.nx;
+  const int cc = tid - G::NHX, cq = cc / 16, crow = (cc % 16) / 4, ccol = cc % 4;
+  const int lrow = cq < 2 ? crow : TY + 4 + crow, lcol = (cq & 1) == 0 ? ccol : TX + 4 + ccol;
+  t.cng_y = y0 - 4 + lrow;
+  t.cng_x = x0 - 4 + lcol;
+  t.cnl = lrow * G::LX + lcol;
+  t.cnon = cc >= 0 && cc < 64 && t.cng_y >= 0 && t.cng_y < a.ny && t.cng_x >= 0 &&
+           t.cng_x < a.nx;
   return t;
 }
 
@@ -322,6 +331,154 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_fmarch(TtiArgs<T> t, int n
 }
 
 // ---------------------------------------------------------------------------
+// forward, fused: one kernel per step, no intermediates in HBM.  Iteration z
+// stages the lead plane z + 4 (p, q with an x/y halo) and the current plane z
+// (with corners); D_x and D_y of the lead plane enter register queues (the z
+// first differences of the mixed terms need them four planes ahead);
+// D_x (D_y .) of the current plane goes through a second LDS stage.  Eight
+// warm-up iterations before the chunk fill the queues.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, int MINW>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused(TtiArgs<T> t, int ntx, int nty,
+                                                             int nzc, int zchunk) {
+  using G = Geo<TY>;
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
+  __shared__ T Lc[2][2][G::PL];   // current plane p, q (with corners), double buffered
+  __shared__ T Ll[2][G::PL];      // lead plane p, q
+  __shared__ T H[2][TY * G::LX];  // D_y p, D_y q of the current plane, all 72 columns
+  const int64_t N = a.N;
+  T Qp[9], Qq[9], Xp[9], Yp[9], Xq[9], Yq[9];  // p, q, D_x p, D_y p, D_x q, D_y q
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Qp[k] = T(0);
+    Qq[k] = T(0);
+    Xp[k] = Yp[k] = Xq[k] = Yq[k] = T(0);
+  }
+  // prefetched values of the next iteration
+  T fp, fq;                                      // lead interior
+  T lyp[G::NHY], lyq[G::NHY], lxp, lxq;          // lead halo
+  T cyp[G::NHY], cyq[G::NHY], cxp, cxq, ccp, ccq; // current halo and corners
+  T pp, qp, mm, c1, c2, nz, ny, nx;              // current cell
+  auto fetch = [&](int z) {  // iteration z: lead plane z + 4, current plane z
+    const int zl = z + 4;
+    fp = ldz(t.p, a, g.in, zl, g.y, g.x);
+    fq = ldz(t.q, a, g.in, zl, g.y, g.x);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      lyp[k] = ldz(t.p, a, g.hyon[k], zl, g.hyg[k], g.x);
+      lyq[k] = ldz(t.q, a, g.hyon[k], zl, g.hyg[k], g.x);
+    }
+    lxp = ldz(t.p, a, g.hxon, zl, g.hxg_y, g.hxg_x);
+    lxq = ldz(t.q, a, g.hxon, zl, g.hxg_y, g.hxg_x);
+    const bool out = z >= z0;
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      cyp[k] = ldz(t.p, a, out && g.hyon[k], z, g.hyg[k], g.x);
+      cyq[k] = ldz(t.q, a, out && g.hyon[k], z, g.hyg[k], g.x);
+    }
+    cxp = ldz(t.p, a, out && g.hxon, z, g.hxg_y, g.hxg_x);
+    cxq = ldz(t.q, a, out && g.hxon, z, g.hxg_y, g.hxg_x);
+    ccp = ldz(t.p, a, out && g.cnon, z, g.cng_y, g.cng_x);
+    ccq = ldz(t.q, a, out && g.cnon, z, g.cng_y, g.cng_x);
+    const bool oc = out && g.in;
+    pp = ldz(t.pp, a, oc, z, g.y, g.x);
+    qp = ldz(t.qp, a, oc, z, g.y, g.x);
+    mm = ldz(a.m, a, oc, z, g.y, g.x);
+    c1 = ldz(t.coef, a, oc, z, g.y, g.x);
+    c2 = ldz(t.coef + N, a, oc, z, g.y, g.x);
+    nz = ldz(t.coef + 2 * N, a, oc, z, g.y, g.x);
+    ny = ldz(t.coef + 3 * N, a, oc, z, g.y, g.x);
+    nx = ldz(t.coef + 4 * N, a, oc, z, g.y, g.x);
+  };
+  const int zs = z0 - 8;
+  fetch(zs);
+  for (int z = zs; z < z1; ++z) {
+    const bool out = z >= z0;  // uniform over the workgroup
+    Qp[8] = fp;
+    Qq[8] = fq;
+    const T cpp = pp, cqp = qp, cm = mm, cc1 = c1, cc2 = c2, cnz = nz, cny = ny, cnx = nx;
+    T *Lp = Lc[z & 1][0], *Lq = Lc[z & 1][1];
+    Ll[0][g.lc] = fp;
+    Ll[1][g.lc] = fq;
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      Ll[0][g.hyl[k]] = lyp[k];
+      Ll[1][g.hyl[k]] = lyq[k];
+    }
+    if (threadIdx.x < G::NHX) {
+      Ll[0][g.hxl] = lxp;
+      Ll[1][g.hxl] = lxq;
+    }
+    if (out) {
+      Lp[g.lc] = Qp[4];
+      Lq[g.lc] = Qq[4];
+#pragma unroll
+      for (int k = 0; k < G::NHY; ++k) {
+        Lp[g.hyl[k]] = cyp[k];
+        Lq[g.hyl[k]] = cyq[k];
+      }
+      if (threadIdx.x < G::NHX) {
+        Lp[g.hxl] = cxp;
+        Lq[g.hxl] = cxq;
+      }
+      if (threadIdx.x >= G::NHX && threadIdx.x < G::NHX + 64) {
+        Lp[g.cnl] = ccp;
+        Lq[g.cnl] = ccq;
+      }
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    // queue fronts: first differences of the lead plane
+    Xp[8] = d1l(t, Ll[0] + g.lc, 1);
+    Yp[8] = d1l(t, Ll[0] + g.lc, G::LX);
+    Xq[8] = d1l(t, Ll[1] + g.lc, 1);
+    Yq[8] = d1l(t, Ll[1] + g.lc, G::LX);
+    if (out) {
+      const int hr = threadIdx.x / TX, hc = threadIdx.x % TX + 4;
+      H[0][hr * G::LX + hc] = d1l(t, Lp + g.lc, G::LX);
+      H[1][hr * G::LX + hc] = d1l(t, Lq + g.lc, G::LX);
+      if (threadIdx.x < G::NHX) {
+        const int r = threadIdx.x / 8, lcx = g.hxl - (4 + r) * G::LX;
+        H[0][r * G::LX + lcx] = d1l(t, Lp + g.hxl, G::LX);
+        H[1][r * G::LX + lcx] = d1l(t, Lq + g.hxl, G::LX);
+      }
+    }
+    __syncthreads();
+    if (out && g.in) {
+      const int hrow = (threadIdx.x / TX) * G::LX + threadIdx.x % TX + 4;
+      const T pzz = d2q(t, Qp), qzz = d2q(t, Qq);
+      const T pxx = d2l(t, Lp + g.lc, 1), qxx = d2l(t, Lq + g.lc, 1);
+      const T pyy = d2l(t, Lp + g.lc, G::LX), qyy = d2l(t, Lq + g.lc, G::LX);
+      const T pxy = d1l(t, H[0] + hrow, 1), qxy = d1l(t, H[1] + hrow, 1);
+      const T pxz = d1q(t, Xp), qxz = d1q(t, Xq);
+      const T pyz = d1q(t, Yp), qyz = d1q(t, Yq);
+      const T lp = (pzz + pyy) + pxx;
+      const T mix_p = (cnx * cny) * pxy + (cnx * cnz) * pxz + (cny * cnz) * pyz;
+      const T mix_q = (cnx * cny) * qxy + (cnx * cnz) * qxz + (cny * cnz) * qyz;
+      const T hzp = ((cnz * cnz) * pzz + (cny * cny) * pyy + (cnx * cnx) * pxx) + T(2) * mix_p;
+      const T hzq = ((cnz * cnz) * qzz + (cny * cny) * qyy + (cnx * cnx) * qxx) + T(2) * mix_q;
+      const T h0p = lp - hzp;
+      const T damp = sponge_a(a, z, g.y, g.x);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      sto(t.pn, o, tti_update(a, Qp[4], cpp, cm, cc1 * h0p + cc2 * hzq, damp));
+      sto(t.qn, o, tti_update(a, Qq[4], cqp, cm, cc2 * h0p + hzq, damp));
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      Qp[k] = Qp[k + 1];
+      Qq[k] = Qq[k + 1];
+      Xp[k] = Xp[k + 1];
+      Yp[k] = Yp[k + 1];
+      Xq[k] = Xq[k + 1];
+      Yq[k] = Yq[k + 1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // adjoint, in-plane: g0 = w1, g1 = w2, g2 = E_xz(w1), g3 = E_xz(w2),
 // g4 = E_xy(w1), g5 = E_xy(w2)
 // ---------------------------------------------------------------------------
@@ -541,7 +698,7 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
 
 // one TTI step with the tiled kernels (prep with TYP rows, march with TYM
 // rows); g needs 4 (forward) / 6 (adjoint) slots of N
-template <typename T, int TYP, int TYM>
+template <typename T, int TYP, int TYM, bool FUSED = false>
 static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
@@ -549,7 +706,10 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
   const TtiGrid gm = tti_grid(a.nz, a.ny, a.nx, TYM, target_blocks);
   const dim3 bp(TX * TYP), bm(TX * TYM);
   const dim3 np(gp.ntx * gp.nty * gp.nzc), nm(gm.ntx * gm.nty * gm.nzc);
-  if (!adjoint) {
+  if (!adjoint && FUSED) {
+    hipLaunchKernelGGL((k_tti_ffused<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
+                       gm.zchunk);
+  } else if (!adjoint) {
     hipLaunchKernelGGL((k_tti_fprep<T, TYP, 1>), np, bp, 0, st, t, gp.ntx, gp.nty, gp.nzc,
                        gp.zchunk);
     hipLaunchKernelGGL((k_tti_fmarch<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
@@ -564,13 +724,17 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 }
 
 // tile shapes (prep / march rows of 64 columns): 1 = 8 / 8, 2 = 4 / 4,
-// 3 = 8 / 4 (default)
+// 3 = 8 / 4 (default), 4 = as 3 with the fused forward kernel (4 rows),
+// 5 = as 3 with the fused forward kernel (8 rows)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
   switch (shape) {
     case 1: return tti_step_tiled<T, 8, 8>(t, adjoint, target_blocks, st);
     case 2: return tti_step_tiled<T, 4, 4>(t, adjoint, target_blocks, st);
+    case 4: return tti_step_tiled<T, 8, 4, true>(t, adjoint, target_blocks, st);
+    case 5: return adjoint ? tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st)
+                           : tti_step_tiled<T, 8, 8, true>(t, adjoint, target_blocks, st);
     default: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
   }
 }

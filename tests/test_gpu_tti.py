@@ -43,10 +43,12 @@ def variant(request):
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
                                            ((-1, 1), (40, 21, 70)), ((-1, 2), (40, 21, 70)),
-                                           ((-1, 3), (40, 21, 70))], indirect=["variant"])
+                                           ((-1, 3), (40, 21, 70)), ((-1, 4), (40, 21, 70)),
+                                           ((-1, 5), (40, 21, 70)), ((-1, 4), (18, 16, 20))],
+                         indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
-    (tile shapes 1..3: 64 x 8 and 64 x 4 columns)."""
+    (tile shapes 1..3: 64 x 8 and 64 x 4 columns; 4, 5: fused forward step)."""
     wl, an = synth.workload_tti(shape=shape, nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
                                 rec_stride=7, dtype=np.float64)
     g = Grid.of(wl)
@@ -123,7 +125,8 @@ def test_tti_f32_bf16x2_fused_gradient():
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
 
 
-def test_tti_f32_tiled_equals_simple_kernels():
+@pytest.mark.parametrize("shape", [3, 4])
+def test_tti_f32_tiled_equals_simple_kernels(shape):
     """The tiled TTI step (mixed terms once per unordered pair, intermediates
     staged per plane) against the one-thread-per-cell step on the same FP32
     inputs: equal to FP32 rounding for the data, the compressed fields and the
@@ -141,11 +144,14 @@ def test_tti_f32_tiled_equals_simple_kernels():
     out = {}
     for v in (0, -1):
         P.set_stencil_variant(v)
+        P.set_tti_shape(shape)
         try:
             out[v] = P.fwi_gradient_tti(*args, fused=False)
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
+            P.set_tti_shape(3)
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
-    say("  TTI tiled vs simple (f32): " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+    say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
+        " ".join(f"{k} {v:.2e}" for k, v in e.items()))
     assert e["resid"] < 1e-6 and max(e.values()) < 5e-5
