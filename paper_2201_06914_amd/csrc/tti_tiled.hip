@@ -680,6 +680,168 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_amarch(TtiArgs<T> t, int n
   }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint, fused: one kernel per step.  The lead plane z + 4 carries n_x n_z w
+// and n_y n_z w (x / y halo) for the E_xz queue fronts, and the z-queue fronts
+// w1, n_z^2 w1, n_z^2 w2; the current plane z carries w1, n_x^2 w, n_y^2 w and
+// n_x n_y w (with corners, for the second LDS stage D_x (D_y .)).  The own
+// cell's w2, n_x, n_y, lp, lq reach plane z through 5-deep delay queues.
+// Current-plane LDS is single buffered: three barriers per plane.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, int MINW>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int ntx, int nty,
+                                                             int nzc, int zchunk) {
+  using G = Geo<TY>;
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
+  // current plane: w1, n_x^2 w1, n_y^2 w1, n_x^2 w2, n_y^2 w2, n_x n_y w1, n_x n_y w2
+  __shared__ T Lc[7][G::PL];
+  __shared__ T Ll[4][G::PL];      // lead plane: n_x n_z w1, n_x n_z w2, n_y n_z w1, n_y n_z w2
+  __shared__ T H[2][TY * G::LX];  // D_y (n_x n_y w1), D_y (n_x n_y w2)
+  const int64_t N = a.N;
+  const T *c1f = t.coef, *c2f = t.coef + N, *nzf = t.coef + 2 * N, *nyf = t.coef + 3 * N,
+          *nxf = t.coef + 4 * N;
+  struct In {
+    T lp, lq, c1, c2, nz, ny, nx;
+  };
+  auto load = [&](bool on, int z, int y, int x, bool withz) {
+    In c;
+    c.lp = ldz(t.p, a, on, z, y, x);
+    c.lq = ldz(t.q, a, on, z, y, x);
+    c.c1 = ldz(c1f, a, on, z, y, x);
+    c.c2 = ldz(c2f, a, on, z, y, x);
+    c.nz = withz ? ldz(nzf, a, on, z, y, x) : T(0);
+    c.ny = ldz(nyf, a, on, z, y, x);
+    c.nx = ldz(nxf, a, on, z, y, x);
+    return c;
+  };
+  T W[9], Z1[9], Z2[9], E1[9], E2[9];               // z queues
+  T Dw2[5], Dnx[5], Dny[5], Dlp[5], Dlq[5];         // delays: [4] lead plane, [0] plane z
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W[k] = Z1[k] = Z2[k] = E1[k] = E2[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) Dw2[k] = Dnx[k] = Dny[k] = Dlp[k] = Dlq[k] = T(0);
+  In li, ly[G::NHY], lx, cy[G::NHY], cx, cn;
+  T lpp, lqp, mm;
+  auto fetch = [&](int z) {
+    const int zl = z + 4;
+    li = load(g.in, zl, g.y, g.x, true);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) ly[k] = load(g.hyon[k], zl, g.hyg[k], g.x, true);
+    lx = load(g.hxon, zl, g.hxg_y, g.hxg_x, true);
+    const bool out = z >= z0;
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) cy[k] = load(out && g.hyon[k], z, g.hyg[k], g.x, false);
+    cx = load(out && g.hxon, z, g.hxg_y, g.hxg_x, false);
+    cn = load(out && g.cnon, z, g.cng_y, g.cng_x, false);
+    const bool oc = out && g.in;
+    lpp = ldz(t.pp, a, oc, z, g.y, g.x);
+    lqp = ldz(t.qp, a, oc, z, g.y, g.x);
+    mm = ldz(a.m, a, oc, z, g.y, g.x);
+  };
+  auto w1of = [](const In &c) { return c.c1 * c.lp + c.c2 * c.lq; };
+  auto w2of = [](const In &c) { return c.c2 * c.lp + c.lq; };
+  // current-plane LDS values of one cell (halo cells: LDS offset l)
+  auto stage_cur = [&](int l, T w1, T w2, T nx, T ny) {
+    Lc[0][l] = w1;
+    Lc[1][l] = (nx * nx) * w1;
+    Lc[2][l] = (ny * ny) * w1;
+    Lc[3][l] = (nx * nx) * w2;
+    Lc[4][l] = (ny * ny) * w2;
+    Lc[5][l] = (nx * ny) * w1;
+    Lc[6][l] = (nx * ny) * w2;
+  };
+  const int zs = z0 - 8;
+  fetch(zs);
+  for (int z = zs; z < z1; ++z) {
+    const bool out = z >= z0;  // uniform over the workgroup
+    // lead plane: queue fronts and LDS
+    {
+      const T w1 = w1of(li), w2 = w2of(li);
+      W[8] = w1;
+      Z1[8] = (li.nz * li.nz) * w1;
+      Z2[8] = (li.nz * li.nz) * w2;
+      Dw2[4] = w2;
+      Dnx[4] = li.nx;
+      Dny[4] = li.ny;
+      Dlp[4] = li.lp;
+      Dlq[4] = li.lq;
+      Ll[0][g.lc] = (li.nx * li.nz) * w1;
+      Ll[1][g.lc] = (li.nx * li.nz) * w2;
+      Ll[2][g.lc] = (li.ny * li.nz) * w1;
+      Ll[3][g.lc] = (li.ny * li.nz) * w2;
+    }
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      const T v1 = w1of(ly[k]), v2 = w2of(ly[k]);
+      Ll[2][g.hyl[k]] = (ly[k].ny * ly[k].nz) * v1;
+      Ll[3][g.hyl[k]] = (ly[k].ny * ly[k].nz) * v2;
+    }
+    if (threadIdx.x < G::NHX) {
+      const T v1 = w1of(lx), v2 = w2of(lx);
+      Ll[0][g.hxl] = (lx.nx * lx.nz) * v1;
+      Ll[1][g.hxl] = (lx.nx * lx.nz) * v2;
+    }
+    // current plane
+    const T clpp = lpp, clqp = lqp, cm = mm;
+    if (out) {
+      stage_cur(g.lc, W[4], Dw2[0], Dnx[0], Dny[0]);
+#pragma unroll
+      for (int k = 0; k < G::NHY; ++k)
+        stage_cur(g.hyl[k], w1of(cy[k]), w2of(cy[k]), cy[k].nx, cy[k].ny);
+      if (threadIdx.x < G::NHX) stage_cur(g.hxl, w1of(cx), w2of(cx), cx.nx, cx.ny);
+      if (threadIdx.x >= G::NHX && threadIdx.x < G::NHX + 64)
+        stage_cur(g.cnl, w1of(cn), w2of(cn), cn.nx, cn.ny);
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    E1[8] = d1l(t, Ll[0] + g.lc, 1) + d1l(t, Ll[2] + g.lc, G::LX);
+    E2[8] = d1l(t, Ll[1] + g.lc, 1) + d1l(t, Ll[3] + g.lc, G::LX);
+    if (out) {
+      const int hr = threadIdx.x / TX, hc = threadIdx.x % TX + 4;
+      H[0][hr * G::LX + hc] = d1l(t, Lc[5] + g.lc, G::LX);
+      H[1][hr * G::LX + hc] = d1l(t, Lc[6] + g.lc, G::LX);
+      if (threadIdx.x < G::NHX) {
+        const int r = threadIdx.x / 8, lcx = g.hxl - (4 + r) * G::LX;
+        H[0][r * G::LX + lcx] = d1l(t, Lc[5] + g.hxl, G::LX);
+        H[1][r * G::LX + lcx] = d1l(t, Lc[6] + g.hxl, G::LX);
+      }
+    }
+    __syncthreads();
+    if (out && g.in) {
+      const int hrow = (threadIdx.x / TX) * G::LX + threadIdx.x % TX + 4;
+      const T lw1 = (d2q(t, W) + d2l(t, Lc[0] + g.lc, G::LX)) + d2l(t, Lc[0] + g.lc, 1);
+      const T hz1 = ((d2q(t, Z1) + d2l(t, Lc[2] + g.lc, G::LX)) + d2l(t, Lc[1] + g.lc, 1)) +
+                    T(2) * (d1l(t, H[0] + hrow, 1) + d1q(t, E1));
+      const T hz2 = ((d2q(t, Z2) + d2l(t, Lc[4] + g.lc, G::LX)) + d2l(t, Lc[3] + g.lc, 1)) +
+                    T(2) * (d1l(t, H[1] + hrow, 1) + d1q(t, E2));
+      const T damp = sponge_a(a, z, g.y, g.x);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      sto(t.pn, o, tti_update(a, Dlp[0], clpp, cm, lw1 - hz1, damp));
+      sto(t.qn, o, tti_update(a, Dlq[0], clqp, cm, hz2, damp));
+    }
+    __syncthreads();  // the current-plane LDS is rewritten next iteration
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      W[k] = W[k + 1];
+      Z1[k] = Z1[k + 1];
+      Z2[k] = Z2[k + 1];
+      E1[k] = E1[k + 1];
+      E2[k] = E2[k + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Dw2[k] = Dw2[k + 1];
+      Dnx[k] = Dnx[k + 1];
+      Dny[k] = Dny[k + 1];
+      Dlp[k] = Dlp[k + 1];
+      Dlq[k] = Dlq[k + 1];
+    }
+  }
+}
+
 // grid of one tiled launch: (64 x ty) column tiles, z split in chunks until
 // target_blocks workgroups (chunks of at least 16 planes)
 struct TtiGrid {
@@ -698,7 +860,7 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
 
 // one TTI step with the tiled kernels (prep with TYP rows, march with TYM
 // rows); g needs 4 (forward) / 6 (adjoint) slots of N
-template <typename T, int TYP, int TYM, bool FUSED = false>
+template <typename T, int TYP, int TYM, bool FUSED = false, bool AFUSED = false>
 static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
@@ -706,10 +868,21 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
   const TtiGrid gm = tti_grid(a.nz, a.ny, a.nx, TYM, target_blocks);
   const dim3 bp(TX * TYP), bm(TX * TYM);
   const dim3 np(gp.ntx * gp.nty * gp.nzc), nm(gm.ntx * gm.nty * gm.nzc);
-  if (!adjoint && FUSED) {
-    hipLaunchKernelGGL((k_tti_ffused<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
-                       gm.zchunk);
-  } else if (!adjoint) {
+  if constexpr (FUSED) {
+    if (!adjoint) {
+      hipLaunchKernelGGL((k_tti_ffused<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
+                         gm.zchunk);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (AFUSED) {
+    if (adjoint) {
+      hipLaunchKernelGGL((k_tti_afused<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
+                         gm.zchunk);
+      return hipGetLastError();
+    }
+  }
+  if (!adjoint) {
     hipLaunchKernelGGL((k_tti_fprep<T, TYP, 1>), np, bp, 0, st, t, gp.ntx, gp.nty, gp.nzc,
                        gp.zchunk);
     hipLaunchKernelGGL((k_tti_fmarch<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
@@ -725,7 +898,7 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 
 // tile shapes (prep / march rows of 64 columns): 1 = 8 / 8, 2 = 4 / 4,
 // 3 = 8 / 4, 4 (default) = as 3 with the fused forward kernel (4 rows),
-// 5 = as 3 with the fused forward kernel (8 rows)
+// 5 = as 3 with the fused forward kernel (8 rows), 6 = both steps fused (4 rows)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -735,6 +908,7 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
     case 5: return adjoint ? tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st)
                            : tti_step_tiled<T, 8, 8, true>(t, adjoint, target_blocks, st);
     case 3: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
+    case 6: return tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
     default: return tti_step_tiled<T, 8, 4, true>(t, adjoint, target_blocks, st);
   }
 }
