@@ -897,8 +897,8 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 }
 
 // tile shapes (prep / march rows of 64 columns): 1 = 8 / 8, 2 = 4 / 4,
-// 3 = 8 / 4, 4 (default) = as 3 with the fused forward kernel (4 rows),
-// 5 = as 3 with the fused forward kernel (8 rows), 6 = both steps fused (4 rows)
+// 3 = 8 / 4, 4 = as 3 with the fused forward kernel (4 rows), 5 = as 3 with
+// the fused forward kernel (8 rows), 6 (default) = both steps fused (4 rows)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -908,8 +908,8 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
     case 5: return adjoint ? tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st)
                            : tti_step_tiled<T, 8, 8, true>(t, adjoint, target_blocks, st);
     case 3: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
-    case 6: return tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
-    default: return tti_step_tiled<T, 8, 4, true>(t, adjoint, target_blocks, st);
+    case 4: return tti_step_tiled<T, 8, 4, true>(t, adjoint, target_blocks, st);
+    default: return tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
   }
 }
 

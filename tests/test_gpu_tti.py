@@ -38,14 +38,14 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(4)
+    P.set_tti_shape(6)
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
                                            ((-1, 1), (40, 21, 70)), ((-1, 2), (40, 21, 70)),
                                            ((-1, 3), (40, 21, 70)), ((-1, 4), (40, 21, 70)),
                                            ((-1, 5), (40, 21, 70)), ((-1, 6), (40, 21, 70)),
-                                           ((-1, 4), (18, 16, 20))],
+                                           ((-1, 6), (18, 16, 20))],
                          indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
@@ -152,7 +152,7 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
-            P.set_tti_shape(4)
+            P.set_tti_shape(6)
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
     say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
         " ".join(f"{k} {v:.2e}" for k, v in e.items()))
