@@ -311,8 +311,7 @@ def bench_tti(shape, nt: int, r: int, stride: int):
     finite = bool(torch.isfinite(out["grad"]).all().item())
     print("tti: gradient done", file=sys.stderr, flush=True)
     tr = measured_traffic("tti", shape, r, 32)
-    traffic = (round(0.5 * (tr["tti_fprep"] + tr["tti_fmarch"] + tr["tti_aprep"]
-                            + tr["tti_amarch"])) if tr else None)
+    traffic = round(0.5 * (tr["tti_ffused"] + tr["tti_afused"])) if tr else None
     return {"workload": f"TTI {shape[0]}x{shape[1]}x{shape[2]}, nt={nt}, r={r} on p and q, "
                         f"k=32, bf16x2, fused imaging, one shot",
             "value": round(2.0 * N * nt / (ms * 1e-3) / 1e9, 2), "unit": "Gcell-updates/s",
