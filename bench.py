@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--unfused", action="store_true",
                     help="store Vbar and run the separate imaging kernel (default: fused imaging)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the one step with the other imaging variant (fused / separate)")
     ap.add_argument("--no-exact", action="store_true",
                     help="skip the exact (checkpointed FP32) comparator run")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -382,17 +384,19 @@ def main():
     misfit = float(out["misfit"].item())
     finite = bool(torch.isfinite(out["grad"]).all().item())
     # one step of the other variant, for comparison
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    if fused:
-        other = P.fwi_gradient(plan, m, src, q, rec, d_obs, Z, work=work)
-    else:
-        other = step(True)
-    torch.cuda.synchronize()
-    other_ms = (time.perf_counter() - t2) * 1e3
-    other_misfit = float(other["misfit"].item())
-    del other
-    torch.cuda.empty_cache()
+    other_ms, other_misfit = None, None
+    if not a.no_other:
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if fused:
+            other = P.fwi_gradient(plan, m, src, q, rec, d_obs, Z, work=work)
+        else:
+            other = step(True)
+        torch.cuda.synchronize()
+        other_ms = (time.perf_counter() - t2) * 1e3
+        other_misfit = float(other["misfit"].item())
+        del other
+        torch.cuda.empty_cache()
     # the exact gradient (Eq. 2, FP32, uniform checkpointing) on the same inputs
     exact = None
     if not a.no_exact:
@@ -491,8 +495,9 @@ def main():
         "grad_rel_err_vs_exact": exact["grad_rel_err_vs_exact"] if exact else None,
         "exact_comparator": exact,
         "misfit": misfit, "grad_finite": finite,
-        ("unfused_ms_per_step" if fused else "fused_ms_per_step"): round(other_ms, 1),
-        "misfit_same_in_both": misfit == other_misfit,
+        ("unfused_ms_per_step" if fused else "fused_ms_per_step"):
+            round(other_ms, 1) if other_ms is not None else None,
+        "misfit_same_in_both": misfit == other_misfit if other_ms is not None else None,
         "image_avg_ms": round(im_ms / max(im_n, 1), 2),
     }
     if not a.no_batched:
