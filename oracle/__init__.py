@@ -334,3 +334,46 @@ def tti_probed_gradient(g: Grid, m, aniso, src_pos, q, rec_pos, d_obs, Z):
     r = np.shape(Z)[1]
     img = image(f["bar"][0], a["bar"][0], -1.0 / r) + image(f["bar"][1], a["bar"][1], -1.0 / r)
     return J, img, f, a
+
+
+# ---------------------------------------------------------------------------
+# range-finder probes (Section "Randomized trace estimation": probing vectors
+# Q from a partial QR factorization of A Z, Z a Rademacher +-1 matrix).  A is
+# read as the forward history H [nt][N] of u_tt, sketched in space: Y = H Omega
+# with Omega [N][r] Rademacher, Q = qr(Y), then Eq. 3 with Z = Q and scale 1
+# (Q Q^T is an orthogonal projector, no 1/r).
+# ---------------------------------------------------------------------------
+def sketch_signs(N: int, r: int, seed: int) -> np.ndarray:
+    """Omega [N][r]: entry (x, i) = 1 - 2 b with b the bit i % 64 of word i // 64
+    of the Philox4x64-10 block (key (seed, 0)) at counter (x + 1, 0, 0, 0).
+    numpy's Philox increments its counter before each block, so a generator
+    started at counter 0 yields exactly the blocks of cells 0, 1, 2, ..."""
+    assert 0 < r <= 256
+    bg = np.random.Philox(counter=[0, 0, 0, 0], key=[int(seed), 0])
+    w = bg.random_raw(4 * N).reshape(N, 4)
+    i = np.arange(r)
+    bits = (w[:, i // 64] >> (i % 64).astype(np.uint64)) & np.uint64(1)
+    return 1.0 - 2.0 * bits.astype(np.float64)
+
+
+def sketch(g: Grid, m, src_pos, q, seed: int, r: int) -> np.ndarray:
+    """Y [nt][r] = H Omega, H [nt][N] the forward history of u_tt."""
+    rec = np.zeros((1, 3))
+    f = forward(g, m, src_pos, q, rec, what="utt", hist=True, want_d=False)
+    return f["hist"] @ sketch_signs(g.N, r, seed)
+
+
+def range_finder(Y: np.ndarray) -> np.ndarray:
+    """Orthonormal basis [nt][r] of the column space of Y (Householder QR)."""
+    Q, _ = np.linalg.qr(np.asarray(Y, np.float64))
+    return Q
+
+
+def rf_gradient(g: Grid, m, src_pos, q, rec_pos, d_obs, seed: int, r: int):
+    """J and g = -sum_i Ubar[i] * Vbar[i] with Z = Q = range_finder(sketch)."""
+    Y = sketch(g, m, src_pos, q, seed, r)
+    Q = range_finder(Y)
+    f = forward(g, m, src_pos, q, rec_pos, Z=Q, what="utt")
+    J, res = misfit(f["d"], d_obs)
+    a = adjoint(g, m, rec_pos, res, Z=Q)
+    return J, image(f["Ubar"], a["Vbar"], -1.0), Q, Y
