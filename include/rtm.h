@@ -216,6 +216,41 @@ rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_p
                         void *resid, void *grad, double *misfit, void *work,
                         size_t work_bytes, rtm_stream stream);
 
+/* Range-finder probes (Section "Randomized trace estimation": probing vectors
+ * Q from a partial QR factorization of A Z with Z a Rademacher +-1 matrix).
+ * A is read as the forward history H [nt][N] of u_tt and Z as a sign matrix
+ * Omega [N][r] in space:  Y = H Omega  [nt][r],  Q = orthonormal columns of Y,
+ * and the gradient is Eq. 3 with Z = Q and scale -1 (Q Q^T is a projector;
+ * there is no 1/r).  Omega[x][i] = 1 - 2 b with b the bit i % 64 of word
+ * i / 64 of the Philox4x64-10 block (Salmon et al., SC 2011) with key
+ * (seed, 0) at counter (x + 1, 0, 0, 0), x the flat cell index; it is
+ * regenerated in the kernels, never stored.  Limits: r <= 256,
+ * k_block <= 128, k_block * r <= 8192, and for FP32 fields
+ * ceil(k_block / 32) * ceil(r / 32) <= 8 (else RTM_E_UNSUPPORTED).  All three
+ * calls need `work` of rtm_rf_workspace_bytes (the plan workspace plus sketch
+ * scratch).
+ * rtm_sketch:         forward sweep (no data, no probing) that writes
+ *                     Y  device [nt][r] FP64 (overwritten).
+ * rtm_orthonormalize: Q  device [nt][r] field dtype (overwritten) from Y by
+ *                     Gram-Schmidt applied twice in FP64; a column whose
+ *                     remainder falls below 1e-12 of its norm is zero.
+ * fwi_gradient_rf:    sketch, orthonormalize into Q, then the probed gradient
+ *                     of fwi_gradient with Z = Q and scale -1 (Ubar, Vbar,
+ *                     resid, grad, misfit as there; Vbar is required).  The
+ *                     probes are real, so the plan's probe dtype must equal its
+ *                     field dtype (F32 or F64). */
+rtm_status rtm_rf_workspace_bytes(const rtm_plan *plan, size_t *bytes);
+rtm_status rtm_sketch(const rtm_plan *plan, const void *m, const double *src_pos, const void *q,
+                      uint64_t seed, double *Y, void *work, size_t work_bytes,
+                      rtm_stream stream);
+rtm_status rtm_orthonormalize(const rtm_plan *plan, const double *Y, void *Q, void *work,
+                              size_t work_bytes, rtm_stream stream);
+rtm_status fwi_gradient_rf(const rtm_plan *plan, const void *m, const double *src_pos,
+                           const void *q, const double *rec_pos, const void *d_obs,
+                           uint64_t seed, void *Q, void *Ubar, void *Vbar, void *resid,
+                           void *grad, double *misfit, void *work, size_t work_bytes,
+                           rtm_stream stream);
+
 /* Exact gradient of the same misfit (Eq. 2, full zero-lag correlation
  * -sum_n u_tt^n lam^n), the comparator of the probed estimate.  The forward
  * history is not stored: uniform checkpointing keeps (u^{jc}, u^{jc-1}) every

@@ -19,7 +19,8 @@ EXPORTS = (
     "rtm_adjoint_image", "rtm_set_stencil_blocks", "rtm_autotune_stencil",
     "rtm_batch_create", "rtm_batch_destroy", "rtm_batch_workspace_bytes", "fwi_gradient_batched",
     "rtm_tti_workspace_bytes", "rtm_tti_forward_probe", "rtm_tti_adjoint_probe",
-    "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape",
+    "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape", "rtm_rf_workspace_bytes",
+    "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf",
 )
 
 
@@ -89,6 +90,16 @@ def load() -> ctypes.CDLL:
     L.rtm_exact_workspace_bytes.restype = ctypes.c_int
     L.fwi_gradient_exact.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, i32, _vp, _vp, _vp, _vp, sz, _vp]
     L.fwi_gradient_exact.restype = ctypes.c_int
+    u64 = ctypes.c_uint64
+    L.rtm_rf_workspace_bytes.argtypes = [_vp, ctypes.POINTER(sz)]
+    L.rtm_rf_workspace_bytes.restype = ctypes.c_int
+    L.rtm_sketch.argtypes = [_vp, _vp, _dp, _vp, u64, _vp, _vp, sz, _vp]
+    L.rtm_sketch.restype = ctypes.c_int
+    L.rtm_orthonormalize.argtypes = [_vp, _vp, _vp, _vp, sz, _vp]
+    L.rtm_orthonormalize.restype = ctypes.c_int
+    L.fwi_gradient_rf.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, u64, _vp, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, sz, _vp]
+    L.fwi_gradient_rf.restype = ctypes.c_int
     L.rtm_adjoint_image.argtypes = [_vp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, dbl, _vp, _vp, sz,
                                     _vp]
     L.rtm_adjoint_image.restype = ctypes.c_int

@@ -455,6 +455,74 @@ def fwi_gradient_exact(plan: Plan, m, src_pos, q, rec_pos, d_obs, checkpoint_eve
     return {"grad": g, "misfit": J, "resid": res, "workspace_bytes": int(n.value)}
 
 
+def rf_workspace_bytes(plan: Plan) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.load().rtm_rf_workspace_bytes(plan.handle, ctypes.byref(n)),
+           "rtm_rf_workspace_bytes")
+    return int(n.value)
+
+
+def _rf_work(plan: Plan, work, device):
+    n = rf_workspace_bytes(plan)
+    if work is None:
+        work = torch.empty(n, dtype=torch.uint8, device=device)
+    if work.numel() < n or not work.is_cuda:
+        raise ValueError("workspace too small for the range-finder calls")
+    return work
+
+
+def rtm_sketch(plan: Plan, m, src_pos, q, seed: int, work=None) -> torch.Tensor:
+    """Y [nt][r] (FP64): the space sketch H Omega of the u_tt history."""
+    s = plan.spec
+    dev = m.device
+    work = _rf_work(plan, work, dev)
+    Y = torch.empty((s.nt, s.r), dtype=torch.float64, device=dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    _check(_lib.load().rtm_sketch(plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
+                                  _dev(q, plan.dtype, s.nt * s.nsrc, "q"), int(seed),
+                                  _dev(Y, torch.float64, s.nt * s.r, "Y"),
+                                  ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(dev)),
+           "rtm_sketch")
+    return Y
+
+
+def rtm_orthonormalize(plan: Plan, Y, work=None) -> torch.Tensor:
+    """Q [nt][r] (field dtype): orthonormal columns spanning the columns of Y."""
+    s = plan.spec
+    dev = Y.device
+    work = _rf_work(plan, work, dev)
+    Q = torch.empty((s.nt, s.r), dtype=plan.dtype, device=dev)
+    _check(_lib.load().rtm_orthonormalize(plan.handle, _dev(Y, torch.float64, s.nt * s.r, "Y"),
+                                          _dev(Q, plan.dtype, s.nt * s.r, "Q"),
+                                          ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                          _stream(dev)), "rtm_orthonormalize")
+    return Q
+
+
+def fwi_gradient_rf(plan: Plan, m, src_pos, q, rec_pos, d_obs, seed: int, work=None) -> dict:
+    """Probed gradient with range-finder probes Q = orth(H Omega), scale -1."""
+    s = plan.spec
+    dev = m.device
+    work = _rf_work(plan, work, dev)
+    Q = torch.empty((s.nt, s.r), dtype=plan.dtype, device=dev)
+    U, V = plan.empty_bar(dev), plan.empty_bar(dev)
+    res = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev)
+    g = torch.empty(plan.N, dtype=plan.dtype, device=dev)
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    nb = s.r * plan.Npad
+    _check(_lib.load().fwi_gradient_rf(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
+        _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp,
+        _dev(d_obs, plan.dtype, s.nt * s.nrec, "d_obs"), int(seed),
+        _dev(Q, plan.dtype, s.nt * s.r, "Q"), _dev(U, plan.dtype, nb, "Ubar"),
+        _dev(V, plan.dtype, nb, "Vbar"), _dev(res, plan.dtype, s.nt * s.nrec, "resid"),
+        _dev(g, plan.dtype, plan.N, "grad"), _dev(J, torch.float64, 1, "misfit"),
+        ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(dev)), "fwi_gradient_rf")
+    return {"grad": g, "misfit": J, "Q": Q, "Ubar": U, "Vbar": V, "resid": res}
+
+
 def set_exact_fused(on: bool) -> None:
     _lib.load().rtm_set_exact_fused(1 if on else 0)
 

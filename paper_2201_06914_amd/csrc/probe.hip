@@ -16,33 +16,12 @@
 //   k_probe_vec   FP64 / FP32 FMA path (any real Z), thread per cell, 32
 //                 probe rows per pass; the accumulation order is the per-step
 //                 order bar += z_n s^n.
-#include "rtm_internal.h"
+#include "ring.h"
 
 namespace rtm {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
-
-// level j of the block, s0 - 1 <= j <= s0 + R - 2 (one wrap at most)
-template <typename T>
-__device__ __forceinline__ const T *ring_level(const ProbeArgs<T> &p, int j) {
-  int slot = p.slot0 + (j - p.s0 + 1);
-  if (slot >= p.R) slot -= p.R;
-  return p.ring + (int64_t)slot * p.ld;
-}
-
-// probed value of local step t at cell c
-template <typename T>
-__device__ __forceinline__ T probed(const ProbeArgs<T> &p, int t, int64_t c) {
-  const int s = p.s0 + t;
-  if (p.mode == PROBE_UTT) {
-    const T un = ring_level(p, s + 1)[c];
-    const T u0 = ring_level(p, s)[c];
-    const T um = ring_level(p, s - 1)[c];
-    return (un - T(2) * u0 + um) * p.inv_dt2;
-  }
-  return ring_level(p, p.mode == PROBE_NEW ? s + 1 : s)[c];
-}
 
 __device__ __forceinline__ int64_t bar_index(int64_t x, int i, int r) {
   return ((x >> 5) * r + i) * 32 + (x & 31);

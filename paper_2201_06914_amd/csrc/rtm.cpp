@@ -430,6 +430,10 @@ struct SweepIO {
   const void *fuse_U = nullptr;
   void *fuse_img = nullptr;
   double fuse_scale = 0.0;
+  // space sketch of u_tt (range-finder probes): Y [nt][r] rows per block
+  double *sketch_Y = nullptr;
+  void *sketch_partial = nullptr;
+  uint64_t sketch_seed = 0;
 };
 
 template <typename T>
@@ -466,7 +470,7 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       HIP_TRY(launch_inject<T>(a, inj, inj_vals + (int64_t)n * inj.npts, a.next, st));
     if (smp_out && smp.npts > 0)
       HIP_TRY(launch_sample<T>(smp, a.next, smp_out + (int64_t)n * smp.npts, st));
-    if ((bar || io.fuse_img) && (s + 1 - s0 == d.k_block || s == d.nt - 1)) {
+    if ((bar || io.fuse_img || io.sketch_Y) && (s + 1 - s0 == d.k_block || s == d.nt - 1)) {
       ProbeArgs<T> p{};
       p.ring = ring;
       p.ld = P->ld;
@@ -481,6 +485,15 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       p.bar = bar;
       p.inv_dt2 = (T)(1.0 / (d.dt * d.dt));
       p.mode = io.mode;
+      if (io.sketch_Y) {
+        ProbeArgs<T> ps = p;
+        ps.mode = PROBE_UTT;
+        HIP_TRY(launch_sketch<T>(ps, io.sketch_seed, io.sketch_partial, io.sketch_Y, st));
+      }
+      if (!bar && !io.fuse_img) {
+        s0 = s + 1;
+        continue;
+      }
       TimedLaunch tp;
       prof_begin(io.adjoint ? KT_PROBE_ADJ : KT_PROBE, s, st, &tp);
       if constexpr (sizeof(T) == 4) {
@@ -698,7 +711,8 @@ template <typename T>
 static rtm_status gradient_impl(const rtm_plan *P, const void *m, const double *src_pos,
                                 const void *q, const double *rec_pos, const void *d_obs,
                                 const void *Z, rtm_dtype zt, void *Ubar, void *Vbar, void *resid,
-                                void *grad, double *misfit, void *work, hipStream_t st) {
+                                void *grad, double *misfit, void *work, hipStream_t st,
+                                double scale) {
   PointTables<T> src_t, rec_t;
   char *w = static_cast<char *>(work);
   rtm_status s = upload_points<T>(P, w, st, src_pos, &src_t, rec_pos, &rec_t);
@@ -730,14 +744,14 @@ static rtm_status gradient_impl(const rtm_plan *P, const void *m, const double *
     HIP_TRY(launch_fill<T>(static_cast<T *>(grad), P->N, T(0), st));
     b.fuse_U = Ubar;
     b.fuse_img = grad;
-    b.fuse_scale = -1.0 / P->d.r;
+    b.fuse_scale = scale;
     return run_sweep<T>(P, b, rec_t, none, w, st);
   }
   if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
   TimedLaunch ti;
   prof_begin(KT_IMAGE, 0, st, &ti);
   HIP_TRY(launch_image<T>(static_cast<const T *>(Ubar), static_cast<const T *>(Vbar), P->N,
-                          P->d.r, -1.0 / P->d.r, static_cast<T *>(grad), st));
+                          P->d.r, scale, static_cast<T *>(grad), st));
   prof_end(st, &ti);
   return RTM_OK;
 }
@@ -757,9 +771,120 @@ extern "C" rtm_status fwi_gradient(const rtm_plan *P, const void *m, const doubl
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (P->d.field_dtype == RTM_F64)
     return gradient_impl<double>(P, m, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid, grad,
-                                 misfit, work, st);
+                                 misfit, work, st, -1.0 / P->d.r);
   return gradient_impl<float>(P, m, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid, grad,
-                              misfit, work, st);
+                              misfit, work, st, -1.0 / P->d.r);
+}
+
+// ---------------------------------------------------------------------------
+// range-finder probes: space sketch, orthonormal columns, projected gradient
+// ---------------------------------------------------------------------------
+struct RfLayout {
+  size_t partial, Y, V, total;
+};
+static RfLayout rf_layout(const rtm_plan *P) {
+  RfLayout L;
+  L.partial = P->total;
+  const size_t pe = (size_t)sketch_partial_elems(P->N, P->d.k_block, P->d.r) * P->esz;
+  L.Y = align256(L.partial + pe);
+  const size_t yb = (size_t)P->d.nt * P->d.r * sizeof(double);
+  L.V = align256(L.Y + yb);
+  L.total = align256(L.V + yb);
+  return L;
+}
+
+static rtm_status check_rf(const rtm_plan *P, size_t work_bytes) {
+  const rtm_desc &d = P->d;
+  if (d.r > 256) return fail(RTM_E_UNSUPPORTED, "the space sketch supports r <= 256");
+  if (d.k_block > 128 || (int64_t)d.k_block * d.r > 8192)
+    return fail(RTM_E_UNSUPPORTED, "the space sketch needs k_block <= 128 and k_block * r <= 8192");
+  if (d.field_dtype == RTM_F32 && ((d.k_block + 31) / 32) * ((d.r + 31) / 32) > 8)
+    return fail(RTM_E_UNSUPPORTED, "the FP32 space sketch needs ceil(k/32) * ceil(r/32) <= 8");
+  if (work_bytes < rf_layout(P).total)
+    return fail(RTM_E_WORKSPACE, "work has %zu bytes, range-finder calls need %zu", work_bytes,
+                rf_layout(P).total);
+  return RTM_OK;
+}
+
+extern "C" rtm_status rtm_rf_workspace_bytes(const rtm_plan *P, size_t *bytes) {
+  g_last_error.clear();
+  if (!P || !bytes) return fail(RTM_E_ARG, "NULL argument");
+  *bytes = rf_layout(P).total;
+  return RTM_OK;
+}
+
+template <typename T>
+static rtm_status sketch_impl(const rtm_plan *P, const void *m, const double *src_pos,
+                              const void *q, uint64_t seed, double *Y, char *w, hipStream_t st) {
+  PointTables<T> src_t, none;
+  rtm_status s = upload_points<T>(P, w, st, src_pos, &src_t, nullptr, &none);
+  if (s) return s;
+  SweepIO f;
+  f.adjoint = false;
+  f.m = m;
+  f.inj_vals = q;
+  f.mode = PROBE_UTT;
+  f.sketch_Y = Y;
+  f.sketch_partial = w + rf_layout(P).partial;
+  f.sketch_seed = seed;
+  return run_sweep<T>(P, f, src_t, none, w, st);
+}
+
+extern "C" rtm_status rtm_sketch(const rtm_plan *P, const void *m, const double *src_pos,
+                                 const void *q, uint64_t seed, double *Y, void *work,
+                                 size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  if ((s = check_rf(P, work_bytes))) return s;
+  if (!Y) return fail(RTM_E_ARG, "Y is NULL");
+  if (P->d.nsrc > 0 && (!src_pos || !q)) return fail(RTM_E_ARG, "src_pos and q are required");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(work);
+  if (P->d.field_dtype == RTM_F64) return sketch_impl<double>(P, m, src_pos, q, seed, Y, w, st);
+  return sketch_impl<float>(P, m, src_pos, q, seed, Y, w, st);
+}
+
+extern "C" rtm_status rtm_orthonormalize(const rtm_plan *P, const double *Y, void *Q, void *work,
+                                         size_t work_bytes, rtm_stream stream) {
+  g_last_error.clear();
+  if (!P || !Y || !Q || !work) return fail(RTM_E_ARG, "NULL argument");
+  rtm_status s = check_rf(P, work_bytes);
+  if (s) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  double *V = reinterpret_cast<double *>(static_cast<char *>(work) + rf_layout(P).V);
+  if (P->d.field_dtype == RTM_F64)
+    HIP_TRY(launch_orthonormalize<double>(Y, P->d.nt, P->d.r, V, static_cast<double *>(Q), st));
+  else
+    HIP_TRY(launch_orthonormalize<float>(Y, P->d.nt, P->d.r, V, static_cast<float *>(Q), st));
+  return RTM_OK;
+}
+
+extern "C" rtm_status fwi_gradient_rf(const rtm_plan *P, const void *m, const double *src_pos,
+                                      const void *q, const double *rec_pos, const void *d_obs,
+                                      uint64_t seed, void *Q, void *Ubar, void *Vbar, void *resid,
+                                      void *grad, double *misfit, void *work, size_t work_bytes,
+                                      rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  if ((s = check_rf(P, work_bytes))) return s;
+  if (!src_pos || !q || !rec_pos || !d_obs || !Q || !Ubar || !Vbar || !resid || !grad || !misfit)
+    return fail(RTM_E_ARG, "fwi_gradient_rf needs every array");
+  if (P->d.probe_dtype != P->d.field_dtype)
+    return fail(RTM_E_UNSUPPORTED, "range-finder probes are real: the probe dtype must be the "
+                                   "field dtype (F32 or F64)");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(work);
+  double *Y = reinterpret_cast<double *>(w + rf_layout(P).Y);
+  if (P->d.field_dtype == RTM_F64) {
+    if ((s = sketch_impl<double>(P, m, src_pos, q, seed, Y, w, st))) return s;
+    if ((s = rtm_orthonormalize(P, Y, Q, work, work_bytes, stream))) return s;
+    return gradient_impl<double>(P, m, src_pos, q, rec_pos, d_obs, Q, RTM_F64, Ubar, Vbar, resid,
+                                 grad, misfit, work, st, -1.0);
+  }
+  if ((s = sketch_impl<float>(P, m, src_pos, q, seed, Y, w, st))) return s;
+  if ((s = rtm_orthonormalize(P, Y, Q, work, work_bytes, stream))) return s;
+  return gradient_impl<float>(P, m, src_pos, q, rec_pos, d_obs, Q, RTM_F32, Ubar, Vbar, resid,
+                              grad, misfit, work, st, -1.0);
 }
 
 // ---------------------------------------------------------------------------

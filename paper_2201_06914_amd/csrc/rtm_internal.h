@@ -118,6 +118,17 @@ hipError_t launch_stencil_epi(int ndim, const StepArgs<T> &a, int variant, int t
 template <typename T>
 hipError_t launch_inject_epi(const StepArgs<T> &a, const PointTables<T> &pt, const T *vals,
                              T *field, int epi, const EpiArgs<T> &e, hipStream_t st);
+// range-finder probes: space sketch of one k-step block into rows zrow0 ..
+// zrow0 + kb - 1 of Y [nt][r] (FP64), partial scratch of
+// sketch_partial_elems(N, kb, r) elements of T; orthonormal columns of Y into
+// Q (V: FP64 scratch of nt x r)
+int64_t sketch_grid(int64_t N);
+int64_t sketch_partial_elems(int64_t N, int kb, int r);
+template <typename T>
+hipError_t launch_sketch(const ProbeArgs<T> &p, uint64_t seed, void *partial, double *Y,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_orthonormalize(const double *Y, int nt, int r, double *V, T *Q, hipStream_t st);
 // batched sweep step (all shots, one launch each): stencil over the tile
 // table, then injection / sampling of level s+1 for time index n
 template <typename T>

@@ -130,6 +130,50 @@ def test_calls_reject_before_launch(L):
     L.rtm_plan_destroy(h)
 
 
+@pytest.mark.parametrize("kw,code", [
+    (dict(r=300, k_block=16), 7),                    # r > 256
+    (dict(r=128, k_block=96), 7),                    # k * r > 8192
+    (dict(r=200, k_block=40), 7),                    # FP32: ceil(k/32) ceil(r/32) = 14 > 8
+])
+def test_range_finder_limits_rejected_on_host(L, kw, code):
+    """The sketch limits are checked before any launch (fake addresses)."""
+    c, h = _create(L, **kw)
+    assert c == 0, L.rtm_last_error()
+    n = ctypes.c_size_t()
+    assert L.rtm_rf_workspace_bytes(h, ctypes.byref(n)) == 0
+    fake = ctypes.c_void_p(1 << 20)
+    src = np.array([[8.0, 10.0, 20.0]])
+    sp = src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.rtm_sketch(h, fake, sp, fake, 1, fake, fake, n.value, None) == code
+    assert b"sketch" in L.rtm_last_error()
+    L.rtm_plan_destroy(h)
+
+
+def test_range_finder_workspace_and_probe_dtype_checks(L):
+    from paper_2201_06914_amd import _lib
+    c, h = _create(L)
+    n, base = ctypes.c_size_t(), ctypes.c_size_t()
+    L.rtm_rf_workspace_bytes(h, ctypes.byref(n))
+    L.rtm_plan_workspace_bytes(h, ctypes.byref(base))
+    assert n.value > base.value
+    fake = ctypes.c_void_p(1 << 20)
+    dp = ctypes.POINTER(ctypes.c_double)
+    src = np.array([[8.0, 10.0, 20.0]])
+    rec = np.array([[8.0, 10.0, 20.0 + k] for k in range(4)])
+    sp, rp = src.ctypes.data_as(dp), rec.ctypes.data_as(dp)
+    # too small for the sketch scratch
+    assert L.rtm_sketch(h, fake, sp, fake, 1, fake, fake, base.value, None) == 5
+    # BF16 probe plan: range-finder probes are real
+    assert L.fwi_gradient_rf(h, fake, sp, fake, rp, fake, 1, fake, fake, fake, fake, fake, fake,
+                             fake, n.value, None) == 7
+    L.rtm_plan_destroy(h)
+    c, h = _create(L, probe_dtype=_lib.RTM_F32)
+    L.rtm_rf_workspace_bytes(h, ctypes.byref(n))
+    assert L.fwi_gradient_rf(h, fake, sp, fake, rp, fake, 1, fake, None, fake, fake, fake, fake,
+                             fake, n.value, None) == 1      # Ubar missing
+    L.rtm_plan_destroy(h)
+
+
 def test_python_binding_is_marshalling_only():
     """Every numerical step of the sweeps is in librtm; the binding holds no
     stencil, probing or imaging arithmetic (no torch math calls on tensors)."""
