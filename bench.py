@@ -262,8 +262,35 @@ def bench_rsweep(n: int, nt: int, variant: int):
         del B, outs, work, shots
         torch.cuda.empty_cache()
         print(f"rsweep: r={r} done", file=sys.stderr, flush=True)
+    # range-finder probes: Q = orth(H Omega) per shot, FP32 probing, scale -1
+    rf_rows = []
+    for r in (16, 32, 64):
+        pr = P.Plan(P.PlanSpec(3, (n, n, n), h, dt, nt, nb, 4500.0, 1e-3, 4500.0, "f32", "f32",
+                               r, 32, 1, rec.shape[0]))
+        wb = P.rf_workspace_bytes(pr)
+        rwork = torch.empty(wb, dtype=torch.uint8, device="cuda")
+
+        def rf_all():
+            g = torch.zeros(N, dtype=torch.float64, device="cuda")
+            for i, (s, d) in enumerate(zip(srcs, dobs)):
+                o = P.fwi_gradient_rf(pr, mb, s, q, rec, d, 300 + 10 * i + r, work=rwork)
+                g += o["grad"].double()
+                del o
+            return g
+        P.set_stencil_variant(variant)
+        gq, t_rf = timed(rf_all)
+        err = float(torch.linalg.vector_norm(gq - ge) / torch.linalg.vector_norm(ge))
+        cos = float((gq * ge).sum() / (torch.linalg.vector_norm(gq) * torch.linalg.vector_norm(ge)))
+        rf_rows.append({"r": r, "ms": round(t_rf, 1), "speedup_vs_exact": round(t_exact / t_rf, 3),
+                        "grad_rel_err": round(err, 5), "cosine": round(cos, 5),
+                        "fd_rel_diff": round(abs(float((gq * dm.double()).sum()) - fd) / abs(fd), 5),
+                        "memory_gb_per_shot": round((wb + 2 * r * pr.Npad * 4) / 1e9, 2)})
+        del rwork, gq
+        torch.cuda.empty_cache()
+        print(f"rsweep: range finder r={r} done", file=sys.stderr, flush=True)
     return {"workload": f"{n}^3 salt model, 4 shots, nt={nt}, h=12.5 m, 10 Hz, gradient at the "
                         f"smoothed model, d_obs modelled from the true model",
+            "range_finder": rf_rows,
             "exact_ms": round(t_exact, 1),
             "exact_memory_gb_per_shot": round(ewb / 1e9, 2),
             "full_history_gb_per_shot": round(nt * N * 4 / 1e9, 1),
