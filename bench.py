@@ -262,10 +262,11 @@ def bench_rsweep(n: int, nt: int, variant: int):
         del B, outs, work, shots
         torch.cuda.empty_cache()
         print(f"rsweep: r={r} done", file=sys.stderr, flush=True)
-    # range-finder probes: Q = orth(H Omega) per shot, FP32 probing, scale -1
+    # range-finder probes: Q = orth(H Omega) per shot (space sketch on MFMA),
+    # real probes split bf16 hi + lo on MFMA, fused imaging, scale -1
     rf_rows = []
     for r in (16, 32, 64):
-        pr = P.Plan(P.PlanSpec(3, (n, n, n), h, dt, nt, nb, 4500.0, 1e-3, 4500.0, "f32", "f32",
+        pr = P.Plan(P.PlanSpec(3, (n, n, n), h, dt, nt, nb, 4500.0, 1e-3, 4500.0, "f32", "bf16x2",
                                r, 32, 1, rec.shape[0]))
         wb = P.rf_workspace_bytes(pr)
         rwork = torch.empty(wb, dtype=torch.uint8, device="cuda")
@@ -284,7 +285,7 @@ def bench_rsweep(n: int, nt: int, variant: int):
         rf_rows.append({"r": r, "ms": round(t_rf, 1), "speedup_vs_exact": round(t_exact / t_rf, 3),
                         "grad_rel_err": round(err, 5), "cosine": round(cos, 5),
                         "fd_rel_diff": round(abs(float((gq * dm.double()).sum()) - fd) / abs(fd), 5),
-                        "memory_gb_per_shot": round((wb + 2 * r * pr.Npad * 4) / 1e9, 2)})
+                        "memory_gb_per_shot": round((wb + r * pr.Npad * 4) / 1e9, 2)})
         del rwork, gq
         torch.cuda.empty_cache()
         print(f"rsweep: range finder r={r} done", file=sys.stderr, flush=True)

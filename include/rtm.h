@@ -164,8 +164,10 @@ const char *rtm_last_error(void);
  *                                 w is q = w / h^ndim)
  *   rec_pos  host   [nrec][3]
  *   d_pred   device [nt][nrec]    d[n] = Pr u^{n+1}; may be NULL
- *   Z        device [nt][r]       dtype z_dtype (RTM_I8 for the BF16 paths,
- *                                 else RTM_I8 or the field dtype)
+ *   Z        device [nt][r]       dtype z_dtype: RTM_I8 (+-1) on every path;
+ *                                 real probes as RTM_F32 on the BF16X2 path
+ *                                 (split into bf16 hi + lo) or in the field
+ *                                 dtype on the F32 / F64 paths
  *   Ubar     device [r*Npad]      tile-major, overwritten
  *   final_state device [2][N]     u^{nt}, u^{nt-1}; may be NULL
  */
@@ -236,9 +238,10 @@ rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_p
  *                     remainder falls below 1e-12 of its norm is zero.
  * fwi_gradient_rf:    sketch, orthonormalize into Q, then the probed gradient
  *                     of fwi_gradient with Z = Q and scale -1 (Ubar, Vbar,
- *                     resid, grad, misfit as there; Vbar is required).  The
- *                     probes are real, so the plan's probe dtype must equal its
- *                     field dtype (F32 or F64). */
+ *                     resid, grad, misfit as there).  The probes are real: the
+ *                     plan's probe dtype is BF16X2 (Q split into bf16 hi + lo
+ *                     on MFMA; Vbar NULL selects fused imaging) or equals its
+ *                     field dtype (F32 / F64 FMA path, Vbar required). */
 rtm_status rtm_rf_workspace_bytes(const rtm_plan *plan, size_t *bytes);
 rtm_status rtm_sketch(const rtm_plan *plan, const void *m, const double *src_pos, const void *q,
                       uint64_t seed, double *Y, void *work, size_t work_bytes,

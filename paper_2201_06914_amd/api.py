@@ -499,13 +499,19 @@ def rtm_orthonormalize(plan: Plan, Y, work=None) -> torch.Tensor:
     return Q
 
 
-def fwi_gradient_rf(plan: Plan, m, src_pos, q, rec_pos, d_obs, seed: int, work=None) -> dict:
-    """Probed gradient with range-finder probes Q = orth(H Omega), scale -1."""
+def fwi_gradient_rf(plan: Plan, m, src_pos, q, rec_pos, d_obs, seed: int, fused=None,
+                    work=None) -> dict:
+    """Probed gradient with range-finder probes Q = orth(H Omega), scale -1.
+    fused (default: on for BF16X2 plans) folds the imaging into the adjoint
+    probe blocks and stores no Vbar."""
     s = plan.spec
     dev = m.device
     work = _rf_work(plan, work, dev)
+    if fused is None:
+        fused = s.probe == "bf16x2"
     Q = torch.empty((s.nt, s.r), dtype=plan.dtype, device=dev)
-    U, V = plan.empty_bar(dev), plan.empty_bar(dev)
+    U = plan.empty_bar(dev)
+    V = None if fused else plan.empty_bar(dev)
     res = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev)
     g = torch.empty(plan.N, dtype=plan.dtype, device=dev)
     J = torch.empty(1, dtype=torch.float64, device=dev)

@@ -115,6 +115,39 @@ __device__ __forceinline__ void fill_probe_lds(const ProbeArgs<float> &p, const 
   __syncthreads();
 }
 
+// Real probes Q (range finder): the same A-operand order, each value split
+// into bf16 hi (ldsA[e]) and bf16 lo (ldsA[MT KS 64 + e]).
+__device__ __forceinline__ void fill_probe_lds_q(const ProbeArgs<float> &p, const float *Z, int MT,
+                                                 int KS, bf16x8 *ldsA) {
+  const int n = MT * KS * 64;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int l = e & 63;
+    const int ks = (e >> 6) % KS;
+    const int mt = (e >> 6) / KS;
+    const int i = mt * 32 + (l & 31);
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int t = ks * 16 + 8 * (l >> 5) + q;
+      float zv = 0.f;
+      if (t < p.kb && i < p.r) zv = Z[(int64_t)(p.zrow0 + p.zdir * t) * p.r + i];
+      const __bf16 hb = (__bf16)zv;
+      hi[q] = hb;
+      lo[q] = (__bf16)(zv - (float)hb);
+    }
+    ldsA[e] = hi;
+    ldsA[n + e] = lo;
+  }
+  __syncthreads();
+}
+
+template <bool QF>
+__device__ __forceinline__ void fill_a(const ProbeArgs<float> &p, const void *Z, int MT, int KS,
+                                       bf16x8 *ldsA) {
+  if constexpr (QF) fill_probe_lds_q(p, static_cast<const float *>(Z), MT, KS, ldsA);
+  else fill_probe_lds(p, static_cast<const int8_t *>(Z), MT, KS, ldsA);
+}
+
 // The B operand of step chunk ks for this lane: its 8 probed values (local
 // steps tb .. tb+7, tb = 16 ks + 8 half), rounded to bf16 (hi) and, with
 // SPLIT, the bf16 rounding of the remainder (lo).  FAST: no masking needed.
@@ -156,14 +189,15 @@ __device__ __forceinline__ void probe_operand(const ProbeArgs<float> &p, int ks,
 // Fast kernel: full 32-cell tiles [0, tile_end), kb == 16 KS, MT % MTC == 0 -
 // no load or store is masked.  MTC row tiles (32 probes each) are accumulated
 // together, so their 16 x MTC loads per lane are in flight at once.
-template <int KS, bool SPLIT, int MODE, bool FUSED, int MTC>
+template <int KS, bool SPLIT, int MODE, bool FUSED, int MTC, bool QF>
 __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
-                                                         const int8_t *__restrict__ Z, int MT,
+                                                         const void *__restrict__ Z, int MT,
                                                          const float *__restrict__ Uf,
                                                          float *__restrict__ img, float scale,
                                                          int64_t tile_end) {
   extern __shared__ bf16x8 ldsA[];
-  fill_probe_lds(p, Z, MT, KS, ldsA);
+  fill_a<QF>(p, Z, MT, KS, ldsA);
+  const int alo_off = MT * KS * 64;  // QF: the lo halves of A
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int col = lane & 31;
@@ -215,9 +249,12 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
         }
 #pragma unroll
         for (int j = 0; j < MTC; ++j) {
-          const bf16x8 a = ldsA[((mt0 + j) * KS + ks) * 64 + lane];
+          const int ai = ((mt0 + j) * KS + ks) * 64 + lane;
+          const bf16x8 a = ldsA[ai];
           acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bhi, acc[j], 0, 0, 0);
           if (SPLIT) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo, acc[j], 0, 0, 0);
+          if (QF)
+            acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ldsA[alo_off + ai], bhi, acc[j], 0, 0, 0);
         }
       }
       if (FUSED) {
@@ -242,14 +279,15 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
 
 // Edge kernel: tiles [tile_begin, ntiles) with any masking (ragged last tile,
 // a block shorter than 16 KS, r not a multiple of 32).  One row tile at a time.
-template <int KS, bool SPLIT, int MODE, bool FUSED>
+template <int KS, bool SPLIT, int MODE, bool FUSED, bool QF>
 __global__ __launch_bounds__(256) void k_probe_mfma_edge(ProbeArgs<float> p,
-                                                         const int8_t *__restrict__ Z, int MT,
+                                                         const void *__restrict__ Z, int MT,
                                                          const float *__restrict__ Uf,
                                                          float *__restrict__ img, float scale,
                                                          int64_t tile_begin) {
   extern __shared__ bf16x8 ldsA[];
-  fill_probe_lds(p, Z, MT, KS, ldsA);
+  fill_a<QF>(p, Z, MT, KS, ldsA);
+  const int alo_off = MT * KS * 64;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int col = lane & 31;
@@ -280,9 +318,11 @@ __global__ __launch_bounds__(256) void k_probe_mfma_edge(ProbeArgs<float> p,
       }
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8 a = ldsA[(mt * KS + ks) * 64 + lane];
+        const int ai = (mt * KS + ks) * 64 + lane;
+        const bf16x8 a = ldsA[ai];
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bhi[ks], acc, 0, 0, 0);
         if (SPLIT) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[ks], acc, 0, 0, 0);
+        if (QF) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ldsA[alo_off + ai], bhi[ks], acc, 0, 0, 0);
       }
       float *Uo = p.bar + tbase + mt * 32 * 32 + loff;
 #pragma unroll
@@ -307,10 +347,10 @@ struct FuseArgs {
   float scale = 0.f;
 };
 
-template <int KS, bool SPLIT, int MODE, bool FUSED>
-static void launch_probe_kernels(const ProbeArgs<float> &p, const int8_t *Z, int MT,
+template <int KS, bool SPLIT, int MODE, bool FUSED, bool QF>
+static void launch_probe_kernels(const ProbeArgs<float> &p, const void *Z, int MT,
                                  const FuseArgs &f, hipStream_t st) {
-  const size_t shm = sizeof(bf16x8) * (size_t)MT * KS * 64;
+  const size_t shm = sizeof(bf16x8) * (size_t)MT * KS * 64 * (QF ? 2 : 1);
   const int64_t ntiles = (p.N + 31) / 32;
   const int64_t nfull = p.N / 32;
   auto grid_for = [](int64_t tiles) -> unsigned {
@@ -321,54 +361,56 @@ static void launch_probe_kernels(const ProbeArgs<float> &p, const int8_t *Z, int
   const bool fastk = p.kb == 16 * KS && p.r % 32 == 0;
   int64_t done = 0;
   if (fastk && nfull > 0 && MT % 4 == 0 && !FUSED) {
-    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 4>), dim3(grid_for(nfull)),
+    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 4, QF>), dim3(grid_for(nfull)),
                        dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
     done = nfull;
   } else if (fastk && nfull > 0 && MT % 2 == 0) {
-    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 2>), dim3(grid_for(nfull)),
+    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 2, QF>), dim3(grid_for(nfull)),
                        dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
     done = nfull;
   }
   if (done < ntiles)
-    hipLaunchKernelGGL((k_probe_mfma_edge<KS, SPLIT, MODE, FUSED>), dim3(grid_for(ntiles - done)),
+    hipLaunchKernelGGL((k_probe_mfma_edge<KS, SPLIT, MODE, FUSED, QF>), dim3(grid_for(ntiles - done)),
                        dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, done);
 }
 
-template <int KS, bool SPLIT>
-static void launch_mfma_mode(const ProbeArgs<float> &p, const int8_t *Z, int MT,
+template <int KS, bool SPLIT, bool QF>
+static void launch_mfma_mode(const ProbeArgs<float> &p, const void *Z, int MT,
                              const FuseArgs &f, hipStream_t st) {
   if (f.img) {  // fused imaging: adjoint levels only
-    launch_probe_kernels<KS, SPLIT, PROBE_NEW, true>(p, Z, MT, f, st);
+    launch_probe_kernels<KS, SPLIT, PROBE_NEW, true, QF>(p, Z, MT, f, st);
     return;
   }
   switch (p.mode) {
-    case PROBE_UTT: launch_probe_kernels<KS, SPLIT, PROBE_UTT, false>(p, Z, MT, f, st); break;
-    case PROBE_NEW: launch_probe_kernels<KS, SPLIT, PROBE_NEW, false>(p, Z, MT, f, st); break;
-    default: launch_probe_kernels<KS, SPLIT, PROBE_CUR, false>(p, Z, MT, f, st);
+    case PROBE_UTT: launch_probe_kernels<KS, SPLIT, PROBE_UTT, false, QF>(p, Z, MT, f, st); break;
+    case PROBE_NEW: launch_probe_kernels<KS, SPLIT, PROBE_NEW, false, QF>(p, Z, MT, f, st); break;
+    default: launch_probe_kernels<KS, SPLIT, PROBE_CUR, false, QF>(p, Z, MT, f, st);
   }
 }
 
 template <int KS>
-static void launch_mfma_ks(const ProbeArgs<float> &p, const int8_t *Z, bool split, int MT,
-                           const FuseArgs &f, hipStream_t st) {
-  if (split)
-    launch_mfma_mode<KS, true>(p, Z, MT, f, st);
+static void launch_mfma_ks(const ProbeArgs<float> &p, const void *Z, bool zf32, bool split,
+                           int MT, const FuseArgs &f, hipStream_t st) {
+  if (zf32)
+    launch_mfma_mode<KS, true, true>(p, Z, MT, f, st);
+  else if (split)
+    launch_mfma_mode<KS, true, false>(p, Z, MT, f, st);
   else
-    launch_mfma_mode<KS, false>(p, Z, MT, f, st);
+    launch_mfma_mode<KS, false, false>(p, Z, MT, f, st);
 }
 
-hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const int8_t *Z, bool split,
+hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const void *Z, bool zf32, bool split,
                              const float *Uf, float *img, float scale, hipStream_t st) {
   const FuseArgs f{Uf, img, scale};
   const int MT = (p.r + 31) / 32;
   int KS = (p.kb + 15) / 16;
   KS = KS <= 1 ? 1 : KS <= 2 ? 2 : KS <= 4 ? 4 : 8;
-  if (p.kb > 128) return hipErrorInvalidValue;
+  if (p.kb > 128 || (zf32 && !split)) return hipErrorInvalidValue;
   switch (KS) {
-    case 1: launch_mfma_ks<1>(p, Z, split, MT, f, st); break;
-    case 2: launch_mfma_ks<2>(p, Z, split, MT, f, st); break;
-    case 4: launch_mfma_ks<4>(p, Z, split, MT, f, st); break;
-    default: launch_mfma_ks<8>(p, Z, split, MT, f, st); break;
+    case 1: launch_mfma_ks<1>(p, Z, zf32, split, MT, f, st); break;
+    case 2: launch_mfma_ks<2>(p, Z, zf32, split, MT, f, st); break;
+    case 4: launch_mfma_ks<4>(p, Z, zf32, split, MT, f, st); break;
+    default: launch_mfma_ks<8>(p, Z, zf32, split, MT, f, st); break;
   }
   return hipGetLastError();
 }

@@ -498,8 +498,7 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       prof_begin(io.adjoint ? KT_PROBE_ADJ : KT_PROBE, s, st, &tp);
       if constexpr (sizeof(T) == 4) {
         if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
-          HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io.Z),
-                                    d.probe_dtype == RTM_BF16X2,
+          HIP_TRY(launch_probe_mfma(p, io.Z, io.zt == RTM_F32, d.probe_dtype == RTM_BF16X2,
                                     static_cast<const float *>(io.fuse_U),
                                     static_cast<float *>(io.fuse_img), (float)io.fuse_scale, st));
         } else {
@@ -539,8 +538,11 @@ static rtm_status check_probe(const rtm_plan *P, const void *Z, rtm_dtype zt, co
     return fail(RTM_E_ARG, "Z and the compressed field must both be given or both be NULL");
   if (!Z) return RTM_OK;
   const rtm_dtype pd = P->d.probe_dtype;
-  if (pd == RTM_BF16 || pd == RTM_BF16X2) {
-    if (zt != RTM_I8) return fail(RTM_E_DTYPE, "the BF16 probe paths need +-1 probes (RTM_I8)");
+  if (pd == RTM_BF16) {
+    if (zt != RTM_I8) return fail(RTM_E_DTYPE, "the BF16 probe path needs +-1 probes (RTM_I8)");
+  } else if (pd == RTM_BF16X2) {
+    if (zt != RTM_I8 && zt != RTM_F32)
+      return fail(RTM_E_DTYPE, "the BF16X2 probe path takes RTM_I8 (+-1) or RTM_F32 probes");
   } else if (zt != RTM_I8 && zt != P->d.field_dtype) {
     return fail(RTM_E_DTYPE, "Z must be RTM_I8 or the field dtype");
   }
@@ -867,11 +869,14 @@ extern "C" rtm_status fwi_gradient_rf(const rtm_plan *P, const void *m, const do
   rtm_status s = check_common(P, m, work, work_bytes);
   if (s) return s;
   if ((s = check_rf(P, work_bytes))) return s;
-  if (!src_pos || !q || !rec_pos || !d_obs || !Q || !Ubar || !Vbar || !resid || !grad || !misfit)
-    return fail(RTM_E_ARG, "fwi_gradient_rf needs every array");
-  if (P->d.probe_dtype != P->d.field_dtype)
-    return fail(RTM_E_UNSUPPORTED, "range-finder probes are real: the probe dtype must be the "
-                                   "field dtype (F32 or F64)");
+  if (!src_pos || !q || !rec_pos || !d_obs || !Q || !Ubar || !resid || !grad || !misfit)
+    return fail(RTM_E_ARG, "fwi_gradient_rf needs every array except Vbar");
+  const rtm_dtype pd = P->d.probe_dtype;
+  if (pd != P->d.field_dtype && pd != RTM_BF16X2)
+    return fail(RTM_E_UNSUPPORTED, "range-finder probes are real: the probe dtype must be "
+                                   "BF16X2 or the field dtype");
+  if (!Vbar && pd != RTM_BF16X2)
+    return fail(RTM_E_UNSUPPORTED, "fused imaging (Vbar = NULL) needs the BF16X2 probe path");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(work);
   double *Y = reinterpret_cast<double *>(w + rf_layout(P).Y);
@@ -1354,8 +1359,7 @@ static rtm_status batch_enqueue(const rtm_batch *b, const rtm_shot_io *io, doubl
       p.bar = adj ? nullptr : static_cast<float *>(io[i].Ubar);
       p.inv_dt2 = (float)(1.0 / (d.dt * d.dt));
       p.mode = adj ? PROBE_NEW : PROBE_UTT;
-      HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io[i].Z),
-                                d.probe_dtype == RTM_BF16X2,
+      HIP_TRY(launch_probe_mfma(p, io[i].Z, false, d.probe_dtype == RTM_BF16X2,
                                 adj ? static_cast<const float *>(io[i].Ubar) : nullptr,
                                 adj ? static_cast<float *>(io[i].grad) : nullptr,
                                 (float)(-1.0 / d.r), st));
@@ -1580,8 +1584,7 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
         if constexpr (sizeof(T) == 4) {
           if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
             const float *Uf = io.fuse_img ? static_cast<const float *>(io.fuse_U) + f * barn : nullptr;
-            HIP_TRY(launch_probe_mfma(p, static_cast<const int8_t *>(io.Z),
-                                      d.probe_dtype == RTM_BF16X2, Uf,
+            HIP_TRY(launch_probe_mfma(p, io.Z, io.zt == RTM_F32, d.probe_dtype == RTM_BF16X2, Uf,
                                       static_cast<float *>(io.fuse_img), (float)io.fuse_scale, st));
             continue;
           }

@@ -69,11 +69,13 @@ __device__ __forceinline__ void sign_words(int64_t x, uint64_t seed, int nw, uin
 // MFMA sketch (FP32 levels).  MT = ceil(kb / 32) row tiles (steps), NT =
 // ceil(r / 32) column tiles (probes), MT * NT <= 8.
 // ---------------------------------------------------------------------------
-template <int MT, int NT>
+// CELLS cells per staged chunk (256 for blocks of up to 32 steps, 64 above):
+// every thread computes one cell's sign words, every wave CELLS / 64 K steps.
+template <int MT, int NT, int CELLS>
 __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_t seed,
                                                      int64_t chunk, float *__restrict__ partial) {
-  __shared__ float Ll[130 * SK_CELLS];            // levels s0 - 1 .. s0 + kb, [lev][c]
-  __shared__ uint32_t Lb[SK_MAXW * SK_CELLS];     // sign words, [word][c]
+  __shared__ float Ll[(MT * 32 + 2) * CELLS];     // levels s0 - 1 .. s0 + kb, [lev][c]
+  __shared__ uint32_t Lb[SK_MAXW * CELLS];        // sign words, [word][c]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
   const int nw = (p.r + 31) >> 5;
@@ -85,15 +87,20 @@ __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_
     for (int v = 0; v < 16; ++v) acc[a][v] = 0.f;
   const int64_t xb = (int64_t)blockIdx.x * chunk;
   const int64_t xe = xb + chunk < p.N ? xb + chunk : p.N;
-  for (int64_t c0 = xb; c0 < xe; c0 += SK_CELLS) {
-    for (int e = threadIdx.x; e < nlev * SK_CELLS; e += 256) {
-      const int lv = e / SK_CELLS, c = e % SK_CELLS;
-      const int64_t x = c0 + c;
-      Ll[e] = x < xe ? ring_level(p, p.s0 - 1 + lv)[x] : 0.f;
+  for (int64_t c0 = xb; c0 < xe; c0 += CELLS) {
+    for (int lv = 0; lv < nlev; ++lv) {
+      const float *L = ring_level(p, p.s0 - 1 + lv);
+#pragma unroll
+      for (int c = threadIdx.x; c < CELLS; c += 256) {
+        const int64_t x = c0 + c;
+        Ll[lv * CELLS + c] = x < xe ? L[x] : 0.f;
+      }
     }
-    if (threadIdx.x < SK_CELLS) sign_words(c0 + threadIdx.x, seed, nw, Lb + threadIdx.x, SK_CELLS);
+    for (int c = threadIdx.x; c < CELLS; c += 256) sign_words(c0 + c, seed, nw, Lb + c, CELLS);
     __syncthreads();
-    const int cb = 16 * wave + 8 * half;  // this lane's 8 cells of the K step
+#pragma unroll
+    for (int ks = 0; ks < CELLS / 64; ++ks) {
+    const int cb = 64 * ks + 16 * wave + 8 * half;  // this lane's 8 cells of the K step
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int t = mt * 32 + col;
@@ -102,8 +109,8 @@ __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_
       for (int v = 0; v < 8; ++v) {
         float d2 = 0.f;
         if (t < p.kb) {
-          const float *L = Ll + t * SK_CELLS + cb + v;
-          d2 = (L[2 * SK_CELLS] - 2.f * L[SK_CELLS] + L[0]) * p.inv_dt2;
+          const float *L = Ll + t * CELLS + cb + v;
+          d2 = (L[2 * CELLS] - 2.f * L[CELLS] + L[0]) * p.inv_dt2;
         }
         const __bf16 hb = (__bf16)d2;
         ahi[v] = hb;
@@ -115,7 +122,7 @@ __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_
         sk_bf16x8 b;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
-          const uint32_t wd = Lb[(i >> 5) * SK_CELLS + cb + v];
+          const uint32_t wd = Lb[(i >> 5) * CELLS + cb + v];
           const float s = i < p.r ? (((wd >> (i & 31)) & 1u) ? -1.f : 1.f) : 0.f;
           b[v] = (__bf16)s;
         }
@@ -123,6 +130,7 @@ __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_
         acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, b, acc[a], 0, 0, 0);
         acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, b, acc[a], 0, 0, 0);
       }
+    }
     }
     __syncthreads();
   }
@@ -221,8 +229,12 @@ int64_t sketch_partial_elems(int64_t N, int kb, int r) {
 template <int MT, int NT>
 static void sketch_mfma(const ProbeArgs<float> &p, uint64_t seed, int64_t g, int64_t chunk,
                         float *partial, hipStream_t st) {
-  hipLaunchKernelGGL((k_sketch_mfma<MT, NT>), dim3((unsigned)g), dim3(256), 0, st, p, seed,
-                     chunk, partial);
+  if constexpr (MT == 1)
+    hipLaunchKernelGGL((k_sketch_mfma<MT, NT, 256>), dim3((unsigned)g), dim3(256), 0, st, p, seed,
+                       chunk, partial);
+  else
+    hipLaunchKernelGGL((k_sketch_mfma<MT, NT, 64>), dim3((unsigned)g), dim3(256), 0, st, p, seed,
+                       chunk, partial);
 }
 
 template <typename T>
@@ -231,7 +243,7 @@ hipError_t launch_sketch(const ProbeArgs<T> &p, uint64_t seed, void *partial, do
   if (p.kb > 128 || p.r > 256 || p.kb * p.r > 8192) return hipErrorInvalidValue;
   const int64_t g = sketch_grid(p.N);
   int64_t chunk = (p.N + g - 1) / g;
-  chunk = (chunk + SK_CELLS - 1) / SK_CELLS * SK_CELLS;
+  chunk = (chunk + 255) / 256 * 256;   // whole chunks of either staging width
   const int kr = p.kb * p.r;
   int nparts;
   if constexpr (sizeof(T) == 4) {

@@ -117,8 +117,8 @@ def test_calls_reject_before_launch(L):
     # Z without Ubar
     assert L.rtm_forward_probe(h, fake, sp, fake, rp, fake, fake, _lib.RTM_I8, 1, None, None,
                                fake, n.value, None) == 1
-    # float Z on the BF16 path
-    assert L.rtm_forward_probe(h, fake, sp, fake, rp, fake, fake, _lib.RTM_F32, 1, fake, None,
+    # FP64 Z on the BF16X2 path (it takes RTM_I8 or RTM_F32)
+    assert L.rtm_forward_probe(h, fake, sp, fake, rp, fake, fake, _lib.RTM_F64, 1, fake, None,
                                fake, n.value, None) == 3
     # receiver outside the grid
     assert L.rtm_forward_probe(h, fake, sp, fake, rp, fake, fake, _lib.RTM_I8, 1, fake, None,
@@ -163,14 +163,23 @@ def test_range_finder_workspace_and_probe_dtype_checks(L):
     sp, rp = src.ctypes.data_as(dp), rec.ctypes.data_as(dp)
     # too small for the sketch scratch
     assert L.rtm_sketch(h, fake, sp, fake, 1, fake, fake, base.value, None) == 5
-    # BF16 probe plan: range-finder probes are real
+    L.rtm_plan_destroy(h)
+    # plain BF16 probe plan: real probes need the hi + lo split
+    c, h = _create(L, probe_dtype=_lib.RTM_BF16)
+    L.rtm_rf_workspace_bytes(h, ctypes.byref(n))
     assert L.fwi_gradient_rf(h, fake, sp, fake, rp, fake, 1, fake, fake, fake, fake, fake, fake,
                              fake, n.value, None) == 7
+    n2 = ctypes.c_size_t()
+    L.rtm_plan_workspace_bytes(h, ctypes.byref(n2))
+    assert L.rtm_forward_probe(h, fake, sp, fake, rp, fake, fake, _lib.RTM_F32, 1, fake, None,
+                               fake, n2.value, None) == 3
     L.rtm_plan_destroy(h)
     c, h = _create(L, probe_dtype=_lib.RTM_F32)
     L.rtm_rf_workspace_bytes(h, ctypes.byref(n))
     assert L.fwi_gradient_rf(h, fake, sp, fake, rp, fake, 1, fake, None, fake, fake, fake, fake,
                              fake, n.value, None) == 1      # Ubar missing
+    assert L.fwi_gradient_rf(h, fake, sp, fake, rp, fake, 1, fake, fake, None, fake, fake, fake,
+                             fake, n.value, None) == 7      # fused imaging needs BF16X2
     L.rtm_plan_destroy(h)
 
 

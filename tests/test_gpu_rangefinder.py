@@ -121,6 +121,46 @@ def test_fwi_gradient_rf_f32_3d_given_its_probes():
     assert e < 1e-4
 
 
+def test_rf_gradient_bf16x2_fused_given_its_probes():
+    """BF16X2 plan: the real probes are split into bf16 hi + lo on MFMA (three
+    products per step chunk) and the imaging is fused; compared through the
+    oracle run with the GPU's own Q (FP64, scale -1)."""
+    wl = synth.workload_small_3d(shape=(24, 22, 38), nt=80, nb=5)
+    g = Grid.of(wl)
+    r, seed = 32, 4
+    rng = np.random.default_rng(6)
+    d_obs = (0.05 * rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))).astype(np.float32)
+    plan = _plan(wl, "f32", "bf16x2", r, 32)
+    out = P.fwi_gradient_rf(plan, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32),
+                            wl.rec_pos, dev(d_obs, torch.float32), seed)
+    torch.cuda.synchronize()
+    assert out["Vbar"] is None
+    Q = host(out["Q"]).astype(np.float64)
+    _, g0, _, _ = oracle.probed_gradient(g, wl.m, wl.src_pos, wl.q, wl.rec_pos, d_obs, Q)
+    e = rel(host(out["grad"]), g0 * r)
+    say(f"  rf gradient BF16X2 fused given Q: {e:.2e}")
+    assert e < 1e-3
+
+
+@pytest.mark.parametrize("k", [16, 32, 20])
+def test_real_probes_on_mfma_equal_fma_path(k):
+    """Gaussian probes through fwi_gradient: BF16X2 (MFMA, hi + lo on both
+    operands; k = 20 takes the edge kernel) against the FP32 FMA path."""
+    wl = synth.workload_small_3d(shape=(20, 18, 40), nt=60, nb=4)
+    r = 32
+    rng = np.random.default_rng(12)
+    Zf = rng.standard_normal((wl.nt, r)).astype(np.float32)
+    d_obs = (0.05 * rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))).astype(np.float32)
+    args = (dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32), wl.rec_pos,
+            dev(d_obs, torch.float32), dev(Zf, torch.float32))
+    gm = P.fwi_gradient(_plan(wl, "f32", "bf16x2", r, k), *args, fused=True)
+    gv = P.fwi_gradient(_plan(wl, "f32", "f32", r, k), *args)
+    torch.cuda.synchronize()
+    e = rel(host(gm["grad"]), host(gv["grad"]))
+    say(f"  real probes MFMA vs FMA (k = {k}): {e:.2e}")
+    assert e < 2e-4
+
+
 def test_rf_gradient_equals_exact_when_rank_at_most_r():
     """N = 30 cells <= r = 30 < nt = 80 on the GPU (F64): the projected gradient
     equals the exact checkpointed gradient."""
