@@ -74,7 +74,10 @@ __device__ __forceinline__ void sign_words(int64_t x, uint64_t seed, int nw, uin
 template <int MT, int NT, int CELLS>
 __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_t seed,
                                                      int64_t chunk, float *__restrict__ partial) {
-  __shared__ float Ll[(MT * 32 + 2) * CELLS];     // levels s0 - 1 .. s0 + kb, [lev][c]
+  // levels s0 - 1 .. s0 + kb, [lev][c] with an odd row stride: the A operand
+  // reads one row per lane, so rows must fall in different banks
+  constexpr int LS = CELLS + 1;
+  __shared__ float Ll[(MT * 32 + 2) * LS];
   __shared__ uint32_t Lb[SK_MAXW * CELLS];        // sign words, [word][c]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5, col = lane & 31;
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_
 #pragma unroll
       for (int c = threadIdx.x; c < CELLS; c += 256) {
         const int64_t x = c0 + c;
-        Ll[lv * CELLS + c] = x < xe ? L[x] : 0.f;
+        Ll[lv * LS + c] = x < xe ? L[x] : 0.f;
       }
     }
     for (int c = threadIdx.x; c < CELLS; c += 256) sign_words(c0 + c, seed, nw, Lb + c, CELLS);
@@ -109,8 +112,8 @@ __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_
       for (int v = 0; v < 8; ++v) {
         float d2 = 0.f;
         if (t < p.kb) {
-          const float *L = Ll + t * CELLS + cb + v;
-          d2 = (L[2 * CELLS] - 2.f * L[CELLS] + L[0]) * p.inv_dt2;
+          const float *L = Ll + t * LS + cb + v;
+          d2 = (L[2 * LS] - 2.f * L[LS] + L[0]) * p.inv_dt2;
         }
         const __bf16 hb = (__bf16)d2;
         ahi[v] = hb;
@@ -159,7 +162,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_sketch_vec(ProbeArgs<T> p, uint64_t seed, int64_t chunk,
                                                     T *__restrict__ partial) {
   constexpr int CW = 32;                        // cells per staged chunk
-  __shared__ T Ls[128 * CW];                    // u_tt [t][c]
+  __shared__ T Ls[128 * CW];                    // u_tt [t][c] (rows read broadcast)
   __shared__ uint32_t Lb[SK_MAXW * CW];         // [word][c]
   const int kr = p.kb * p.r, nw = (p.r + 31) >> 5;
   T acc[32];
@@ -202,15 +205,25 @@ __global__ __launch_bounds__(256) void k_sketch_vec(ProbeArgs<T> p, uint64_t see
   }
 }
 
-// Y[row0 + t][i] = sum over nparts partials (fixed order)
+// Two fixed-order stages: group g (blockIdx.y) sums partials g, g + G, ...
+// into stage[g][q]; then Y[row0 + t][i] = sum over g of stage[g][q].
+constexpr int SK_GROUPS = 64;
 template <typename PT>
 __global__ __launch_bounds__(256) void k_sketch_reduce(const PT *__restrict__ partial, int nparts,
-                                                       int kb, int r, int row0,
-                                                       double *__restrict__ Y) {
+                                                       int kr, double *__restrict__ stage) {
   const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= kb * r) return;
+  if (q >= kr) return;
   double s = 0.0;
-  for (int w = 0; w < nparts; ++w) s += (double)partial[(int64_t)w * kb * r + q];
+  for (int w = blockIdx.y; w < nparts; w += SK_GROUPS) s += (double)partial[(int64_t)w * kr + q];
+  stage[(int64_t)blockIdx.y * kr + q] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sketch_final(const double *__restrict__ stage, int kr,
+                                                      int r, int row0, double *__restrict__ Y) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= kr) return;
+  double s = 0.0;
+  for (int g = 0; g < SK_GROUPS; ++g) s += stage[(int64_t)g * kr + q];
   const int t = q / r, i = q - t * r;
   Y[(int64_t)(row0 + t) * r + i] = s;
 }
@@ -221,9 +234,11 @@ int64_t sketch_grid(int64_t N) {
 }
 
 // elements of the partial buffer launch_sketch needs (floats for the MFMA
-// path, field elements for the vector path; four per workgroup covers both)
+// path, field elements for the vector path; four per workgroup covers both),
+// followed by the FP64 stage of the reduction (SK_GROUPS rows, counted in
+// doubles = two floats each, so sized for either element type)
 int64_t sketch_partial_elems(int64_t N, int kb, int r) {
-  return sketch_grid(N) * 4 * (int64_t)kb * r;
+  return (sketch_grid(N) * 4 + 2 * SK_GROUPS) * (int64_t)kb * r;
 }
 
 template <int MT, int NT>
@@ -269,14 +284,22 @@ hipError_t launch_sketch(const ProbeArgs<T> &p, uint64_t seed, void *partial, do
       default: return hipErrorInvalidValue;
     }
     nparts = (int)(g * 4);
-    hipLaunchKernelGGL((k_sketch_reduce<float>), dim3((kr + 255) / 256), dim3(256), 0, st,
-                       static_cast<const float *>(partial), nparts, p.kb, p.r, p.zrow0, Y);
+    double *stage = reinterpret_cast<double *>(pf + (int64_t)nparts * kr);
+    hipLaunchKernelGGL((k_sketch_reduce<float>), dim3((kr + 255) / 256, SK_GROUPS), dim3(256), 0,
+                       st, static_cast<const float *>(partial), nparts, kr, stage);
+    hipLaunchKernelGGL(k_sketch_final, dim3((kr + 255) / 256), dim3(256), 0, st, stage, kr, p.r,
+                       p.zrow0, Y);
   } else {
-    hipLaunchKernelGGL((k_sketch_vec<T>), dim3((unsigned)g), dim3(256), 0, st, p, seed, chunk,
-                       static_cast<T *>(partial));
+    T *pt = static_cast<T *>(partial);
+    hipLaunchKernelGGL((k_sketch_vec<T>), dim3((unsigned)g), dim3(256), 0, st, p, seed, chunk, pt);
     nparts = (int)g;
-    hipLaunchKernelGGL((k_sketch_reduce<T>), dim3((kr + 255) / 256), dim3(256), 0, st,
-                       static_cast<const T *>(partial), nparts, p.kb, p.r, p.zrow0, Y);
+    // the vector path uses g rows of T; the stage starts after 4 g rows of floats
+    double *stage = reinterpret_cast<double *>(static_cast<float *>(partial) +
+                                               (int64_t)g * 4 * kr);
+    hipLaunchKernelGGL((k_sketch_reduce<T>), dim3((kr + 255) / 256, SK_GROUPS), dim3(256), 0, st,
+                       static_cast<const T *>(partial), nparts, kr, stage);
+    hipLaunchKernelGGL(k_sketch_final, dim3((kr + 255) / 256), dim3(256), 0, st, stage, kr, p.r,
+                       p.zrow0, Y);
   }
   return hipGetLastError();
 }
