@@ -90,13 +90,24 @@ __global__ __launch_bounds__(256) void k_sketch_mfma(ProbeArgs<float> p, uint64_
     for (int v = 0; v < 16; ++v) acc[a][v] = 0.f;
   const int64_t xb = (int64_t)blockIdx.x * chunk;
   const int64_t xe = xb + chunk < p.N ? xb + chunk : p.N;
+  // staging: thread -> cell c = tid % CELLS, levels lv0, lv0 + LSTEP, ...; all
+  // of a thread's loads are issued before any is stored to LDS
+  constexpr int LSTEP = 256 / CELLS;
+  constexpr int NLV = (MT * 32 + 2 + LSTEP - 1) / LSTEP;
+  const int sc = threadIdx.x % CELLS, lv0 = threadIdx.x / CELLS;
   for (int64_t c0 = xb; c0 < xe; c0 += CELLS) {
-    for (int lv = 0; lv < nlev; ++lv) {
-      const float *L = ring_level(p, p.s0 - 1 + lv);
+    {
+      const int64_t x = c0 + sc;
+      float vals[NLV];
 #pragma unroll
-      for (int c = threadIdx.x; c < CELLS; c += 256) {
-        const int64_t x = c0 + c;
-        Ll[lv * LS + c] = x < xe ? L[x] : 0.f;
+      for (int k = 0; k < NLV; ++k) {
+        const int lv = lv0 + k * LSTEP;
+        vals[k] = (lv < nlev && x < xe) ? ring_level(p, p.s0 - 1 + lv)[x] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < NLV; ++k) {
+        const int lv = lv0 + k * LSTEP;
+        if (lv < nlev) Ll[lv * LS + sc] = vals[k];
       }
     }
     for (int c = threadIdx.x; c < CELLS; c += 256) sign_words(c0 + c, seed, nw, Lb + c, CELLS);
