@@ -218,6 +218,18 @@ rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_p
                         void *resid, void *grad, double *misfit, void *work,
                         size_t work_bytes, rtm_stream stream);
 
+/* Subsurface-offset image volume (Eq. 4) for horizontal offsets along x:
+ *   gathers[h + nh][x] = scale * sum_f sum_i Ubar_f[i][x + h] Vbar_f[i][x - h],
+ * h = -nh .. nh, with x + h and x - h moved along the x axis of the cell's
+ * row and zero where either leaves it; h = 0 is rtm_image.
+ *   Ubar, Vbar device tile-major, nfield (1, or 2 for the TTI p and q
+ *              fields) compressed fields of r * Npad elements each
+ *   gathers    device [2 nh + 1][N] field dtype, overwritten
+ *   0 <= nh <= 64 (else RTM_E_UNSUPPORTED); scale = 1/r gives Eq. 4. */
+rtm_status rtm_offset_gathers(const rtm_plan *plan, const void *Ubar, const void *Vbar,
+                              int32_t nfield, int32_t nh, double scale, void *gathers,
+                              rtm_stream stream);
+
 /* Range-finder probes (Section "Randomized trace estimation": probing vectors
  * Q from a partial QR factorization of A Z with Z a Rademacher +-1 matrix).
  * A is read as the forward history H [nt][N] of u_tt and Z as a sign matrix

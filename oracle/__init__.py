@@ -377,3 +377,22 @@ def rf_gradient(g: Grid, m, src_pos, q, rec_pos, d_obs, seed: int, r: int):
     J, res = misfit(f["d"], d_obs)
     a = adjoint(g, m, rec_pos, res, Z=Q)
     return J, image(f["Ubar"], a["Vbar"], -1.0), Q, Y
+
+
+# ---------------------------------------------------------------------------
+# subsurface-offset image volume (Eq. 4)
+# ---------------------------------------------------------------------------
+def offset_gathers(Ubar, Vbar, shape, nh: int, scale: float) -> np.ndarray:
+    """G [2 nh + 1][N]: G[h + nh][x] = scale * sum_i Ubar[i][x + h] Vbar[i][x - h]
+    with the offset h along x (the last axis), zero where x + h or x - h leaves
+    the row.  Ubar, Vbar are [r][N] (rows)."""
+    nz, ny, nx = shape
+    U = np.asarray(Ubar, np.float64).reshape(-1, nz, ny, nx)
+    V = np.asarray(Vbar, np.float64).reshape(-1, nz, ny, nx)
+    G = np.zeros((2 * nh + 1, nz, ny, nx))
+    for h in range(-nh, nh + 1):
+        for x in range(nx):
+            xu, xv = x + h, x - h
+            if 0 <= xu < nx and 0 <= xv < nx:
+                G[h + nh, :, :, x] = (U[:, :, :, xu] * V[:, :, :, xv]).sum(axis=0)
+    return scale * G.reshape(2 * nh + 1, -1)

@@ -20,7 +20,7 @@ EXPORTS = (
     "rtm_batch_create", "rtm_batch_destroy", "rtm_batch_workspace_bytes", "fwi_gradient_batched",
     "rtm_tti_workspace_bytes", "rtm_tti_forward_probe", "rtm_tti_adjoint_probe",
     "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape", "rtm_rf_workspace_bytes",
-    "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf",
+    "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf", "rtm_offset_gathers",
 )
 
 
@@ -100,6 +100,8 @@ def load() -> ctypes.CDLL:
     L.fwi_gradient_rf.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, u64, _vp, _vp, _vp, _vp, _vp,
                                   _vp, _vp, sz, _vp]
     L.fwi_gradient_rf.restype = ctypes.c_int
+    L.rtm_offset_gathers.argtypes = [_vp, _vp, _vp, i32, i32, dbl, _vp, _vp]
+    L.rtm_offset_gathers.restype = ctypes.c_int
     L.rtm_adjoint_image.argtypes = [_vp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, dbl, _vp, _vp, sz,
                                     _vp]
     L.rtm_adjoint_image.restype = ctypes.c_int

@@ -455,6 +455,23 @@ def fwi_gradient_exact(plan: Plan, m, src_pos, q, rec_pos, d_obs, checkpoint_eve
     return {"grad": g, "misfit": J, "resid": res, "workspace_bytes": int(n.value)}
 
 
+def rtm_offset_gathers(plan: Plan, Ubar, Vbar, nh: int, scale=None, nfield: int = 1,
+                       out=None) -> torch.Tensor:
+    """Eq. 4 along x: [2 nh + 1][N] image volume, offset -nh first; scale
+    defaults to 1/r."""
+    s = plan.spec
+    dev = Ubar.device
+    nb = nfield * s.r * plan.Npad
+    G = out if out is not None else torch.empty((2 * nh + 1, plan.N), dtype=plan.dtype,
+                                                device=dev)
+    _check(_lib.load().rtm_offset_gathers(
+        plan.handle, _dev(Ubar, plan.dtype, nb, "Ubar"), _dev(Vbar, plan.dtype, nb, "Vbar"),
+        int(nfield), int(nh), float(1.0 / s.r if scale is None else scale),
+        _dev(G, plan.dtype, (2 * nh + 1) * plan.N, "gathers"), _stream(dev)),
+        "rtm_offset_gathers")
+    return G
+
+
 def rf_workspace_bytes(plan: Plan) -> int:
     n = ctypes.c_size_t()
     _check(_lib.load().rtm_rf_workspace_bytes(plan.handle, ctypes.byref(n)),

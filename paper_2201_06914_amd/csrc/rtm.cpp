@@ -678,6 +678,28 @@ extern "C" rtm_status rtm_image(const rtm_plan *P, const void *U, const void *V,
   return RTM_OK;
 }
 
+extern "C" rtm_status rtm_offset_gathers(const rtm_plan *P, const void *Ubar, const void *Vbar,
+                                         int32_t nfield, int32_t nh, double scale, void *gathers,
+                                         rtm_stream stream) {
+  g_last_error.clear();
+  if (!P || !Ubar || !Vbar || !gathers) return fail(RTM_E_ARG, "NULL argument");
+  if (nfield != 1 && nfield != 2) return fail(RTM_E_ARG, "nfield must be 1 or 2");
+  if (nh < 0 || nh > 64) return fail(RTM_E_UNSUPPORTED, "offsets: 0 <= nh <= 64");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t fs = (int64_t)P->d.r * P->Npad;
+  if (P->d.field_dtype == RTM_F64)
+    HIP_TRY(launch_offset_gathers<double>(static_cast<const double *>(Ubar),
+                                          static_cast<const double *>(Vbar), nfield, fs, P->N,
+                                          (int)P->d.nx, P->d.r, nh, scale,
+                                          static_cast<double *>(gathers), st));
+  else
+    HIP_TRY(launch_offset_gathers<float>(static_cast<const float *>(Ubar),
+                                         static_cast<const float *>(Vbar), nfield, fs, P->N,
+                                         (int)P->d.nx, P->d.r, nh, scale,
+                                         static_cast<float *>(gathers), st));
+  return RTM_OK;
+}
+
 extern "C" rtm_status rtm_bar_to_rows(const rtm_plan *P, const void *bar, void *rows,
                                       rtm_stream stream) {
   g_last_error.clear();

@@ -129,6 +129,10 @@ hipError_t launch_sketch(const ProbeArgs<T> &p, uint64_t seed, void *partial, do
                          hipStream_t st);
 template <typename T>
 hipError_t launch_orthonormalize(const double *Y, int nt, int r, double *V, T *Q, hipStream_t st);
+// subsurface-offset image volume along x (Eq. 4): G [2 nh + 1][N], nh <= 64
+template <typename T>
+hipError_t launch_offset_gathers(const T *U, const T *V, int nfield, int64_t fstride, int64_t N,
+                                 int nx, int r, int nh, double scale, T *G, hipStream_t st);
 // batched sweep step (all shots, one launch each): stencil over the tile
 // table, then injection / sampling of level s+1 for time index n
 template <typename T>
