@@ -29,7 +29,7 @@ def _tile_major(rows, Npad):
 
 def _plan(shape, r, field):
     ndim = 2 if shape[1] == 1 else 3
-    return P.Plan(P.PlanSpec(ndim, shape, 10.0, 1e-3, 16, 2, 3000.0, 1e-3, 3000.0, field,
+    return P.Plan(P.PlanSpec(ndim, shape, 10.0, 1e-3, 16, 1, 3000.0, 1e-3, 3000.0, field,
                              field, r, 16, 1, 1))
 
 
@@ -56,7 +56,7 @@ def test_offset_gathers_match_oracle(shape, r, nh, field):
 
 
 def test_two_fields_are_summed():
-    shape, r, nh = (4, 2, 70), 16, 10
+    shape, r, nh = (4, 3, 70), 16, 10
     plan = _plan(shape, r, "f64")
     N = int(np.prod(shape))
     rng = np.random.default_rng(5)
