@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-tti", action="store_true",
                     help="skip the 300x400x400 TTI gradient section")
     ap.add_argument("--tti-nt", type=int, default=2500)
+    ap.add_argument("--no-gathers", action="store_true",
+                    help="skip the 81-offset image volume at the TTI grid")
     ap.add_argument("--cpu-planes", type=int, default=24)
     ap.add_argument("--cpu-nt", type=int, default=80)
     return ap.parse_args()
@@ -353,6 +355,38 @@ def bench_tti(shape, nt: int, r: int, stride: int):
             "misfit": float(out["misfit"].item()), "grad_finite": finite}
 
 
+def bench_gathers(shape, r: int, nh: int):
+    """Subsurface-offset image volume (Eq. 4) at the TTI grid: 2 nh + 1
+    offsets along x from the p and q compressed fields (r probes each).  The
+    kernel's cost does not depend on the values; the fields are seeded
+    Gaussian noise of the compressed fields' shape."""
+    import numpy as np
+    import torch
+
+    import paper_2201_06914_amd as P
+    plan = P.Plan(P.PlanSpec(3, shape, 12.5, 1e-3, 64, 10, 4500.0, 1e-3, 4500.0, "f32", "bf16x2",
+                             r, 32, 1, 1))
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    nb = 2 * r * plan.Npad
+    U = torch.randn(nb, generator=gen, device="cuda")
+    V = torch.randn(nb, generator=gen, device="cuda")
+    G = torch.empty((2 * nh + 1, plan.N), device="cuda")
+    P.rtm_offset_gathers(plan, U, V, nh, nfield=2, out=G)       # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P.rtm_offset_gathers(plan, U, V, nh, nfield=2, out=G)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3
+    N = int(np.prod(shape))
+    alg = (2 * nb + (2 * nh + 1) * N) * 4.0
+    macs = 2.0 * r * N * (2 * nh + 1)
+    return {"workload": f"{shape[0]}x{shape[1]}x{shape[2]}, {2 * nh + 1} offsets along x, r={r} "
+                        f"on p and q, fp32", "ms": round(ms, 2),
+            "GBps_algorithmic": round(alg / (ms * 1e-3) / 1e9, 1),
+            "GMACs": round(macs / (ms * 1e-3) / 1e9, 1),
+            "output_gb": round((2 * nh + 1) * N * 4 / 1e9, 2)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -553,6 +587,13 @@ def main():
             rec_line["tti"] = bench_tti((300, 400, 400), a.tti_nt, 64, a.prof_stride)
         except Exception as e:
             rec_line["tti"] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
+    if not a.no_gathers:
+        torch.cuda.empty_cache()
+        try:
+            rec_line["offset_gathers"] = bench_gathers((300, 400, 400), 64, 40)
+        except Exception as e:
+            rec_line["offset_gathers"] = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         torch.cuda.empty_cache()
