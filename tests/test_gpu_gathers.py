@@ -35,10 +35,12 @@ def _plan(shape, r, field):
 
 @pytest.mark.parametrize("shape,r,nh,field", [
     ((7, 1, 75), 12, 40, "f64"), ((5, 3, 130), 20, 64, "f64"), ((4, 1, 30), 8, 40, "f64"),
-    ((6, 4, 97), 33, 40, "f32"), ((3, 5, 64), 16, 7, "f32")])
+    ((6, 4, 97), 33, 40, "f32"), ((3, 5, 64), 16, 7, "f32"), ((5, 3, 70), 5, 0, "f64"),
+    ((3, 3, 40), 3, 1, "f64"), ((4, 3, 66), 17, 33, "f32"), ((3, 1, 200), 9, 63, "f64")])
 def test_offset_gathers_match_oracle(shape, r, nh, field):
-    """Ragged rows (x not a multiple of the 64-cell segment), nh up to 64, rows
-    shorter than the offsets, r not a multiple of the 16-row probe chunk."""
+    """Ragged rows (x not a multiple of the 64-cell segment), nh up to 64 (each
+    offset-block width and both V alignments), rows shorter than the offsets, r
+    not a multiple of the 16-row probe chunk."""
     plan = _plan(shape, r, field)
     N = int(np.prod(shape))
     rng = np.random.default_rng(sum(shape) + r)
@@ -73,7 +75,8 @@ def test_two_fields_are_summed():
 
 def test_zero_offset_equals_image_on_swept_fields():
     """The GPU's own compressed fields (forward u_tt and adjoint probes):
-    offset 0 of the volume equals rtm_image bit for bit in FP64."""
+    offset 0 of the volume equals rtm_image in FP64 up to the order in which
+    the probe products are summed."""
     wl = synth.workload_small_2d(shape=(30, 34), nt=64, r=16)
     plan = P.Plan.for_workload(wl, field="f64", probe="f64")
     m, q, Z = dev(wl.m, torch.float64), dev(wl.q, torch.float64), dev(wl.Z, torch.int8)
