@@ -104,11 +104,25 @@ __device__ __forceinline__ void sto(T *f, uint32_t o, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(f) + o) = v;
 }
 
-// field value at (z, y, x) of a column known to lie inside the x-y range; zero
-// for planes outside the grid
+// field value at (z, y, x), zero where the cell is off (outside the x-y range or
+// a plane outside the grid).  A raw buffer load over the field's N values
+// returns zero for an offset past the end, so an off cell takes the offset
+// N * sizeof(T) instead of a branch around the load.
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t o, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)o, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t o, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)o, 0, 0));
+}
 template <typename T>
 __device__ __forceinline__ T ldz(const T *f, const StepArgs<T> &a, bool on, int z, int y, int x) {
-  return (on && z >= 0 && z < a.nz) ? ldo(f, cidx(a, z, y, x)) : T(0);
+  const uint32_t end = (uint32_t)a.N * (uint32_t)sizeof(T);
+  // gfx9 buffer descriptor word 3: 32-bit data format, no swizzle
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(f), (short)0, (int)end, 0x00020000);
+  const bool ok = on & (z >= 0) & (z < a.nz);  // no short circuit: one select
+  const uint32_t o = cidx(a, z, y, x);
+  return buf_ld(r, ok ? o : end, T(0));
 }
 
 // first difference from a 9-value window centred at w[4] (w[4] unused)
@@ -898,7 +912,8 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 
 // tile shapes (prep / march rows of 64 columns): 1 = 8 / 8, 2 = 4 / 4,
 // 3 = 8 / 4, 4 = as 3 with the fused forward kernel (4 rows), 5 = as 3 with
-// the fused forward kernel (8 rows), 6 (default) = both steps fused (4 rows)
+// the fused forward kernel (8 rows), 6 (default) = both steps fused (4 rows),
+// 7 = both fused, forward 4 rows and transpose 8 rows, 8 = both fused (8 rows)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -909,6 +924,9 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
                            : tti_step_tiled<T, 8, 8, true>(t, adjoint, target_blocks, st);
     case 3: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
     case 4: return tti_step_tiled<T, 8, 4, true>(t, adjoint, target_blocks, st);
+    case 7: return adjoint ? tti_step_tiled<T, 8, 8, true, true>(t, adjoint, target_blocks, st)
+                           : tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
+    case 8: return tti_step_tiled<T, 8, 8, true, true>(t, adjoint, target_blocks, st);
     default: return tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
   }
 }

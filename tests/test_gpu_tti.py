@@ -45,12 +45,13 @@ def variant(request):
                                            ((-1, 1), (40, 21, 70)), ((-1, 2), (40, 21, 70)),
                                            ((-1, 3), (40, 21, 70)), ((-1, 4), (40, 21, 70)),
                                            ((-1, 5), (40, 21, 70)), ((-1, 6), (40, 21, 70)),
-                                           ((-1, 6), (18, 16, 20))],
+                                           ((-1, 6), (18, 16, 20)), ((-1, 7), (40, 21, 70)),
+                                           ((-1, 8), (40, 21, 70))],
                          indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
     (tile shapes 1..3: 64 x 8 and 64 x 4 columns; 4, 5: fused forward step; 6:
-    both steps fused)."""
+    both steps fused; 7, 8: both fused, the transpose step on 64 x 8 tiles)."""
     wl, an = synth.workload_tti(shape=shape, nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
                                 rec_stride=7, dtype=np.float64)
     g = Grid.of(wl)
@@ -127,7 +128,7 @@ def test_tti_f32_bf16x2_fused_gradient():
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
 
 
-@pytest.mark.parametrize("shape", [3, 4, 6])
+@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8])
 def test_tti_f32_tiled_equals_simple_kernels(shape):
     """The tiled TTI step (mixed terms once per unordered pair, intermediates
     staged per plane) against the one-thread-per-cell step on the same FP32
