@@ -27,11 +27,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(part: str, grid, r, k):
+def measured_traffic(part: str, grid, **params):
     """HBM bytes per dispatch measured with rocprofv3 --pmc (FETCH_SIZE and
     WRITE_SIZE, scaled by a plain copy of known size) for one workload
-    ("acoustic" or "tti"), keyed by kernel, if the kernel sources are unchanged
-    since the counters were taken and the workload matches; else None."""
+    ("acoustic", "tti" or "gathers"), keyed by kernel, if the kernel sources
+    are unchanged since the counters were taken and the workload (grid and
+    params) matches; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
@@ -39,12 +40,13 @@ def measured_traffic(part: str, grid, r, k):
     with open(path) as f:
         rec = json.load(f)
     h = hashlib.sha256()
-    for name in ("stencil.hip", "probe.hip", "misc.hip", "tti.hip", "tti_tiled.hip"):
+    for name in ("stencil.hip", "probe.hip", "misc.hip", "tti.hip", "tti_tiled.hip",
+                 "gathers.hip"):
         with open(os.path.join(ROOT, "paper_2201_06914_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     w = rec.get(part)
     if rec.get("source_hash") != h.hexdigest()[:16] or not w or w.get("grid") != list(grid) \
-            or w.get("r") != r or w.get("k") != k:
+            or any(w.get(k) != v for k, v in params.items()):
         return None
     return {key: v["read_bytes"] + v["write_bytes"] for key, v in w["kernels"].items()}
 
@@ -342,7 +344,7 @@ def bench_tti(shape, nt: int, r: int, stride: int):
     gbs = bpc * N / (avg_us * 1e-6) / 1e9
     finite = bool(torch.isfinite(out["grad"]).all().item())
     print("tti: gradient done", file=sys.stderr, flush=True)
-    tr = measured_traffic("tti", shape, r, 32)
+    tr = measured_traffic("tti", shape, r=r, k=32)
     traffic = round(0.5 * (tr["tti_ffused"] + tr["tti_afused"])) if tr else None
     return {"workload": f"TTI {shape[0]}x{shape[1]}x{shape[2]}, nt={nt}, r={r} on p and q, "
                         f"k=32, bf16x2, fused imaging, one shot",
@@ -386,12 +388,15 @@ def bench_gathers(shape, r: int, nh: int):
     # fp32 vector peak 157.3 TFLOP/s counts packed FMA (2 per lane); unpacked
     # FMA (what this library emits) tops out at half of it
     tflops = 2 * macs / (ms * 1e-3) / 1e12
+    tr = measured_traffic("gathers", shape, r=r, nh=nh)
+    traffic = round(tr["gathers"] / 1e9, 2) if tr and "gathers" in tr else None
     return {"workload": f"{shape[0]}x{shape[1]}x{shape[2]}, {2 * nh + 1} offsets along x, r={r} "
                         f"on p and q, fp32", "ms": round(ms, 2),
             "GBps_algorithmic": round(alg / (ms * 1e-3) / 1e9, 1),
             "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": 157.3,
                          "unit": "TFLOP/s", "frac": round(tflops / 157.3, 3),
                          "frac_of_unpacked_fma": round(tflops / 78.65, 3)},
+            "algorithmic_gb": round(alg / 1e9, 2), "traffic_gb": traffic,
             "output_gb": round((2 * nh + 1) * N * 4 / 1e9, 2)}
 
 
@@ -546,7 +551,7 @@ def main():
              "mfma_tflops": round((2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 *
                                   math.ceil(k / 16) * N * 2 * nblk * a.steps /
                                   (pr_ms * 1e-3) / 1e12, 2) if pr_n else None}
-    tr = measured_traffic("acoustic", (384, 512, 512), r, k) if fused else None
+    tr = measured_traffic("acoustic", (384, 512, 512), r=r, k=k) if fused else None
     if tr:
         stencil["traffic"] = round(tr["stencil"])
         probe["traffic"] = round(0.5 * (tr["probe_fwd"] + tr["probe_adj"]))
