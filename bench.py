@@ -357,6 +357,25 @@ def bench_tti(shape, nt: int, r: int, stride: int):
             "misfit": float(out["misfit"].item()), "grad_finite": finite}
 
 
+def hbm_copy_gbps(mib: int = 2048, reps: int = 5) -> float:
+    """Measured HBM ceiling for streaming kernels: a plain device-to-device
+    copy of mib MiB (read + write bytes over the HIP-event time)."""
+    import torch
+    nel = mib * (1 << 20) // 4
+    x = torch.ones(nel, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        y.copy_(x)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del x, y
+    return 2.0 * nel * 4 / (ms * 1e-3) / 1e9
+
+
 def bench_gathers(shape, r: int, nh: int):
     """Subsurface-offset image volume (Eq. 4) at the TTI grid: 2 nh + 1
     offsets along x from the p and q compressed fields (r probes each).  The
@@ -575,6 +594,14 @@ def main():
         "misfit_same_in_both": misfit == other_misfit if other_ms is not None else None,
         "image_avg_ms": round(im_ms / max(im_n, 1), 2),
     }
+    try:
+        cp = hbm_copy_gbps()
+        rec_line["hbm_copy_GBps"] = round(cp, 1)
+        rec_line["hbm_copy_kernel"] = "torch copy_ of 2 GiB float32 (HIP events)"
+        for rl in (dominant, other):
+            rl["frac_of_copy"] = round(rl["achieved"] / cp, 4)
+    except Exception as e:
+        rec_line["hbm_copy_GBps"] = {"error": f"{type(e).__name__}: {e}"}
     if not a.no_batched:
         del bars, work, m, q, Z, d_obs
         if "out" in locals():
