@@ -3,15 +3,22 @@
 // h = -nh .. nh, x +- h along the grid's x axis (zero where either leaves
 // the row).  h = 0 is the image of Eq. 3.
 //
-// k_offset_gathers: a workgroup owns a 64-cell segment of one x row; chunks
-// of 16 probe rows of both compressed fields (the segment plus an nh-cell
-// halo and a margin on each side, zero outside the row) are staged in LDS.
-// Products along a diagonal share an operand (x + h fixed: the same U; x - h
-// fixed: the same V), so a thread owning GCX cells x BH offsets reads
-// GCX + BH values of each field per probe row (16-byte LDS reads) for
-// GCX BH products.  The workgroup's threads form nslice slices over the probe
-// rows of each chunk; the slices add up through LDS at the end.  Threads are
-// placed in a slice so that the 16-byte reads meet no LDS bank conflicts.
+// A workgroup owns a 64-cell segment of one x row; chunks of 16 probe rows of
+// both compressed fields (the segment plus an nh-cell halo and a margin on
+// each side, zero outside the row) are staged in LDS.  Products along a
+// diagonal share an operand (x + h fixed: the same U; x - h fixed: the same
+// V), so a thread owning GCX cells x BH offsets reads GCX + BH values of each
+// field per probe row (16-byte LDS reads) for GCX BH products.  The
+// workgroup's threads form nslice slices over the probe rows of each chunk;
+// the slices add up through LDS at the end.  Threads are placed in a slice so
+// that the 16-byte reads meet no LDS bank conflicts.
+//
+// k_offset_gathers_f32 stages with direct global -> LDS loads into two
+// buffers: chunk c + 1 streams into one while chunk c is multiplied out of
+// the other.  The buffers are two distinct LDS arrays and the chunk loop
+// alternates them statically, so the compiler can tell the in-flight loads
+// from the reads and does not wait for the former before the latter.
+// k_offset_gathers (FP64) stages through registers, one chunk at a time.
 #include "rtm_internal.h"
 
 namespace rtm {
@@ -43,124 +50,216 @@ __host__ __device__ constexpr int gather_ls(int nh) { return (GX + 2 * nh + 2 * 
 
 // cells per thread: 8 in FP32, 4 in FP64 (register budget)
 template <typename T> constexpr int gather_cx() { return sizeof(T) == 4 ? 8 : 4; }
-}  // namespace
 
+struct GatherArgs {
+  int64_t fstride, N;
+  int nfield, nx, r, nh, nseg, nblk, nslice, slice_thr, hgs;
+};
+
+// A thread's place: slice sl, offset block hg (offsets hg BH - nh ..), cell
+// block cb.  A 16-byte LDS read is served in 4 passes of 16 lanes: lane bit 5
+// and the parity of lane bits 2..4 select the pass, k = (lane bits 3..4,
+// 0..1) the place in it; a bank is a 16-byte chunk mod 16.  Pass gp holds
+// 16 / CB consecutive offset blocks x all cell blocks: in FP32 one even and
+// one odd block, whose chunks (2 cb + 3 hg) differ in parity, so no two lanes
+// of a pass meet in a bank at different addresses.
 template <typename T>
-__global__ __launch_bounds__(256) void k_offset_gathers(const T *__restrict__ U,
-                                                        const T *__restrict__ V, int nfield,
-                                                        int64_t fstride, int64_t N, int nx,
-                                                        int r, int nh, T scale, int nseg,
-                                                        int nblk, int nslice, int slice_thr,
-                                                        int hgs, T *__restrict__ G) {
-  constexpr int GCX = gather_cx<T>(), BH = GBH, CB = GX / GCX, NACC = GCX * BH;
-  constexpr int RK = NACC / 3;  // accumulators handed over per reduction round
-  extern __shared__ __align__(16) unsigned char gsm[];
-  const int LS = gather_ls(nh);
-  T *LU = reinterpret_cast<T *>(gsm), *LV = LU + GIC * LS;
-  int b = blockIdx.x;
-  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);  // XCD-aware: a row's
-  const int row = b / nseg, seg = b % nseg;                      // segments share an L2
-  const int xs = seg * GX;
-  const int64_t rb = (int64_t)row * nx;
-  const int nthr = blockDim.x;
-  // slice sl, offset block hg (cells' offsets hg BH - nh ..), cell block cb.
-  // A 16-byte LDS read is served in 4 passes of 16 lanes: lane bit 5 and the
-  // parity of lane bits 2..4 select the pass, k = (lane bits 3..4, 0..1) the
-  // place in it; a bank is a 16-byte chunk mod 16.  Pass gp holds 16 / CB
-  // consecutive offset blocks x all cell blocks: in FP32 one even and one odd
-  // block, whose chunks (2 cb + 3 hg) differ in parity, so no two lanes of a
-  // pass meet in a bank at different addresses.
-  const int sl = threadIdx.x / slice_thr, t = threadIdx.x % slice_thr;
-  const int l = t & 63, q = (l >> 2) & 7;
-  const int gp = 4 * (t >> 6) + 2 * (l >> 5) + (__builtin_popcount(q) & 1);
-  const int k = 4 * (q >> 1) + (l & 3);
-  const int hg = gp * (16 / CB) + k / CB, cb = k % CB;
-  const bool comp = hg < hgs;
-  const int nout = 2 * nh + 1;
-  // V is staged shifted by sv so that every thread's V reads start 16-byte aligned
-  const int sv = (4 - (2 * nh) % 4) % 4;
-  const int ubase = GCX * cb + hg * BH + GM;
-  const int vbase = GCX * cb - hg * BH - BH + 2 * nh + GM + sv;
-  T acc[NACC], keep = T(0);
-#pragma unroll
-  for (int k = 0; k < NACC; ++k) acc[k] = T(0);
-  for (int f = 0; f < nfield; ++f) {
-    const T *Uf = U + f * fstride, *Vf = V + f * fstride;
-    for (int i0 = 0; i0 < r; i0 += GIC) {
-      __syncthreads();
-      for (int p = threadIdx.x; p < LS; p += nthr) {
-        // staged column p holds x = xs - nh + (p - GM) for U, one sv further left for V
-        const int xu = xs - nh + p - GM, xv = xu - sv;
-        const bool oku = xu >= 0 && xu < nx, okv = xv >= 0 && xv < nx;
-        const T *pu = Uf + gbar_index(rb + (oku ? xu : 0), i0, r);
-        const T *pv = Vf + gbar_index(rb + (okv ? xv : 0), i0, r);
-        T vu[GIC], vw[GIC];
-#pragma unroll
-        for (int ii = 0; ii < GIC; ++ii) {
-          const bool in = i0 + ii < r;
-          vu[ii] = (oku && in) ? pu[ii * 32] : T(0);
-          vw[ii] = (okv && in) ? pv[ii * 32] : T(0);
-        }
-#pragma unroll
-        for (int ii = 0; ii < GIC; ++ii) {
-          LU[ii * LS + p] = vu[ii];
-          LV[ii * LS + p] = vw[ii];
-        }
-      }
-      __syncthreads();
-      if (comp) {
-        const int iend = min(GIC, r - i0);
-        for (int ii = sl; ii < iend; ii += nslice) {
-          T uu[BH + GCX], vv[BH + GCX];
-#pragma unroll
-          for (int q = 0; q < BH + GCX; q += 4) {
-            lds4(LU + ii * LS + ubase + q, uu + q);
-            lds4(LV + ii * LS + vbase + q, vv + q);
-          }
-          // cell GCX cb + j, offset hg BH + m - nh: U at staged ubase + j + m,
-          // V at staged vbase + BH + j - m
-#pragma unroll
-          for (int j = 0; j < GCX; ++j)
-#pragma unroll
-            for (int m = 0; m < BH; ++m) acc[j * BH + m] += uu[j + m] * vv[BH + j - m];
-          // uu[BH + GCX - 1] and vv[0] are read but not needed; using them
-          // keeps the reads whole 16-byte ones (the conflict-free placement
-          // above holds for those, not for narrower pieces)
-          keep = fma(uu[BH + GCX - 1], vv[0], keep);
-        }
-      }
-    }
+struct GatherThread {
+  static constexpr int GCX = gather_cx<T>(), BH = GBH, CB = GX / GCX, NACC = GCX * BH;
+  int sl, t, hg, cb, ubase, vbase, sv, xs;
+  int64_t rb;
+  bool comp;
+  __device__ explicit GatherThread(const GatherArgs &a) {
+    int b = blockIdx.x;
+    if ((a.nblk & 7) == 0) b = (b & 7) * (a.nblk >> 3) + (b >> 3);  // XCD-aware: a row's
+    const int row = b / a.nseg;                                       // segments share an L2
+    xs = (b % a.nseg) * GX;
+    rb = (int64_t)row * a.nx;
+    sl = threadIdx.x / a.slice_thr;
+    t = threadIdx.x % a.slice_thr;
+    const int l = t & 63, q = (l >> 2) & 7;
+    const int gp = 4 * (t >> 6) + 2 * (l >> 5) + (__builtin_popcount(q) & 1);
+    const int k = 4 * (q >> 1) + (l & 3);
+    hg = gp * (16 / CB) + k / CB;
+    cb = k % CB;
+    comp = hg < a.hgs;
+    // V is staged shifted by sv so that every thread's V reads start 16-byte aligned
+    sv = (4 - (2 * a.nh) % 4) % 4;
+    ubase = GCX * cb + hg * BH + GM;
+    vbase = GCX * cb - hg * BH - BH + 2 * a.nh + GM + sv;
   }
-  // slices 1 .. nslice - 1 hand their sums to slice 0 through LDS, RK at a time
-  T *LR = reinterpret_cast<T *>(gsm);
+};
+
+// multiply out one staged chunk (probe rows i0 .. i0 + 15) from BU / BV
+template <typename T>
+__device__ __forceinline__ void gather_chunk(const GatherThread<T> &th, const GatherArgs &a,
+                                             const T *BU, const T *BV, int LS, int i0,
+                                             T (&acc)[GatherThread<T>::NACC], T &keep) {
+  constexpr int GCX = GatherThread<T>::GCX, BH = GBH;
+  if (!th.comp) return;
+  const int iend = min(GIC, a.r - i0);
+  for (int ii = th.sl; ii < iend; ii += a.nslice) {
+    T uu[BH + GCX], vv[BH + GCX];
+#pragma unroll
+    for (int q = 0; q < BH + GCX; q += 4) {
+      lds4(BU + ii * LS + th.ubase + q, uu + q);
+      lds4(BV + ii * LS + th.vbase + q, vv + q);
+    }
+    // cell GCX cb + j, offset hg BH + m - nh: U at staged ubase + j + m,
+    // V at staged vbase + BH + j - m
+#pragma unroll
+    for (int j = 0; j < GCX; ++j)
+#pragma unroll
+      for (int m = 0; m < BH; ++m) acc[j * BH + m] += uu[j + m] * vv[BH + j - m];
+    // uu[BH + GCX - 1] and vv[0] are read but not needed; using them keeps the
+    // reads whole 16-byte ones (the conflict-free placement holds for those,
+    // not for narrower pieces)
+    keep = fma(uu[BH + GCX - 1], vv[0], keep);
+  }
+}
+
+// slices 1 .. nslice - 1 hand their sums to slice 0 through LR (LDS), RK at a
+// time; slice 0 writes the volume
+template <typename T>
+__device__ __forceinline__ void gather_finish(const GatherThread<T> &th, const GatherArgs &a,
+                                              T *LR, T (&acc)[GatherThread<T>::NACC], T keep,
+                                              T scale, T *__restrict__ G) {
+  constexpr int GCX = GatherThread<T>::GCX, BH = GBH, NACC = GatherThread<T>::NACC;
+  constexpr int RK = NACC / 3;
 #pragma unroll
   for (int k0 = 0; k0 < NACC; k0 += RK) {
-    for (int s = 1; s < nslice; ++s) {
+    for (int s = 1; s < a.nslice; ++s) {
       __syncthreads();
-      if (sl == s) {
+      if (th.sl == s) {
 #pragma unroll
-        for (int k = 0; k < RK; ++k) LR[k * slice_thr + t] = acc[k0 + k];
+        for (int k = 0; k < RK; ++k) LR[k * a.slice_thr + th.t] = acc[k0 + k];
       }
       __syncthreads();
-      if (sl == 0) {
+      if (th.sl == 0) {
 #pragma unroll
-        for (int k = 0; k < RK; ++k) acc[k0 + k] += LR[k * slice_thr + t];
+        for (int k = 0; k < RK; ++k) acc[k0 + k] += LR[k * a.slice_thr + th.t];
       }
     }
   }
-  if (nslice < 0) G[0] = keep;  // never: nslice >= 1
-  if (sl != 0 || !comp) return;
+  if (a.nslice < 0) G[0] = keep;  // never: nslice >= 1
+  if (th.sl != 0 || !th.comp) return;
+  const int nout = 2 * a.nh + 1;
 #pragma unroll
   for (int m = 0; m < BH; ++m) {
-    const int hi = hg * BH + m;
+    const int hi = th.hg * BH + m;
     if (hi < nout) {
 #pragma unroll
       for (int j = 0; j < GCX; ++j) {
-        const int x = xs + GCX * cb + j;
-        if (x < nx) G[(int64_t)hi * N + rb + x] = scale * acc[j * BH + m];
+        const int x = th.xs + GCX * th.cb + j;
+        if (x < a.nx) G[(int64_t)hi * a.N + th.rb + x] = scale * acc[j * BH + m];
       }
     }
   }
+}
+}  // namespace
+
+// FP32, direct global -> LDS staging, two static buffers of row stride <= MAXLS
+template <int MAXLS>
+__global__ __launch_bounds__(256) void k_offset_gathers_f32(const float *__restrict__ U,
+                                                            const float *__restrict__ V,
+                                                            GatherArgs a, float scale,
+                                                            float *__restrict__ G) {
+  constexpr int NACC = GatherThread<float>::NACC;
+  constexpr int BUFN = 2 * GIC * MAXLS;
+  __shared__ __align__(16) float SA[BUFN];
+  __shared__ __align__(16) float SB[BUFN];
+  const GatherThread<float> th(a);
+  const int LS = gather_ls(a.nh);
+  // thread p < LS owns staged column p (256 threads >= LS); U rows at S,
+  // V rows at S + GIC LS; a wave's loads land at the wave's first column + lane
+  const int p = threadIdx.x;
+  const int wbase = __builtin_amdgcn_readfirstlane(p & ~63);  // wave-uniform
+  const int xu = th.xs - a.nh + p - GM, xv = xu - th.sv;
+  const bool stg = p < LS;
+  const bool oku = stg && xu >= 0 && xu < a.nx, okv = stg && xv >= 0 && xv < a.nx;
+  const int64_t gu = th.rb + (oku ? xu : 0), gv = th.rb + (okv ? xv : 0);
+  // columns outside the row are never loaded: zero them once in both buffers
+  if (stg) {
+    for (int ii = 0; ii < GIC; ++ii) {
+      if (!oku) SA[ii * LS + p] = SB[ii * LS + p] = 0.f;
+      if (!okv) SA[(GIC + ii) * LS + p] = SB[(GIC + ii) * LS + p] = 0.f;
+    }
+  }
+  const int cpf = (a.r + GIC - 1) / GIC, nch = a.nfield * cpf;  // chunk c = (field, 16 rows)
+  auto issue = [&](int c, float *S) {
+    const int f = c / cpf, i0 = (c % cpf) * GIC;
+    // probe row i0 + ii of a column sits ii * 32 values after row i0
+    const float *pu = U + f * a.fstride + gbar_index(gu, i0, a.r);
+    const float *pv = V + f * a.fstride + gbar_index(gv, i0, a.r);
+    const int nrow = min(GIC, a.r - i0);
+#pragma unroll
+    for (int ii = 0; ii < GIC; ++ii) {
+      if (ii < nrow) {
+        if (oku) __builtin_amdgcn_global_load_lds(pu + ii * 32, S + ii * LS + wbase, 4, 0, 0);
+        if (okv)
+          __builtin_amdgcn_global_load_lds(pv + ii * 32, S + (GIC + ii) * LS + wbase, 4, 0, 0);
+      }
+    }
+  };
+  float acc[NACC], keep = 0.f;
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = 0.f;
+  issue(0, SA);
+  for (int c = 0; c < nch; c += 2) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's loads of chunk c
+    __syncthreads();                     // everyone's; and chunk c - 1 is multiplied out
+    if (c + 1 < nch) issue(c + 1, SB);
+    gather_chunk(th, a, SA, SA + GIC * LS, LS, (c % cpf) * GIC, acc, keep);
+    if (c + 1 >= nch) break;
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (c + 2 < nch) issue(c + 2, SA);
+    gather_chunk(th, a, SB, SB + GIC * LS, LS, ((c + 1) % cpf) * GIC, acc, keep);
+  }
+  gather_finish(th, a, SA, acc, keep, scale, G);
+}
+
+// any type: register staging, one chunk at a time, dynamic LDS
+template <typename T>
+__global__ __launch_bounds__(256) void k_offset_gathers(const T *__restrict__ U,
+                                                        const T *__restrict__ V, GatherArgs a,
+                                                        T scale, T *__restrict__ G) {
+  constexpr int NACC = GatherThread<T>::NACC;
+  extern __shared__ __align__(16) unsigned char gsm[];
+  const GatherThread<T> th(a);
+  const int LS = gather_ls(a.nh);
+  T *LU = reinterpret_cast<T *>(gsm), *LV = LU + GIC * LS;
+  T acc[NACC], keep = T(0);
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = T(0);
+  const int cpf = (a.r + GIC - 1) / GIC, nch = a.nfield * cpf;
+  for (int c = 0; c < nch; ++c) {
+    const int f = c / cpf, i0 = (c % cpf) * GIC;
+    const T *Uf = U + f * a.fstride, *Vf = V + f * a.fstride;
+    __syncthreads();
+    for (int p = threadIdx.x; p < LS; p += blockDim.x) {
+      // staged column p holds x = xs - nh + (p - GM) for U, one sv further left for V
+      const int xu = th.xs - a.nh + p - GM, xv = xu - th.sv;
+      const bool oku = xu >= 0 && xu < a.nx, okv = xv >= 0 && xv < a.nx;
+      const T *pu = Uf + gbar_index(th.rb + (oku ? xu : 0), i0, a.r);
+      const T *pv = Vf + gbar_index(th.rb + (okv ? xv : 0), i0, a.r);
+      T vu[GIC], vw[GIC];
+#pragma unroll
+      for (int ii = 0; ii < GIC; ++ii) {
+        const bool in = i0 + ii < a.r;
+        vu[ii] = (oku && in) ? pu[ii * 32] : T(0);
+        vw[ii] = (okv && in) ? pv[ii * 32] : T(0);
+      }
+#pragma unroll
+      for (int ii = 0; ii < GIC; ++ii) {
+        LU[ii * LS + p] = vu[ii];
+        LV[ii * LS + p] = vw[ii];
+      }
+    }
+    __syncthreads();
+    gather_chunk(th, a, LU, LV, LS, i0, acc, keep);
+  }
+  gather_finish(th, a, LU, acc, keep, scale, G);
 }
 
 template <typename T>
@@ -168,22 +267,42 @@ hipError_t launch_offset_gathers(const T *U, const T *V, int nfield, int64_t fst
                                  int nx, int r, int nh, double scale, T *G, hipStream_t st) {
   if (nh < 0 || nh > GMAXH) return hipErrorInvalidValue;
   constexpr int GCX = gather_cx<T>(), CB = GX / GCX;
+  GatherArgs a;
+  a.fstride = fstride;
+  a.N = N;
+  a.nfield = nfield;
+  a.nx = nx;
+  a.r = r;
+  a.nh = nh;
   const int nout = 2 * nh + 1;
-  const int hgs = (nout + GBH - 1) / GBH;           // offset blocks
-  const int slice_thr = 64 * ((hgs * CB + 63) / 64);  // whole waves of (offset, cell) blocks
-  const int nslice = 256 / slice_thr;
-  const int nthr = nslice * slice_thr;
+  a.hgs = (nout + GBH - 1) / GBH;               // offset blocks
+  a.slice_thr = 64 * ((a.hgs * CB + 63) / 64);  // whole waves of (offset, cell) blocks
+  a.nslice = 256 / a.slice_thr;
+  const int nthr = a.nslice * a.slice_thr;
   const int64_t rows = N / nx;
-  const int nseg = (nx + GX - 1) / GX;
-  const int64_t nblk = rows * nseg;
+  a.nseg = (nx + GX - 1) / GX;
+  const int64_t nblk = rows * a.nseg;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t stage = 2 * (size_t)GIC * gather_ls(nh);
-  const size_t reduce = (size_t)slice_thr * (GCX * GBH / 3);
-  const size_t lds = (stage > reduce ? stage : reduce) * sizeof(T);
-  hipLaunchKernelGGL((k_offset_gathers<T>), dim3((unsigned)nblk), dim3(nthr), lds, st, U, V,
-                     nfield, fstride, N, nx, r, nh, (T)scale, nseg, (int)nblk, nslice, slice_thr,
-                     hgs, G);
+  a.nblk = (int)nblk;
+  const int ls = gather_ls(nh);
+  const size_t reduce = (size_t)a.slice_thr * (GCX * GBH / 3);
+  if constexpr (sizeof(T) == 4) {
+    // 256 threads stage one column each; the reduction fits in one buffer
+    if (nthr != 256 || ls > 256 || reduce > 2 * (size_t)GIC * gather_ls(40))
+      return hipErrorInvalidValue;
+    if (ls <= gather_ls(40))
+      hipLaunchKernelGGL((k_offset_gathers_f32<gather_ls(40)>), dim3(a.nblk), dim3(nthr), 0, st,
+                         U, V, a, (float)scale, G);
+    else
+      hipLaunchKernelGGL((k_offset_gathers_f32<gather_ls(GMAXH)>), dim3(a.nblk), dim3(nthr), 0,
+                         st, U, V, a, (float)scale, G);
+  } else {
+    const size_t stage = 2 * (size_t)GIC * ls;
+    const size_t lds = (stage > reduce ? stage : reduce) * sizeof(T);
+    hipLaunchKernelGGL((k_offset_gathers<T>), dim3(a.nblk), dim3(nthr), lds, st, U, V, a,
+                       (T)scale, G);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_offset_gathers<float>(const float *, const float *, int, int64_t,
