@@ -221,11 +221,17 @@ rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_p
 /* Subsurface-offset image volume (Eq. 4) for horizontal offsets along x:
  *   gathers[h + nh][x] = scale * sum_f sum_i Ubar_f[i][x + h] Vbar_f[i][x - h],
  * h = -nh .. nh, with x + h and x - h moved along the x axis of the cell's
- * row and zero where either leaves it; h = 0 is rtm_image.
+ * row and zero where either leaves it; h = 0 is the rtm_image sum (here
+ * accumulated in the field dtype, in another order, so equal to rounding).
  *   Ubar, Vbar device tile-major, nfield (1, or 2 for the TTI p and q
- *              fields) compressed fields of r * Npad elements each
- *   gathers    device [2 nh + 1][N] field dtype, overwritten
- *   0 <= nh <= 64 (else RTM_E_UNSUPPORTED); scale = 1/r gives Eq. 4. */
+ *              fields) compressed fields of r * Npad elements each, the
+ *              second field right after the first; read only
+ *   gathers    device [2 nh + 1][N] field dtype, overwritten; must not
+ *              overlap Ubar or Vbar
+ *   scale      1/r gives Eq. 4
+ * Errors: NULL pointer or nfield not 1 / 2 -> RTM_E_ARG; nh outside 0..64 ->
+ * RTM_E_UNSUPPORTED; a failed launch -> RTM_E_HIP.  Stream-ordered; no
+ * workspace. */
 rtm_status rtm_offset_gathers(const rtm_plan *plan, const void *Ubar, const void *Vbar,
                               int32_t nfield, int32_t nh, double scale, void *gathers,
                               rtm_stream stream);

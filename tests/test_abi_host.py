@@ -127,6 +127,12 @@ def test_calls_reject_before_launch(L):
     # NULL model
     assert L.rtm_adjoint_probe(h, None, rp, fake, None, None, None, _lib.RTM_I8, None, fake,
                                n.value, None) == 1
+    # offset gathers: nfield 1 or 2, 0 <= nh <= 64, no NULL
+    assert L.rtm_offset_gathers(h, fake, fake, 3, 10, 1.0, fake, None) == 1
+    assert L.rtm_offset_gathers(h, fake, fake, 1, 65, 1.0, fake, None) == 7
+    assert L.rtm_offset_gathers(h, fake, fake, 1, -1, 1.0, fake, None) == 7
+    assert L.rtm_offset_gathers(h, None, fake, 1, 10, 1.0, fake, None) == 1
+    assert L.rtm_offset_gathers(h, fake, fake, 2, 10, 1.0, None, None) == 1
     L.rtm_plan_destroy(h)
 
 
