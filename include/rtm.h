@@ -72,7 +72,8 @@ typedef enum {
   RTM_E_WORKSPACE = 5,   /* work buffer smaller than required */
   RTM_E_HIP = 6,         /* a HIP runtime call failed */
   RTM_E_UNSUPPORTED = 7, /* valid request this build does not implement */
-  RTM_E_POINTS = 8       /* a source / receiver position outside the grid */
+  RTM_E_POINTS = 8,      /* a source / receiver position outside the grid */
+  RTM_E_NONFINITE = 9    /* (rtm_stream_status) a sweep met a non-finite value */
 } rtm_status;
 
 typedef enum {
@@ -156,6 +157,18 @@ void rtm_profile_enable(int32_t stride);
 rtm_status rtm_profile_read(int32_t kind, double *total_ms, int64_t *count);
 /* Message of the last HIP failure seen by this thread (empty if none). */
 const char *rtm_last_error(void);
+
+/* Device-side status of the last sweeping call on this workspace (any of the
+ * forward / adjoint / gradient / sketch calls, acoustic or TTI, single shot):
+ * each such call clears a watch word in `work` once its points are validated,
+ * and sets it when the final wavefield level(s) of a sweep, the gradient or
+ * image it returns, or the misfit holds a NaN or an infinity (a NaN or Inf in
+ * m, the wavelet, the data or the anisotropy, or a blow-up, spreads to
+ * these).  Synchronizes `stream`, then returns RTM_OK or RTM_E_NONFINITE;
+ * the word is left as it is.  work: the device workspace of the call (256-byte
+ * aligned); NULL plan or work -> RTM_E_ARG.  The batched calls keep no watch
+ * word. */
+rtm_status rtm_stream_status(const rtm_plan *plan, const void *work, rtm_stream stream);
 
 /* Forward sweep with on-the-fly probing (Eq. 3, Ubar = Z^T u_tt or Z^T u).
  *   m        device [N]           slowness squared

@@ -15,4 +15,5 @@ from .api import (Plan, PlanSpec, RtmError, bar_index, cfl_bound, fwi_gradient, 
                   autotune_stencil, set_stencil_blocks, Batch,
                   rtm_tti_forward_probe, rtm_tti_adjoint_probe, fwi_gradient_tti,
                   set_exact_fused, set_tti_shape, rf_workspace_bytes, rtm_sketch,
-                  rtm_orthonormalize, fwi_gradient_rf, rtm_offset_gathers)
+                  rtm_orthonormalize, fwi_gradient_rf, rtm_offset_gathers,
+                  stream_status)

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "librtm.so")
 
 RTM_F64, RTM_F32, RTM_BF16, RTM_BF16X2, RTM_I8 = 0, 1, 2, 3, 4
 RTM_PROBE_U, RTM_PROBE_UTT = 0, 1
+RTM_E_NONFINITE = 9
 
 # every symbol include/rtm.h declares
 EXPORTS = (
@@ -21,6 +22,7 @@ EXPORTS = (
     "rtm_tti_workspace_bytes", "rtm_tti_forward_probe", "rtm_tti_adjoint_probe",
     "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape", "rtm_rf_workspace_bytes",
     "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf", "rtm_offset_gathers",
+    "rtm_stream_status",
 )
 
 
@@ -101,6 +103,7 @@ def load() -> ctypes.CDLL:
                                   _vp, _vp, sz, _vp]
     L.fwi_gradient_rf.restype = ctypes.c_int
     L.rtm_offset_gathers.argtypes = [_vp, _vp, _vp, i32, i32, dbl, _vp, _vp]
+    L.rtm_stream_status.argtypes = [_vp, _vp, _vp]
     L.rtm_offset_gathers.restype = ctypes.c_int
     L.rtm_adjoint_image.argtypes = [_vp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, dbl, _vp, _vp, sz,
                                     _vp]

@@ -472,6 +472,18 @@ def rtm_offset_gathers(plan: Plan, Ubar, Vbar, nh: int, scale=None, nfield: int 
     return G
 
 
+def stream_status(plan: Plan, work: torch.Tensor) -> bool:
+    """True if the last sweeping call on this workspace kept every checked
+    value finite (final wavefield levels, gradient / image, misfit); False if
+    it met a NaN or an infinity.  Synchronizes the current stream."""
+    code = _lib.load().rtm_stream_status(plan.handle, ctypes.c_void_p(work.data_ptr()),
+                                         _stream(work.device))
+    if code == _lib.RTM_E_NONFINITE:
+        return False
+    _check(code, "rtm_stream_status")
+    return True
+
+
 def rf_workspace_bytes(plan: Plan) -> int:
     n = ctypes.c_size_t()
     _check(_lib.load().rtm_rf_workspace_bytes(plan.handle, ctypes.byref(n)),

@@ -42,6 +42,33 @@ hipError_t launch_copy(T *d, const T *s, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n)), dim3(256), 0, st, d, s, n);
   return hipGetLastError();
 }
+// Non-finite watch: any non-finite value among x[0..n) sets status[0] = 1
+// (plain stores of the same value; the word is cleared by k_status_clear).
+template <typename T>
+__global__ __launch_bounds__(256) void k_flag_nonfinite(const T *__restrict__ x, int64_t n,
+                                                        uint32_t *status) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256)
+    bad |= !isfinite(x[i]);
+  if (bad) status[0] = 1u;
+}
+__global__ void k_status_clear(uint32_t *status) {
+  if (threadIdx.x == 0) status[0] = 0u;
+}
+template <typename T>
+hipError_t launch_flag_nonfinite(const T *x, int64_t n, uint32_t *status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_flag_nonfinite<T>), dim3(grid_for(n)), dim3(256), 0, st, x, n, status);
+  return hipGetLastError();
+}
+hipError_t launch_status_clear(uint32_t *status, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, st, status);
+  return hipGetLastError();
+}
+template hipError_t launch_flag_nonfinite<float>(const float *, int64_t, uint32_t *, hipStream_t);
+template hipError_t launch_flag_nonfinite<double>(const double *, int64_t, uint32_t *,
+                                                  hipStream_t);
 template hipError_t launch_fill<float>(float *, int64_t, float, hipStream_t);
 template hipError_t launch_fill<double>(double *, int64_t, double, hipStream_t);
 template hipError_t launch_copy<float>(float *, const float *, int64_t, hipStream_t);

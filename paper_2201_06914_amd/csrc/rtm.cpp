@@ -108,7 +108,7 @@ struct rtm_plan {
   int64_t Npad = 0;  // N rounded up to whole 32-cell tiles (compressed-field layout)
   int R = 0;
   size_t esz = 0;
-  Region ring, red;
+  Region ring, red, status;  // status: the non-finite watch word (uint32)
   PointRegion src, rec;
   size_t tab_off = 0, tab_bytes = 0;
   size_t total = 0;
@@ -150,11 +150,25 @@ extern "C" const char *rtm_status_str(rtm_status s) {
     case RTM_E_HIP: return "HIP runtime error";
     case RTM_E_UNSUPPORTED: return "unsupported request";
     case RTM_E_POINTS: return "point outside the grid";
+    case RTM_E_NONFINITE: return "non-finite value in a wavefield or an output";
   }
   return "unknown status";
 }
 
 extern "C" const char *rtm_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" rtm_status rtm_stream_status(const rtm_plan *P, const void *work, rtm_stream stream) {
+  g_last_error.clear();
+  if (!P || !work) return fail(RTM_E_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(RTM_E_ARG, "work must be 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  uint32_t word = 0;
+  HIP_TRY(hipMemcpyAsync(&word, static_cast<const char *>(work) + P->status.off, sizeof(word),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (word) return fail(RTM_E_NONFINITE, "a non-finite value reached a wavefield or an output");
+  return RTM_OK;
+}
 
 extern "C" void rtm_set_stencil_variant(int v) {
   g_stencil_variant = (v >= -1 && v <= kStencilVariants) ? v : -1;
@@ -248,6 +262,7 @@ extern "C" rtm_status rtm_plan_create(const rtm_desc *desc, rtm_plan **out) {
   size_t cur = 0;
   place(cur, p->ring, (size_t)p->R * p->ld * p->esz);
   place(cur, p->red, sizeof(double) * (kReduceBlocks + 8));
+  place(cur, p->status, sizeof(uint32_t));
   p->tab_off = cur;
   place_points(cur, p->src, d.nsrc, p->esz);
   place_points(cur, p->rec, d.nrec, p->esz);
@@ -360,8 +375,14 @@ static PointTables<T> device_points(const PointRegion &pr, char *work, int32_t n
   return t;
 }
 
+static uint32_t *status_word(const rtm_plan *P, char *work) {
+  return reinterpret_cast<uint32_t *>(work + P->status.off);
+}
+
 // Builds the tables of the given point sets and copies them into the
-// workspace (stream ordered; waits for the copy so host memory can go).
+// workspace (stream ordered; waits for the copy so host memory can go).  Once
+// the points are valid, the call's non-finite watch word is cleared: every
+// sweeping call passes through here first.
 template <typename T>
 static rtm_status upload_points(const rtm_plan *P, char *work, hipStream_t st,
                                 const double *src_pos, PointTables<T> *src_t,
@@ -380,6 +401,7 @@ static rtm_status upload_points(const rtm_plan *P, char *work, hipStream_t st,
     stage_points<T>(P, P->rec, hr, host);
     *rec_t = device_points<T>(P->rec, work, P->d.nrec, (int32_t)hr.icell.size());
   }
+  HIP_TRY(launch_status_clear(status_word(P, work), st));
   if (P->tab_bytes) {
     HIP_TRY(hipMemcpyAsync(work + P->tab_off, host.data(), P->tab_bytes, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -516,6 +538,8 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
     HIP_TRY(launch_copy<T>(fs, level(d.nt), P->N, st));
     HIP_TRY(launch_copy<T>(fs + P->N, level(d.nt - 1), P->N, st));
   }
+  // a field that went non-finite anywhere stays so: the last level tells
+  HIP_TRY(launch_flag_nonfinite<T>(level(d.nt), P->N, status_word(P, work), st));
   return RTM_OK;
 }
 
@@ -769,14 +793,17 @@ static rtm_status gradient_impl(const rtm_plan *P, const void *m, const double *
     b.fuse_U = Ubar;
     b.fuse_img = grad;
     b.fuse_scale = scale;
-    return run_sweep<T>(P, b, rec_t, none, w, st);
+    if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
+  } else {
+    if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
+    TimedLaunch ti;
+    prof_begin(KT_IMAGE, 0, st, &ti);
+    HIP_TRY(launch_image<T>(static_cast<const T *>(Ubar), static_cast<const T *>(Vbar), P->N,
+                            P->d.r, scale, static_cast<T *>(grad), st));
+    prof_end(st, &ti);
   }
-  if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
-  TimedLaunch ti;
-  prof_begin(KT_IMAGE, 0, st, &ti);
-  HIP_TRY(launch_image<T>(static_cast<const T *>(Ubar), static_cast<const T *>(Vbar), P->N,
-                          P->d.r, scale, static_cast<T *>(grad), st));
-  prof_end(st, &ti);
+  HIP_TRY(launch_flag_nonfinite<T>(static_cast<const T *>(grad), P->N, status_word(P, w), st));
+  HIP_TRY(launch_flag_nonfinite<double>(misfit, 1, status_word(P, w), st));
   return RTM_OK;
 }
 
@@ -1045,6 +1072,8 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
       }
     }
   }
+  HIP_TRY(launch_flag_nonfinite<T>(grad, N, status_word(P, w), st));
+  HIP_TRY(launch_flag_nonfinite<double>(misfit, 1, status_word(P, w), st));
   return RTM_OK;
 }
 
@@ -1616,6 +1645,8 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
       s0 = s + 1;
     }
   }
+  HIP_TRY(launch_flag_nonfinite<T>(lv(ringP, d.nt), N, status_word(P, w), st));
+  HIP_TRY(launch_flag_nonfinite<T>(lv(ringQ, d.nt), N, status_word(P, w), st));
   return RTM_OK;
 }
 
@@ -1741,16 +1772,19 @@ static rtm_status tti_grad_impl(const rtm_plan *P, const void *m, const void *an
     b.fuse_U = Ubar;
     b.fuse_img = grad;
     b.fuse_scale = -1.0 / P->d.r;
-    return run_tti_sweep<T>(P, b, rec_t, none, w, st);
+    if ((s = run_tti_sweep<T>(P, b, rec_t, none, w, st))) return s;
+  } else {
+    b.bar = Vbar;
+    if ((s = run_tti_sweep<T>(P, b, rec_t, none, w, st))) return s;
+    // grad = -(1/r) sum_i (Ubar_p Vbar_p + Ubar_q Vbar_q): two images summed
+    T *gq = reinterpret_cast<T *>(w + P->total) + (int64_t)(P->R + 5) * P->ld;  // scratch level
+    const T *U = static_cast<const T *>(Ubar), *V = static_cast<const T *>(Vbar);
+    HIP_TRY(launch_image<T>(U, V, P->N, P->d.r, -1.0 / P->d.r, static_cast<T *>(grad), st));
+    HIP_TRY(launch_image<T>(U + barn, V + barn, P->N, P->d.r, -1.0 / P->d.r, gq, st));
+    HIP_TRY(launch_axpy<T>(static_cast<T *>(grad), gq, P->N, st));
   }
-  b.bar = Vbar;
-  if ((s = run_tti_sweep<T>(P, b, rec_t, none, w, st))) return s;
-  // grad = -(1/r) sum_i (Ubar_p Vbar_p + Ubar_q Vbar_q): two images summed
-  T *gq = reinterpret_cast<T *>(w + P->total) + (int64_t)(P->R + 5) * P->ld;  // scratch level
-  const T *U = static_cast<const T *>(Ubar), *V = static_cast<const T *>(Vbar);
-  HIP_TRY(launch_image<T>(U, V, P->N, P->d.r, -1.0 / P->d.r, static_cast<T *>(grad), st));
-  HIP_TRY(launch_image<T>(U + barn, V + barn, P->N, P->d.r, -1.0 / P->d.r, gq, st));
-  HIP_TRY(launch_axpy<T>(static_cast<T *>(grad), gq, P->N, st));
+  HIP_TRY(launch_flag_nonfinite<T>(static_cast<const T *>(grad), P->N, status_word(P, w), st));
+  HIP_TRY(launch_flag_nonfinite<double>(misfit, 1, status_word(P, w), st));
   return RTM_OK;
 }
 

@@ -196,6 +196,9 @@ hipError_t launch_axpy(T *y, const T *x, int64_t n, hipStream_t st);  // y += x
 template <typename T>
 hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
 template <typename T>
+hipError_t launch_flag_nonfinite(const T *x, int64_t n, uint32_t *status, hipStream_t st);
+hipError_t launch_status_clear(uint32_t *status, hipStream_t st);
+template <typename T>
 hipError_t launch_image(const T *U, const T *V, int64_t N, int r, double scale, T *img,
                         hipStream_t st);
 // res = d - d_obs (in place over d when res == d), misfit = 0.5 * sum res^2

@@ -127,6 +127,10 @@ def test_calls_reject_before_launch(L):
     # NULL model
     assert L.rtm_adjoint_probe(h, None, rp, fake, None, None, None, _lib.RTM_I8, None, fake,
                                n.value, None) == 1
+    # stream status: NULL plan / work, misaligned work
+    assert L.rtm_stream_status(None, fake, None) == 1
+    assert L.rtm_stream_status(h, None, None) == 1
+    assert L.rtm_stream_status(h, ctypes.c_void_p((1 << 20) + 4), None) == 1
     # offset gathers: nfield 1 or 2, 0 <= nh <= 64, no NULL
     assert L.rtm_offset_gathers(h, fake, fake, 3, 10, 1.0, fake, None) == 1
     assert L.rtm_offset_gathers(h, fake, fake, 1, 65, 1.0, fake, None) == 7

@@ -1,0 +1,72 @@
+"""The non-finite watch word (rtm_stream_status) on the GPU: clean sweeps
+report OK; a NaN in the model, an infinity in the observed data or a NaN in
+the anisotropy reaches the checked values and is reported; the next clean
+call on the same workspace clears it."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import dev, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+import paper_2201_06914_amd as P  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_forward_nan_model_flagged_then_cleared():
+    wl = synth.workload_small_2d(shape=(30, 34), nt=64, r=16)
+    plan = P.Plan.for_workload(wl, field="f64", probe="f64")
+    work = plan.workspace("cuda")
+    q, Z = dev(wl.q, torch.float64), dev(wl.Z, torch.int8)
+    m = dev(wl.m, torch.float64)
+    P.rtm_forward_probe(plan, m, wl.src_pos, q, wl.rec_pos, Z=Z, work=work)
+    ok_clean = P.stream_status(plan, work)
+    bad = wl.m.copy()
+    bad[15, 0, 17] = np.nan
+    P.rtm_forward_probe(plan, dev(bad, torch.float64), wl.src_pos, q, wl.rec_pos, Z=Z, work=work)
+    ok_nan = P.stream_status(plan, work)
+    P.rtm_forward_probe(plan, m, wl.src_pos, q, wl.rec_pos, Z=Z, work=work)
+    ok_again = P.stream_status(plan, work)
+    say(f"  forward: clean {ok_clean}, NaN model {ok_nan}, clean again {ok_again}")
+    assert ok_clean and not ok_nan and ok_again
+
+
+def test_gradient_inf_data_flagged():
+    wl = synth.workload_small_3d(shape=(20, 18, 40), nt=60, nb=4)
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2")
+    work = plan.workspace("cuda")
+    d_obs = np.zeros((wl.nt, wl.rec_pos.shape[0]), dtype=np.float32)
+    args = (plan, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32), wl.rec_pos)
+    Z = dev(wl.Z, torch.int8)
+    P.fwi_gradient(*args, dev(d_obs, torch.float32), Z, work=work, fused=True)
+    ok_clean = P.stream_status(plan, work)
+    d_obs[10, 1] = np.inf
+    P.fwi_gradient(*args, dev(d_obs, torch.float32), Z, work=work, fused=True)
+    ok_inf = P.stream_status(plan, work)
+    say(f"  gradient: clean {ok_clean}, Inf in d_obs {ok_inf}")
+    assert ok_clean and not ok_inf
+
+
+def test_tti_nan_anisotropy_flagged():
+    wl, an = synth.workload_tti(shape=(18, 16, 20), nt=40, r=8, sigma=2.0, nb=4, f0=15.0,
+                                rec_stride=7, dtype=np.float32)
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", c_max=wl.c_ref)
+    from paper_2201_06914_amd.api import tti_workspace
+    work = tti_workspace(plan, "cuda")
+    m, q, Z = dev(wl.m, torch.float32), dev(wl.q, torch.float32), dev(wl.Z, torch.int8)
+    P.rtm_tti_forward_probe(plan, m, dev(an, torch.float32), wl.src_pos, q, wl.rec_pos, Z=Z,
+                            work=work)
+    ok_clean = P.stream_status(plan, work)
+    bad = an.copy()
+    bad.reshape(bad.shape[0], -1)[0, 100] = np.nan
+    P.rtm_tti_forward_probe(plan, m, dev(bad, torch.float32), wl.src_pos, q, wl.rec_pos, Z=Z,
+                            work=work)
+    ok_nan = P.stream_status(plan, work)
+    say(f"  TTI: clean {ok_clean}, NaN anisotropy {ok_nan}")
+    assert ok_clean and not ok_nan
