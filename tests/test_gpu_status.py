@@ -28,7 +28,7 @@ def test_forward_nan_model_flagged_then_cleared():
     P.rtm_forward_probe(plan, m, wl.src_pos, q, wl.rec_pos, Z=Z, work=work)
     ok_clean = P.stream_status(plan, work)
     bad = wl.m.copy()
-    bad[15, 0, 17] = np.nan
+    bad[15 * 34 + 17] = np.nan
     P.rtm_forward_probe(plan, dev(bad, torch.float64), wl.src_pos, q, wl.rec_pos, Z=Z, work=work)
     ok_nan = P.stream_status(plan, work)
     P.rtm_forward_probe(plan, m, wl.src_pos, q, wl.rec_pos, Z=Z, work=work)
