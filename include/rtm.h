@@ -190,6 +190,27 @@ rtm_status rtm_forward_probe(const rtm_plan *plan, const void *m, const double *
                              void *Ubar, void *final_state, void *work, size_t work_bytes,
                              rtm_stream stream);
 
+/* The forward sweep of rtm_forward_probe over steps n_begin .. n_end - 1 only
+ * (checkpoint / resume: the state (u^n, u^{n-1}) plus the partial Ubar is a
+ * complete checkpoint, since Ubar is a sum over steps).
+ *   0 <= n_begin < n_end <= nt; n_begin a multiple of k_block, n_end a
+ *     multiple of k_block or nt (else RTM_E_ARG), so the probe blocks are
+ *     those of the whole sweep and a run split into ranges equals the
+ *     uninterrupted run bit for bit
+ *   state_in  device [2][N]: u^{n_begin}, u^{n_begin - 1} (the state_out of
+ *             the previous range); required exactly when n_begin > 0
+ *   state_out device [2][N] or NULL: u^{n_end}, u^{n_end - 1}
+ *   Ubar      as rtm_forward_probe, overwritten when n_begin = 0 and
+ *             accumulated into otherwise
+ *   d_pred    rows n_begin .. n_end - 1 of [nt][nrec] written, others kept
+ * Other arguments as rtm_forward_probe. */
+rtm_status rtm_forward_probe_range(const rtm_plan *plan, const void *m, const double *src_pos,
+                                   const void *q, const double *rec_pos, void *d_pred,
+                                   const void *Z, rtm_dtype z_dtype, rtm_probe_field what,
+                                   void *Ubar, int32_t n_begin, int32_t n_end,
+                                   const void *state_in, void *state_out, void *work,
+                                   size_t work_bytes, rtm_stream stream);
+
 /* Adjoint (time-reversed) sweep with probing: Vbar = Z^T lam, row n of Z
  * paired with lam^n.
  *   rec_pos host [nrec][3], res device [nt][nrec] (the adjoint source)

@@ -22,7 +22,7 @@ EXPORTS = (
     "rtm_tti_workspace_bytes", "rtm_tti_forward_probe", "rtm_tti_adjoint_probe",
     "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape", "rtm_rf_workspace_bytes",
     "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf", "rtm_offset_gathers",
-    "rtm_stream_status",
+    "rtm_stream_status", "rtm_forward_probe_range",
 )
 
 
@@ -104,6 +104,8 @@ def load() -> ctypes.CDLL:
     L.fwi_gradient_rf.restype = ctypes.c_int
     L.rtm_offset_gathers.argtypes = [_vp, _vp, _vp, i32, i32, dbl, _vp, _vp]
     L.rtm_stream_status.argtypes = [_vp, _vp, _vp]
+    L.rtm_forward_probe_range.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, _vp, i32, i32, _vp, i32,
+                                          i32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.rtm_offset_gathers.restype = ctypes.c_int
     L.rtm_adjoint_image.argtypes = [_vp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, dbl, _vp, _vp, sz,
                                     _vp]

@@ -358,6 +358,34 @@ def rtm_forward_probe(plan: Plan, m, src_pos, q, rec_pos=None, Z=None, what: str
     return out
 
 
+def rtm_forward_probe_range(plan: Plan, m, src_pos, q, rec_pos, Z, n_begin: int, n_end: int,
+                            state_in=None, Ubar=None, d=None, what: str = "utt",
+                            work=None) -> dict:
+    """Forward sweep over steps n_begin .. n_end - 1 (ends on probe-block
+    boundaries) from state_in = (u^{n_begin}, u^{n_begin - 1}); Ubar and d
+    carry over from the previous range (fresh ones when n_begin = 0).
+    Returns {"d", "Ubar", "state"} with state = (u^{n_end}, u^{n_end - 1})."""
+    s = plan.spec
+    dev = m.device
+    if d is None:
+        d = torch.empty((s.nt, s.nrec), dtype=plan.dtype, device=dev)
+    U = Ubar if Ubar is not None else plan.empty_bar(dev)
+    F = torch.empty((2, plan.N), dtype=plan.dtype, device=dev)
+    work = _work(plan, work, dev)
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    zp, zt = _z(plan, Z)
+    code = _lib.load().rtm_forward_probe_range(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
+        _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp, _dev(d, plan.dtype, s.nt * s.nrec, "d"),
+        zp, zt, _lib.RTM_PROBE_UTT if what == "utt" else _lib.RTM_PROBE_U,
+        _dev(U, plan.dtype, s.r * plan.Npad, "Ubar"), int(n_begin), int(n_end),
+        _dev(state_in, plan.dtype, 2 * plan.N, "state_in"), _dev(F, plan.dtype, 2 * plan.N, "state"),
+        ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(dev))
+    _check(code, "rtm_forward_probe_range")
+    return {"d": d, "Ubar": U, "state": F}
+
+
 def rtm_adjoint_probe(plan: Plan, m, rec_pos, res, Z=None, src_pos=None, want_qadj=False,
                       work=None) -> dict:
     s = plan.spec

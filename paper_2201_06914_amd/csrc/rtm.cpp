@@ -447,7 +447,11 @@ struct SweepIO {
   rtm_dtype zt = RTM_I8;
   int mode = PROBE_UTT;
   void *bar = nullptr;             // [r][N] or NULL
-  void *final_state = nullptr;     // [2][N] or NULL
+  void *final_state = nullptr;     // [2][N] or NULL: levels n_end, n_end - 1
+  // step range (forward only): steps n_begin .. n_end - 1 from state_in
+  // (levels n_begin, n_begin - 1; zero when NULL); bar accumulates if n_begin > 0
+  int n_begin = 0, n_end = -1;
+  const void *state_in = nullptr;
   // fused adjoint imaging (MFMA paths): img += scale * sum_i fuse_U[i] (Z_b^T S_b)[i]
   const void *fuse_U = nullptr;
   void *fuse_img = nullptr;
@@ -472,14 +476,21 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
   if (ndim == 3 && sizeof(T) == 4) variant = kStencilTiled;
   if (g_stencil_variant >= 0) variant = g_stencil_variant;
   StepArgs<T> a = step_args<T>(P, static_cast<const T *>(io.m));
-  HIP_TRY(launch_fill<T>(level(-1), P->N, T(0), st));
-  HIP_TRY(launch_fill<T>(level(0), P->N, T(0), st));
+  const int nb = io.n_begin, ne = io.n_end < 0 ? d.nt : io.n_end;
+  if (io.state_in) {
+    const T *si = static_cast<const T *>(io.state_in);
+    HIP_TRY(launch_copy<T>(level(nb), si, P->N, st));
+    HIP_TRY(launch_copy<T>(level(nb - 1), si + P->N, P->N, st));
+  } else {
+    HIP_TRY(launch_fill<T>(level(nb - 1), P->N, T(0), st));
+    HIP_TRY(launch_fill<T>(level(nb), P->N, T(0), st));
+  }
   T *bar = static_cast<T *>(io.bar);
-  if (bar) HIP_TRY(launch_fill<T>(bar, (int64_t)d.r * P->Npad, T(0), st));
+  if (bar && nb == 0) HIP_TRY(launch_fill<T>(bar, (int64_t)d.r * P->Npad, T(0), st));
   const T *inj_vals = static_cast<const T *>(io.inj_vals);
   T *smp_out = static_cast<T *>(io.smp_out);
-  int s0 = 0;
-  for (int s = 0; s < d.nt; ++s) {
+  int s0 = nb;
+  for (int s = nb; s < ne; ++s) {
     const int n = io.adjoint ? d.nt - 1 - s : s;
     a.cur = level(s);
     a.prev = level(s - 1);
@@ -492,7 +503,8 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       HIP_TRY(launch_inject<T>(a, inj, inj_vals + (int64_t)n * inj.npts, a.next, st));
     if (smp_out && smp.npts > 0)
       HIP_TRY(launch_sample<T>(smp, a.next, smp_out + (int64_t)n * smp.npts, st));
-    if ((bar || io.fuse_img || io.sketch_Y) && (s + 1 - s0 == d.k_block || s == d.nt - 1)) {
+    if ((bar || io.fuse_img || io.sketch_Y) &&
+        (s + 1 - s0 == d.k_block || s == d.nt - 1 || s == ne - 1)) {
       ProbeArgs<T> p{};
       p.ring = ring;
       p.ld = P->ld;
@@ -535,11 +547,11 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
   }
   if (io.final_state) {
     T *fs = static_cast<T *>(io.final_state);
-    HIP_TRY(launch_copy<T>(fs, level(d.nt), P->N, st));
-    HIP_TRY(launch_copy<T>(fs + P->N, level(d.nt - 1), P->N, st));
+    HIP_TRY(launch_copy<T>(fs, level(ne), P->N, st));
+    HIP_TRY(launch_copy<T>(fs + P->N, level(ne - 1), P->N, st));
   }
   // a field that went non-finite anywhere stays so: the last level tells
-  HIP_TRY(launch_flag_nonfinite<T>(level(d.nt), P->N, status_word(P, work), st));
+  HIP_TRY(launch_flag_nonfinite<T>(level(ne), P->N, status_word(P, work), st));
   return RTM_OK;
 }
 
@@ -577,7 +589,8 @@ template <typename T>
 static rtm_status forward_impl(const rtm_plan *P, const void *m, const double *src_pos,
                                const void *q, const double *rec_pos, void *d_pred, const void *Z,
                                rtm_dtype zt, rtm_probe_field what, void *Ubar, void *fin,
-                               void *work, hipStream_t st) {
+                               void *work, hipStream_t st, int n_begin = 0, int n_end = -1,
+                               const void *state_in = nullptr) {
   PointTables<T> src_t, rec_t;
   rtm_status s = upload_points<T>(P, static_cast<char *>(work), st, src_pos, &src_t,
                                   d_pred ? rec_pos : nullptr, &rec_t);
@@ -592,6 +605,9 @@ static rtm_status forward_impl(const rtm_plan *P, const void *m, const double *s
   io.mode = what == RTM_PROBE_U ? PROBE_CUR : PROBE_UTT;
   io.bar = Ubar;
   io.final_state = fin;
+  io.n_begin = n_begin;
+  io.n_end = n_end;
+  io.state_in = state_in;
   return run_sweep<T>(P, io, src_t, rec_t, static_cast<char *>(work), st);
 }
 
@@ -612,6 +628,34 @@ extern "C" rtm_status rtm_forward_probe(const rtm_plan *P, const void *m, const 
                                 final_state, work, st);
   return forward_impl<float>(P, m, src_pos, q, rec_pos, d_pred, Z, zt, what, Ubar, final_state,
                              work, st);
+}
+
+extern "C" rtm_status rtm_forward_probe_range(const rtm_plan *P, const void *m,
+                                              const double *src_pos, const void *q,
+                                              const double *rec_pos, void *d_pred, const void *Z,
+                                              rtm_dtype zt, rtm_probe_field what, void *Ubar,
+                                              int32_t n_begin, int32_t n_end,
+                                              const void *state_in, void *state_out, void *work,
+                                              size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_common(P, m, work, work_bytes);
+  if (s) return s;
+  const int nt = P->d.nt, k = P->d.k_block;
+  if (n_begin < 0 || n_end <= n_begin || n_end > nt)
+    return fail(RTM_E_ARG, "need 0 <= n_begin < n_end <= nt");
+  if (n_begin % k != 0 || (n_end % k != 0 && n_end != nt))
+    return fail(RTM_E_ARG, "range ends must fall on probe-block boundaries (multiples of k_block, or nt)");
+  if ((n_begin > 0) != (state_in != nullptr))
+    return fail(RTM_E_ARG, "state_in is required exactly when n_begin > 0");
+  if (P->d.nsrc > 0 && (!src_pos || !q)) return fail(RTM_E_ARG, "src_pos and q are required");
+  if (d_pred && P->d.nrec > 0 && !rec_pos) return fail(RTM_E_ARG, "rec_pos is required with d_pred");
+  if (what != RTM_PROBE_U && what != RTM_PROBE_UTT) return fail(RTM_E_ARG, "bad probe field");
+  if ((s = check_probe(P, Z, zt, Ubar))) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (P->d.field_dtype == RTM_F64)
+    return forward_impl<double>(P, m, src_pos, q, rec_pos, d_pred, Z, zt, what, Ubar, state_out,
+                                work, st, n_begin, n_end, state_in);
+  return forward_impl<float>(P, m, src_pos, q, rec_pos, d_pred, Z, zt, what, Ubar, state_out,
+                             work, st, n_begin, n_end, state_in);
 }
 
 template <typename T>

@@ -127,6 +127,19 @@ def test_calls_reject_before_launch(L):
     # NULL model
     assert L.rtm_adjoint_probe(h, None, rp, fake, None, None, None, _lib.RTM_I8, None, fake,
                                n.value, None) == 1
+    # step range: ends on probe-block boundaries (k_block = 16, nt = 50), state
+    # exactly when resuming
+    fr = L.rtm_forward_probe_range
+    assert fr(h, fake, sp, fake, None, None, fake, _lib.RTM_I8, 1, fake, 8, 32, fake, None,
+              fake, n.value, None) == 1                       # n_begin % k != 0
+    assert fr(h, fake, sp, fake, None, None, fake, _lib.RTM_I8, 1, fake, 16, 40, fake, None,
+              fake, n.value, None) == 1                       # n_end neither % k nor nt
+    assert fr(h, fake, sp, fake, None, None, fake, _lib.RTM_I8, 1, fake, 16, 32, None, None,
+              fake, n.value, None) == 1                       # resume without state
+    assert fr(h, fake, sp, fake, None, None, fake, _lib.RTM_I8, 1, fake, 0, 16, fake, None,
+              fake, n.value, None) == 1                       # state at n_begin = 0
+    assert fr(h, fake, sp, fake, None, None, fake, _lib.RTM_I8, 1, fake, 32, 64, fake, None,
+              fake, n.value, None) == 1                       # n_end > nt
     # stream status: NULL plan / work, misaligned work
     assert L.rtm_stream_status(None, fake, None) == 1
     assert L.rtm_stream_status(h, None, None) == 1
