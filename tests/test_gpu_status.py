@@ -70,3 +70,26 @@ def test_tti_nan_anisotropy_flagged():
     ok_nan = P.stream_status(plan, work)
     say(f"  TTI: clean {ok_clean}, NaN anisotropy {ok_nan}")
     assert ok_clean and not ok_nan
+
+
+def test_unstable_run_is_flagged():
+    """A plan that under-declares c_max by 3x (with a 3x longer dt) passes the
+    host CFL check (it sees the same dt c_max / h) but steps the real model
+    at three times the stable Courant number (0.77 against the 0.55 bound; the
+    Nyquist mode grows ~5x per step): the field overflows FP32 within the 128
+    steps and the status word reports it; the honest plan does not."""
+    wl = synth.workload_small_2d(shape=(30, 34), nt=128, r=16)
+
+    def plan_of(dt, c_max):
+        return P.Plan(P.PlanSpec(2, wl.shape, wl.h, dt, wl.nt, wl.nb, wl.c_ref, wl.R, c_max,
+                                 "f32", "f32", 16, 16, int(np.shape(wl.src_pos)[0]),
+                                 int(np.shape(wl.rec_pos)[0])))
+    res = {}
+    for tag, pl in (("honest", plan_of(wl.dt, wl.c_ref)),
+                    ("c_max / 3", plan_of(3 * wl.dt, wl.c_ref / 3))):
+        work = pl.workspace("cuda")
+        P.rtm_forward_probe(pl, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32),
+                            wl.rec_pos, work=work)
+        res[tag] = P.stream_status(pl, work)
+    say(f"  finite: {res}")
+    assert res["honest"] and not res["c_max / 3"]
