@@ -219,9 +219,12 @@ def autotune_stencil(plan: Plan, m, work=None, steps: int = 20, apply: bool = Tr
     """Times every stencil variant on this plan's grid (after checking each
     against the one-thread-per-cell kernel bit for bit) and, with apply=True,
     selects the fastest.  `cache`: a JSON file keyed by (arch, grid, dtype)
-    that stores the choice across runs."""
+    that stores the choice across runs (default: the RTM_TUNE_CACHE
+    environment variable, if set)."""
     import json
     import os
+    if cache is None:
+        cache = os.environ.get("RTM_TUNE_CACHE") or None
     key = None
     if cache:
         props = torch.cuda.get_device_properties(m.device)
