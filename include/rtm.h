@@ -325,10 +325,10 @@ void rtm_set_exact_fused(int32_t on);
 /* Tuning hook, process wide: tile shape of the tiled TTI step kernels, as
  * rows of 64 columns for the in-plane pass / the z-marching pass: 1 = 8 / 8,
  * 2 = 4 / 4, 3 = 8 / 4; 4 and 5: as 3 for the transpose step, and the forward
- * step as one fused kernel of 4 or 8 rows; 6 (default): both steps as one
- * fused kernel each (4 rows); 7: both fused, the forward step on 4 rows and
- * the transpose step on 8 rows; 8: both fused on 8 rows; other values
- * select 6.
+ * step as one fused kernel of 4 or 8 rows; 6: both steps as one fused
+ * kernel each (4 rows); 7 (default): both fused, the forward step on 4 rows
+ * and the transpose step on 8 rows; 8: both fused on 8 rows; other values
+ * select 7.
  * rtm_set_stencil_variant(0) forces the one-thread-per-cell TTI kernels
  * instead.  Results agree to rounding. */
 void rtm_set_tti_shape(int32_t shape);

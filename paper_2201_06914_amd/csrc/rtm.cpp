@@ -33,7 +33,7 @@ static thread_local std::string g_last_error;
 static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled variant id
 static int g_stencil_blocks = 1024; // tiled stencil: split z until this many workgroups
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
-static int g_tti_shape = 6;         // tiled TTI tile shape (1..8)
+static int g_tti_shape = 7;         // tiled TTI tile shape (1..8)
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
@@ -176,7 +176,7 @@ extern "C" void rtm_set_stencil_variant(int v) {
 
 extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
 
-extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 8) ? shape : 6; }
+extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 8) ? shape : 7; }
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
   g_stencil_blocks = blocks > 0 ? blocks : 1024;

@@ -700,7 +700,8 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_amarch(TtiArgs<T> t, int n
 // w1, n_z^2 w1, n_z^2 w2; the current plane z carries w1, n_x^2 w, n_y^2 w and
 // n_x n_y w (with corners, for the second LDS stage D_x (D_y .)).  The own
 // cell's w2, n_x, n_y, lp, lq reach plane z through 5-deep delay queues.
-// Current-plane LDS is single buffered: three barriers per plane.
+// Current-plane LDS is double buffered (two barriers per plane) where it fits
+// in LDS; FP64 on 64 x 8 tiles keeps one buffer and a third barrier.
 // ---------------------------------------------------------------------------
 template <typename T, int TY, int MINW>
 __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int ntx, int nty,
@@ -711,7 +712,9 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int n
   block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
   const TtiTile<TY> g = tile_of<TY>(a, bx, by);
   // current plane: w1, n_x^2 w1, n_y^2 w1, n_x^2 w2, n_y^2 w2, n_x n_y w1, n_x n_y w2
-  __shared__ T Lc[7][G::PL];
+  // (NB buffers: plane z writes buffer z & 1 while others may still read z - 1's)
+  constexpr int NB = (sizeof(T) == 8 && TY == 8) ? 1 : 2;
+  __shared__ T LcB[NB][7][G::PL];
   __shared__ T Ll[4][G::PL];      // lead plane: n_x n_z w1, n_x n_z w2, n_y n_z w1, n_y n_z w2
   __shared__ T H[2][TY * G::LX];  // D_y (n_x n_y w1), D_y (n_x n_y w2)
   const int64_t N = a.N;
@@ -758,7 +761,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int n
   auto w1of = [](const In &c) { return c.c1 * c.lp + c.c2 * c.lq; };
   auto w2of = [](const In &c) { return c.c2 * c.lp + c.lq; };
   // current-plane LDS values of one cell (halo cells: LDS offset l)
-  auto stage_cur = [&](int l, T w1, T w2, T nx, T ny) {
+  auto stage_cur = [&](T (*Lc)[G::PL], int l, T w1, T w2, T nx, T ny) {
     Lc[0][l] = w1;
     Lc[1][l] = (nx * nx) * w1;
     Lc[2][l] = (ny * ny) * w1;
@@ -771,6 +774,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int n
   fetch(zs);
   for (int z = zs; z < z1; ++z) {
     const bool out = z >= z0;  // uniform over the workgroup
+    T(*Lc)[G::PL] = LcB[NB == 2 ? (z & 1) : 0];
     // lead plane: queue fronts and LDS
     {
       const T w1 = w1of(li), w2 = w2of(li);
@@ -801,13 +805,13 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int n
     // current plane
     const T clpp = lpp, clqp = lqp, cm = mm;
     if (out) {
-      stage_cur(g.lc, W[4], Dw2[0], Dnx[0], Dny[0]);
+      stage_cur(Lc, g.lc, W[4], Dw2[0], Dnx[0], Dny[0]);
 #pragma unroll
       for (int k = 0; k < G::NHY; ++k)
-        stage_cur(g.hyl[k], w1of(cy[k]), w2of(cy[k]), cy[k].nx, cy[k].ny);
-      if (threadIdx.x < G::NHX) stage_cur(g.hxl, w1of(cx), w2of(cx), cx.nx, cx.ny);
+        stage_cur(Lc, g.hyl[k], w1of(cy[k]), w2of(cy[k]), cy[k].nx, cy[k].ny);
+      if (threadIdx.x < G::NHX) stage_cur(Lc, g.hxl, w1of(cx), w2of(cx), cx.nx, cx.ny);
       if (threadIdx.x >= G::NHX && threadIdx.x < G::NHX + 64)
-        stage_cur(g.cnl, w1of(cn), w2of(cn), cn.nx, cn.ny);
+        stage_cur(Lc, g.cnl, w1of(cn), w2of(cn), cn.nx, cn.ny);
     }
     if (z + 1 < z1) fetch(z + 1);
     __syncthreads();
@@ -836,7 +840,10 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int n
       sto(t.pn, o, tti_update(a, Dlp[0], clpp, cm, lw1 - hz1, damp));
       sto(t.qn, o, tti_update(a, Dlq[0], clqp, cm, hz2, damp));
     }
-    __syncthreads();  // the current-plane LDS is rewritten next iteration
+    // one current-plane buffer: it is rewritten next iteration.  Two: the
+    // next iteration writes the other one; the lead plane and H are rewritten
+    // only after the next iteration's first / this iteration's second barrier
+    if constexpr (NB == 1) __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       W[k] = W[k + 1];
@@ -912,8 +919,9 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 
 // tile shapes (prep / march rows of 64 columns): 1 = 8 / 8, 2 = 4 / 4,
 // 3 = 8 / 4, 4 = as 3 with the fused forward kernel (4 rows), 5 = as 3 with
-// the fused forward kernel (8 rows), 6 (default) = both steps fused (4 rows),
-// 7 = both fused, forward 4 rows and transpose 8 rows, 8 = both fused (8 rows)
+// the fused forward kernel (8 rows), 6 = both steps fused (4 rows), 7 (the
+// library's default) = both fused, forward 4 rows and transpose 8 rows,
+// 8 = both fused (8 rows)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -927,7 +935,7 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
     case 7: return adjoint ? tti_step_tiled<T, 8, 8, true, true>(t, adjoint, target_blocks, st)
                            : tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
     case 8: return tti_step_tiled<T, 8, 8, true, true>(t, adjoint, target_blocks, st);
-    default: return tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
+    default: return tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);  // 6
   }
 }
 

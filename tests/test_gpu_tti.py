@@ -38,7 +38,7 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(6)
+    P.set_tti_shape(7)  # the default
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
@@ -153,7 +153,7 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
-            P.set_tti_shape(6)
+            P.set_tti_shape(7)  # the default
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
     say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
         " ".join(f"{k} {v:.2e}" for k, v in e.items()))
