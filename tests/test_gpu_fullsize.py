@@ -1,9 +1,11 @@
-"""Full-size parity: the 384 x 512 x 512 layered 3D grid (r = 128 probes,
+"""Full-size parity.  The 384 x 512 x 512 layered 3D grid (r = 128 probes,
 k = 32, BF16X2 MFMA probing, FP32 fields) through fwi_gradient - the launch
 configuration the benchmark times - truncated to nt = 64 steps so the FP64
-oracle can follow it.  Traces (the whole 512 x 512 receiver plane) and the
-misfit are compared in full; the compressed fields and the gradient on a
-sample of cells (near the source, in the sponge, at grid corners, random)."""
+oracle can follow it: traces (the whole 512 x 512 receiver plane) and the
+misfit in full, the compressed fields and the gradient on a sample of cells
+(near the source, in the sponge, at grid corners, random).  The 300 x 400 x
+400 TTI grid through properties that hold at any size (dot test, isotropic
+limit), and its 81-offset image volume on sampled rows against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -63,3 +65,70 @@ def test_fullsize_layered_3d_gradient_truncated():
     say("  " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()))
     assert e["d"] < 1e-5 and e["J"] < 2e-5
     assert e["U"] < 1e-4 and e["V"] < 1e-4 and e["g"] < 1e-3
+
+
+def test_fullsize_tti_dot_test_and_isotropic_limit():
+    """TTI at its full size (300 x 400 x 400, full receiver plane) in the
+    launch configuration the benchmark times (FP32, tiled fused step kernels),
+    truncated to 48 steps: the forward map and its transpose pass the dot
+    test, and with eps = delta = 0 the forward traces equal the acoustic ones
+    (to FP32 rounding: the TTI step forms H0 = L - Hz, the acoustic one L)."""
+    require_gpu()
+    nt = 48
+    wl, an = synth.workload_tti(nt=nt)
+    say(f"case: full-size TTI {wl.shape} nt={nt} nrec={wl.rec_pos.shape[0]}")
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", c_max=wl.c_ref)
+    rng = np.random.default_rng(21)
+    m, a = dev(wl.m, torch.float32), dev(an, torch.float32)
+    qx = dev(rng.standard_normal((nt, 1)).astype(np.float32), torch.float32)
+    y = dev(rng.standard_normal((nt, wl.rec_pos.shape[0])).astype(np.float32), torch.float32)
+    d = P.rtm_tti_forward_probe(plan, m, a, wl.src_pos, qx, wl.rec_pos)["d"]
+    qa = P.rtm_tti_adjoint_probe(plan, m, a, wl.rec_pos, y, src_pos=wl.src_pos,
+                                 want_qadj=True)["qadj"]
+    lhs = P.rtm_dot(plan, d.reshape(-1), y.reshape(-1)).item()
+    rhs = P.rtm_dot(plan, qx.reshape(-1), qa.reshape(-1)).item()
+    say(f"  full-size TTI dot test: {lhs:.9e} {rhs:.9e} rel {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+    iso = an.copy()
+    iso[0] = 0.0
+    iso[1] = 0.0
+    d_tti = host(P.rtm_tti_forward_probe(plan, m, dev(iso, torch.float32), wl.src_pos, qx,
+                                         wl.rec_pos)["d"])
+    d_ac = host(P.rtm_forward_probe(plan, m, wl.src_pos, qx, wl.rec_pos)["d"])
+    e = rel(d_tti, d_ac)
+    say(f"  full-size isotropic TTI vs acoustic: {e:.2e}")
+    assert e < 1e-5
+
+
+def test_fullsize_offset_gathers_sampled_rows():
+    """The 81-offset image volume at 300 x 400 x 400 from two r = 64 compressed
+    fields (the benchmark's launch): whole x rows, all offsets, compared with
+    the oracle evaluated on those rows' probe values."""
+    require_gpu()
+    shape, r, nh = (300, 400, 400), 64, 40
+    plan = P.Plan(P.PlanSpec(3, shape, 12.5, 1e-3, 64, 10, 4500.0, 1e-3, 4500.0, "f32",
+                             "bf16x2", r, 32, 1, 1))
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    nb = 2 * r * plan.Npad
+    U = torch.randn(nb, generator=gen, device="cuda")
+    V = torch.randn(nb, generator=gen, device="cuda")
+    G = P.rtm_offset_gathers(plan, U, V, nh, nfield=2)
+    torch.cuda.synchronize()
+    nz, ny, nx = shape
+    rng = np.random.default_rng(3)
+    rows = [(0, 0), (nz - 1, ny - 1)] + [tuple(v) for v in
+                                         np.stack([rng.integers(0, nz, 30),
+                                                   rng.integers(0, ny, 30)], 1)]
+    worst = 0.0
+    for z, yy in rows:
+        cells = (z * ny + yy) * nx + np.arange(nx)
+        bi = torch.from_numpy(P.bar_index(plan, cells)).cuda()   # [r][nx] offsets in a field
+        fs = r * plan.Npad
+        Ur = [host(U[f * fs + bi]) for f in range(2)]
+        Vr = [host(V[f * fs + bi]) for f in range(2)]
+        G0 = sum(oracle.offset_gathers(Ur[f].astype(np.float64), Vr[f].astype(np.float64),
+                                       (1, 1, nx), nh, 1.0 / r) for f in range(2))
+        Gr = host(G[:, torch.from_numpy(cells).cuda()]).astype(np.float64)
+        worst = max(worst, rel(Gr, G0))
+    say(f"  full-size gathers, {len(rows)} rows: worst rel {worst:.2e}")
+    assert worst < 1e-5
