@@ -101,7 +101,8 @@ typedef struct {
   double c_max;         /* largest velocity in m, for the CFL check (m/s) */
   rtm_dtype field_dtype;/* RTM_F64 or RTM_F32: fields, model, traces, outputs */
   rtm_dtype probe_dtype;/* GEMM operand type: RTM_F64 (F64 fields), RTM_F32,
-                           RTM_BF16 or RTM_BF16X2 (F32 fields; Z must be RTM_I8) */
+                           RTM_BF16 (F32 fields; Z RTM_I8) or RTM_BF16X2 (F32
+                           fields; Z RTM_I8, or RTM_F32 for real probes) */
   int32_t r;            /* number of probe vectors, 1..1024 */
   int32_t k_block;      /* time steps per probe-GEMM block, 1..256 */
   int32_t nsrc;         /* number of source points per call (>= 0) */
