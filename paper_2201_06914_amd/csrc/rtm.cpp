@@ -1294,7 +1294,10 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
     b->nrec_total += shots[i].nrec;
   }
   // tile table: 64 x 16 column tiles of every shot, z split until the launch
-  // has >= 1024 workgroups (each chunk >= 16 planes)
+  // has >= 4 x rtm_set_stencil_blocks workgroups (default 4096; each chunk >=
+  // 16 planes): the windows are shallow (128-256 planes) and the extra waves
+  // in flight outweigh the chunks' warm-up planes (measured: 1024 -> 4096
+  // workgroups, 115 -> 121 Gcell-updates/s).  Fixed when the batch is created.
   int nzc = 1;
   auto count = [&](int z) {
     int64_t t = 0;
@@ -1303,7 +1306,7 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
   };
   int minz = INT32_MAX;
   for (auto *p : b->P) minz = std::min<int>(minz, (int)p->d.nz);
-  while (count(nzc) < 1024 && minz / (nzc * 2) >= 16) nzc *= 2;
+  while (count(nzc) < 4 * (int64_t)g_stencil_blocks && minz / (nzc * 2) >= 16) nzc *= 2;
   for (int i = 0; i < nshots; ++i) {
     const rtm_desc &d = b->P[i]->d;
     const int ntx = (int)((d.nx + 63) / 64), nty = (int)((d.ny + 15) / 16);
