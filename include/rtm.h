@@ -131,10 +131,10 @@ const char *rtm_status_str(rtm_status s);
  * of a plane loaded four planes ahead, with the column fronts.  Every choice
  * gives bitwise-identical levels.  Batched shots run the 64x16 variants 3,
  * 11, 7 or 12 (8..10 select 7, 13 selects 12, the others 1).
- * rtm_set_stencil_blocks: the tiled kernels split z until a launch has at
- * least this many workgroups of 256 threads' worth (default 1024; a 512
- * thread shape aims at half as many); a batch's tile table (made by
- * rtm_batch_create) aims at four times as many. */
+ * rtm_set_stencil_blocks: the tiled kernels (acoustic and TTI) split z until
+ * a launch has at least this many workgroups of 256 threads' worth (default
+ * 2048; a 512 thread shape aims at half as many); a batch's tile table (made
+ * by rtm_batch_create) aims at twice as many. */
 void rtm_set_stencil_variant(int variant);
 void rtm_set_stencil_blocks(int32_t blocks);
 /* Autotuner and race check for the stencil: runs one step of every variant

@@ -31,7 +31,7 @@ using namespace rtm;
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
 static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled variant id
-static int g_stencil_blocks = 1024; // tiled stencil: split z until this many workgroups
+static int g_stencil_blocks = 2048; // tiled stencil: split z until this many workgroups
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
 static int g_tti_shape = 7;         // tiled TTI tile shape (1..8)
 
@@ -179,7 +179,7 @@ extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
 extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 8) ? shape : 7; }
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
-  g_stencil_blocks = blocks > 0 ? blocks : 1024;
+  g_stencil_blocks = blocks > 0 ? blocks : 2048;
 }
 
 extern "C" void rtm_profile_enable(int32_t stride) {
@@ -1294,7 +1294,7 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
     b->nrec_total += shots[i].nrec;
   }
   // tile table: 64 x 16 column tiles of every shot, z split until the launch
-  // has >= 4 x rtm_set_stencil_blocks workgroups (default 4096; each chunk >=
+  // has >= 2 x rtm_set_stencil_blocks workgroups (default 4096; each chunk >=
   // 16 planes): the windows are shallow (128-256 planes) and the extra waves
   // in flight outweigh the chunks' warm-up planes (measured: 1024 -> 4096
   // workgroups, 115 -> 121 Gcell-updates/s).  Fixed when the batch is created.
@@ -1306,7 +1306,7 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
   };
   int minz = INT32_MAX;
   for (auto *p : b->P) minz = std::min<int>(minz, (int)p->d.nz);
-  while (count(nzc) < 4 * (int64_t)g_stencil_blocks && minz / (nzc * 2) >= 16) nzc *= 2;
+  while (count(nzc) < 2 * (int64_t)g_stencil_blocks && minz / (nzc * 2) >= 16) nzc *= 2;
   for (int i = 0; i < nshots; ++i) {
     const rtm_desc &d = b->P[i]->d;
     const int ntx = (int)((d.nx + 63) / 64), nty = (int)((d.ny + 15) / 16);

@@ -350,4 +350,4 @@ def test_autotuner_race_check_all_variants_bitwise_equal():
         P.set_stencil_blocks(blocks)
         r2 = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=1, apply=False)
         assert r2["mismatch"] == [0] * len(r2["mismatch"])
-    P.set_stencil_blocks(1024)
+    P.set_stencil_blocks(2048)  # the default
