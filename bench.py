@@ -422,7 +422,7 @@ def bench_gathers(shape, r: int, nh: int):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark measures one GPU only; --gpus must be 1 "
                                    "(shot or z-slab sharding across GPUs is not built)"}))
         sys.exit(2)
     import numpy as np

@@ -71,7 +71,7 @@ typedef enum {
   RTM_E_CFL = 4,         /* dt * c_max / h above the stability bound */
   RTM_E_WORKSPACE = 5,   /* work buffer smaller than required */
   RTM_E_HIP = 6,         /* a HIP runtime call failed */
-  RTM_E_UNSUPPORTED = 7, /* valid request this build does not implement */
+  RTM_E_UNSUPPORTED = 7, /* valid request the library does not implement */
   RTM_E_POINTS = 8,      /* a source / receiver position outside the grid */
   RTM_E_NONFINITE = 9    /* (rtm_stream_status) a sweep met a non-finite value */
 } rtm_status;
