@@ -3,7 +3,7 @@
 // h = -nh .. nh, x +- h along the grid's x axis (zero where either leaves
 // the row).  h = 0 is the image of Eq. 3.
 //
-// A workgroup owns a 64-cell segment of one x row; chunks of 16 probe rows of
+// A workgroup owns a segment of 64 (or 72) cells of one x row; chunks of 16 probe rows of
 // both compressed fields (the segment plus an nh-cell halo and a margin on
 // each side, zero outside the row) are staged in LDS.  Products along a
 // diagonal share an operand (x + h fixed: the same U; x - h fixed: the same
@@ -11,7 +11,10 @@
 // field per probe row (16-byte LDS reads) for GCX BH products.  The
 // workgroup's threads form nslice slices over the probe rows of each chunk;
 // the slices add up through LDS at the end.  Threads are placed in a slice so
-// that the 16-byte reads meet no LDS bank conflicts.
+// that the 16-byte reads meet no LDS bank conflicts.  With 7 offset blocks
+// (73 to 84 offsets, e.g. -500 .. 500 m at 12.5 m) FP32 segments are 72 cells:
+// 9 cell blocks x 7 offset blocks fill 63 of a wave's 64 lanes (64-cell
+// segments fill 56), placed by a table instead of the formula.
 //
 // k_offset_gathers_f32 stages with direct global -> LDS loads into two
 // buffers: chunk c + 1 streams into one while chunk c is multiplied out of
@@ -24,7 +27,6 @@
 namespace rtm {
 
 namespace {
-constexpr int GX = 64;     // cells per segment
 constexpr int GIC = 16;    // probe rows per staged chunk
 constexpr int GMAXH = 64;  // largest nh
 constexpr int GBH = 12;    // offsets per thread
@@ -45,8 +47,19 @@ __device__ __forceinline__ void lds4(const double *p, double *o) {
   o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
 }
 
-// staged row stride: margin + (segment + 2 nh halo) + margin, 4-aligned
-__host__ __device__ constexpr int gather_ls(int nh) { return (GX + 2 * nh + 2 * GM + 3) & ~3; }
+// staged row stride: margin + (segment of gx cells + 2 nh halo) + margin, 4-aligned
+__host__ __device__ constexpr int gather_ls(int gx, int nh) {
+  return (gx + 2 * nh + 2 * GM + 3) & ~3;
+}
+
+// 72-cell segments: (cell block | offset block << 4) of place k in pass gp
+// (0xFF: idle).  Found by a search under the bank model below: in each pass
+// the chunks 2 cb + 3 hg (U) and 2 cb - 3 hg (V) are distinct mod 16 or equal.
+__constant__ uint8_t kPlace72[4][16] = {
+    {0x02, 0x11, 0x12, 0x17, 0x18, 0x21, 0x22, 0x24, 0x26, 0x31, 0x34, 0x45, 0x48, 0x51, 0x58, 0x67},
+    {0x01, 0x04, 0x07, 0x08, 0x10, 0x25, 0x27, 0x30, 0x37, 0x41, 0x44, 0x47, 0x50, 0x53, 0x57, 0x64},
+    {0x03, 0x14, 0x16, 0x20, 0x32, 0x33, 0x35, 0x38, 0x42, 0x43, 0x55, 0x60, 0x61, 0x63, 0x65, 0x66},
+    {0x00, 0x05, 0x06, 0x13, 0x15, 0x23, 0x28, 0x36, 0x40, 0x46, 0x52, 0x54, 0x56, 0x62, 0x68, 0xFF}};
 
 // cells per thread: 8 in FP32, 4 in FP64 (register budget)
 template <typename T> constexpr int gather_cx() { return sizeof(T) == 4 ? 8 : 4; }
@@ -63,7 +76,7 @@ struct GatherArgs {
 // 16 / CB consecutive offset blocks x all cell blocks: in FP32 one even and
 // one odd block, whose chunks (2 cb + 3 hg) differ in parity, so no two lanes
 // of a pass meet in a bank at different addresses.
-template <typename T>
+template <typename T, int GX>
 struct GatherThread {
   static constexpr int GCX = gather_cx<T>(), BH = GBH, CB = GX / GCX, NACC = GCX * BH;
   int sl, t, hg, cb, ubase, vbase, sv, xs;
@@ -80,8 +93,14 @@ struct GatherThread {
     const int l = t & 63, q = (l >> 2) & 7;
     const int gp = 4 * (t >> 6) + 2 * (l >> 5) + (__builtin_popcount(q) & 1);
     const int k = 4 * (q >> 1) + (l & 3);
-    hg = gp * (16 / CB) + k / CB;
-    cb = k % CB;
+    if constexpr (GX == 72) {  // one wave per slice, 7 offset blocks
+      const int e = kPlace72[gp & 3][k];
+      hg = e == 0xFF ? a.hgs : e >> 4;
+      cb = e == 0xFF ? 0 : e & 15;
+    } else {
+      hg = gp * (16 / CB) + k / CB;
+      cb = k % CB;
+    }
     comp = hg < a.hgs;
     // V is staged shifted by sv so that every thread's V reads start 16-byte aligned
     sv = (4 - (2 * a.nh) % 4) % 4;
@@ -91,11 +110,11 @@ struct GatherThread {
 };
 
 // multiply out one staged chunk (probe rows i0 .. i0 + 15) from BU / BV
-template <typename T>
-__device__ __forceinline__ void gather_chunk(const GatherThread<T> &th, const GatherArgs &a,
+template <typename T, int GX>
+__device__ __forceinline__ void gather_chunk(const GatherThread<T, GX> &th, const GatherArgs &a,
                                              const T *BU, const T *BV, int LS, int i0,
-                                             T (&acc)[GatherThread<T>::NACC], T &keep) {
-  constexpr int GCX = GatherThread<T>::GCX, BH = GBH;
+                                             T (&acc)[GatherThread<T, GX>::NACC], T &keep) {
+  constexpr int GCX = GatherThread<T, GX>::GCX, BH = GBH;
   if (!th.comp) return;
   const int iend = min(GIC, a.r - i0);
   for (int ii = th.sl; ii < iend; ii += a.nslice) {
@@ -120,11 +139,11 @@ __device__ __forceinline__ void gather_chunk(const GatherThread<T> &th, const Ga
 
 // slices 1 .. nslice - 1 hand their sums to slice 0 through LR (LDS), RK at a
 // time; slice 0 writes the volume
-template <typename T>
-__device__ __forceinline__ void gather_finish(const GatherThread<T> &th, const GatherArgs &a,
-                                              T *LR, T (&acc)[GatherThread<T>::NACC], T keep,
+template <typename T, int GX>
+__device__ __forceinline__ void gather_finish(const GatherThread<T, GX> &th, const GatherArgs &a,
+                                              T *LR, T (&acc)[GatherThread<T, GX>::NACC], T keep,
                                               T scale, T *__restrict__ G) {
-  constexpr int GCX = GatherThread<T>::GCX, BH = GBH, NACC = GatherThread<T>::NACC;
+  constexpr int GCX = GatherThread<T, GX>::GCX, BH = GBH, NACC = GatherThread<T, GX>::NACC;
   constexpr int RK = NACC / 3;
 #pragma unroll
   for (int k0 = 0; k0 < NACC; k0 += RK) {
@@ -158,18 +177,19 @@ __device__ __forceinline__ void gather_finish(const GatherThread<T> &th, const G
 }
 }  // namespace
 
-// FP32, direct global -> LDS staging, two static buffers of row stride <= MAXLS
-template <int MAXLS>
+// FP32, direct global -> LDS staging, two static buffers of row stride <= MAXLS,
+// GX-cell segments
+template <int MAXLS, int GX>
 __global__ __launch_bounds__(256) void k_offset_gathers_f32(const float *__restrict__ U,
                                                             const float *__restrict__ V,
                                                             GatherArgs a, float scale,
                                                             float *__restrict__ G) {
-  constexpr int NACC = GatherThread<float>::NACC;
+  constexpr int NACC = GatherThread<float, GX>::NACC;
   constexpr int BUFN = 2 * GIC * MAXLS;
   __shared__ __align__(16) float SA[BUFN];
   __shared__ __align__(16) float SB[BUFN];
-  const GatherThread<float> th(a);
-  const int LS = gather_ls(a.nh);
+  const GatherThread<float, GX> th(a);
+  const int LS = gather_ls(GX, a.nh);
   // thread p < LS owns staged column p (256 threads >= LS); U rows at S,
   // V rows at S + GIC LS; a wave's loads land at the wave's first column + lane
   const int p = threadIdx.x;
@@ -224,10 +244,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_offset_gathers(const T *__restrict__ U,
                                                         const T *__restrict__ V, GatherArgs a,
                                                         T scale, T *__restrict__ G) {
-  constexpr int NACC = GatherThread<T>::NACC;
+  constexpr int GX = 64;
+  constexpr int NACC = GatherThread<T, GX>::NACC;
   extern __shared__ __align__(16) unsigned char gsm[];
-  const GatherThread<T> th(a);
-  const int LS = gather_ls(a.nh);
+  const GatherThread<T, GX> th(a);
+  const int LS = gather_ls(GX, a.nh);
   T *LU = reinterpret_cast<T *>(gsm), *LV = LU + GIC * LS;
   T acc[NACC], keep = T(0);
 #pragma unroll
@@ -266,7 +287,7 @@ template <typename T>
 hipError_t launch_offset_gathers(const T *U, const T *V, int nfield, int64_t fstride, int64_t N,
                                  int nx, int r, int nh, double scale, T *G, hipStream_t st) {
   if (nh < 0 || nh > GMAXH) return hipErrorInvalidValue;
-  constexpr int GCX = gather_cx<T>(), CB = GX / GCX;
+  constexpr int GCX = gather_cx<T>();
   GatherArgs a;
   a.fstride = fstride;
   a.N = N;
@@ -275,28 +296,36 @@ hipError_t launch_offset_gathers(const T *U, const T *V, int nfield, int64_t fst
   a.r = r;
   a.nh = nh;
   const int nout = 2 * nh + 1;
-  a.hgs = (nout + GBH - 1) / GBH;               // offset blocks
+  a.hgs = (nout + GBH - 1) / GBH;  // offset blocks
+  // FP32 with 7 offset blocks: 72-cell segments (9 cell blocks, table placement)
+  const int gx = (sizeof(T) == 4 && a.hgs == 7) ? 72 : 64;
+  const int CB = gx / GCX;
   a.slice_thr = 64 * ((a.hgs * CB + 63) / 64);  // whole waves of (offset, cell) blocks
   a.nslice = 256 / a.slice_thr;
   const int nthr = a.nslice * a.slice_thr;
   const int64_t rows = N / nx;
-  a.nseg = (nx + GX - 1) / GX;
+  a.nseg = (nx + gx - 1) / gx;
   const int64_t nblk = rows * a.nseg;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   a.nblk = (int)nblk;
-  const int ls = gather_ls(nh);
+  const int ls = gather_ls(gx, nh);
   const size_t reduce = (size_t)a.slice_thr * (GCX * GBH / 3);
   if constexpr (sizeof(T) == 4) {
     // 256 threads stage one column each; the reduction fits in one buffer
-    if (nthr != 256 || ls > 256 || reduce > 2 * (size_t)GIC * gather_ls(40))
-      return hipErrorInvalidValue;
-    if (ls <= gather_ls(40))
-      hipLaunchKernelGGL((k_offset_gathers_f32<gather_ls(40)>), dim3(a.nblk), dim3(nthr), 0, st,
-                         U, V, a, (float)scale, G);
-    else
-      hipLaunchKernelGGL((k_offset_gathers_f32<gather_ls(GMAXH)>), dim3(a.nblk), dim3(nthr), 0,
-                         st, U, V, a, (float)scale, G);
+    constexpr int LS40 = gather_ls(64, 40), LS72 = gather_ls(72, 41), LSMAX = gather_ls(64, GMAXH);
+    if (nthr != 256 || ls > 256 || reduce > 2 * (size_t)GIC * LS40) return hipErrorInvalidValue;
+    if (gx == 72) {
+      if (a.slice_thr != 64 || ls > LS72) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_offset_gathers_f32<LS72, 72>), dim3(a.nblk), dim3(nthr), 0, st, U, V,
+                         a, (float)scale, G);
+    } else if (ls <= LS40) {
+      hipLaunchKernelGGL((k_offset_gathers_f32<LS40, 64>), dim3(a.nblk), dim3(nthr), 0, st, U, V,
+                         a, (float)scale, G);
+    } else {
+      hipLaunchKernelGGL((k_offset_gathers_f32<LSMAX, 64>), dim3(a.nblk), dim3(nthr), 0, st, U,
+                         V, a, (float)scale, G);
+    }
   } else {
     const size_t stage = 2 * (size_t)GIC * ls;
     const size_t lds = (stage > reduce ? stage : reduce) * sizeof(T);
