@@ -38,13 +38,16 @@ def _plan(shape, r, field):
     ((6, 4, 97), 33, 40, "f32"), ((3, 5, 64), 16, 7, "f32"), ((5, 3, 70), 5, 0, "f64"),
     ((3, 3, 40), 3, 1, "f64"), ((4, 3, 66), 17, 33, "f32"), ((3, 1, 200), 9, 63, "f64"),
     ((3, 3, 150), 9, 47, "f32"), ((4, 3, 130), 20, 55, "f32"), ((3, 3, 140), 35, 64, "f32"),
-    ((3, 3, 150), 11, 36, "f32"), ((4, 3, 30), 7, 41, "f32"), ((3, 4, 145), 18, 38, "f32")])
+    ((3, 3, 150), 11, 36, "f32"), ((4, 3, 30), 7, 41, "f32"), ((3, 4, 145), 18, 38, "f32"),
+    ((3, 3, 300), 6, 40, "f32"), ((4, 3, 20), 3, 5, "f32"), ((3, 3, 129), 4, 0, "f32"),
+    ((3, 3, 257), 13, 60, "f32")])
 def test_offset_gathers_match_oracle(shape, r, nh, field):
-    """Ragged rows (x not a multiple of the 64- or 72-cell segment), nh up to
-    64 (one and two waves per probe slice, both V alignments, every FP32 LDS
-    buffer size, the 72-cell segments of 7 offset blocks: nh 36 .. 41), rows
-    shorter than the offsets or a segment, r not a multiple of the 16-row
-    probe chunk."""
+    """Ragged rows (x not a multiple of the segment: 64 cells in FP64, 128 in
+    FP32), rows of one to three FP32 segments and rows shorter than the
+    offsets or a 32-cell tile; nh 0 .. 64 (FP64: one and two waves per probe
+    slice, both V alignments; FP32: 1 .. 9 b tiles, products written out in
+    one or two rounds); r below, at and between multiples of the 4-row MFMA
+    step and of the probe chunk."""
     plan = _plan(shape, r, field)
     N = int(np.prod(shape))
     rng = np.random.default_rng(sum(shape) + r)
