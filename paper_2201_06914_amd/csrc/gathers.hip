@@ -44,7 +44,7 @@ __host__ __device__ constexpr int gather_ls(int gx, int nh) {
   return (gx + 2 * nh + 2 * GM + 3) & ~3;
 }
 
-// cells per thread: 8 in FP32, 4 in FP64 (register budget)
+// cells per thread of the vector kernel (register budget; it runs FP64 only)
 template <typename T> constexpr int gather_cx() { return sizeof(T) == 4 ? 8 : 4; }
 
 struct GatherArgs {
@@ -56,9 +56,9 @@ struct GatherArgs {
 // block cb.  A 16-byte LDS read is served in 4 passes of 16 lanes: lane bit 5
 // and the parity of lane bits 2..4 select the pass, k = (lane bits 3..4,
 // 0..1) the place in it; a bank is a 16-byte chunk mod 16.  Pass gp holds
-// 16 / CB consecutive offset blocks x all cell blocks: in FP32 one even and
-// one odd block, whose chunks (2 cb + 3 hg) differ in parity, so no two lanes
-// of a pass meet in a bank at different addresses.
+// 16 / CB consecutive offset blocks x all cell blocks.  In FP64 (CB = 16
+// blocks of 4 cells) that is one offset block, whose reads start at chunks
+// 2 cb + const: cell blocks 8 apart share a bank (two-way conflicts).
 template <typename T, int GX>
 struct GatherThread {
   static constexpr int GCX = gather_cx<T>(), BH = GBH, CB = GX / GCX, NACC = GCX * BH;
