@@ -265,9 +265,12 @@ rtm_status fwi_gradient(const rtm_plan *plan, const void *m, const double *src_p
  *   gathers    device [2 nh + 1][N] field dtype, overwritten; must not
  *              overlap Ubar or Vbar
  *   scale      1/r gives Eq. 4
- * Errors: NULL pointer or nfield not 1 / 2 -> RTM_E_ARG; nh outside 0..64 ->
- * RTM_E_UNSUPPORTED; a failed launch -> RTM_E_HIP.  Stream-ordered; no
- * workspace. */
+ * FP32 runs on the matrix cores (v_mfma_f32_16x16x4f32: FP32 products and
+ * sums), FP64 on the vector ALUs.
+ * Errors: NULL pointer or nfield not 1 / 2 -> RTM_E_ARG; nh outside 0..64,
+ * or FP32 fields with (nx / 32 + 2) * r * 128 >= 2^31 (a row's fields are
+ * addressed with 32-bit offsets) -> RTM_E_UNSUPPORTED; a failed launch ->
+ * RTM_E_HIP.  Stream-ordered; no workspace. */
 rtm_status rtm_offset_gathers(const rtm_plan *plan, const void *Ubar, const void *Vbar,
                               int32_t nfield, int32_t nh, double scale, void *gathers,
                               rtm_stream stream);

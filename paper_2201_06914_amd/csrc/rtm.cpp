@@ -753,6 +753,10 @@ extern "C" rtm_status rtm_offset_gathers(const rtm_plan *P, const void *Ubar, co
   if (!P || !Ubar || !Vbar || !gathers) return fail(RTM_E_ARG, "NULL argument");
   if (nfield != 1 && nfield != 2) return fail(RTM_E_ARG, "nfield must be 1 or 2");
   if (nh < 0 || nh > 64) return fail(RTM_E_UNSUPPORTED, "offsets: 0 <= nh <= 64");
+  if (P->d.field_dtype == RTM_F32 && ((int64_t)P->d.nx / 32 + 2) * P->d.r * 128 >= ((int64_t)1 << 31))
+    return fail(RTM_E_UNSUPPORTED,
+                "FP32 offset gathers need (nx / 32 + 2) * r * 128 < 2^31 (a row's fields "
+                "are addressed with 32-bit offsets)");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int64_t fs = (int64_t)P->d.r * P->Npad;
   if (P->d.field_dtype == RTM_F64)

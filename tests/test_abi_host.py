@@ -151,6 +151,12 @@ def test_calls_reject_before_launch(L):
     assert L.rtm_offset_gathers(h, None, fake, 1, 10, 1.0, fake, None) == 1
     assert L.rtm_offset_gathers(h, fake, fake, 2, 10, 1.0, None, None) == 1
     L.rtm_plan_destroy(h)
+    # FP32 offset gathers address a row's fields with 32-bit offsets:
+    # (nx / 32 + 2) r 128 >= 2^31 is refused before any launch
+    c, h = _create(L, nz=3, ny=3, nx=600000, nb=1, r=1024, k_block=16)
+    assert c == 0
+    assert L.rtm_offset_gathers(h, fake, fake, 1, 10, 1.0, fake, None) == 7
+    L.rtm_plan_destroy(h)
 
 
 @pytest.mark.parametrize("kw,code", [
