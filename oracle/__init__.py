@@ -40,41 +40,52 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def load(path: str):
+    """Opens a compiled oracle library and declares its functions' signatures
+    (``lib()`` caches the one built from ``oracle.c``)."""
+    L = ctypes.CDLL(path)
+    L.orc_forward.restype = ctypes.c_int
+    L.orc_forward.argtypes = [
+        ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+        _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
+        ctypes.c_int, ctypes.c_long, _lp, _dp, _dp, _dp]
+    L.orc_adjoint.restype = ctypes.c_int
+    L.orc_adjoint.argtypes = [
+        ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+        _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
+        ctypes.c_long, _lp, _dp, _dp, _dp, _dp]
+    L.orc_laplacian.restype = None
+    L.orc_laplacian.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long,
+                                ctypes.c_double, _dp, _dp]
+    L.orc_damping_profile.restype = None
+    L.orc_damping_profile.argtypes = [ctypes.c_long, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, _dp]
+    L.orc_num_threads.restype = ctypes.c_int
+    L.orc_tti_apply.restype = None
+    L.orc_tti_apply.argtypes = [ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+                                _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.orc_tti_sweep.restype = ctypes.c_int
+    L.orc_tti_sweep.argtypes = [
+        ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+        _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp,
+        ctypes.c_int, _dp, _dp, _dp, _dp]
+    for name in ("orc_sample_points", "orc_inject_points"):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_int,
+                      _dp, _dp, _dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        L.orc_forward.restype = ctypes.c_int
-        L.orc_forward.argtypes = [
-            ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
-            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-            _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
-            ctypes.c_int, ctypes.c_long, _lp, _dp, _dp, _dp]
-        L.orc_adjoint.restype = ctypes.c_int
-        L.orc_adjoint.argtypes = [
-            ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
-            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-            _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
-            ctypes.c_long, _lp, _dp, _dp, _dp, _dp]
-        L.orc_laplacian.restype = None
-        L.orc_laplacian.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long,
-                                    ctypes.c_double, _dp, _dp]
-        L.orc_damping_profile.restype = None
-        L.orc_damping_profile.argtypes = [ctypes.c_long, ctypes.c_int, ctypes.c_double,
-                                          ctypes.c_double, ctypes.c_double, _dp]
-        L.orc_num_threads.restype = ctypes.c_int
-        L.orc_tti_apply.restype = None
-        L.orc_tti_apply.argtypes = [ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
-                                    _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp]
-        L.orc_tti_sweep.restype = ctypes.c_int
-        L.orc_tti_sweep.argtypes = [
-            ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
-            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-            _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp,
-            ctypes.c_int, _dp, _dp, _dp, _dp]
-        _lib = L
+        _lib = load(_LIB)
     return _lib
 
 
@@ -122,6 +133,34 @@ def damping_profile(n: int, nb: int, h: float, c_ref: float, R: float) -> np.nda
     out = np.empty(n, dtype=np.float64)
     lib().orc_damping_profile(n, nb, h, c_ref, R, out.ctypes.data_as(_dp))
     return out
+
+
+def sample_points(ndim: int, field: np.ndarray, pos) -> np.ndarray:
+    """Pr: multilinear interpolation of field [nz][ny][nx] at positions [n][3]
+    (z, y, x) in grid units."""
+    f = np.ascontiguousarray(field, dtype=np.float64)
+    nz, ny, nx = f.shape
+    p, pp = _d(np.reshape(pos, (-1, 3)))
+    out = np.zeros(p.shape[0])
+    rc = lib().orc_sample_points(ndim, nz, ny, nx, p.shape[0], pp, f.ctypes.data_as(_dp),
+                                 out.ctypes.data_as(_dp))
+    if rc != 0:
+        raise ValueError(f"oracle sampling rejected its input (code {rc})")
+    return out
+
+
+def inject_points(ndim: int, shape, pos, val) -> np.ndarray:
+    """Ps^T: a zero field [nz][ny][nx] with val[p] spread onto the corners of
+    position p by the multilinear weights."""
+    nz, ny, nx = shape
+    f = np.zeros((nz, ny, nx))
+    p, pp = _d(np.reshape(pos, (-1, 3)))
+    v, vp = _d(np.ravel(val))
+    assert v.size == p.shape[0]
+    rc = lib().orc_inject_points(ndim, nz, ny, nx, p.shape[0], pp, vp, f.ctypes.data_as(_dp))
+    if rc != 0:
+        raise ValueError(f"oracle injection rejected its input (code {rc})")
+    return f
 
 
 def forward(g: Grid, m, src_pos, q, rec_pos, Z=None, what: str = "utt", sample_idx=None,

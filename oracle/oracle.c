@@ -190,6 +190,29 @@ static void sample(const pt_t *pts, int np, const double *field, double *out) {
   }
 }
 
+/* The point operators on their own (Ps^T and Pr of the sweeps), so that the
+ * multilinear weights can be checked without a time step:
+ *   orc_sample_points: out[p] = sum_c w_c field[c] for each position
+ *   orc_inject_points: field[c] += w_c val[p] (field accumulated, not cleared)
+ * Return 0, or -2 if a position lies outside the grid (nothing written). */
+int orc_sample_points(int ndim, long nz, long ny, long nx, int np, const double *pos,
+                      const double *field, double *out) {
+  int err = 0;
+  pt_t *pts = make_points(ndim, nz, ny, nx, np, pos, &err);
+  if (!err) sample(pts, np, field, out);
+  free(pts);
+  return err;
+}
+
+int orc_inject_points(int ndim, long nz, long ny, long nx, int np, const double *pos,
+                      const double *val, double *field) {
+  int err = 0;
+  pt_t *pts = make_points(ndim, nz, ny, nx, np, pos, &err);
+  if (!err) inject(pts, np, val, field);
+  free(pts);
+  return err;
+}
+
 /* ------------------------------------------------------------------------ */
 /* one time step of the damped recursion                                     */
 /* ------------------------------------------------------------------------ */
