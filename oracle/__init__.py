@@ -71,7 +71,7 @@ def load(path: str):
         ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long, ctypes.c_double,
         ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
         _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp,
-        ctypes.c_int, _dp, _dp, _dp, _dp]
+        ctypes.c_int, _dp, ctypes.c_long, _lp, _dp, _dp, _dp]
     for name in ("orc_sample_points", "orc_inject_points"):
         f = getattr(L, name)
         f.restype = ctypes.c_int
@@ -306,7 +306,7 @@ def tti_apply(eps, delta, theta, phi, p, q, h, transpose=False):
 
 
 def _tti_sweep(adjoint, g: Grid, m, aniso, inj_pos, inj_val, smp_pos, Z=None, hist=None,
-               want_hist=False):
+               want_hist=False, sample_idx=None):
     nz, ny, nx = g.shape
     N = g.N
     m, mp = _d(np.ravel(m))
@@ -324,10 +324,15 @@ def _tti_sweep(adjoint, g: Grid, m, aniso, inj_pos, inj_val, smp_pos, Z=None, hi
         out["d" if not adjoint else "qadj"] = smp
     r = 0
     zp = up = None
+    sidx = None
     if Z is not None:
         Zd, zp = _d(Z)
         r = Zd.shape[1]
-        Ub = np.zeros((2, r, N))
+        M = N
+        if sample_idx is not None:
+            sidx = np.ascontiguousarray(sample_idx, dtype=np.int64)
+            M = sidx.size
+        Ub = np.zeros((2, r, M))
         up = Ub.ctypes.data_as(_dp)
         out["bar"] = Ub
     fh = corr = None
@@ -341,7 +346,9 @@ def _tti_sweep(adjoint, g: Grid, m, aniso, inj_pos, inj_val, smp_pos, Z=None, hi
     rc = lib().orc_tti_sweep(
         int(adjoint), nz, ny, nx, g.h, g.dt, g.nt, g.nb, g.c_ref, g.R, mp,
         *(x[1] for x in an), ip.shape[0], ipp, ivp, nsmp, sp,
-        smp.ctypes.data_as(_dp) if smp is not None else None, r, zp, up,
+        smp.ctypes.data_as(_dp) if smp is not None else None, r, zp,
+        sidx.size if sidx is not None else 0,
+        sidx.ctypes.data_as(_lp) if sidx is not None else None, up,
         fh.ctypes.data_as(_dp) if fh is not None else None,
         corr.ctypes.data_as(_dp) if corr is not None else None)
     if rc != 0:
@@ -349,14 +356,18 @@ def _tti_sweep(adjoint, g: Grid, m, aniso, inj_pos, inj_val, smp_pos, Z=None, hi
     return out
 
 
-def tti_forward(g: Grid, m, aniso, src_pos, q, rec_pos, Z=None, hist=False):
-    """d [nt][nrec] = p at the receivers; bar [2][r][N] = Z^T (p_tt, q_tt)."""
-    return _tti_sweep(False, g, m, aniso, src_pos, q, rec_pos, Z=Z, want_hist=hist)
+def tti_forward(g: Grid, m, aniso, src_pos, q, rec_pos, Z=None, hist=False, sample_idx=None):
+    """d [nt][nrec] = p at the receivers; bar [2][r][M] = Z^T (p_tt, q_tt) on
+    the cells sample_idx (all N cells when None)."""
+    return _tti_sweep(False, g, m, aniso, src_pos, q, rec_pos, Z=Z, want_hist=hist,
+                      sample_idx=sample_idx)
 
 
-def tti_adjoint(g: Grid, m, aniso, rec_pos, res, src_pos=None, Z=None, fwd_hist=None):
-    """bar [2][r][N] = Z^T (lam_p, lam_q); qadj = Ps (lam_p + lam_q); corr."""
-    return _tti_sweep(True, g, m, aniso, rec_pos, res, src_pos, Z=Z, hist=fwd_hist)
+def tti_adjoint(g: Grid, m, aniso, rec_pos, res, src_pos=None, Z=None, fwd_hist=None,
+                sample_idx=None):
+    """bar [2][r][M] = Z^T (lam_p, lam_q); qadj = Ps (lam_p + lam_q); corr."""
+    return _tti_sweep(True, g, m, aniso, rec_pos, res, src_pos, Z=Z, hist=fwd_hist,
+                      sample_idx=sample_idx)
 
 
 def tti_exact_gradient(g: Grid, m, aniso, src_pos, q, rec_pos, d_obs):
@@ -366,10 +377,10 @@ def tti_exact_gradient(g: Grid, m, aniso, src_pos, q, rec_pos, d_obs):
     return J, -a["corr"]
 
 
-def tti_probed_gradient(g: Grid, m, aniso, src_pos, q, rec_pos, d_obs, Z):
-    f = tti_forward(g, m, aniso, src_pos, q, rec_pos, Z=Z)
+def tti_probed_gradient(g: Grid, m, aniso, src_pos, q, rec_pos, d_obs, Z, sample_idx=None):
+    f = tti_forward(g, m, aniso, src_pos, q, rec_pos, Z=Z, sample_idx=sample_idx)
     J, res = misfit(f["d"], d_obs)
-    a = tti_adjoint(g, m, aniso, rec_pos, res, Z=Z)
+    a = tti_adjoint(g, m, aniso, rec_pos, res, Z=Z, sample_idx=sample_idx)
     r = np.shape(Z)[1]
     img = image(f["bar"][0], a["bar"][0], -1.0 / r) + image(f["bar"][1], a["bar"][1], -1.0 / r)
     return J, img, f, a

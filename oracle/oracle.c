@@ -502,7 +502,8 @@ void orc_tti_apply(long nz, long ny, long nx, double h, const double *eps, const
  * leapfrog of the acoustic case applied to p and q.
  *   forward: q_src [nt][ninj] injected into p and q; d[n] = Pr p^{n+1}
  *   adjoint: res [nt][ninj] injected into lam_p only; qadj[n] = Ps (lp + lq)^n
- * Probing (Z, Ubar [2][r][M]): forward probes (p_tt, q_tt); adjoint (lp, lq).
+ * Probing (Z, Ubar [2][r][M]): forward probes (p_tt, q_tt); adjoint (lp, lq);
+ * M = nsample cells sample_idx[0..nsample-1] when nsample > 0, else all N.
  * fhist [2][nt][N] (forward: written with p_tt, q_tt; adjoint: read) and
  * corr [N]: adjoint only, corr += p_tt lp + q_tt lq.
  */
@@ -510,8 +511,8 @@ int orc_tti_sweep(int adjoint, long nz, long ny, long nx, double h, double dt, i
                   double c_ref, double R, const double *m, const double *eps,
                   const double *delta, const double *theta, const double *phi, int ninj,
                   const double *inj_pos, const double *inj_val, int nsmp, const double *smp_pos,
-                  double *smp_out, int r, const double *Z, double *Ubar, double *fhist,
-                  double *corr) {
+                  double *smp_out, int r, const double *Z, long nsample,
+                  const long *sample_idx, double *Ubar, double *fhist, double *corr) {
   const long N = nz * ny * nx;
   int err = 0;
   pt_t *ip = make_points(3, nz, ny, nx, ninj, inj_pos, &err);
@@ -563,8 +564,10 @@ int orc_tti_sweep(int adjoint, long nz, long ny, long nx, double h, double dt, i
           corr[i] += fhist[(long)n * N + i] * sfp[i] + fhist[((long)nt + n) * N + i] * sfq[i];
     }
     if (Ubar) {
-      probe_rank1(N, r, Z + (long)n * r, 0, NULL, sfp, Ubar);
-      probe_rank1(N, r, Z + (long)n * r, 0, NULL, sfq, Ubar + (long)r * N);
+      const long M = nsample > 0 ? nsample : N;
+      const long *sidx = nsample > 0 ? sample_idx : NULL;
+      probe_rank1(N, r, Z + (long)n * r, M, sidx, sfp, Ubar);
+      probe_rank1(N, r, Z + (long)n * r, M, sidx, sfq, Ubar + (long)r * M);
     }
     double *t = p0;
     p0 = p1;

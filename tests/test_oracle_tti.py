@@ -129,3 +129,20 @@ def test_tti_orthogonal_probes_exact():
     _, gp, _, _ = oracle.tti_probed_gradient(g, m, an, src, qv, rec, d_obs, H)
     _, ge = oracle.tti_exact_gradient(g, m, an, src, qv, rec, d_obs)
     assert np.linalg.norm(gp - ge) <= 1e-12 * np.linalg.norm(ge)
+
+
+def test_tti_sampled_cells_match_full_probing():
+    """Probing a subset of cells in the TTI sweeps gives exactly the matching
+    columns of both compressed fields."""
+    wl, an = synth.workload_tti(shape=(14, 12, 16), nt=30, r=5, sigma=2.0, nb=3, f0=15.0,
+                                rec_stride=5, dtype=np.float64)
+    g = Grid.of(wl)
+    idx = np.array([0, 7, 100, 1234, g.N - 1])
+    full = oracle.tti_forward(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos, Z=wl.Z)["bar"]
+    part = oracle.tti_forward(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos, Z=wl.Z,
+                              sample_idx=idx)["bar"]
+    np.testing.assert_array_equal(part, full[:, :, idx])
+    res = np.random.default_rng(1).standard_normal((g.nt, wl.rec_pos.shape[0]))
+    fa = oracle.tti_adjoint(g, wl.m, an, wl.rec_pos, res, Z=wl.Z)["bar"]
+    pa = oracle.tti_adjoint(g, wl.m, an, wl.rec_pos, res, Z=wl.Z, sample_idx=idx)["bar"]
+    np.testing.assert_array_equal(pa, fa[:, :, idx])
