@@ -361,7 +361,8 @@ __global__ __launch_bounds__(256) void k_offset_gathers_mfma(const float *__rest
   }
 }
 
-// rounds of 32-cell tiles whose products fit the two staging buffers
+// rounds of 32-cell tiles whose products fit the three staging buffers (the
+// output rows leave through the same LDS)
 template <int NBT, int NT, int GR>
 static int gm_rounds(int nh) {
   const int nout = 2 * nh + 1, room = 3 * gm_buf(NT, NBT, GR);

@@ -757,6 +757,16 @@ extern "C" rtm_status rtm_offset_gathers(const rtm_plan *P, const void *Ubar, co
     return fail(RTM_E_UNSUPPORTED,
                 "FP32 offset gathers need (nx / 32 + 2) * r * 128 < 2^31 (a row's fields "
                 "are addressed with 32-bit offsets)");
+  {
+    // one workgroup of 256 threads per segment of an x row (128 cells in FP32,
+    // 64 in FP64); a dispatch holds fewer than 2^32 work items
+    const int64_t seg = P->d.field_dtype == RTM_F32 ? 128 : 64;
+    const int64_t wgs = (P->N / P->d.nx) * ((P->d.nx + seg - 1) / seg);
+    if (wgs * 256 >= ((int64_t)1 << 32))
+      return fail(RTM_E_UNSUPPORTED,
+                  "offset gathers need rows * ceil(nx / %lld) * 256 < 2^32 work items (got "
+                  "%lld workgroups)", (long long)seg, (long long)wgs);
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int64_t fs = (int64_t)P->d.r * P->Npad;
   if (P->d.field_dtype == RTM_F64)

@@ -157,6 +157,15 @@ def test_calls_reject_before_launch(L):
     assert c == 0
     assert L.rtm_offset_gathers(h, fake, fake, 1, 10, 1.0, fake, None) == 7
     L.rtm_plan_destroy(h)
+    # one 256-thread workgroup per row segment: 2^24 rows of a 16-cell x axis
+    # would need 2^32 work items in one dispatch, refused before any launch
+    for fd, pd in ((_lib.RTM_F32, _lib.RTM_BF16X2), (_lib.RTM_F64, _lib.RTM_F64)):
+        c, h = _create(L, nz=4096, ny=4096, nx=16, nb=1, r=4, k_block=16, field_dtype=fd,
+                       probe_dtype=pd)
+        assert c == 0, L.rtm_last_error()
+        assert L.rtm_offset_gathers(h, fake, fake, 1, 10, 1.0, fake, None) == 7
+        assert b"2^32" in L.rtm_last_error()
+        L.rtm_plan_destroy(h)
 
 
 @pytest.mark.parametrize("kw,code", [
