@@ -403,6 +403,29 @@ rtm_status fwi_gradient_batched(rtm_batch *batch, const rtm_shot_io *io, double 
                                 int32_t use_graph, void *work, size_t work_bytes,
                                 rtm_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the probed
+ * gradient of fwi_gradient, same arguments and results, with the workspace
+ * taken from a static device array of RTM_NOALLOC_SCRATCH_BYTES (256 MiB)
+ * instead of `work`.  The library holds that array on every GPU it runs on,
+ * from the first call there until the process ends; it calls no hipMalloc,
+ * hipFree or allocating library routine.
+ *   plan  a plan with rtm_plan_workspace_bytes <= RTM_NOALLOC_SCRATCH_BYTES,
+ *         else RTM_E_WORKSPACE before any HIP call (the message gives both
+ *         sizes)
+ *   other arguments and errors as fwi_gradient; the current HIP device is
+ *         the one that runs the call
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call initialises what it reads).  Calls that overlap
+ * in time on one GPU (different streams or threads) race and give wrong
+ * results: order them, e.g. on one stream.  The array holds the call's
+ * non-finite watch word, so rtm_stream_status does not apply. */
+#define RTM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+rtm_status fwi_gradient_noalloc(const rtm_plan *plan, const void *m, const double *src_pos,
+                                const void *q, const double *rec_pos, const void *d_obs,
+                                const void *Z, rtm_dtype z_dtype, void *Ubar, void *Vbar,
+                                void *resid, void *grad, double *misfit, rtm_stream stream);
+
 /* Converts a tile-major compressed field (device [r*Npad]) to rows (device
  * [r][N], caller-owned): rows[i][x] = bar[((x/32)*r + i)*32 + x%32]. */
 rtm_status rtm_bar_to_rows(const rtm_plan *plan, const void *bar, void *rows, rtm_stream stream);

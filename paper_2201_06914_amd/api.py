@@ -458,6 +458,28 @@ def fwi_gradient(plan: Plan, m, src_pos, q, rec_pos, d_obs, Z, work=None, bars=N
     return {"grad": g, "misfit": J, "Ubar": U, "Vbar": V, "resid": res}
 
 
+def fwi_gradient_noalloc(plan: Plan, m, src_pos, q, rec_pos, d_obs, Z, bars, resid, grad,
+                         misfit) -> None:
+    """fwi_gradient with the workspace in the library's static device array
+    (no device allocation in the call): every output is passed in.  bars =
+    (Ubar, Vbar) with Vbar None for fused imaging; resid [nt][nrec], grad [N]
+    of the plan's dtype, misfit FP64 [1]."""
+    s = plan.spec
+    dev = m.device
+    U, V = bars
+    sp, spp = _pos(src_pos, s.nsrc, "src_pos")
+    rp, rpp = _pos(rec_pos, s.nrec, "rec_pos")
+    zp, zt = _z(plan, Z)
+    code = _lib.load().fwi_gradient_noalloc(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), spp,
+        _dev(q, plan.dtype, s.nt * s.nsrc, "q"), rpp,
+        _dev(d_obs, plan.dtype, s.nt * s.nrec, "d_obs"), zp, zt,
+        _dev(U, plan.dtype, s.r * plan.Npad, "Ubar"), _dev(V, plan.dtype, s.r * plan.Npad, "Vbar"),
+        _dev(resid, plan.dtype, s.nt * s.nrec, "resid"), _dev(grad, plan.dtype, plan.N, "grad"),
+        _dev(misfit, torch.float64, 1, "misfit"), _stream(dev))
+    _check(code, "fwi_gradient_noalloc")
+
+
 def fwi_gradient_exact(plan: Plan, m, src_pos, q, rec_pos, d_obs, checkpoint_every: int = 0,
                        work=None) -> dict:
     """Exact gradient (Eq. 2) with uniform checkpointing; the comparator of

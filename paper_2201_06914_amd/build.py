@@ -12,7 +12,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librtm.so")
-SOURCES = ["stencil.hip", "probe.hip", "misc.hip", "tti.hip", "tti_tiled.hip", "sketch.hip", "gathers.hip", "rtm.cpp"]
+SOURCES = ["stencil.hip", "probe.hip", "misc.hip", "tti.hip", "tti_tiled.hip", "sketch.hip", "gathers.hip", "noalloc.hip", "rtm.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -74,6 +74,11 @@ static rtm_status fail(rtm_status s, const char *fmt, ...) {
   return s;
 }
 
+namespace rtm {
+// sets the message of rtm_last_error from other translation units of the library
+rtm_status note_error(rtm_status s, const char *msg) { return fail(s, "%s", msg); }
+}  // namespace rtm
+
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
     hipError_t e_ = (expr);                                                             \

@@ -168,6 +168,29 @@ def test_calls_reject_before_launch(L):
         L.rtm_plan_destroy(h)
 
 
+def test_noalloc_refuses_plans_above_its_static_workspace(L):
+    """fwi_gradient_noalloc checks the plan's workspace against its static
+    array (256 MiB) before any HIP call (fake addresses)."""
+    from paper_2201_06914_amd import _lib
+    fake = ctypes.c_void_p(1 << 20)
+    src = np.array([[8.0, 10.0, 20.0]])
+    rec = np.array([[9.0, 10.0, 20.0]] * 4)
+    sp = src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rp = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    # 160^3 cells x 4 B x (16 + 2) levels = 295 MB > 256 MiB
+    c, h = _create(L, nz=160, ny=160, nx=160, nb=6, r=16, k_block=16)
+    assert c == 0, L.rtm_last_error()
+    n = ctypes.c_size_t()
+    assert L.rtm_plan_workspace_bytes(h, ctypes.byref(n)) == 0
+    assert n.value > _lib.RTM_NOALLOC_SCRATCH_BYTES
+    assert L.fwi_gradient_noalloc(h, fake, sp, fake, rp, fake, fake, _lib.RTM_I8, fake, None,
+                                  fake, fake, fake, None) == 5
+    assert b"static" in L.rtm_last_error() and str(n.value).encode() in L.rtm_last_error()
+    L.rtm_plan_destroy(h)
+    assert L.fwi_gradient_noalloc(None, fake, sp, fake, rp, fake, fake, _lib.RTM_I8, fake, None,
+                                  fake, fake, fake, None) == 1
+
+
 @pytest.mark.parametrize("kw,code", [
     (dict(r=300, k_block=16), 7),                    # r > 256
     (dict(r=128, k_block=96), 7),                    # k * r > 8192
