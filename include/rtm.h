@@ -157,6 +157,12 @@ rtm_status rtm_autotune_stencil(const rtm_plan *plan, const void *m, void *work,
  * them. */
 void rtm_profile_enable(int32_t stride);
 rtm_status rtm_profile_read(int32_t kind, double *total_ms, int64_t *count);
+/* Reference for the roofline figures: a streaming device-to-device copy of
+ * `bytes` (a multiple of 16; src and dst device, 16-byte aligned, not
+ * overlapping) by 16-byte vectors, stream ordered.  Its bytes read + written
+ * over its time is the HBM rate a read-once / write-once kernel reaches.
+ * NULL or misaligned -> RTM_E_ARG. */
+rtm_status rtm_device_copy(const void *src, void *dst, size_t bytes, rtm_stream stream);
 /* Message of the last HIP failure seen by this thread (empty if none). */
 const char *rtm_last_error(void);
 

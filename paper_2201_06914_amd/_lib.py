@@ -23,6 +23,7 @@ EXPORTS = (
     "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape", "rtm_rf_workspace_bytes",
     "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf", "rtm_offset_gathers",
     "rtm_stream_status", "rtm_forward_probe_range", "fwi_gradient_noalloc",
+    "rtm_device_copy",
 )
 
 RTM_NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -91,6 +92,8 @@ def load() -> ctypes.CDLL:
     L.fwi_gradient_noalloc.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, _vp,
                                        _vp, _vp, _vp, _vp]
     L.fwi_gradient_noalloc.restype = ctypes.c_int
+    L.rtm_device_copy.argtypes = [_vp, _vp, sz, _vp]
+    L.rtm_device_copy.restype = ctypes.c_int
     L.rtm_dot.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, sz, _vp]
     L.rtm_dot.restype = ctypes.c_int
     L.rtm_exact_workspace_bytes.argtypes = [_vp, i32, ctypes.POINTER(sz)]

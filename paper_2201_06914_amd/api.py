@@ -644,6 +644,17 @@ def bar_index(plan: Plan, cells, rows=None) -> np.ndarray:
     return ((x[None, :] // 32) * plan.spec.r + i[:, None]) * 32 + x[None, :] % 32
 
 
+def device_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """Streaming copy src -> dst (same byte size, a multiple of 16) with the
+    library's 16-byte-vector copy kernel: the HBM reference of the roofline."""
+    nb = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda) or dst.numel() * dst.element_size() != nb:
+        raise ValueError("device_copy needs two device tensors of the same byte size")
+    _check(_lib.load().rtm_device_copy(ctypes.c_void_p(src.data_ptr()),
+                                       ctypes.c_void_p(dst.data_ptr()), nb, _stream(src.device)),
+           "rtm_device_copy")
+
+
 def rtm_dot(plan: Plan, a, b, work=None) -> torch.Tensor:
     n = a.numel()
     out = torch.empty(1, dtype=torch.float64, device=a.device)

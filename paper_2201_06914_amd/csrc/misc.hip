@@ -25,6 +25,31 @@ __global__ __launch_bounds__(256) void k_copy(T *__restrict__ d, const T *__rest
     d[i] = s[i];
 }
 
+// Streaming copy of n 16-byte vectors, four per thread per pass (the loads of
+// a pass are issued before its stores): the measured HBM ceiling of a
+// read-once / write-once kernel, the reference the roofline figures are set
+// against.
+__global__ __launch_bounds__(256) void k_copy_x4(float4 *__restrict__ d,
+                                                  const float4 *__restrict__ s, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const float4 a = s[i], b = s[i + stride], c = s[i + 2 * stride], e = s[i + 3 * stride];
+    d[i] = a;
+    d[i + stride] = b;
+    d[i + 2 * stride] = c;
+    d[i + 3 * stride] = e;
+  }
+  for (; i < n; i += stride) d[i] = s[i];
+}
+
+hipError_t launch_copy_x4(void *d, const void *s, int64_t n16, hipStream_t st) {
+  if (n16 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_x4, dim3(2048), dim3(256), 0, st, static_cast<float4 *>(d),
+                     static_cast<const float4 *>(s), n16);
+  return hipGetLastError();
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);

@@ -801,6 +801,15 @@ extern "C" rtm_status rtm_bar_to_rows(const rtm_plan *P, const void *bar, void *
   return RTM_OK;
 }
 
+extern "C" rtm_status rtm_device_copy(const void *src, void *dst, size_t bytes, rtm_stream stream) {
+  g_last_error.clear();
+  if (!src || !dst) return fail(RTM_E_ARG, "NULL argument");
+  if ((bytes & 15) || (reinterpret_cast<uintptr_t>(src) & 15) || (reinterpret_cast<uintptr_t>(dst) & 15))
+    return fail(RTM_E_ARG, "rtm_device_copy needs 16-byte aligned buffers and a size in 16 bytes");
+  HIP_TRY(launch_copy_x4(dst, src, (int64_t)(bytes / 16), reinterpret_cast<hipStream_t>(stream)));
+  return RTM_OK;
+}
+
 extern "C" rtm_status rtm_dot(const rtm_plan *P, const void *a, const void *b, int64_t n,
                               double *out, void *work, size_t work_bytes, rtm_stream stream) {
   g_last_error.clear();

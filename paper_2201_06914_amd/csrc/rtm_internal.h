@@ -195,6 +195,7 @@ template <typename T>
 hipError_t launch_axpy(T *y, const T *x, int64_t n, hipStream_t st);  // y += x
 template <typename T>
 hipError_t launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
+hipError_t launch_copy_x4(void *dst, const void *src, int64_t n16, hipStream_t st);
 template <typename T>
 hipError_t launch_flag_nonfinite(const T *x, int64_t n, uint32_t *status, hipStream_t st);
 hipError_t launch_status_clear(uint32_t *status, hipStream_t st);
