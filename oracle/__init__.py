@@ -291,6 +291,21 @@ def probed_gradient(g: Grid, m, src_pos, q, rec_pos, d_obs, Z, sample_idx=None):
 # ---------------------------------------------------------------------------
 # pseudo-acoustic TTI (coupled p, q); see the header of oracle.c
 # ---------------------------------------------------------------------------
+def stacked_probed_gradient(g: Grid, m, shots, Zs):
+    """The stack over sources (the sum over shots of each shot's probed
+    gradient, Eq. 3, every shot with its own probe matrix; Section
+    "Approximate gradient calculations", the remark after Eq. 4 on noise that
+    stacks out over sources).  shots: (src_pos, q, rec_pos, d_obs) per shot,
+    Zs: the matching probe matrices.  Returns (sum of misfits, summed
+    gradient)."""
+    J, G = 0.0, np.zeros(g.N)
+    for (src_pos, q, rec_pos, d_obs), Z in zip(shots, Zs):
+        Ji, gi, _, _ = probed_gradient(g, m, src_pos, q, rec_pos, d_obs, Z)
+        J += Ji
+        G += gi
+    return J, G
+
+
 def tti_apply(eps, delta, theta, phi, p, q, h, transpose=False):
     """The TTI spatial operator (or its transpose) on fields [nz][ny][nx]."""
     p = np.ascontiguousarray(p, np.float64)
