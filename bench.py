@@ -78,11 +78,16 @@ def parse():
                     help="skip the 300^3 four-shot probe-count sweep against the exact gradient")
     ap.add_argument("--rsweep-n", type=int, default=300)
     ap.add_argument("--rsweep-nt", type=int, default=2000)
+    ap.add_argument("--no-fwi", action="store_true",
+                    help="skip the FWI iterations (stacked probed vs exact) on the 300^3 case")
+    ap.add_argument("--fwi-iters", type=int, default=3)
     ap.add_argument("--no-tti", action="store_true",
                     help="skip the 300x400x400 TTI gradient section")
     ap.add_argument("--tti-nt", type=int, default=2500)
     ap.add_argument("--no-gathers", action="store_true",
                     help="skip the 81-offset image volume at the TTI grid")
+    ap.add_argument("--no-ksweep", action="store_true",
+                    help="skip the k = 64 / 128 runs of the headline gradient")
     ap.add_argument("--cpu-planes", type=int, default=24)
     ap.add_argument("--cpu-nt", type=int, default=80)
     return ap.parse_args()
@@ -91,7 +96,8 @@ def parse():
 def cpu_baseline(planes: int, nt: int, r: int):
     """The FP64 oracle, as it stands, on a z-slab of the same model: `planes`
     x 512 x 512 cells, `nt` steps, forward + adjoint with r-probe compression
-    and the probed image (Gcell-updates/s)."""
+    and the probed image (Gcell-updates/s).  Two more legs time the oracle on
+    the 2D two-layer case in full and on a slab of the TTI model."""
     import numpy as np
 
     import oracle
@@ -102,15 +108,106 @@ def cpu_baseline(planes: int, nt: int, r: int):
     rec = synth.plane_receivers(planes // 2 + 1, 512, 512)
     d_obs = np.zeros((nt, rec.shape[0]))
     t0 = time.perf_counter()
-    oracle.probed_gradient(g, wl.m, src, wl.q, rec, d_obs, wl.Z)
+    J, gref, f, _ = oracle.probed_gradient(g, wl.m, src, wl.q, rec, d_obs, wl.Z)
     dt = time.perf_counter() - t0
-    return {"value": 2.0 * g.N * nt / dt / 1e9, "unit": "Gcell-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, {planes}x512x512 z-slab of the same model, nt={nt}, "
-                      f"r={r}, forward+adjoint with probing + image, {dt:.1f} s"}
+    # kept for the precision comparison (the same slab on the GPU)
+    slab = dict(grid=g, m=wl.m, src=src, q=wl.q, rec=rec, d_obs=d_obs, Z=wl.Z, J=J, grad=gref,
+                d=f["d"], c_ref=wl.c_ref)
+    del wl, f
+    out = {"value": 2.0 * g.N * nt / dt / 1e9, "unit": "Gcell-updates/s",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"FP64 oracle, {planes}x512x512 z-slab of the same model, nt={nt}, "
+                     f"r={r}, forward+adjoint with probing + image, {dt:.1f} s"}
+    print("cpu baseline: 3D slab done", file=sys.stderr, flush=True)
+    # 2D two-layer case (221 x 221, nt = 1000, r = 32, FP64) in full
+    w1 = synth.workload_c1()
+    g1 = oracle.Grid.of(w1)
+    d1 = oracle.forward(g1, w1.m_true, w1.src_pos, w1.q, w1.rec_pos)["d"]
+    t0 = time.perf_counter()
+    oracle.probed_gradient(g1, w1.m, w1.src_pos, w1.q, w1.rec_pos, d1, w1.Z)
+    dt1 = time.perf_counter() - t0
+    out["c1_full"] = {"value": round(2.0 * g1.N * g1.nt / dt1 / 1e9, 5),
+                      "unit": "Gcell-updates/s", "seconds": round(dt1, 2),
+                      "sample": "FP64 oracle, 2D two-layer 221x221, nt=1000, r=32, "
+                                "forward+adjoint with probing + image, in full"}
+    print("cpu baseline: 2D case done", file=sys.stderr, flush=True)
+    # TTI: a 16 x 128 x 128 slab of the layered + salt TTI recipe, 12 steps
+    tp, tn = 16, 12
+    w3, an = synth.workload_tti(shape=(tp, 128, 128), nt=tn, r=64)
+    g3 = oracle.Grid(3, w3.shape, w3.h, w3.dt, tn, min(w3.nb, (tp - 1) // 2), w3.c_ref, w3.R)
+    rec3 = synth.plane_receivers(tp // 2 + 1, 128, 128)
+    t0 = time.perf_counter()
+    oracle.tti_probed_gradient(g3, w3.m, an, np.array([[tp // 2, 64.0, 64.0]]), w3.q, rec3,
+                               np.zeros((tn, rec3.shape[0])), w3.Z)
+    dt3 = time.perf_counter() - t0
+    out["c3_tti_slab"] = {"value": round(2.0 * g3.N * tn / dt3 / 1e9, 6),
+                          "unit": "Gcell-updates/s", "seconds": round(dt3, 2),
+                          "sample": f"FP64 oracle, TTI {tp}x128x128 slab of the layered + salt "
+                                    f"model, nt={tn}, r=64 on p and q, forward+adjoint with "
+                                    f"probing + image"}
+    print("cpu baseline: TTI slab done", file=sys.stderr, flush=True)
+    return out, slab
 
 
-def bench_batched(nt: int, variant: int):
+def bench_precision(slab, shape, nt_full: int, r: int, k: int, variant: int):
+    """The probe-GEMM operand forms side by side: bf16 (one MFMA), bf16 hi + lo
+    (two MFMAs), float16 with per-chunk power-of-two scales (one MFMA) and the
+    FP32 vector path.  Error: the GPU gradient (FP32 fields, each probe form)
+    against the FP64 oracle's probed gradient on the oracle's z-slab of the
+    bench model (same probes, same geometry).  Time: the full-grid gradient
+    over the first nt_full steps."""
+    import numpy as np
+    import torch
+
+    import paper_2201_06914_amd as P
+    import synth
+    g = slab["grid"]
+    m = torch.from_numpy(np.ascontiguousarray(slab["m"], np.float32)).cuda()
+    q = torch.from_numpy(np.ascontiguousarray(slab["q"], np.float32)).cuda()
+    Z = torch.from_numpy(slab["Z"]).cuda()
+    d_obs = torch.from_numpy(np.ascontiguousarray(slab["d_obs"], np.float32)).cuda()
+    gref = slab["grad"]
+    wl = synth.workload_c2(nt=nt_full, r=r, k_block=k, shape=shape)
+    mf, qf, Zf = (torch.from_numpy(a).cuda() for a in (wl.m, wl.q, wl.Z))
+    dof = torch.zeros((nt_full, wl.rec_pos.shape[0]), device="cuda")
+    pf = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=k)
+    rows = []
+    P.set_stencil_variant(variant)
+    for probe in ("bf16", "bf16x2", "f16s", "f32"):
+        fused = probe != "f32"
+        plan = P.Plan(P.PlanSpec(3, g.shape, g.h, g.dt, g.nt, g.nb, g.c_ref, g.R, slab["c_ref"],
+                                 "f32", probe, r, k, 1, slab["rec"].shape[0]))
+        o = P.fwi_gradient(plan, m, slab["src"], q, slab["rec"], d_obs, Z, fused=fused)
+        gg = o["grad"].double().cpu().numpy()
+        err = float(np.linalg.norm(gg - gref) / np.linalg.norm(gref))
+        errJ = abs(float(o["misfit"].item()) - slab["J"]) / slab["J"]
+        full = P.Plan(P.PlanSpec(*[getattr(pf.spec, f) for f in ("ndim", "shape", "h", "dt", "nt",
+                                                                  "nb", "c_ref", "R", "c_max")],
+                                 "f32", probe, r, k, pf.spec.nsrc, pf.spec.nrec))
+        work = full.workspace("cuda")
+        bars = (full.empty_bar("cuda"), None if fused else full.empty_bar("cuda"))
+        run = lambda: P.fwi_gradient(full, mf, wl.src_pos, qf, wl.rec_pos, dof, Zf,  # noqa: E731
+                                     work=work, bars=bars, fused=fused)
+        run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        rows.append({"probe": probe, "imaging": "fused" if fused else "separate",
+                     "grad_rel_err_vs_fp64_oracle": float(f"{err:.3e}"),
+                     "misfit_rel_err": float(f"{errJ:.3e}"),
+                     f"ms_full_grid_nt{nt_full}": round(ms, 1)})
+        del o, work, bars, full, plan
+        torch.cuda.empty_cache()
+        print(f"precision: {probe} done", file=sys.stderr, flush=True)
+    return {"error_case": f"oracle z-slab {g.shape[0]}x{g.shape[1]}x{g.shape[2]} of the bench "
+                          f"model, nt={g.nt}, r={r}, k={k}",
+            "timing_case": f"{shape[0]}x{shape[1]}x{shape[2]}, first {nt_full} steps",
+            "forms": rows}
+
+
+def bench_batched(nt: int):
     """16 shots on uneven windows 128^3 ... 256 x 320 x 320 (181,394,048 cells),
     nt steps, r = 64, k = 32, BF16X2 probes, fused imaging: one stencil launch
     per step for all shots; the whole gradient replayed as one HIP graph.
@@ -131,7 +228,15 @@ def bench_batched(nt: int, variant: int):
                           Z=torch.from_numpy(wl.Z).cuda()))
     cells = sum(int(np.prod(sp.shape)) for sp in specs)
     del wls
+    # the batch's own stencil variant and z-split target (128 steps each)
+    from paper_2201_06914_amd.tune import autotune_batch
+    tuned = autotune_batch(specs, shots)
+    variant, blocks = tuned["best"]
+    print(f"batched: tuned variant {variant}, z-split target {blocks}", file=sys.stderr,
+          flush=True)
+    P.set_stencil_blocks(blocks)
     B = P.Batch(specs)
+    P.set_stencil_blocks(2048)
     outs = B.outputs()
     J = torch.empty(len(shots), dtype=torch.float64, device="cuda")
     work = torch.empty(B.workspace_bytes, dtype=torch.uint8, device="cuda")
@@ -172,7 +277,8 @@ def bench_batched(nt: int, variant: int):
             "ms_first_call_with_capture": round(t_capture, 1),
             "ms_one_shot_at_a_time": round(t_single, 1),
             "speedup_vs_one_shot_at_a_time": round(t_single / t_graph, 3),
-            "graph_equals_eager": bool(same), "stencil_variant": variant}
+            "graph_equals_eager": bool(same), "stencil_variant": variant,
+            "z_split_target": blocks, "autotune_ms_per_step": tuned["ms_per_step"]}
 
 
 def bench_rsweep(n: int, nt: int, variant: int):
@@ -193,9 +299,9 @@ def bench_rsweep(n: int, nt: int, variant: int):
     mt, mb = torch.from_numpy(m_true).cuda(), torch.from_numpy(m0).cuda()
     N = n ** 3
 
-    def spec(r):
+    def spec(r, k=32):
         return P.PlanSpec(3, (n, n, n), h, dt, nt, nb, 4500.0, 1e-3, 4500.0, "f32", "bf16x2", r,
-                          32, 1, rec.shape[0])
+                          k, 1, rec.shape[0])
     # observed data (untimed setup)
     p_obs = P.Plan(spec(16))
     dobs = [P.rtm_forward_probe(p_obs, mt, s, q, rec)["d"] for s in srcs]
@@ -241,8 +347,9 @@ def bench_rsweep(n: int, nt: int, variant: int):
     fd = (misfit_at(mb + eps * dm) - misfit_at(mb - eps * dm)) / (2 * eps)
     lin_exact = float((ge * dm.double()).sum())
     rows = []
-    for r in (16, 32, 64, 128):
-        B = P.Batch([spec(r)] * 4)
+    for r, k in ((16, 32), (32, 32), (64, 32), (128, 32), (64, 64), (64, 128), (128, 64),
+                 (128, 128)):
+        B = P.Batch([spec(r, k)] * 4)
         shots = [dict(m=mb, src_pos=s, q=q, rec_pos=rec, d_obs=d,
                       Z=torch.from_numpy(synth.rademacher(nt, r, 300 + 10 * i + r)).cuda())
                  for i, (s, d) in enumerate(zip(srcs, dobs))]
@@ -256,7 +363,8 @@ def bench_rsweep(n: int, nt: int, variant: int):
         gp = sum(o["grad"].double() for o in outs)
         err = float(torch.linalg.vector_norm(gp - ge) / torch.linalg.vector_norm(ge))
         cos = float((gp * ge).sum() / (torch.linalg.vector_norm(gp) * torch.linalg.vector_norm(ge)))
-        rows.append({"r": r, "ms": round(t_pr, 1), "speedup_vs_exact": round(t_exact / t_pr, 3),
+        rows.append({"r": r, "k": k, "ms": round(t_pr, 1),
+                     "speedup_vs_exact": round(t_exact / t_pr, 3),
                      "grad_rel_err": round(err, 4), "cosine": round(cos, 4),
                      "fd_rel_diff": round(abs(float((gp * dm.double()).sum()) - fd) / abs(fd), 4),
                      "memory_gb_4_shots": round((B.workspace_bytes + sum(o["Ubar"].numel() * 4
@@ -265,7 +373,7 @@ def bench_rsweep(n: int, nt: int, variant: int):
                                                                           for o in outs)) / 4e9, 2)})
         del B, outs, work, shots
         torch.cuda.empty_cache()
-        print(f"rsweep: r={r} done", file=sys.stderr, flush=True)
+        print(f"rsweep: r={r} k={k} done", file=sys.stderr, flush=True)
     # range-finder probes: Q = orth(H Omega) per shot (space sketch on MFMA),
     # real probes split bf16 hi + lo on MFMA, fused imaging, scale -1
     rf_rows = []
@@ -301,6 +409,55 @@ def bench_rsweep(n: int, nt: int, variant: int):
             "full_history_gb_per_shot": round(nt * N * 4 / 1e9, 1),
             "fd_vs_exact_rel_diff": round(abs(lin_exact - fd) / abs(fd), 5),
             "misfit": Je, "probed": rows}
+
+
+def bench_fwi(n: int, nt: int, iters: int, r: int, variant: int):
+    """FWI on the 300^3 salt model with 4 shots: `iters` iterations with
+    stacked probed gradients (every shot draws fresh probes each iteration;
+    r probes, k = 32, BF16X2, fused imaging, shots batched into one stacked
+    gradient) and as many with the exact gradient (uniform checkpointing),
+    each followed by a backtracking line search on the misfit.  Misfit and
+    relative model error ||m - m_true|| / ||m0 - m_true|| per iteration."""
+    import numpy as np
+    import torch
+
+    import paper_2201_06914_amd as P
+    import synth
+    from paper_2201_06914_amd import fwi
+    h, dt, nb = 12.5, 1e-3, 10
+    m_true, m0 = synth.model_salt_300(n)
+    srcs, rec = synth.shots_salt_300(n)
+    q = torch.from_numpy(synth.source_signature(nt, dt, 10.0, h, 3).astype(np.float32)).cuda()
+    mt, mb = torch.from_numpy(m_true).cuda(), torch.from_numpy(m0).cuda()
+    m_min, m_max = 0.8 * float(m_true.min()), 1.2 * float(m_true.max())
+    spec = P.PlanSpec(3, (n, n, n), h, dt, nt, nb, 4500.0, 1e-3, float(1.0 / np.sqrt(m_min)),
+                      "f32", "bf16x2", r, 32, 1, rec.shape[0])
+    p_obs = P.Plan(spec)
+    shots = [fwi.Shot(s, q, rec, P.rtm_forward_probe(p_obs, mt, s, q, rec)["d"]) for s in srcs]
+    del p_obs
+    torch.cuda.empty_cache()
+    P.set_stencil_variant(variant)
+    out = {}
+    for name, exact in (("probed", False), ("exact", True)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = fwi.fwi(spec, mb, shots, iters=iters, seed=500, step=0.02, m_min=m_min,
+                      m_max=m_max, exact=exact, m_true=mt)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        out[name] = {"misfit": [round(x["misfit"], 6) for x in res["history"]]
+                     + [round(res["final_misfit"], 6)],
+                     "model_err": [round(x["model_err"], 5) for x in res["history"]]
+                     + [round(res["final_model_err"], 5)],
+                     "alpha": [x["alpha"] for x in res["history"]],
+                     "trials": [x["trials"] for x in res["history"]],
+                     "seconds": round(sec, 1)}
+        del res
+        torch.cuda.empty_cache()
+        print(f"fwi: {name} done", file=sys.stderr, flush=True)
+    return {"workload": f"{n}^3 salt model, 4 shots stacked, nt={nt}, r={r} (fresh probes per "
+                        f"shot and iteration), k=32, bf16x2, fused; exact: checkpointed FP32",
+            "iterations": iters, **out}
 
 
 def bench_tti(shape, nt: int, r: int, stride: int):
@@ -358,17 +515,20 @@ def bench_tti(shape, nt: int, r: int, stride: int):
 
 
 def hbm_copy_gbps(mib: int = 2048, reps: int = 5) -> float:
-    """Measured HBM ceiling for streaming kernels: a plain device-to-device
-    copy of mib MiB (read + write bytes over the HIP-event time)."""
+    """Measured HBM ceiling of a read-once / write-once kernel: the library's
+    16-byte-vector streaming copy (rtm_device_copy) of mib MiB, read + write
+    bytes over its HIP-event time on the stream it runs on."""
     import torch
+
+    from paper_2201_06914_amd.api import device_copy
     nel = mib * (1 << 20) // 4
     x = torch.ones(nel, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
-    y.copy_(x)
+    device_copy(x, y)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
     for _ in range(reps):
-        y.copy_(x)
+        device_copy(x, y)
     ev[1].record()
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1]) / reps
@@ -493,10 +653,11 @@ def main():
         torch.cuda.empty_cache()
     # the exact gradient (Eq. 2, FP32, uniform checkpointing) on the same inputs
     exact = None
+    ge = None
+    g_probed = out["grad"].double()
+    del out
+    torch.cuda.empty_cache()
     if not a.no_exact:
-        g_probed = out["grad"].double()
-        del out
-        torch.cuda.empty_cache()
         ewb = P.exact_workspace_bytes(plan)
         ework = torch.empty(ewb, dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
@@ -519,18 +680,64 @@ def main():
                                "full_history_fp32": round(full_hist / 1e9, 1)},
                  "memory_reduction_vs_full_history": round(full_hist / probed_bytes, 1),
                  "memory_ratio_vs_checkpointed": round(ewb / probed_bytes, 2)}
-        del ework, ex, ge, g_probed
+        del ework, ex
         torch.cuda.empty_cache()
         print("exact comparator done", file=sys.stderr, flush=True)
-    if a.copy_calib_mb:
-        nel = a.copy_calib_mb * (1 << 20) // 4
-        x = torch.ones(nel, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
-
+    # probe block length: the same gradient with k = 64 and 128 (the ring grows
+    # to k + 2 levels, the compressed field is read and written once per block)
+    ksweep = None
+    if not a.no_ksweep:
+        import dataclasses
+        ksweep = [{"k": k, "ms": round(ms_step, 1),
+                   "probe_fwd_avg_us": round(pf_ms / max(pf_n, 1) * 1e3, 1),
+                   "probe_adj_avg_us": round(pa_ms / max(pa_n, 1) * 1e3, 1),
+                   "memory_gb_ring_plus_ubar": round((plan.workspace_bytes + r * plan.Npad * 4)
+                                                     / 1e9, 2)}]
+        if exact:
+            ksweep[0]["speedup_vs_exact"] = exact["speedup_vs_exact"]
+            ksweep[0]["grad_rel_err_vs_exact"] = exact["grad_rel_err_vs_exact"]
+        for k2 in (64, 128):
+            if k2 == k:
+                continue
+            p2 = P.Plan(dataclasses.replace(plan.spec, k_block=k2))
+            w2 = p2.workspace("cuda")
+            P.profile_enable(a.prof_stride)
+            for kk in ("probe", "probe_adj"):
+                P.profile_read(kk)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            o2 = P.fwi_gradient(p2, m, src, q, rec, d_obs, Z, work=w2, bars=bars, fused=fused)
+            torch.cuda.synchronize()
+            ms2 = (time.perf_counter() - t4) * 1e3
+            P.profile_enable(0)
+            f_ms, f_n = P.profile_read("probe")
+            b_ms, b_n = P.profile_read("probe_adj")
+            g2 = o2["grad"].double()
+            row = {"k": k2, "ms": round(ms2, 1),
+                   "value": round(2.0 * N * nt / (ms2 * 1e-3) / 1e9, 2),
+                   "probe_fwd_avg_us": round(f_ms / max(f_n, 1) * 1e3, 1),
+                   "probe_adj_avg_us": round(b_ms / max(b_n, 1) * 1e3, 1),
+                   "probe_ms_per_gradient": round(f_ms + b_ms, 1),
+                   "memory_gb_ring_plus_ubar": round((p2.workspace_bytes + r * plan.Npad * 4)
+                                                     / 1e9, 2),
+                   "grad_rel_diff_vs_k32": round(float(torch.linalg.vector_norm(g2 - g_probed)
+                                                       / torch.linalg.vector_norm(g_probed)), 8)}
+            if ge is not None:
+                row["speedup_vs_exact"] = round(exact["exact_ms_per_step"] / ms2, 3)
+                row["grad_rel_err_vs_exact"] = round(float(torch.linalg.vector_norm(g2 - ge)
+                                                           / torch.linalg.vector_norm(ge)), 4)
+            ksweep.append(row)
+            del o2, g2, w2, p2
+            torch.cuda.empty_cache()
+            print(f"k sweep: k={k2} done", file=sys.stderr, flush=True)
+        from paper_2201_06914_amd.tune import autotune_k_block
+        kt = autotune_k_block(plan.spec, m, src, q, rec, Z, candidates=(16, 32, 64, 128))
+        ksweep.append({"autotuned_k": kt["best"], "ms_per_step_256": kt["ms_per_step"],
+                       "memory_gb": kt["memory_gb"]})
+        torch.cuda.empty_cache()
+        print(f"k autotune: {kt['best']}", file=sys.stderr, flush=True)
+    del g_probed, ge
+    torch.cuda.empty_cache()
 
     # algorithmic bytes (FP32 fields, FP32 compressed fields)
     st_bytes = 16.0 * N                                   # read u^n, u^{n-1}, m; write u^{n+1}
@@ -541,40 +748,44 @@ def main():
     # and read + write the image
     fwd_b = sum((4.0 * (kb + 2) + 8.0 * r) * N for kb in kbs)
     adj_b = sum((4.0 * kb + (4.0 * r + 8.0 if fused else 8.0 * r)) * N for kb in kbs)
-    pr_bytes_step = fwd_b + adj_b
     st_avg = st_ms / max(st_n, 1)
-    pr_ms, pr_n = pf_ms + pa_ms, pf_n + pa_n
-    pr_avg = pr_ms / max(pr_n, 1)
-    st_tot = st_avg * 2 * nt                              # ms per step
-    pr_tot = pr_ms / a.steps
     st_ach = st_bytes / (st_avg * 1e-3) / 1e9
-    pr_ach = pr_bytes_step * a.steps / (pr_ms * 1e-3) / 1e9 if pr_n else 0.0
     pf_ach = fwd_b * a.steps / (pf_ms * 1e-3) / 1e9 if pf_n else 0.0
     pa_ach = adj_b * a.steps / (pa_ms * 1e-3) / 1e9 if pa_n else 0.0
-    stencil = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS,
-               "unit": "GB/s", "frac": round(st_ach / HBM_PEAK_GBS, 4), "traffic": None,
-               "kernel": f"k_stencil3d_tiled (variant {tune['best']})",
-               "avg_launch_us": round(st_avg * 1e3, 2), "autotune_us": tune.get("us"),
-               "launches_timed": st_n, "bytes_per_launch": st_bytes, "ms_per_step": round(st_tot, 1)}
-    probe = {"bound": "hbm", "achieved": round(pr_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-             "frac": round(pr_ach / HBM_PEAK_GBS, 4), "traffic": None,
-             "kernel": "k_probe_mfma_fast (forward u_tt + adjoint" +
-                       (" fused imaging)" if fused else ")"),
-             "avg_launch_us": round(pr_avg * 1e3, 2), "launches_timed": pr_n,
-             "bytes_per_launch_avg": pr_bytes_step / (2 * nblk),
-             "ms_per_step": round(pr_tot, 1),
-             "forward": {"avg_launch_us": round(pf_ms / max(pf_n, 1) * 1e3, 1),
-                         "GBps": round(pf_ach, 1), "bytes_per_launch": fwd_b / nblk},
-             "adjoint": {"avg_launch_us": round(pa_ms / max(pa_n, 1) * 1e3, 1),
-                         "GBps": round(pa_ach, 1), "bytes_per_launch": adj_b / nblk},
-             "mfma_tflops": round((2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 *
-                                  math.ceil(k / 16) * N * 2 * nblk * a.steps /
-                                  (pr_ms * 1e-3) / 1e12, 2) if pr_n else None}
+    mfma_flop = (2 if a.probe == "bf16x2" else 1) * 2.0 * r * 16 * math.ceil(k / 16) * N * nblk
     tr = measured_traffic("acoustic", (384, 512, 512), r=r, k=k) if fused else None
-    if tr:
-        stencil["traffic"] = round(tr["stencil"])
-        probe["traffic"] = round(0.5 * (tr["probe_fwd"] + tr["probe_adj"]))
-    dominant, other = (probe, stencil) if pr_tot > st_tot else (stencil, probe)
+    tr_src = ("stored rocprofv3 --pmc record profiles/pmc_traffic.json (FETCH_SIZE + WRITE_SIZE "
+              "per dispatch, copy-calibrated), taken on these kernel sources (hash match), not "
+              "measured in this run") if tr else None
+
+    def entry(kernel, ach, avg_ms, n, bpl, ms_per_step, traffic, extra=None):
+        e = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+             "traffic_source": tr_src if traffic is not None else None,
+             "kernel": kernel, "avg_launch_us": round(avg_ms * 1e3, 2), "launches_timed": n,
+             "bytes_per_launch": bpl, "ms_per_step": round(ms_per_step, 1)}
+        e.update(extra or {})
+        return e
+    kern = {
+        "probe_forward": entry(
+            f"k_probe_mfma_fast (forward probe GEMM on u_tt, {a.probe}, k={k})", pf_ach,
+            pf_ms / max(pf_n, 1), pf_n, fwd_b / nblk, pf_ms / a.steps,
+            round(tr["probe_fwd"]) if tr else None,
+            {"bytes_per_cell_per_block": 4 * (k + 2) + 8 * r,
+             "mfma_tflops": round(mfma_flop * a.steps / (pf_ms * 1e-3) / 1e12, 2) if pf_n
+             else None}),
+        "probe_adjoint": entry(
+            "k_probe_mfma_fast (adjoint probe GEMM" + (" with fused imaging)" if fused else ")"),
+            pa_ach, pa_ms / max(pa_n, 1), pa_n, adj_b / nblk, pa_ms / a.steps,
+            round(tr["probe_adj"]) if tr else None,
+            {"bytes_per_cell_per_block": 4 * k + (4 * r + 8 if fused else 8 * r)}),
+        "stencil": entry(
+            f"k_stencil3d_tiled (variant {tune['best']})", st_ach, st_avg, st_n, st_bytes,
+            st_avg * 2 * nt, round(tr["stencil"]) if tr else None,
+            {"bytes_per_cell": 16, "autotune_us": tune.get("us")}),
+    }
+    dom = max(kern, key=lambda kk: kern[kk]["ms_per_step"])
+    pr_bytes_step = fwd_b + adj_b
     path_bytes = 2 * nt * st_bytes + pr_bytes_step
     rec_line = {
         "metric": "Gcell-updates/s fwd+adj w/ probing, %HBM peak; gradient rel. error vs exact",
@@ -584,10 +795,12 @@ def main():
         "config": {"workload": f"3d-layered-384x512x512-nt{nt}-r{r}-k{k}", "grid": [384, 512, 512],
                    "nt": nt, "r": r, "k_block": k, "probe_operand": a.probe, "shots": 1,
                    "imaging": "fused" if fused else "separate", "parallelism": "single-gpu"},
-        "roofline": dominant, "roofline_other": other,
+        "roofline": dict(kern[dom], dominant=dom),
+        "roofline_kernels": kern,
         "hbm_frac_path": round(path_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "grad_rel_err_vs_exact": exact["grad_rel_err_vs_exact"] if exact else None,
         "exact_comparator": exact,
+        "k_sweep": ksweep,
         "misfit": misfit, "grad_finite": finite,
         ("unfused_ms_per_step" if fused else "fused_ms_per_step"):
             round(other_ms, 1) if other_ms is not None else None,
@@ -597,19 +810,28 @@ def main():
     try:
         cp = hbm_copy_gbps()
         rec_line["hbm_copy_GBps"] = round(cp, 1)
-        rec_line["hbm_copy_kernel"] = "torch copy_ of 2 GiB float32 (HIP events)"
-        for rl in (dominant, other):
-            rl["frac_of_copy"] = round(rl["achieved"] / cp, 4)
+        rec_line["hbm_copy_kernel"] = "rtm_device_copy (k_copy_x4, 16-byte vectors), 2 GiB, HIP events"
+        for e in kern.values():
+            e["frac_of_copy"] = round(e["achieved"] / cp, 4)
+        rec_line["roofline"]["frac_of_copy"] = kern[dom]["frac_of_copy"]
     except Exception as e:
         rec_line["hbm_copy_GBps"] = {"error": f"{type(e).__name__}: {e}"}
+    if a.copy_calib_mb:      # a plain copy of known size, for PMC calibration
+        from paper_2201_06914_amd.api import device_copy
+        nel = a.copy_calib_mb * (1 << 20) // 4
+        x = torch.ones(nel, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            device_copy(x, y)
+        torch.cuda.synchronize()
+        del x, y
     if not a.no_batched:
         del bars, work, m, q, Z, d_obs
         if "out" in locals():
             del out
         torch.cuda.empty_cache()
         try:
-            rec_line["batched"] = bench_batched(a.batched_nt,
-                                                tune["best"] if tune["best"] >= 1 else 7)
+            rec_line["batched"] = bench_batched(a.batched_nt)
         except Exception as e:  # a failing section must not lose the headline line
             rec_line["batched"] = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
@@ -620,6 +842,14 @@ def main():
                                               tune["best"] if tune["best"] >= 1 else 7)
         except Exception as e:
             rec_line["rsweep"] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
+    if not a.no_fwi:
+        torch.cuda.empty_cache()
+        try:
+            rec_line["fwi"] = bench_fwi(a.rsweep_n, a.rsweep_nt, a.fwi_iters, 64,
+                                        tune["best"] if tune["best"] >= 1 else 7)
+        except Exception as e:
+            rec_line["fwi"] = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
     if not a.no_tti:
         torch.cuda.empty_cache()
@@ -637,7 +867,12 @@ def main():
         torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         torch.cuda.empty_cache()
-        rec_line["cpu_baseline"] = cpu_baseline(a.cpu_planes, a.cpu_nt, r)
+        rec_line["cpu_baseline"], slab = cpu_baseline(a.cpu_planes, a.cpu_nt, r)
+        try:
+            rec_line["precision"] = bench_precision(slab, (384, 512, 512), 256, r, k,
+                                                    tune["best"] if tune["best"] >= 1 else 7)
+        except Exception as e:
+            rec_line["precision"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(rec_line), flush=True)
 
 

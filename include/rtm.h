@@ -81,7 +81,10 @@ typedef enum {
   RTM_F32 = 1,    /* float */
   RTM_BF16 = 2,   /* probe operand: bfloat16, round to nearest even */
   RTM_BF16X2 = 3, /* probe operand: bfloat16 hi + bfloat16 lo split (16-bit mantissa) */
-  RTM_I8 = 4      /* probe matrix entries +-1 stored as int8 */
+  RTM_I8 = 4,     /* probe matrix entries +-1 stored as int8 */
+  RTM_F16S = 5    /* probe operand: float16 after a power-of-two scale shared by
+                     each 16-step chunk of a 32-cell tile (its largest magnitude
+                     mapped below 2^15), one MFMA per chunk; +-1 probes exact */
 } rtm_dtype;
 
 typedef enum {
@@ -101,8 +104,9 @@ typedef struct {
   double c_max;         /* largest velocity in m, for the CFL check (m/s) */
   rtm_dtype field_dtype;/* RTM_F64 or RTM_F32: fields, model, traces, outputs */
   rtm_dtype probe_dtype;/* GEMM operand type: RTM_F64 (F64 fields), RTM_F32,
-                           RTM_BF16 (F32 fields; Z RTM_I8) or RTM_BF16X2 (F32
-                           fields; Z RTM_I8, or RTM_F32 for real probes) */
+                           RTM_BF16 or RTM_F16S (F32 fields; Z RTM_I8) or
+                           RTM_BF16X2 (F32 fields; Z RTM_I8, or RTM_F32 for
+                           real probes) */
   int32_t r;            /* number of probe vectors, 1..1024 */
   int32_t k_block;      /* time steps per probe-GEMM block, 1..256 */
   int32_t nsrc;         /* number of source points per call (>= 0) */
@@ -137,9 +141,15 @@ const char *rtm_status_str(rtm_status s);
  * by rtm_batch_create) aims at twice as many. */
 void rtm_set_stencil_variant(int variant);
 void rtm_set_stencil_blocks(int32_t blocks);
+/* Tuning hook, process wide: with on != 0 (default) the tiled stencil of the
+ * sweeps (single shot and batched) marches each z-chunk upwards on even steps
+ * and downwards on odd ones, so a step begins on the planes the previous step
+ * touched last; 0 marches upwards always.  Bitwise-identical results. */
+void rtm_set_stencil_alternate(int32_t on);
 /* Autotuner and race check for the stencil: runs one step of every variant
  * (0..13 in 3D, 0 in 2D) from the same pattern levels in the ring of `work`,
- * counts elements that differ bitwise from variant 0 (mismatch[v]), times
+ * counts elements that differ bitwise from variant 0 in either z-marching
+ * direction (mismatch[v]), times
  * `steps` launches of each (us[v], microseconds per launch; us and mismatch
  * may be NULL or hold 14 entries) and returns in *best the fastest variant
  * with no mismatch.  It does not change the current variant.  Needs
@@ -174,8 +184,8 @@ const char *rtm_last_error(void);
  * m, the wavelet, the data or the anisotropy, or a blow-up, spreads to
  * these).  Synchronizes `stream`, then returns RTM_OK or RTM_E_NONFINITE;
  * the word is left as it is.  work: the device workspace of the call (256-byte
- * aligned); NULL plan or work -> RTM_E_ARG.  The batched calls keep no watch
- * word. */
+ * aligned); NULL plan or work -> RTM_E_ARG.  The batched calls have their own
+ * watch word (rtm_batch_stream_status). */
 rtm_status rtm_stream_status(const rtm_plan *plan, const void *work, rtm_stream stream);
 
 /* Forward sweep with on-the-fly probing (Eq. 3, Ubar = Z^T u_tt or Z^T u).
@@ -232,7 +242,7 @@ rtm_status rtm_adjoint_probe(const rtm_plan *plan, const void *m, const double *
                              size_t work_bytes, rtm_stream stream);
 
 /* Adjoint sweep with the probed imaging condition folded into its probe
- * blocks (BF16 / BF16X2 plans): image[x] = scale * sum_i Ubar[i][x] Vbar[i][x]
+ * blocks (BF16 / BF16X2 / F16S plans): image[x] = scale * sum_i Ubar[i][x] Vbar[i][x]
  * with Vbar = Z^T lam accumulated block by block and never stored (by
  * linearity the same image as rtm_adjoint_probe + rtm_image, summed in float).
  *   Ubar device [r*Npad] tile-major (from rtm_forward_probe), image device [N]. */
@@ -246,11 +256,19 @@ rtm_status rtm_adjoint_image(const rtm_plan *plan, const void *m, const double *
 rtm_status rtm_image(const rtm_plan *plan, const void *Ubar, const void *Vbar, double scale,
                      void *image, rtm_stream stream);
 
+/* Residual and misfit of predicted data (the adjoint source of Eq. 2's
+ * gradient): resid = d_pred - d_obs and misfit[0] = 1/2 sum resid^2, the sum
+ * in double in a fixed order (deterministic).  d_pred, d_obs, resid device
+ * [nt][nrec] field dtype (resid may be d_pred itself); misfit device double
+ * [1]; work as for the sweeps (its reduction partials are used). */
+rtm_status rtm_residual(const rtm_plan *plan, const void *d_pred, const void *d_obs, void *resid,
+                        double *misfit, void *work, size_t work_bytes, rtm_stream stream);
+
 /* Probed FWI gradient of J = 1/2 sum |d_pred - d_obs|^2 (Eq. 2 estimated by
  * Eq. 3): forward probing u_tt, residual, adjoint probing, image with scale
  * -1/r.  Ubar, Vbar device [r*Npad] (tile-major) and resid device [nt][nrec] are outputs
  * (resid = d_pred - d_obs); grad device [N]; misfit device double [1].
- * Vbar may be NULL on the BF16 / BF16X2 paths: the adjoint sweep then folds
+ * Vbar may be NULL on the BF16 / BF16X2 / F16S paths: the adjoint sweep then folds
  * the imaging condition into its probe blocks (grad += -1/r sum_i Ubar[i]
  * (Z_b^T Lambda_b)[i], equal to the image of Eq. 3 by linearity) and Vbar is
  * never stored; the sum over blocks is then in float, not double. */
@@ -361,10 +379,20 @@ rtm_status fwi_gradient_exact(const rtm_plan *plan, const void *m, const double 
  * receivers record p.  The gradient is -sum_n (p_tt lam_p + q_tt lam_q), so
  * both fields are compressed: Ubar / Vbar are [2][r*Npad] (p then q, each
  * tile-major).  aniso: device [4][N] (eps, delta, theta, phi in radians) of
- * the field dtype; delta <= eps keeps the system stable, and c_max in the
- * plan must be the largest velocity times sqrt(1 + 2 eps).
+ * the field dtype.
+ * Stability screen: before it writes anything, each TTI call reads m, eps and
+ * delta once on the device and synchronizes `stream`.  With the coefficients
+ * frozen at a cell the operator's symbol is [[c1, c2], [c2, 1]] diag(h0, hz)
+ * (c1 = 1 + 2 eps, c2 = sqrt(1 + 2 delta), h0, hz >= 0 the symbols of -H0,
+ * -Hz, h0 + hz that of -L); for delta <= eps its eigenvalues are real and at
+ * most max(1, c1) (h0 + hz), so the acoustic CFL bound holds with velocity
+ * v sqrt(max(1, 1 + 2 eps)).  Hence: a cell with delta > eps, eps <= -1/2
+ * or delta <= -1/2 -> RTM_E_ARG (not clipped); a plan c_max below
+ * max v sqrt(max(1, 1 + 2 eps)) (1e-6 relative slack) -> RTM_E_CFL.
+ * rtm_tti_spectral_radius measures the discrete operator's actual spectral
+ * radius on a model.
  *   rtm_tti_adjoint_probe: qadj[n] = Ps (lam_p + lam_q)^n (adjoint of q -> d).
- *   fwi_gradient_tti: Vbar may be NULL on BF16 paths (fused imaging). */
+ *   fwi_gradient_tti: Vbar may be NULL on the MFMA probe paths (fused imaging). */
 rtm_status rtm_tti_workspace_bytes(const rtm_plan *plan, size_t *bytes);
 rtm_status rtm_tti_forward_probe(const rtm_plan *plan, const void *m, const void *aniso,
                                  const double *src_pos, const void *q, const double *rec_pos,
@@ -374,13 +402,26 @@ rtm_status rtm_tti_adjoint_probe(const rtm_plan *plan, const void *m, const void
                                  const double *rec_pos, const void *res, const double *src_pos,
                                  void *qadj, const void *Z, rtm_dtype z_dtype, void *Vbar,
                                  void *work, size_t work_bytes, rtm_stream stream);
+/* Spectral radius of m^{-1} A, A the discrete TTI operator above without the
+ * sponge, on this plan's grid and the given model, by power iteration: from a
+ * seeded pseudo-random unit vector (p, q), `iters` times w = m^{-1} A v (one
+ * forward step with a zero previous level: w = (next - 2 v) / dt^2),
+ * v = w / |w|; *rho (host) = |w| of the last iteration, which approaches the
+ * spectral radius from below as iters grows (real spectrum for delta <= eps).
+ * The leapfrog is stable for dt <= 2 / sqrt(rho).  The screen of the TTI
+ * calls is not applied (a rejected model can be measured).  work: as the
+ * other TTI calls (rtm_tti_workspace_bytes); overwrites its rings; iters in
+ * 1..10^6, else RTM_E_ARG.  Synchronizes `stream`. */
+rtm_status rtm_tti_spectral_radius(const rtm_plan *plan, const void *m, const void *aniso,
+                                   int32_t iters, uint64_t seed, double *rho, void *work,
+                                   size_t work_bytes, rtm_stream stream);
 rtm_status fwi_gradient_tti(const rtm_plan *plan, const void *m, const void *aniso,
                             const double *src_pos, const void *q, const double *rec_pos,
                             const void *d_obs, const void *Z, rtm_dtype z_dtype, void *Ubar,
                             void *Vbar, void *resid, void *grad, double *misfit, void *work,
                             size_t work_bytes, rtm_stream stream);
 
-/* Batched shots (3D, F32 fields, BF16 / BF16X2 probes).  Each descriptor is
+/* Batched shots (3D, F32 fields, BF16 / BF16X2 / F16S probes).  Each descriptor is
  * one shot's sub-domain window (its own nz, ny, nx, nb, c_ref, c_max, nsrc,
  * nrec); nt, dt, h, r, k_block and the probe dtype must agree.  One launch
  * per time step advances every shot (a tile table spans all windows), one
@@ -389,7 +430,15 @@ rtm_status fwi_gradient_tti(const rtm_plan *plan, const void *m, const void *ani
  * gradient (fused imaging, no Vbar) and misfit[i] (device double [nshots]).
  * use_graph != 0 captures the whole launch sequence into a HIP graph on the
  * first call and replays it while the pointers, positions and stencil variant
- * stay the same (the batch object caches it; not thread safe). */
+ * stay the same (the batch object caches it; not thread safe).
+ * Stacking (the image / gradient summed over sources, each shot with its own
+ * probe matrix Z): shots with the same grid may pass the same `grad`
+ * pointer; that buffer then receives the sum of their gradients, added probe
+ * block by probe block in shot order (deterministic).  Shots that share a
+ * `grad` but not a grid, or a `grad` that is also another array of a shot,
+ * -> RTM_E_ARG.  Each call keeps a non-finite watch word in `work` (cleared
+ * at its start; set when a shot's last adjoint level, gradient or misfit is a
+ * NaN or an infinity), read by rtm_batch_stream_status. */
 typedef struct rtm_batch rtm_batch;
 typedef struct {
   const void *m;          /* device [N_i] slowness squared */
@@ -408,6 +457,10 @@ rtm_status rtm_batch_workspace_bytes(const rtm_batch *batch, size_t *bytes);
 rtm_status fwi_gradient_batched(rtm_batch *batch, const rtm_shot_io *io, double *misfit,
                                 int32_t use_graph, void *work, size_t work_bytes,
                                 rtm_stream stream);
+/* The batched counterpart of rtm_stream_status: synchronizes `stream`, then
+ * returns RTM_E_NONFINITE if the last fwi_gradient_batched call on `work`
+ * met a non-finite value, else RTM_OK.  NULL or misaligned -> RTM_E_ARG. */
+rtm_status rtm_batch_stream_status(const rtm_batch *batch, const void *work, rtm_stream stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the probed

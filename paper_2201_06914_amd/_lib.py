@@ -7,7 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librtm.so")
 
-RTM_F64, RTM_F32, RTM_BF16, RTM_BF16X2, RTM_I8 = 0, 1, 2, 3, 4
+RTM_F64, RTM_F32, RTM_BF16, RTM_BF16X2, RTM_I8, RTM_F16S = 0, 1, 2, 3, 4, 5
 RTM_PROBE_U, RTM_PROBE_UTT = 0, 1
 RTM_E_NONFINITE = 9
 
@@ -23,7 +23,8 @@ EXPORTS = (
     "fwi_gradient_tti", "rtm_set_exact_fused", "rtm_set_tti_shape", "rtm_rf_workspace_bytes",
     "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf", "rtm_offset_gathers",
     "rtm_stream_status", "rtm_forward_probe_range", "fwi_gradient_noalloc",
-    "rtm_device_copy",
+    "rtm_device_copy", "rtm_residual", "rtm_batch_stream_status", "rtm_tti_spectral_radius",
+    "rtm_set_stencil_alternate",
 )
 
 RTM_NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -92,6 +93,13 @@ def load() -> ctypes.CDLL:
     L.fwi_gradient_noalloc.argtypes = [_vp, _vp, _dp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, _vp,
                                        _vp, _vp, _vp, _vp]
     L.fwi_gradient_noalloc.restype = ctypes.c_int
+    L.rtm_tti_spectral_radius.argtypes = [_vp, _vp, _vp, i32, ctypes.c_uint64,
+                                          ctypes.POINTER(dbl), _vp, sz, _vp]
+    L.rtm_tti_spectral_radius.restype = ctypes.c_int
+    L.rtm_residual.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, sz, _vp]
+    L.rtm_residual.restype = ctypes.c_int
+    L.rtm_batch_stream_status.argtypes = [_vp, _vp, _vp]
+    L.rtm_batch_stream_status.restype = ctypes.c_int
     L.rtm_device_copy.argtypes = [_vp, _vp, sz, _vp]
     L.rtm_device_copy.restype = ctypes.c_int
     L.rtm_dot.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, sz, _vp]
@@ -118,6 +126,8 @@ def load() -> ctypes.CDLL:
     L.rtm_adjoint_image.argtypes = [_vp, _vp, _dp, _vp, _vp, ctypes.c_int, _vp, dbl, _vp, _vp, sz,
                                     _vp]
     L.rtm_adjoint_image.restype = ctypes.c_int
+    L.rtm_set_stencil_alternate.argtypes = [i32]
+    L.rtm_set_stencil_alternate.restype = None
     L.rtm_set_stencil_blocks.argtypes = [i32]
     L.rtm_set_stencil_blocks.restype = None
     L.rtm_autotune_stencil.argtypes = [_vp, _vp, _vp, sz, i32, ctypes.POINTER(i32),

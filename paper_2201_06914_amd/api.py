@@ -16,7 +16,7 @@ from . import _lib
 
 _FIELD = {"f64": _lib.RTM_F64, "f32": _lib.RTM_F32}
 _PROBE = {"f64": _lib.RTM_F64, "f32": _lib.RTM_F32, "bf16": _lib.RTM_BF16,
-          "bf16x2": _lib.RTM_BF16X2}
+          "bf16x2": _lib.RTM_BF16X2, "f16s": _lib.RTM_F16S}
 _TORCH = {"f64": torch.float64, "f32": torch.float32}
 
 
@@ -46,7 +46,7 @@ class PlanSpec:
     R: float
     c_max: float
     field: str = "f32"    # "f64" | "f32"
-    probe: str = "bf16x2" # "f64" | "f32" | "bf16" | "bf16x2"
+    probe: str = "bf16x2" # "f64" | "f32" | "bf16" | "bf16x2" | "f16s"
     r: int = 1
     k_block: int = 32
     nsrc: int = 1
@@ -143,15 +143,34 @@ class Batch:
             self._destroy(h)
             self._h = None
 
-    def outputs(self, device="cuda") -> list:
-        """Preallocated per-shot outputs (reuse them to replay a captured graph)."""
+    def outputs(self, device="cuda", stack: bool = False) -> list:
+        """Preallocated per-shot outputs (reuse them to replay a captured graph).
+        stack=True gives every shot the same gradient buffer (the shots must
+        share one grid): fwi_gradient then returns the stacked gradient, the
+        sum over shots, in each outs[i]["grad"]."""
         outs = []
+        shared = None
+        if stack:
+            if len({tuple(sp.shape) for sp in self.specs}) != 1:
+                raise ValueError("stacking needs every shot on the same grid")
+            shared = torch.empty(self.N[0], dtype=torch.float32, device=device)
         for sp, n, npad in zip(self.specs, self.N, self.Npad):
             outs.append({"Ubar": torch.empty((npad // 32, sp.r, 32), dtype=torch.float32,
                                              device=device),
                          "resid": torch.empty((sp.nt, sp.nrec), dtype=torch.float32, device=device),
-                         "grad": torch.empty(n, dtype=torch.float32, device=device)})
+                         "grad": shared if stack else torch.empty(n, dtype=torch.float32,
+                                                                  device=device)})
         return outs
+
+    def stream_status(self, work: torch.Tensor) -> bool:
+        """True if the last fwi_gradient call on `work` kept every checked value
+        finite; False if it met a NaN or an infinity.  Synchronizes."""
+        code = _lib.load().rtm_batch_stream_status(self._h, ctypes.c_void_p(work.data_ptr()),
+                                                   _stream(work.device))
+        if code == _lib.RTM_E_NONFINITE:
+            return False
+        _check(code, "rtm_batch_stream_status")
+        return True
 
     def fwi_gradient(self, shots, outs=None, misfit=None, use_graph=False, work=None):
         """shots: per shot dict(m, src_pos, q, rec_pos, d_obs, Z).  Returns
@@ -208,6 +227,11 @@ def set_stencil_variant(v: int) -> None:
 
 
 N_STENCIL_VARIANTS = 14
+
+
+def set_stencil_alternate(on: bool) -> None:
+    """Tiled stencil marches z up / down on alternate steps (default on)."""
+    _lib.load().rtm_set_stencil_alternate(1 if on else 0)
 
 
 def set_stencil_blocks(blocks: int) -> None:
@@ -525,6 +549,24 @@ def rtm_offset_gathers(plan: Plan, Ubar, Vbar, nh: int, scale=None, nfield: int 
     return G
 
 
+def rtm_residual(plan: Plan, d_pred, d_obs, resid=None, work=None):
+    """(resid, misfit): resid = d_pred - d_obs, misfit = 1/2 sum resid^2 (FP64,
+    device tensor [1]).  resid may be d_pred itself."""
+    s = plan.spec
+    dev = d_pred.device
+    resid = resid if resid is not None else torch.empty_like(d_pred)
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    work = _work(plan, work, dev)
+    n = s.nt * s.nrec
+    _check(_lib.load().rtm_residual(plan.handle, _dev(d_pred, plan.dtype, n, "d_pred"),
+                                    _dev(d_obs, plan.dtype, n, "d_obs"),
+                                    _dev(resid, plan.dtype, n, "resid"),
+                                    _dev(J, torch.float64, 1, "misfit"),
+                                    ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(dev)),
+           "rtm_residual")
+    return resid, J
+
+
 def stream_status(plan: Plan, work: torch.Tensor) -> bool:
     """True if the last sweeping call on this workspace kept every checked
     value finite (final wavefield levels, gradient / image, misfit); False if
@@ -727,6 +769,20 @@ def rtm_tti_adjoint_probe(plan: Plan, m, aniso, rec_pos, res, Z=None, src_pos=No
     if qa is not None:
         out["qadj"] = qa
     return out
+
+
+def tti_spectral_radius(plan: Plan, m, aniso, iters: int = 200, seed: int = 1,
+                        work=None) -> float:
+    """Power-iteration estimate of the spectral radius of m^{-1} A (TTI
+    operator, no sponge); the leapfrog is stable for dt <= 2 / sqrt(rho)."""
+    dev = m.device
+    work = work if work is not None else tti_workspace(plan, dev)
+    rho = ctypes.c_double()
+    _check(_lib.load().rtm_tti_spectral_radius(
+        plan.handle, _dev(m, plan.dtype, plan.N, "m"), _dev(aniso, plan.dtype, 4 * plan.N, "aniso"),
+        int(iters), int(seed), ctypes.byref(rho), ctypes.c_void_p(work.data_ptr()), work.numel(),
+        _stream(dev)), "rtm_tti_spectral_radius")
+    return float(rho.value)
 
 
 def fwi_gradient_tti(plan: Plan, m, aniso, src_pos, q, rec_pos, d_obs, Z, fused: bool = False,

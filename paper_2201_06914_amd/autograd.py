@@ -55,7 +55,7 @@ class ProbedModeling(torch.autograd.Function):
         m, Ubar, Z = ctx.saved_tensors
         plan = ctx.plan
         res = grad_d.detach().to(plan.dtype).contiguous()
-        if plan.spec.probe in ("bf16", "bf16x2"):
+        if plan.spec.probe in ("bf16", "bf16x2", "f16s"):
             g = _adjoint_image_fused(plan, m, ctx.rec_pos, res, Z, Ubar, ctx.work)
         else:
             V = rtm_adjoint_probe(plan, m, ctx.rec_pos, res, Z=Z, work=ctx.work)["Vbar"]

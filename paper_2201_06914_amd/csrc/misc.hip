@@ -25,28 +25,30 @@ __global__ __launch_bounds__(256) void k_copy(T *__restrict__ d, const T *__rest
     d[i] = s[i];
 }
 
-// Streaming copy of n 16-byte vectors, four per thread per pass (the loads of
-// a pass are issued before its stores): the measured HBM ceiling of a
-// read-once / write-once kernel, the reference the roofline figures are set
-// against.
-__global__ __launch_bounds__(256) void k_copy_x4(float4 *__restrict__ d,
-                                                  const float4 *__restrict__ s, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const float4 a = s[i], b = s[i + stride], c = s[i + 2 * stride], e = s[i + 3 * stride];
-    d[i] = a;
-    d[i + stride] = b;
-    d[i + 2 * stride] = c;
-    d[i + 3 * stride] = e;
-  }
-  for (; i < n; i += stride) d[i] = s[i];
+// Streaming copy by 16-byte vectors: each workgroup moves four consecutive
+// runs of 256 vectors (all four loads issued before the stores), one
+// workgroup per 1024 vectors, non-temporal loads and stores (each byte is
+// touched once).  It is the measured HBM ceiling of a read-once / write-once
+// kernel, the reference the roofline figures are set against.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy_x4(f32x4 *__restrict__ d, const f32x4 *__restrict__ s,
+                                                  int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  f32x4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + 256 * k < n) v[k] = __builtin_nontemporal_load(s + base + 256 * k);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + 256 * k < n) __builtin_nontemporal_store(v[k], d + base + 256 * k);
 }
 
 hipError_t launch_copy_x4(void *d, const void *s, int64_t n16, hipStream_t st) {
   if (n16 <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_x4, dim3(2048), dim3(256), 0, st, static_cast<float4 *>(d),
-                     static_cast<const float4 *>(s), n16);
+  const int64_t nblk = (n16 + 1023) / 1024;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy_x4, dim3((unsigned)nblk), dim3(256), 0, st, static_cast<f32x4 *>(d),
+                     static_cast<const f32x4 *>(s), n16);
   return hipGetLastError();
 }
 

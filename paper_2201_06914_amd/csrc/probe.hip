@@ -8,11 +8,15 @@
 //     ((x / 32) * r + i) * 32 + x % 32,
 // so the r x 32 block of one 32-cell tile is contiguous (16 KB at r = 128).
 //
-//   k_probe_mfma  +-1 probes on MFMA: v_mfma_f32_32x32x16_bf16, FP32
-//                 accumulate.  Z (+-1) is exact in bf16; S is rounded to bf16
-//                 (plain) or split into bf16 hi + bf16 lo (two MFMAs, 16-bit
-//                 mantissa).  One wave owns one 32-cell tile and up to 128
-//                 probe rows at a time; Z sits in LDS in A-operand order.
+//   k_probe_mfma  +-1 probes on MFMA, FP32 accumulate.  Z (+-1) is exact in
+//                 bf16 and float16.  S is rounded to bf16 (plain,
+//                 v_mfma_f32_32x32x16_bf16), split into bf16 hi + bf16 lo (two
+//                 MFMAs, 16-bit mantissa), or (F16S) scaled by a power of two
+//                 per 16-step chunk and rounded to float16 (11-bit mantissa,
+//                 v_mfma_f32_32x32x16_f16), the partial product rescaled
+//                 exactly between chunks.  One wave owns one 32-cell tile and
+//                 up to 128 probe rows at a time; Z sits in LDS in A-operand
+//                 order.
 //   k_probe_vec   FP64 / FP32 FMA path (any real Z), thread per cell, 32
 //                 probe rows per pass; the accumulation order is the per-step
 //                 order bar += z_n s^n.
@@ -21,6 +25,7 @@
 namespace rtm {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 __device__ __forceinline__ int64_t bar_index(int64_t x, int i, int r) {
@@ -95,6 +100,8 @@ template hipError_t launch_probe_vec<double>(const ProbeArgs<double> &, const vo
 // ever storing Vbar.
 // Z_b^T in A-operand order: ldsA[(mt KS + ks) 64 + l] holds A[mt 32 + l % 32][ks 16 + 8 (l / 32) + 0..7]
 // with A[i][t] = Z[zrow0 + zdir t][i], zero for t >= kb or i >= r.
+// OP_F16S stores the +-1 entries as float16 (exact as well).
+template <int OP>
 __device__ __forceinline__ void fill_probe_lds(const ProbeArgs<float> &p, const int8_t *Z, int MT,
                                                int KS, bf16x8 *ldsA) {
   for (int e = threadIdx.x; e < MT * KS * 64; e += blockDim.x) {
@@ -103,14 +110,16 @@ __device__ __forceinline__ void fill_probe_lds(const ProbeArgs<float> &p, const 
     const int mt = (e >> 6) / KS;
     const int i = mt * 32 + (l & 31);
     bf16x8 v;
+    f16x8 vh;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int t = ks * 16 + 8 * (l >> 5) + q;
       float zv = 0.f;
       if (t < p.kb && i < p.r) zv = (float)Z[(int64_t)(p.zrow0 + p.zdir * t) * p.r + i];
       v[q] = (__bf16)zv;
+      vh[q] = (_Float16)zv;
     }
-    ldsA[e] = v;
+    ldsA[e] = OP == OP_F16S ? __builtin_bit_cast(bf16x8, vh) : v;
   }
   __syncthreads();
 }
@@ -141,19 +150,24 @@ __device__ __forceinline__ void fill_probe_lds_q(const ProbeArgs<float> &p, cons
   __syncthreads();
 }
 
-template <bool QF>
+template <bool QF, int OP>
 __device__ __forceinline__ void fill_a(const ProbeArgs<float> &p, const void *Z, int MT, int KS,
                                        bf16x8 *ldsA) {
   if constexpr (QF) fill_probe_lds_q(p, static_cast<const float *>(Z), MT, KS, ldsA);
-  else fill_probe_lds(p, static_cast<const int8_t *>(Z), MT, KS, ldsA);
+  else fill_probe_lds<OP>(p, static_cast<const int8_t *>(Z), MT, KS, ldsA);
 }
 
 // The B operand of step chunk ks for this lane: its 8 probed values (local
-// steps tb .. tb+7, tb = 16 ks + 8 half), rounded to bf16 (hi) and, with
-// SPLIT, the bf16 rounding of the remainder (lo).  FAST: no masking needed.
-template <int MODE, bool SPLIT, bool FAST>
+// steps tb .. tb+7, tb = 16 ks + 8 half), rounded to bf16 (hi) and, for
+// OP_BF16X2, the bf16 rounding of the remainder (lo).  OP_F16S: the chunk's
+// 16 x 32 values (the whole wave) share one power-of-two scale 2^-e with e
+// from their largest magnitude (below 2^15 after scaling, so every value is
+// in float16 range), and hi holds the float16 rounding of the scaled values;
+// e is wave-uniform.  FAST: no masking needed.
+template <int MODE, int OP, bool FAST>
 __device__ __forceinline__ void probe_operand(const ProbeArgs<float> &p, int ks, int half,
-                                              int64_t c, bool valid, bf16x8 &bhi, bf16x8 &blo) {
+                                              int64_t c, bool valid, bf16x8 &bhi, bf16x8 &blo,
+                                              int &e) {
   const int tb = ks * 16 + 8 * half;
   float sv[8];
   if (MODE == PROBE_UTT) {
@@ -178,25 +192,56 @@ __device__ __forceinline__ void probe_operand(const ProbeArgs<float> &p, int ks,
       sv[q] = ok ? ring_level(p, lev)[c] : 0.f;
     }
   }
+  if constexpr (OP == OP_F16S) {
+    float mx = 0.f;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const __bf16 hb = (__bf16)sv[q];
-    bhi[q] = hb;
-    if (SPLIT) blo[q] = (__bf16)(sv[q] - (float)hb);
+    for (int q = 0; q < 8; ++q) mx = fmaxf(mx, fabsf(sv[q]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    // mx < 2^x with x the frexp exponent: scaled by 2^-(x - 15) it stays below 2^15
+    e = mx > 0.f ? __builtin_amdgcn_frexp_expf(mx) - 15 : 0;
+    f16x8 hv;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) hv[q] = (_Float16)ldexpf(sv[q], -e);
+    bhi = __builtin_bit_cast(bf16x8, hv);
+  } else {
+    e = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const __bf16 hb = (__bf16)sv[q];
+      bhi[q] = hb;
+      if (OP == OP_BF16X2) blo[q] = (__bf16)(sv[q] - (float)hb);
+    }
+  }
+}
+
+// acc += A * B for one 16-step chunk, in the operand type of OP (QF: real
+// probes split into hi + lo A operands, B hi only)
+template <int OP, bool QF>
+__device__ __forceinline__ f32x16 chunk_mfma(const bf16x8 &a, const bf16x8 &alo, const bf16x8 &bhi,
+                                             const bf16x8 &blo, f32x16 acc) {
+  if constexpr (OP == OP_F16S) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, bhi), acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bhi, acc, 0, 0, 0);
+    if (OP == OP_BF16X2) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo, acc, 0, 0, 0);
+    if (QF) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, acc, 0, 0, 0);
+    return acc;
   }
 }
 
 // Fast kernel: full 32-cell tiles [0, tile_end), kb == 16 KS, MT % MTC == 0 -
 // no load or store is masked.  MTC row tiles (32 probes each) are accumulated
 // together, so their 16 x MTC loads per lane are in flight at once.
-template <int KS, bool SPLIT, int MODE, bool FUSED, int MTC, bool QF>
+template <int KS, int OP, int MODE, bool FUSED, int MTC, bool QF>
 __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
                                                          const void *__restrict__ Z, int MT,
                                                          const float *__restrict__ Uf,
                                                          float *__restrict__ img, float scale,
                                                          int64_t tile_end) {
   extern __shared__ bf16x8 ldsA[];
-  fill_a<QF>(p, Z, MT, KS, ldsA);
+  fill_a<QF, OP>(p, Z, MT, KS, ldsA);
   const int alo_off = MT * KS * 64;  // QF: the lo halves of A
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -210,25 +255,29 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
     // short blocks: build every step chunk's operand once per tile; long
     // blocks (KS >= 4): build each right before its MFMAs to bound registers
     constexpr bool kEarly = KS <= 2;
+    constexpr bool F16 = OP == OP_F16S;
     bf16x8 bhi_e[kEarly ? KS : 1], blo_e[kEarly ? KS : 1];
+    int e_e[kEarly ? KS : 1];
     if (kEarly) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
-        probe_operand<MODE, SPLIT, true>(p, ks, half, c, true, bhi_e[kEarly ? ks : 0],
-                                         blo_e[kEarly ? ks : 0]);
+        probe_operand<MODE, OP, true>(p, ks, half, c, true, bhi_e[kEarly ? ks : 0],
+                                      blo_e[kEarly ? ks : 0], e_e[kEarly ? ks : 0]);
     }
     float part = 0.f;
     for (int mt0 = 0; mt0 < MT; mt0 += MTC) {
       f32x16 acc[MTC];
-      float uf[FUSED ? MTC : 1][16];
-      if (FUSED) {  // issue the forward-field loads before the MFMAs
-        const float *Ut = Uf + tbase + mt0 * 32 * 32 + loff;
+      // FUSED: the forward field; F16S (not fused): the old Ubar, added once
+      // the block's product is back in absolute units
+      float uf[(FUSED || F16) ? MTC : 1][16];
+      if (FUSED || F16) {  // issue these loads before the MFMAs
+        const float *Ut = (FUSED ? Uf : p.bar) + tbase + mt0 * 32 * 32 + loff;
 #pragma unroll
         for (int j = 0; j < MTC; ++j)
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             acc[j][v] = 0.f;
-            uf[FUSED ? j : 0][v] = Ut[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32];
+            uf[(FUSED || F16) ? j : 0][v] = Ut[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32];
           }
       } else {
         const float *Ut = p.bar + tbase + mt0 * 32 * 32 + loff;
@@ -237,31 +286,54 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
 #pragma unroll
           for (int v = 0; v < 16; ++v) acc[j][v] = Ut[(j * 32 + 8 * (v >> 2) + (v & 3)) * 32];
       }
+      int ecur = 0;  // F16S: acc holds the block's partial product in units of 2^ecur
+      // step chunks in groups of at most four, the groups in a rolled loop:
+      // an 8-chunk block (k = 128) then needs the registers of a 4-chunk one
+      constexpr int KSB = KS < 4 ? KS : 4;
+#pragma unroll 1
+      for (int ks0 = 0; ks0 < KS; ks0 += KSB) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        bf16x8 bhi, blo;
-        if (kEarly) {
-          bhi = bhi_e[kEarly ? ks : 0];
-          blo = blo_e[kEarly ? ks : 0];
-        } else {
-          __builtin_amdgcn_sched_barrier(0);
-          probe_operand<MODE, SPLIT, true>(p, ks, half, c, true, bhi, blo);
-        }
+        for (int kk = 0; kk < KSB; ++kk) {
+          const int ks = kEarly ? kk : ks0 + kk;
+          bf16x8 bhi, blo;
+          int eks;
+          if (kEarly) {
+            bhi = bhi_e[kEarly ? kk : 0];
+            blo = blo_e[kEarly ? kk : 0];
+            eks = e_e[kEarly ? kk : 0];
+          } else {
+            __builtin_amdgcn_sched_barrier(0);
+            probe_operand<MODE, OP, true>(p, ks, half, c, true, bhi, blo, eks);
+          }
+          if (F16) {  // move the partial product to this chunk's units (exact)
 #pragma unroll
-        for (int j = 0; j < MTC; ++j) {
-          const int ai = ((mt0 + j) * KS + ks) * 64 + lane;
-          const bf16x8 a = ldsA[ai];
-          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bhi, acc[j], 0, 0, 0);
-          if (SPLIT) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo, acc[j], 0, 0, 0);
-          if (QF)
-            acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ldsA[alo_off + ai], bhi, acc[j], 0, 0, 0);
+            for (int j = 0; j < MTC; ++j)
+#pragma unroll
+              for (int v = 0; v < 16; ++v) acc[j][v] = ldexpf(acc[j][v], ecur - eks);
+            ecur = eks;
+          }
+#pragma unroll
+          for (int j = 0; j < MTC; ++j) {
+            const int ai = ((mt0 + j) * KS + ks) * 64 + lane;
+            acc[j] = chunk_mfma<OP, QF>(ldsA[ai], QF ? ldsA[alo_off + ai] : ldsA[ai], bhi, blo,
+                                        acc[j]);
+          }
         }
+      }
+      if (F16) {
+#pragma unroll
+        for (int j = 0; j < MTC; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            acc[j][v] = ldexpf(acc[j][v], ecur);
+            if (!FUSED) acc[j][v] += uf[(FUSED || F16) ? j : 0][v];
+          }
       }
       if (FUSED) {
 #pragma unroll
         for (int j = 0; j < MTC; ++j)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) part += uf[FUSED ? j : 0][v] * acc[j][v];
+          for (int v = 0; v < 16; ++v) part += uf[(FUSED || F16) ? j : 0][v] * acc[j][v];
       } else {
         float *Uo = p.bar + tbase + mt0 * 32 * 32 + loff;
 #pragma unroll
@@ -279,14 +351,15 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
 
 // Edge kernel: tiles [tile_begin, ntiles) with any masking (ragged last tile,
 // a block shorter than 16 KS, r not a multiple of 32).  One row tile at a time.
-template <int KS, bool SPLIT, int MODE, bool FUSED, bool QF>
+template <int KS, int OP, int MODE, bool FUSED, bool QF>
 __global__ __launch_bounds__(256) void k_probe_mfma_edge(ProbeArgs<float> p,
                                                          const void *__restrict__ Z, int MT,
                                                          const float *__restrict__ Uf,
                                                          float *__restrict__ img, float scale,
                                                          int64_t tile_begin) {
+  constexpr bool F16 = OP == OP_F16S;
   extern __shared__ bf16x8 ldsA[];
-  fill_a<QF>(p, Z, MT, KS, ldsA);
+  fill_a<QF, OP>(p, Z, MT, KS, ldsA);
   const int alo_off = MT * KS * 64;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -300,9 +373,10 @@ __global__ __launch_bounds__(256) void k_probe_mfma_edge(ProbeArgs<float> p,
     const bool valid = c < p.N;
     const int64_t tbase = tile * (int64_t)p.r * 32;
     bf16x8 bhi[KS], blo[KS];
+    int eks[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
-      probe_operand<MODE, SPLIT, false>(p, ks, half, c, valid, bhi[ks], blo[ks]);
+      probe_operand<MODE, OP, false>(p, ks, half, c, valid, bhi[ks], blo[ks], eks[ks]);
     float part = 0.f;
     for (int mt = 0; mt < MT; ++mt) {
       const float *Ut = (FUSED ? Uf : p.bar) + tbase + mt * 32 * 32 + loff;
@@ -313,16 +387,27 @@ __global__ __launch_bounds__(256) void k_probe_mfma_edge(ProbeArgs<float> p,
         const int rr = 8 * (v >> 2) + (v & 3);
         const bool ok = valid && mt * 32 + rr + 4 * half < p.r;
         const float val = ok ? Ut[rr * 32] : 0.f;
-        acc[v] = FUSED ? 0.f : val;
+        acc[v] = (FUSED || F16) ? 0.f : val;
         uf[v] = val;
       }
+      int ecur = 0;  // F16S: units 2^ecur of the block's partial product
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
+        if (F16) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[v] = ldexpf(acc[v], ecur - eks[ks]);
+          ecur = eks[ks];
+        }
         const int ai = (mt * KS + ks) * 64 + lane;
-        const bf16x8 a = ldsA[ai];
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bhi[ks], acc, 0, 0, 0);
-        if (SPLIT) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, blo[ks], acc, 0, 0, 0);
-        if (QF) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ldsA[alo_off + ai], bhi[ks], acc, 0, 0, 0);
+        acc = chunk_mfma<OP, QF>(ldsA[ai], QF ? ldsA[alo_off + ai] : ldsA[ai], bhi[ks], blo[ks],
+                                 acc);
+      }
+      if (F16) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          acc[v] = ldexpf(acc[v], ecur);
+          if (!FUSED) acc[v] += uf[v];
+        }
       }
       float *Uo = p.bar + tbase + mt * 32 * 32 + loff;
 #pragma unroll
@@ -347,7 +432,7 @@ struct FuseArgs {
   float scale = 0.f;
 };
 
-template <int KS, bool SPLIT, int MODE, bool FUSED, bool QF>
+template <int KS, int OP, int MODE, bool FUSED, bool QF>
 static void launch_probe_kernels(const ProbeArgs<float> &p, const void *Z, int MT,
                                  const FuseArgs &f, hipStream_t st) {
   const size_t shm = sizeof(bf16x8) * (size_t)MT * KS * 64 * (QF ? 2 : 1);
@@ -361,56 +446,59 @@ static void launch_probe_kernels(const ProbeArgs<float> &p, const void *Z, int M
   const bool fastk = p.kb == 16 * KS && p.r % 32 == 0;
   int64_t done = 0;
   if (fastk && nfull > 0 && MT % 4 == 0 && !FUSED) {
-    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 4, QF>), dim3(grid_for(nfull)),
+    hipLaunchKernelGGL((k_probe_mfma_fast<KS, OP, MODE, FUSED, 4, QF>), dim3(grid_for(nfull)),
                        dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
     done = nfull;
   } else if (fastk && nfull > 0 && MT % 2 == 0) {
-    hipLaunchKernelGGL((k_probe_mfma_fast<KS, SPLIT, MODE, FUSED, 2, QF>), dim3(grid_for(nfull)),
+    hipLaunchKernelGGL((k_probe_mfma_fast<KS, OP, MODE, FUSED, 2, QF>), dim3(grid_for(nfull)),
                        dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
     done = nfull;
   }
   if (done < ntiles)
-    hipLaunchKernelGGL((k_probe_mfma_edge<KS, SPLIT, MODE, FUSED, QF>), dim3(grid_for(ntiles - done)),
+    hipLaunchKernelGGL((k_probe_mfma_edge<KS, OP, MODE, FUSED, QF>), dim3(grid_for(ntiles - done)),
                        dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, done);
 }
 
-template <int KS, bool SPLIT, bool QF>
+template <int KS, int OP, bool QF>
 static void launch_mfma_mode(const ProbeArgs<float> &p, const void *Z, int MT,
                              const FuseArgs &f, hipStream_t st) {
   if (f.img) {  // fused imaging: adjoint levels only
-    launch_probe_kernels<KS, SPLIT, PROBE_NEW, true, QF>(p, Z, MT, f, st);
+    launch_probe_kernels<KS, OP, PROBE_NEW, true, QF>(p, Z, MT, f, st);
     return;
   }
   switch (p.mode) {
-    case PROBE_UTT: launch_probe_kernels<KS, SPLIT, PROBE_UTT, false, QF>(p, Z, MT, f, st); break;
-    case PROBE_NEW: launch_probe_kernels<KS, SPLIT, PROBE_NEW, false, QF>(p, Z, MT, f, st); break;
-    default: launch_probe_kernels<KS, SPLIT, PROBE_CUR, false, QF>(p, Z, MT, f, st);
+    case PROBE_UTT: launch_probe_kernels<KS, OP, PROBE_UTT, false, QF>(p, Z, MT, f, st); break;
+    case PROBE_NEW: launch_probe_kernels<KS, OP, PROBE_NEW, false, QF>(p, Z, MT, f, st); break;
+    default: launch_probe_kernels<KS, OP, PROBE_CUR, false, QF>(p, Z, MT, f, st);
   }
 }
 
 template <int KS>
-static void launch_mfma_ks(const ProbeArgs<float> &p, const void *Z, bool zf32, bool split,
+static void launch_mfma_ks(const ProbeArgs<float> &p, const void *Z, bool zf32, int op,
                            int MT, const FuseArgs &f, hipStream_t st) {
   if (zf32)
-    launch_mfma_mode<KS, true, true>(p, Z, MT, f, st);
-  else if (split)
-    launch_mfma_mode<KS, true, false>(p, Z, MT, f, st);
+    launch_mfma_mode<KS, OP_BF16X2, true>(p, Z, MT, f, st);
+  else if (op == OP_BF16X2)
+    launch_mfma_mode<KS, OP_BF16X2, false>(p, Z, MT, f, st);
+  else if (op == OP_F16S)
+    launch_mfma_mode<KS, OP_F16S, false>(p, Z, MT, f, st);
   else
-    launch_mfma_mode<KS, false, false>(p, Z, MT, f, st);
+    launch_mfma_mode<KS, OP_BF16, false>(p, Z, MT, f, st);
 }
 
-hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const void *Z, bool zf32, bool split,
+// op: OP_BF16, OP_BF16X2 or OP_F16S; real probes (zf32) need OP_BF16X2
+hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const void *Z, bool zf32, int op,
                              const float *Uf, float *img, float scale, hipStream_t st) {
   const FuseArgs f{Uf, img, scale};
   const int MT = (p.r + 31) / 32;
   int KS = (p.kb + 15) / 16;
   KS = KS <= 1 ? 1 : KS <= 2 ? 2 : KS <= 4 ? 4 : 8;
-  if (p.kb > 128 || (zf32 && !split)) return hipErrorInvalidValue;
+  if (p.kb > 128 || (zf32 && op != OP_BF16X2)) return hipErrorInvalidValue;
   switch (KS) {
-    case 1: launch_mfma_ks<1>(p, Z, zf32, split, MT, f, st); break;
-    case 2: launch_mfma_ks<2>(p, Z, zf32, split, MT, f, st); break;
-    case 4: launch_mfma_ks<4>(p, Z, zf32, split, MT, f, st); break;
-    default: launch_mfma_ks<8>(p, Z, zf32, split, MT, f, st); break;
+    case 1: launch_mfma_ks<1>(p, Z, zf32, op, MT, f, st); break;
+    case 2: launch_mfma_ks<2>(p, Z, zf32, op, MT, f, st); break;
+    case 4: launch_mfma_ks<4>(p, Z, zf32, op, MT, f, st); break;
+    default: launch_mfma_ks<8>(p, Z, zf32, op, MT, f, st); break;
   }
   return hipGetLastError();
 }

@@ -34,6 +34,7 @@ static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled va
 static int g_stencil_blocks = 2048; // tiled stencil: split z until this many workgroups
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
 static int g_tti_shape = 7;         // tiled TTI tile shape (1..8)
+static int g_stencil_alternate = 1; // sweeps: tiled stencil marches z up / down on alternate steps
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
@@ -121,6 +122,14 @@ struct rtm_plan {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// the probe dtypes that run on the MFMA path, and their operand kind
+static bool mfma_probe(rtm_dtype pd) {
+  return pd == RTM_BF16 || pd == RTM_BF16X2 || pd == RTM_F16S;
+}
+static int probe_op(rtm_dtype pd) {
+  return pd == RTM_BF16X2 ? OP_BF16X2 : pd == RTM_F16S ? OP_F16S : OP_BF16;
+}
+
 static void place(size_t &cur, Region &r, size_t bytes) {
   r.off = cur;
   r.bytes = bytes;
@@ -180,6 +189,7 @@ extern "C" void rtm_set_stencil_variant(int v) {
 }
 
 extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
+extern "C" void rtm_set_stencil_alternate(int32_t on) { g_stencil_alternate = on ? 1 : 0; }
 
 extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 8) ? shape : 7; }
 
@@ -243,16 +253,15 @@ extern "C" rtm_status rtm_plan_create(const rtm_desc *desc, rtm_plan **out) {
     return fail(RTM_E_DTYPE, "field dtype must be F64 or F32");
   if (d.field_dtype == RTM_F64 && d.probe_dtype != RTM_F64)
     return fail(RTM_E_DTYPE, "F64 fields need the F64 probe path");
-  if (d.field_dtype == RTM_F32 && d.probe_dtype != RTM_F32 && d.probe_dtype != RTM_BF16 &&
-      d.probe_dtype != RTM_BF16X2)
-    return fail(RTM_E_DTYPE, "F32 fields need an F32, BF16 or BF16X2 probe path");
+  if (d.field_dtype == RTM_F32 && d.probe_dtype != RTM_F32 && !mfma_probe(d.probe_dtype))
+    return fail(RTM_E_DTYPE, "F32 fields need an F32, BF16, BF16X2 or F16S probe path");
   if (d.r < 1 || d.r > 1024) return fail(RTM_E_ARG, "r must be in 1..1024");
   if (d.k_block < 1 || d.k_block > 256) return fail(RTM_E_ARG, "k_block must be in 1..256");
-  if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
+  if (mfma_probe(d.probe_dtype)) {
     const int ks = (d.k_block + 15) / 16;
     const int ksp = ks <= 1 ? 1 : ks <= 2 ? 2 : ks <= 4 ? 4 : 8;
     if (d.k_block > 128 || ((d.r + 31) / 32) * ksp > 64)
-      return fail(RTM_E_UNSUPPORTED, "BF16 probe path needs k_block <= 128 and ceil(r/32)*ceil(k/16) <= 64");
+      return fail(RTM_E_UNSUPPORTED, "the MFMA probe path needs k_block <= 128 and ceil(r/32)*ceil(k/16) <= 64");
   }
   if (d.nsrc < 0 || d.nrec < 0) return fail(RTM_E_ARG, "point counts must be >= 0");
 
@@ -502,7 +511,8 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
     a.next = level(s + 1);
     TimedLaunch tl;
     prof_begin(KT_STENCIL, s, st, &tl);
-    HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
+    HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st,
+                              g_stencil_alternate ? (s & 1) : 0));
     prof_end(st, &tl);
     if (inj.ncell > 0 && inj_vals)
       HIP_TRY(launch_inject<T>(a, inj, inj_vals + (int64_t)n * inj.npts, a.next, st));
@@ -536,8 +546,8 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       TimedLaunch tp;
       prof_begin(io.adjoint ? KT_PROBE_ADJ : KT_PROBE, s, st, &tp);
       if constexpr (sizeof(T) == 4) {
-        if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
-          HIP_TRY(launch_probe_mfma(p, io.Z, io.zt == RTM_F32, d.probe_dtype == RTM_BF16X2,
+        if (mfma_probe(d.probe_dtype)) {
+          HIP_TRY(launch_probe_mfma(p, io.Z, io.zt == RTM_F32, probe_op(d.probe_dtype),
                                     static_cast<const float *>(io.fuse_U),
                                     static_cast<float *>(io.fuse_img), (float)io.fuse_scale, st));
         } else {
@@ -579,8 +589,9 @@ static rtm_status check_probe(const rtm_plan *P, const void *Z, rtm_dtype zt, co
     return fail(RTM_E_ARG, "Z and the compressed field must both be given or both be NULL");
   if (!Z) return RTM_OK;
   const rtm_dtype pd = P->d.probe_dtype;
-  if (pd == RTM_BF16) {
-    if (zt != RTM_I8) return fail(RTM_E_DTYPE, "the BF16 probe path needs +-1 probes (RTM_I8)");
+  if (pd == RTM_BF16 || pd == RTM_F16S) {
+    if (zt != RTM_I8)
+      return fail(RTM_E_DTYPE, "the BF16 and F16S probe paths need +-1 probes (RTM_I8)");
   } else if (pd == RTM_BF16X2) {
     if (zt != RTM_I8 && zt != RTM_F32)
       return fail(RTM_E_DTYPE, "the BF16X2 probe path takes RTM_I8 (+-1) or RTM_F32 probes");
@@ -730,7 +741,7 @@ extern "C" rtm_status rtm_adjoint_image(const rtm_plan *P, const void *m, const 
   if (s) return s;
   if (P->d.nrec > 0 && (!rec_pos || !res)) return fail(RTM_E_ARG, "rec_pos and res are required");
   if (!Z || !Ubar || !image) return fail(RTM_E_ARG, "Z, Ubar and image are required");
-  if (P->d.probe_dtype != RTM_BF16 && P->d.probe_dtype != RTM_BF16X2)
+  if (!mfma_probe(P->d.probe_dtype))
     return fail(RTM_E_UNSUPPORTED, "fused adjoint imaging needs a BF16 probe path");
   if ((s = check_probe(P, Z, zt, Ubar))) return s;
   return adjoint_image_impl<float>(P, m, rec_pos, res, Z, zt, Ubar, scale, image, work,
@@ -798,6 +809,27 @@ extern "C" rtm_status rtm_bar_to_rows(const rtm_plan *P, const void *bar, void *
   else
     HIP_TRY(launch_bar_to_rows<float>(static_cast<const float *>(bar), P->N, P->d.r,
                                       static_cast<float *>(rows), st));
+  return RTM_OK;
+}
+
+extern "C" rtm_status rtm_residual(const rtm_plan *P, const void *d_pred, const void *d_obs,
+                                   void *resid, double *misfit, void *work, size_t work_bytes,
+                                   rtm_stream stream) {
+  g_last_error.clear();
+  if (!P || !d_pred || !d_obs || !resid || !misfit || !work) return fail(RTM_E_ARG, "NULL argument");
+  if (work_bytes < P->total) return fail(RTM_E_WORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(RTM_E_ARG, "work must be 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  double *part = reinterpret_cast<double *>(static_cast<char *>(work) + P->red.off);
+  const int64_t nd = (int64_t)P->d.nt * P->d.nrec;
+  if (P->d.field_dtype == RTM_F64)
+    HIP_TRY(launch_residual_misfit<double>(static_cast<const double *>(d_pred),
+                                           static_cast<const double *>(d_obs),
+                                           static_cast<double *>(resid), nd, part, misfit, st));
+  else
+    HIP_TRY(launch_residual_misfit<float>(static_cast<const float *>(d_pred),
+                                          static_cast<const float *>(d_obs),
+                                          static_cast<float *>(resid), nd, part, misfit, st));
   return RTM_OK;
 }
 
@@ -888,8 +920,8 @@ extern "C" rtm_status fwi_gradient(const rtm_plan *P, const void *m, const doubl
   if (s) return s;
   if (!src_pos || !q || !rec_pos || !d_obs || !Z || !Ubar || !resid || !grad || !misfit)
     return fail(RTM_E_ARG, "fwi_gradient needs every array except Vbar");
-  if (!Vbar && P->d.probe_dtype != RTM_BF16 && P->d.probe_dtype != RTM_BF16X2)
-    return fail(RTM_E_UNSUPPORTED, "fused imaging (Vbar = NULL) needs a BF16 probe path");
+  if (!Vbar && !mfma_probe(P->d.probe_dtype))
+    return fail(RTM_E_UNSUPPORTED, "fused imaging (Vbar = NULL) needs an MFMA probe path (BF16, BF16X2 or F16S)");
   if ((s = check_probe(P, Z, zt, Ubar))) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (P->d.field_dtype == RTM_F64)
@@ -1205,15 +1237,19 @@ static rtm_status autotune_impl(const rtm_plan *P, const void *mv, char *w, int 
   const int last = P->d.ndim == 3 ? kStencilVariants : kStencilSimple;
   rtm_status status = RTM_OK;
   for (int v = kStencilSimple; v <= last && status == RTM_OK; ++v) {
+    // both z-marching directions against the one-thread-per-cell step
     unsigned long long diff = 0;
     hipError_t e = launch_fill<double>(reinterpret_cast<double *>(cnt), 1, 0.0, st);
-    if (e == hipSuccess) e = launch_stencil<T>(P->d.ndim, a, v, g_stencil_blocks, st);
-    if (e == hipSuccess) e = launch_count_diff<T>(s2, s3, N, cnt, st);
+    for (int rev = 0; rev < 2 && e == hipSuccess; ++rev) {
+      e = launch_stencil<T>(P->d.ndim, a, v, g_stencil_blocks, st, rev);
+      if (e == hipSuccess) e = launch_count_diff<T>(s2, s3, N, cnt, st);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(&diff, cnt, sizeof diff, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipEventRecord(e0, st);
     for (int i = 0; i < steps && e == hipSuccess; ++i)
-      e = launch_stencil<T>(P->d.ndim, a, v, g_stencil_blocks, st);
+      e = launch_stencil<T>(P->d.ndim, a, v, g_stencil_blocks, st,
+                            g_stencil_alternate ? (i & 1) : 0);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1262,7 +1298,7 @@ struct rtm_batch {
   int ns = 0;
   std::vector<rtm_plan *> P;
   std::vector<size_t> ring_off;
-  Region red, shots, io_fwd, io_adj, tiles;
+  Region red, status, shots, io_fwd, io_adj, tiles;
   BatchPointRegion src, rec;
   size_t tab_off = 0, tab_bytes = 0, total = 0;
   std::vector<int4> tile_host;
@@ -1301,8 +1337,8 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
   for (int i = 0; i < nshots; ++i) {
     const rtm_desc &d = shots[i];
     if (d.ndim != 3 || d.field_dtype != RTM_F32 ||
-        (d.probe_dtype != RTM_BF16 && d.probe_dtype != RTM_BF16X2))
-      return fail(RTM_E_UNSUPPORTED, "batched shots are 3D, F32 fields, BF16 / BF16X2 probes");
+        !mfma_probe(d.probe_dtype))
+      return fail(RTM_E_UNSUPPORTED, "batched shots are 3D, F32 fields, BF16 / BF16X2 / F16S probes");
     if (d.nt != d0.nt || d.dt != d0.dt || d.h != d0.h || d.r != d0.r ||
         d.k_block != d0.k_block || d.probe_dtype != d0.probe_dtype)
       return fail(RTM_E_ARG, "shot %d: nt, dt, h, r, k_block and probe dtype must agree", i);
@@ -1358,6 +1394,7 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
     cur = align256(cur + (size_t)p->R * p->ld * 4);
   }
   place(cur, b->red, sizeof(double) * (kReduceBlocks + 8) * nshots);
+  place(cur, b->status, sizeof(uint32_t));
   b->tab_off = cur;
   place(cur, b->shots, sizeof(ShotStep<float>) * nshots);
   place(cur, b->io_fwd, sizeof(ShotIO<float>) * nshots);
@@ -1485,7 +1522,7 @@ static rtm_status batch_enqueue(const rtm_batch *b, const rtm_shot_io *io, doubl
       p.bar = adj ? nullptr : static_cast<float *>(io[i].Ubar);
       p.inv_dt2 = (float)(1.0 / (d.dt * d.dt));
       p.mode = adj ? PROBE_NEW : PROBE_UTT;
-      HIP_TRY(launch_probe_mfma(p, io[i].Z, false, d.probe_dtype == RTM_BF16X2,
+      HIP_TRY(launch_probe_mfma(p, io[i].Z, false, probe_op(d.probe_dtype),
                                 adj ? static_cast<const float *>(io[i].Ubar) : nullptr,
                                 adj ? static_cast<float *>(io[i].grad) : nullptr,
                                 (float)(-1.0 / d.r), st));
@@ -1493,6 +1530,8 @@ static rtm_status batch_enqueue(const rtm_batch *b, const rtm_shot_io *io, doubl
     return RTM_OK;
   };
   rtm_status s_;
+  uint32_t *status = reinterpret_cast<uint32_t *>(w + b->status.off);
+  HIP_TRY(launch_status_clear(status, st));
   // forward
   for (int i = 0; i < b->ns; ++i) {
     HIP_TRY(launch_fill<float>(lvl(i, -1), b->P[i]->N, 0.f, st));
@@ -1501,7 +1540,8 @@ static rtm_status batch_enqueue(const rtm_batch *b, const rtm_shot_io *io, doubl
   }
   int s0 = 0;
   for (int s = 0; s < nt; ++s) {
-    HIP_TRY(launch_stencil_batched<float>(shots, tiles, ntiles, s, variant, st));
+    HIP_TRY(launch_stencil_batched<float>(shots, tiles, ntiles, s, variant, st,
+                                          g_stencil_alternate ? (s & 1) : 0));
     HIP_TRY(launch_inject_batched<float>(shots, iof, src_t, s, s, st));
     HIP_TRY(launch_sample_batched<float>(shots, iof, rec_t, s, s, st));
     if (s + 1 - s0 == k || s == nt - 1) {
@@ -1524,13 +1564,36 @@ static rtm_status batch_enqueue(const rtm_batch *b, const rtm_shot_io *io, doubl
   }
   s0 = 0;
   for (int s = 0; s < nt; ++s) {
-    HIP_TRY(launch_stencil_batched<float>(shots, tiles, ntiles, s, variant, st));
+    HIP_TRY(launch_stencil_batched<float>(shots, tiles, ntiles, s, variant, st,
+                                          g_stencil_alternate ? (s & 1) : 0));
     HIP_TRY(launch_inject_batched<float>(shots, ioa, rec_t, s, nt - 1 - s, st));
     if (s + 1 - s0 == k || s == nt - 1) {
       if ((s_ = probe(true, s0, s + 1 - s0))) return s_;
       s0 = s + 1;
     }
   }
+  // non-finite watch: each shot's last adjoint level, its gradient (a stacked
+  // buffer is scanned once per shot that shares it) and its misfit
+  for (int i = 0; i < b->ns; ++i) {
+    HIP_TRY(launch_flag_nonfinite<float>(lvl(i, nt), b->P[i]->N, status, st));
+    HIP_TRY(launch_flag_nonfinite<float>(static_cast<const float *>(io[i].grad), b->P[i]->N,
+                                         status, st));
+    HIP_TRY(launch_flag_nonfinite<double>(misfit + i, 1, status, st));
+  }
+  return RTM_OK;
+}
+
+extern "C" rtm_status rtm_batch_stream_status(const rtm_batch *b, const void *work,
+                                              rtm_stream stream) {
+  g_last_error.clear();
+  if (!b || !work) return fail(RTM_E_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(RTM_E_ARG, "work must be 256-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  uint32_t word = 0;
+  HIP_TRY(hipMemcpyAsync(&word, static_cast<const char *>(work) + b->status.off, sizeof(word),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (word) return fail(RTM_E_NONFINITE, "a non-finite value reached a shot's wavefield or outputs");
   return RTM_OK;
 }
 
@@ -1547,6 +1610,19 @@ extern "C" rtm_status fwi_gradient_batched(rtm_batch *b, const rtm_shot_io *io, 
     if (!x.m || !x.Z || !x.Ubar || !x.grad || !x.d_obs || !x.resid ||
         (b->P[i]->d.nsrc > 0 && (!x.q || !x.src_pos)) || (b->P[i]->d.nrec > 0 && !x.rec_pos))
       return fail(RTM_E_ARG, "shot %d: missing array", i);
+    // stacking: shots may share one gradient buffer when their grids agree;
+    // no gradient buffer may be another shot's input or output array
+    for (int j = 0; j < b->ns; ++j) {
+      const rtm_shot_io &y = io[j];
+      const rtm_desc &di = b->P[i]->d, &dj = b->P[j]->d;
+      if (j != i && x.grad == y.grad &&
+          (di.nz != dj.nz || di.ny != dj.ny || di.nx != dj.nx))
+        return fail(RTM_E_ARG, "shots %d and %d share a gradient buffer but not a grid", i, j);
+      if (x.grad == y.Ubar || x.grad == y.resid || x.grad == y.m || x.grad == y.d_obs ||
+          x.grad == y.q)
+        return fail(RTM_E_ARG, "shot %d: the gradient buffer is also an input or output of "
+                               "shot %d", i, j);
+    }
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(work);
@@ -1584,6 +1660,7 @@ extern "C" rtm_status fwi_gradient_batched(rtm_batch *b, const rtm_shot_io *io, 
   if ((s = stage_batch_points(b, b->rec, io, true, host, &rnp, &rnc, &key))) return s;
   int variant = g_stencil_variant >= kStencilTiled ? g_stencil_variant : 7;
   key = (key ^ (uint64_t)variant) * 1099511628211ull;
+  key = (key ^ (uint64_t)(g_stencil_alternate + 64)) * 1099511628211ull;
   HIP_TRY(hipMemcpyAsync(w + b->tab_off, host.data(), b->tab_bytes, hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   BatchPoints<float> src_t = batch_points(b->src, w, snp, snc);
@@ -1708,9 +1785,9 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
         p.inv_dt2 = (T)(1.0 / (d.dt * d.dt));
         p.mode = io.adjoint ? PROBE_NEW : PROBE_UTT;
         if constexpr (sizeof(T) == 4) {
-          if (d.probe_dtype == RTM_BF16 || d.probe_dtype == RTM_BF16X2) {
+          if (mfma_probe(d.probe_dtype)) {
             const float *Uf = io.fuse_img ? static_cast<const float *>(io.fuse_U) + f * barn : nullptr;
-            HIP_TRY(launch_probe_mfma(p, io.Z, io.zt == RTM_F32, d.probe_dtype == RTM_BF16X2, Uf,
+            HIP_TRY(launch_probe_mfma(p, io.Z, io.zt == RTM_F32, probe_op(d.probe_dtype), Uf,
                                       static_cast<float *>(io.fuse_img), (float)io.fuse_scale, st));
             continue;
           }
@@ -1734,6 +1811,34 @@ static rtm_status check_tti(const rtm_plan *P, const void *m, const void *aniso,
   if (work_bytes < P->total + tti_extra_bytes(P))
     return fail(RTM_E_WORKSPACE, "work has %zu bytes, TTI needs %zu", work_bytes,
                 P->total + tti_extra_bytes(P));
+  return RTM_OK;
+}
+
+// Stability screen of the model before a TTI sweep (one read of m, eps and
+// delta into the reduction partials, then a synchronising copy of two
+// numbers): the plan's c_max must cover max v sqrt(max(1, 1 + 2 eps)) over
+// the cells (the frozen-coefficient bound of the coupled system; see
+// k_tti_screen), and every cell needs delta <= eps with eps, delta > -1/2.
+// Nothing the caller sees is written before it passes.
+static rtm_status screen_tti(const rtm_plan *P, const void *m, const void *aniso, void *work,
+                             hipStream_t st) {
+  double *part = reinterpret_cast<double *>(static_cast<char *>(work) + P->red.off);
+  if (P->d.field_dtype == RTM_F64)
+    HIP_TRY(launch_tti_screen<double>(static_cast<const double *>(m),
+                                      static_cast<const double *>(aniso), P->N, part, st));
+  else
+    HIP_TRY(launch_tti_screen<float>(static_cast<const float *>(m),
+                                     static_cast<const float *>(aniso), P->N, part, st));
+  double out[2] = {0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(out, part + 1024, sizeof out, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (out[1] > 0.0)
+    return fail(RTM_E_ARG, "TTI model: %.0f cells have delta > eps or eps, delta <= -1/2 "
+                           "(the coupled system needs delta <= eps)", out[1]);
+  const double c = std::sqrt(out[0]);
+  if (c > P->d.c_max * (1.0 + 1e-6))
+    return fail(RTM_E_CFL, "TTI model: the largest v sqrt(max(1, 1 + 2 eps)) is %.3f m/s, above "
+                           "the plan's c_max %.3f m/s (its CFL check used c_max)", c, P->d.c_max);
   return RTM_OK;
 }
 
@@ -1768,6 +1873,7 @@ extern "C" rtm_status rtm_tti_forward_probe(const rtm_plan *P, const void *m, co
   if (d_pred && P->d.nrec > 0 && !rec_pos) return fail(RTM_E_ARG, "rec_pos is required");
   if ((s = check_probe(P, Z, zt, Ubar))) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((s = screen_tti(P, m, aniso, work, st))) return s;
   if (P->d.field_dtype == RTM_F64)
     return tti_fwd_impl<double>(P, m, aniso, src_pos, q, rec_pos, d_pred, Z, zt, Ubar, work, st);
   return tti_fwd_impl<float>(P, m, aniso, src_pos, q, rec_pos, d_pred, Z, zt, Ubar, work, st);
@@ -1805,6 +1911,7 @@ extern "C" rtm_status rtm_tti_adjoint_probe(const rtm_plan *P, const void *m, co
   if (qadj && P->d.nsrc > 0 && !src_pos) return fail(RTM_E_ARG, "src_pos is required with qadj");
   if ((s = check_probe(P, Z, zt, Vbar))) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((s = screen_tti(P, m, aniso, work, st))) return s;
   if (P->d.field_dtype == RTM_F64)
     return tti_adj_impl<double>(P, m, aniso, rec_pos, res, src_pos, qadj, Z, zt, Vbar, work, st);
   return tti_adj_impl<float>(P, m, aniso, rec_pos, res, src_pos, qadj, Z, zt, Vbar, work, st);
@@ -1863,6 +1970,43 @@ static rtm_status tti_grad_impl(const rtm_plan *P, const void *m, const void *an
   return RTM_OK;
 }
 
+template <typename T>
+static rtm_status tti_rho_impl(const rtm_plan *P, const void *m, const void *aniso, int iters,
+                               uint64_t seed, double *rho, char *w, hipStream_t st) {
+  const int64_t N = P->N, ld = P->ld;
+  T *ringP = reinterpret_cast<T *>(w + P->ring.off);
+  T *ringQ = reinterpret_cast<T *>(w + P->total);
+  T *coef = ringQ + (int64_t)P->R * ld;
+  T *g = coef + 5 * ld;
+  const int shape = (g_stencil_variant == kStencilSimple || ld * (int64_t)sizeof(T) >= (1LL << 32))
+                        ? 0 : g_tti_shape;
+  StepArgs<T> a = step_args<T>(P, static_cast<const T *>(m));
+  HIP_TRY(launch_tti_coef<T>(static_cast<const T *>(aniso), N, coef, st));
+  double *part = reinterpret_cast<double *>(w + P->red.off);
+  HIP_TRY(tti_power_iteration<T>(a, P->d.h, P->d.dt, coef, ringP, ringQ, ringP + ld, ringQ + ld,
+                                 ringP + 2 * ld, ringQ + 2 * ld, g, shape, g_stencil_blocks, iters,
+                                 (uint32_t)(seed ^ (seed >> 32)), part, st));
+  double w2 = 0.0;
+  HIP_TRY(hipMemcpyAsync(&w2, part + 1024, sizeof w2, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *rho = std::sqrt(w2);
+  return RTM_OK;
+}
+
+extern "C" rtm_status rtm_tti_spectral_radius(const rtm_plan *P, const void *m, const void *aniso,
+                                              int32_t iters, uint64_t seed, double *rho,
+                                              void *work, size_t work_bytes, rtm_stream stream) {
+  rtm_status s = check_tti(P, m, aniso, work, work_bytes);
+  if (s) return s;
+  if (!rho) return fail(RTM_E_ARG, "rho is NULL");
+  if (iters < 1 || iters > 1000000) return fail(RTM_E_ARG, "iters must be in 1..10^6");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(work);
+  if (P->d.field_dtype == RTM_F64)
+    return tti_rho_impl<double>(P, m, aniso, iters, seed, rho, w, st);
+  return tti_rho_impl<float>(P, m, aniso, iters, seed, rho, w, st);
+}
+
 extern "C" rtm_status fwi_gradient_tti(const rtm_plan *P, const void *m, const void *aniso,
                                        const double *src_pos, const void *q,
                                        const double *rec_pos, const void *d_obs, const void *Z,
@@ -1873,10 +2017,11 @@ extern "C" rtm_status fwi_gradient_tti(const rtm_plan *P, const void *m, const v
   if (s) return s;
   if (!src_pos || !q || !rec_pos || !d_obs || !Z || !Ubar || !resid || !grad || !misfit)
     return fail(RTM_E_ARG, "fwi_gradient_tti needs every array except Vbar");
-  if (!Vbar && P->d.probe_dtype != RTM_BF16 && P->d.probe_dtype != RTM_BF16X2)
-    return fail(RTM_E_UNSUPPORTED, "fused imaging (Vbar = NULL) needs a BF16 probe path");
+  if (!Vbar && !mfma_probe(P->d.probe_dtype))
+    return fail(RTM_E_UNSUPPORTED, "fused imaging (Vbar = NULL) needs an MFMA probe path (BF16, BF16X2 or F16S)");
   if ((s = check_probe(P, Z, zt, Ubar))) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((s = screen_tti(P, m, aniso, work, st))) return s;
   if (P->d.field_dtype == RTM_F64)
     return tti_grad_impl<double>(P, m, aniso, src_pos, q, rec_pos, d_obs, Z, zt, Ubar, Vbar, resid,
                                  grad, misfit, work, st);

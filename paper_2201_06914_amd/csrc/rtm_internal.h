@@ -83,6 +83,9 @@ struct ShotIO {
   int32_t n_inj, n_smp;
 };
 
+// operand type of the MFMA probe path: bf16, bf16 hi + lo, or float16 with a
+// power-of-two scale per 16-step chunk and 32-cell tile
+enum ProbeOp : int { OP_BF16 = 0, OP_BF16X2 = 1, OP_F16S = 2 };
 enum ProbeMode : int {
   PROBE_CUR = 0,  // level s          (forward u^n)
   PROBE_UTT = 1,  // levels s-1, s, s+1, second difference / dt^2
@@ -107,9 +110,10 @@ struct ProbeArgs {
 };
 
 // launchers (stream-ordered; return the launch status)
+// rev != 0: the tiled kernels march each z-chunk downwards (same results)
 template <typename T>
 hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
-                          hipStream_t st);
+                          hipStream_t st, int rev = 0);
 // exact comparator: stencil step with a fused epilogue (hipErrorInvalidValue
 // when no tiled kernel serves the grid), and the matching injection
 template <typename T>
@@ -137,7 +141,7 @@ hipError_t launch_offset_gathers(const T *U, const T *V, int nfield, int64_t fst
 // table, then injection / sampling of level s+1 for time index n
 template <typename T>
 hipError_t launch_stencil_batched(const ShotStep<T> *shots, const int4 *tiles, int ntiles, int s,
-                                  int variant, hipStream_t st);
+                                  int variant, hipStream_t st, int rev = 0);
 template <typename T>
 hipError_t launch_inject_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
                                  const BatchPoints<T> &pt, int s, int n, hipStream_t st);
@@ -150,6 +154,16 @@ hipError_t launch_sample_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
 // p + q (adjoint of injecting into both fields)
 template <typename T>
 hipError_t launch_tti_coef(const T *aniso, int64_t N, T *coef, hipStream_t st);
+// TTI stability screen: writes (largest max(1, 1 + 2 eps) / m, count of cells
+// with delta > eps or eps, delta <= -1/2) to part[1024], part[1025]
+// power iteration on m^{-1} A (TTI, no sponge); |m^{-1} A v|^2 of the last
+// iteration (unit v) left in part[1024]
+template <typename T>
+hipError_t tti_power_iteration(const StepArgs<T> &a, double h, double dt, const T *coef, T *p,
+                               T *q, T *pz, T *qz, T *pn, T *qn, T *g, int shape, int target_blocks,
+                               int iters, uint32_t seed, double *part, hipStream_t st);
+template <typename T>
+hipError_t launch_tti_screen(const T *m, const T *aniso, int64_t N, double *part, hipStream_t st);
 // (shape 0: one thread per cell; 1..3: column tiles marching z-chunks, split
 // until target_blocks workgroups)
 template <typename T>
@@ -178,7 +192,7 @@ hipError_t launch_probe_vec(const ProbeArgs<T> &p, const void *Z, bool z_is_i8,
 // (img[c] += scale * sum_i Uf[i][c] (Z_b^T S_b)[i][c]; p.bar unused).
 // Z is int8 +-1, or with zf32 real FP32 probes split into bf16 hi + lo (needs
 // split).
-hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const void *Z, bool zf32, bool split,
+hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const void *Z, bool zf32, int op,
                              const float *Uf, float *img, float scale, hipStream_t st);
 // exact imaging: out = (un - 2 u0 + um) * inv_dt2 ; g -= s * lam
 template <typename T>

@@ -115,9 +115,14 @@ __device__ __forceinline__ const T *at(const T *p, uint32_t off) {
 // column fronts of plane z (four planes ahead of its use) and held in a short
 // register queue, so that a tile's halo loads and its neighbours' interior
 // loads of the same plane are issued close together in time (L2 reuse).
+// rev: march the chunk from z1 - 1 down to z0 instead of up (same per-cell
+// arithmetic: the z terms pair z + j with z - j in a commutative sum, so the
+// levels are bitwise the same either way).  Sweeps alternate the direction
+// from step to step, so that a step starts on the planes the previous step
+// touched last (still in the memory-side cache).
 template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE, bool EH = false>
 __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by, int z0, int z1,
-                                           const EpiArgs<T> &e = EpiArgs<T>{}) {
+                                           const EpiArgs<T> &e = EpiArgs<T>{}, bool rev = false) {
   constexpr int NTH = TX * TYT;
   constexpr int TY = TYT * RY;
   constexpr int LX = TX + 8;
@@ -171,15 +176,19 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
     hxc[k] = col < 4 ? col : TX + col;
   }
 
+  // queue slot k holds plane z + dz (k - 4); the march starts at zs
+  const int dz = rev ? -1 : 1;
+  const int zs = rev ? z1 - 1 : z0;
+  const int nz_chunk = z1 - z0;
   T q[RY][9];
   T front[RY], pv[RY], mm[RY], hyv[NHY], hxv[NHX];
   T es[RY], eg[RY];  // EPI_CORR operands, fetched with the plane they belong to
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) q[j][k] = ldu(z0 - 4 + k, yr[j], x);
-    front[j] = ldu(z0 + 4, yr[j], x);
-    const uint32_t o = off(z0, yr[j], x);
+    for (int k = 0; k < 8; ++k) q[j][k] = ldu(zs + dz * (k - 4), yr[j], x);
+    front[j] = ldu(zs + 4 * dz, yr[j], x);
+    const uint32_t o = off(zs, yr[j], x);
     pv[j] = in[j] ? ld_stream<T, NT>(at(a.prev, o)) : T(0);
     mm[j] = in[j] ? ld_stream<T, NT>(at(a.m, o)) : T(1);
     if constexpr (EPI == EPI_CORR) {
@@ -198,13 +207,14 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
   T hqy[HQ][NHY], hqx[HQ][NHX];
   if constexpr (EH) {
 #pragma unroll
-    for (int d = 0; d < 4; ++d) ldhalo(z0 + d, hqy[d], hqx[d]);
-    ldhalo(z0 + 4, hyv, hxv);
+    for (int d = 0; d < 4; ++d) ldhalo(zs + dz * d, hqy[d], hqx[d]);
+    ldhalo(zs + 4 * dz, hyv, hxv);
   } else {
-    ldhalo(z0, hyv, hxv);
+    ldhalo(zs, hyv, hxv);
   }
 
-  for (int z = z0; z < z1; ++z) {
+  for (int i = 0; i < nz_chunk; ++i) {
+    const int z = zs + dz * i;
     T pvc[RY], mmc[RY], hyc[NHY], hxcv[NHX], esc[RY], egc[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
@@ -238,12 +248,12 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
 #pragma unroll
       for (int k = 0; k < NHX; ++k) hxcv[k] = hxv[k];
     }
-    // prefetch plane z+1
-    if (z + 1 < z1) {
+    // prefetch plane z + dz
+    if (i + 1 < nz_chunk) {
 #pragma unroll
       for (int j = 0; j < RY; ++j) {
-        front[j] = ldu(z + 5, yr[j], x);
-        const uint32_t o = off(z + 1, yr[j], x);
+        front[j] = ldu(z + 5 * dz, yr[j], x);
+        const uint32_t o = off(z + dz, yr[j], x);
         pv[j] = in[j] ? ld_stream<T, NT>(at(a.prev, o)) : T(0);
         mm[j] = in[j] ? ld_stream<T, NT>(at(a.m, o)) : T(1);
         if constexpr (EPI == EPI_CORR) {
@@ -251,9 +261,9 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
           eg[j] = in[j] ? *at(e.g, o) : T(0);
         }
       }
-      ldhalo(EH ? z + 5 : z + 1, hyv, hxv);
+      ldhalo(EH ? z + 5 * dz : z + dz, hyv, hxv);
     }
-    T *L = lds[z & 1];
+    T *L = lds[i & 1];
 #pragma unroll
     for (int j = 0; j < RY; ++j) L[(ty + j * TYT + 4) * LX + tx + 4] = q[j][4];
 #pragma unroll
@@ -292,7 +302,8 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
 template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE, bool EH = false>
 __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int ntx, int nty,
                                                              int nzc, int zchunk,
-                                                             EpiArgs<T> e = EpiArgs<T>{}) {
+                                                             EpiArgs<T> e = EpiArgs<T>{},
+                                                             int rev = 0) {
   // XCD-aware order: consecutive hardware block ids go round-robin over the 8
   // XCDs; give each XCD a contiguous run of tiles so halo re-reads hit its L2.
   const int nblk = ntx * nty * nzc;
@@ -302,7 +313,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
   const int by = (b / ntx) % nty;
   const int bz = b / (ntx * nty);
   const int z0 = bz * zchunk;
-  tiled_body<T, TX, TYT, RY, NT, EPI, EH>(a, bx, by, z0, min(z0 + zchunk, a.nz), e);
+  tiled_body<T, TX, TYT, RY, NT, EPI, EH>(a, bx, by, z0, min(z0 + zchunk, a.nz), e, rev != 0);
 }
 
 // Several shots (independent grids, one ring each) in one launch: entry e of
@@ -311,7 +322,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
 template <typename T, int TX, int TYT, int RY, bool NT, bool EH = false>
 __global__ __launch_bounds__(TX *TYT) void k_stencil3d_batched(const ShotStep<T> *__restrict__ shots,
                                                                const int4 *__restrict__ tiles,
-                                                               int ntiles, int s) {
+                                                               int ntiles, int s, int rev) {
   int b = blockIdx.x;
   if ((ntiles & 7) == 0) b = (b & 7) * (ntiles >> 3) + (b >> 3);
   const int4 t = tiles[b];  // (shot, bx | by << 16, z0, z1)
@@ -320,12 +331,13 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_batched(const ShotStep<T>
   a.cur = sh.ring + (int64_t)(((s + 1) % sh.R)) * sh.ld;
   a.prev = sh.ring + (int64_t)(((s + sh.R) % sh.R)) * sh.ld;
   a.next = sh.ring + (int64_t)(((s + 2) % sh.R)) * sh.ld;
-  tiled_body<T, TX, TYT, RY, NT, EPI_NONE, EH>(a, t.y & 0xffff, t.y >> 16, t.z, t.w);
+  tiled_body<T, TX, TYT, RY, NT, EPI_NONE, EH>(a, t.y & 0xffff, t.y >> 16, t.z, t.w,
+                                              EpiArgs<T>{}, rev != 0);
 }
 
 template <typename T, int TX, int TYT, int RY, bool NT, int EPI = EPI_NONE, bool EH = false>
 static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st,
-                         const EpiArgs<T> &e = EpiArgs<T>{}) {
+                         const EpiArgs<T> &e = EpiArgs<T>{}, int rev = 0) {
   constexpr int TY = TYT * RY;
   const int ntx = (a.nx + TX - 1) / TX;
   const int nty = (a.ny + TY - 1) / TY;
@@ -337,7 +349,7 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
   const int zchunk = (a.nz + nzc - 1) / nzc;
   nzc = (a.nz + zchunk - 1) / zchunk;
   hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT, EPI, EH>), dim3(ntx * nty * nzc),
-                     dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk, e);
+                     dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk, e, rev);
 }
 
 // tiled variants: id -> (TX, threads in y, rows per thread, non-temporal)
@@ -350,28 +362,29 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
 //  12: as 7 and 13: as 9, with early halo loads
 template <typename T>
 hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
-                          hipStream_t st) {
+                          hipStream_t st, int rev) {
+  const EpiArgs<T> e{};
   // the tiled kernels address a level with 32-bit byte offsets
   const bool fits = a.N * (int64_t)sizeof(T) < (int64_t(1) << 32);
   if (ndim == 3 && fits && variant >= kStencilTiled && variant <= kStencilVariants) {
     if constexpr (sizeof(T) == 4) {
       switch (variant) {
-        case 2: launch_tiled<T, 64, 4, 8, false>(a, target_blocks, st); break;
-        case 3: launch_tiled<T, 64, 8, 2, false>(a, target_blocks, st); break;
-        case 4: launch_tiled<T, 64, 2, 8, false>(a, target_blocks, st); break;
-        case 5: launch_tiled<T, 32, 8, 4, false>(a, target_blocks, st); break;
-        case 6: launch_tiled<T, 128, 2, 4, false>(a, target_blocks, st); break;
-        case 7: launch_tiled<T, 64, 4, 4, true>(a, target_blocks, st); break;
-        case 8: launch_tiled<T, 64, 4, 8, true>(a, target_blocks, st); break;
-        case 9: launch_tiled<T, 64, 8, 4, true>(a, target_blocks, st); break;
-        case 10: launch_tiled<T, 64, 16, 2, true>(a, target_blocks, st); break;
-        case 11: launch_tiled<T, 64, 8, 2, true>(a, target_blocks, st); break;
-        case 12: launch_tiled<T, 64, 4, 4, true, EPI_NONE, true>(a, target_blocks, st); break;
-        case 13: launch_tiled<T, 64, 8, 4, true, EPI_NONE, true>(a, target_blocks, st); break;
-        default: launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st); break;
+        case 2: launch_tiled<T, 64, 4, 8, false>(a, target_blocks, st, e, rev); break;
+        case 3: launch_tiled<T, 64, 8, 2, false>(a, target_blocks, st, e, rev); break;
+        case 4: launch_tiled<T, 64, 2, 8, false>(a, target_blocks, st, e, rev); break;
+        case 5: launch_tiled<T, 32, 8, 4, false>(a, target_blocks, st, e, rev); break;
+        case 6: launch_tiled<T, 128, 2, 4, false>(a, target_blocks, st, e, rev); break;
+        case 7: launch_tiled<T, 64, 4, 4, true>(a, target_blocks, st, e, rev); break;
+        case 8: launch_tiled<T, 64, 4, 8, true>(a, target_blocks, st, e, rev); break;
+        case 9: launch_tiled<T, 64, 8, 4, true>(a, target_blocks, st, e, rev); break;
+        case 10: launch_tiled<T, 64, 16, 2, true>(a, target_blocks, st, e, rev); break;
+        case 11: launch_tiled<T, 64, 8, 2, true>(a, target_blocks, st, e, rev); break;
+        case 12: launch_tiled<T, 64, 4, 4, true, EPI_NONE, true>(a, target_blocks, st, e, rev); break;
+        case 13: launch_tiled<T, 64, 8, 4, true, EPI_NONE, true>(a, target_blocks, st, e, rev); break;
+        default: launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st, e, rev); break;
       }
     } else {
-      launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st);
+      launch_tiled<T, 64, 4, 4, false>(a, target_blocks, st, e, rev);
     }
   } else {
     const unsigned nblk = (unsigned)((a.N + 255) / 256);
@@ -383,8 +396,9 @@ hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int targe
   return hipGetLastError();
 }
 
-template hipError_t launch_stencil<float>(int, const StepArgs<float> &, int, int, hipStream_t);
-template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, int, hipStream_t);
+template hipError_t launch_stencil<float>(int, const StepArgs<float> &, int, int, hipStream_t, int);
+template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, int, hipStream_t,
+                                           int);
 
 // Stencil step with an exact-comparator epilogue (3D F32, tiled variants 1
 // and 7; other variants use variant 7).  Returns hipErrorInvalidValue for
@@ -548,37 +562,37 @@ hipError_t launch_sample(const PointTables<T> &pt, const T *field, T *out, hipSt
 // ---------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_stencil_batched(const ShotStep<T> *shots, const int4 *tiles, int ntiles, int s,
-                                  int variant, hipStream_t st) {
+                                  int variant, hipStream_t st, int rev) {
   if (ntiles <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 4) {
     switch (variant) {
       case 3:
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 8, 2, false>), dim3(ntiles), dim3(512), 0,
-                           st, shots, tiles, ntiles, s);
+                           st, shots, tiles, ntiles, s, rev);
         break;
       case 11:
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 8, 2, true>), dim3(ntiles), dim3(512), 0,
-                           st, shots, tiles, ntiles, s);
+                           st, shots, tiles, ntiles, s, rev);
         break;
       case 12:
       case 13:
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, true, true>), dim3(ntiles),
-                           dim3(256), 0, st, shots, tiles, ntiles, s);
+                           dim3(256), 0, st, shots, tiles, ntiles, s, rev);
         break;
       case 7:
       case 8:
       case 9:
       case 10:  // 64 x 32 variants run the 64 x 16 tile table with the variant 7 kernel
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, true>), dim3(ntiles), dim3(256), 0,
-                           st, shots, tiles, ntiles, s);
+                           st, shots, tiles, ntiles, s, rev);
         break;
       default:
         hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, false>), dim3(ntiles), dim3(256), 0,
-                           st, shots, tiles, ntiles, s);
+                           st, shots, tiles, ntiles, s, rev);
     }
   } else {
     hipLaunchKernelGGL((k_stencil3d_batched<T, 64, 4, 4, false>), dim3(ntiles), dim3(256), 0, st,
-                       shots, tiles, ntiles, s);
+                       shots, tiles, ntiles, s, rev);
   }
   return hipGetLastError();
 }
@@ -640,7 +654,7 @@ hipError_t launch_sample_batched(const ShotStep<T> *shots, const ShotIO<T> *io,
   return hipGetLastError();
 }
 template hipError_t launch_stencil_batched<float>(const ShotStep<float> *, const int4 *, int, int,
-                                                  int, hipStream_t);
+                                                  int, hipStream_t, int);
 template hipError_t launch_inject_batched<float>(const ShotStep<float> *, const ShotIO<float> *,
                                                  const BatchPoints<float> &, int, int,
                                                  hipStream_t);

@@ -255,6 +255,195 @@ hipError_t launch_sample_sum(const PointTables<T> &pt, const T *f1, const T *f2,
   return hipGetLastError();
 }
 
+// Stability screen of a TTI model (before a sweep).  With the coefficients
+// frozen at a cell, the coupled operator's symbol is C diag(h0, hz), C =
+// [[1 + 2 eps, sqrt(1 + 2 delta)], [sqrt(1 + 2 delta), 1]], with h0, hz >= 0
+// and h0 + hz the acoustic symbol; for delta <= eps its eigenvalues are real,
+// non-negative and at most max(1, 1 + 2 eps)(h0 + hz), so the acoustic CFL
+// bound holds with the velocity v sqrt(max(1, 1 + 2 eps)).  Each workgroup
+// writes the largest max(1, 1 + 2 eps) / m of its cells and the count of
+// cells with delta > eps, eps <= -1/2 or delta <= -1/2 (finite values only:
+// a NaN or an infinity is left to the non-finite watch); one workgroup folds
+// the partials into out[0] (largest v^2) and out[1] (count).
+constexpr int kScreenBlocks = 512;
+
+__device__ __forceinline__ void screen_fold(double &vmax, double &bad) {
+  __shared__ double sv[4], sb[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    vmax = fmax(vmax, __shfl_down(vmax, off, 64));
+    bad += __shfl_down(bad, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sv[wave] = vmax;
+    sb[wave] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    vmax = fmax(fmax(sv[0], sv[1]), fmax(sv[2], sv[3]));
+    bad = ((sb[0] + sb[1]) + sb[2]) + sb[3];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tti_screen(const T *__restrict__ m,
+                                                    const T *__restrict__ aniso, int64_t N,
+                                                    double *__restrict__ part) {
+  double vmax = 0.0, bad = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    const double mi = m[i], e = aniso[i], d = aniso[N + i];
+    const double c1 = 1.0 + 2.0 * e;
+    if (isfinite(mi) && mi > 0.0 && isfinite(c1)) vmax = fmax(vmax, (c1 > 1.0 ? c1 : 1.0) / mi);
+    if (isfinite(e) && isfinite(d) && (d > e || e <= -0.5 || d <= -0.5)) bad += 1.0;
+  }
+  screen_fold(vmax, bad);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = vmax;
+    part[2 * blockIdx.x + 1] = bad;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tti_screen_final(const double *__restrict__ part,
+                                                          int np, double *__restrict__ out) {
+  double vmax = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) {
+    vmax = fmax(vmax, part[2 * i]);
+    bad += part[2 * i + 1];
+  }
+  screen_fold(vmax, bad);
+  if (threadIdx.x == 0) {
+    out[0] = vmax;
+    out[1] = bad;
+  }
+}
+
+// Power iteration on m^{-1} A, A the coupled TTI operator without sponge,
+// through the forward step with a zero previous level:
+//     next = 2 cur + dt^2 m^{-1} A cur,  so  m^{-1} A cur = (next - 2 cur) / dt^2.
+// The iterate (p, q) is kept at unit norm; |m^{-1} A cur| of the last
+// iteration estimates the spectral radius.  Sums of squares in FP64, fixed
+// order (partials per workgroup, then one workgroup).
+__device__ __forceinline__ double block_sum_d(double v) {
+  __shared__ double sv[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sv[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = ((sv[0] + sv[1]) + sv[2]) + sv[3];
+  return s;
+}
+
+__device__ __forceinline__ double pi_start_value(uint64_t i, uint32_t seed) {
+  uint32_t h = (uint32_t)i * 2654435761u ^ seed;  // Knuth multiplicative hash, then mixing
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  h *= 3266489917u;
+  h ^= h >> 16;
+  return ((double)(h >> 8) - 8388608.0) / 8388608.0;  // [-1, 1)
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pi_start(T *p, T *q, int64_t N, uint32_t seed,
+                                                  double *part) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    const T vp = (T)pi_start_value((uint64_t)i, seed), vq = (T)pi_start_value((uint64_t)(i + N), seed);
+    p[i] = vp;
+    q[i] = vq;
+    acc += (double)vp * (double)vp + (double)vq * (double)vq;
+  }
+  const double sum = block_sum_d(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = sum;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pi_diff(T *pn, T *qn, const T *p, const T *q, int64_t N,
+                                                 T inv_dt2, double *part) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    const T wp = (pn[i] - T(2) * p[i]) * inv_dt2, wq = (qn[i] - T(2) * q[i]) * inv_dt2;
+    pn[i] = wp;
+    qn[i] = wq;
+    acc += (double)wp * (double)wp + (double)wq * (double)wq;
+  }
+  const double sum = block_sum_d(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(256) void k_pi_final(const double *part, int np, double *out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+  const double sum = block_sum_d(acc);
+  if (threadIdx.x == 0) out[0] = sum;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pi_scale(T *p, T *q, const T *wp, const T *wq, int64_t N,
+                                                  const double *sumsq) {
+  const double s = 1.0 / sqrt(sumsq[0]);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    p[i] = (T)((double)wp[i] * s);
+    q[i] = (T)((double)wq[i] * s);
+  }
+}
+
+// levels: p, q (iterate), pz, qz (zero previous levels), pn, qn (next); part:
+// 1026 doubles, |w|^2 of the last iteration left in part[1024]
+template <typename T>
+hipError_t tti_power_iteration(const StepArgs<T> &a0, double h, double dt, const T *coef, T *p,
+                               T *q, T *pz, T *qz, T *pn, T *qn, T *g, int shape, int target_blocks,
+                               int iters, uint32_t seed, double *part, hipStream_t st) {
+  StepArgs<T> a = a0;
+  a.kd = T(0);  // no sponge: the operator alone
+  const int64_t N = a.N;
+  constexpr int NB = 512;
+  hipError_t e;
+  if ((e = launch_fill<T>(pz, N, T(0), st)) != hipSuccess) return e;
+  if ((e = launch_fill<T>(qz, N, T(0), st)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_pi_start<T>), dim3(NB), dim3(256), 0, st, p, q, N, seed, part);
+  hipLaunchKernelGGL(k_pi_final, dim3(1), dim3(256), 0, st, part, NB, part + 1024);
+  hipLaunchKernelGGL((k_pi_scale<T>), dim3(NB), dim3(256), 0, st, p, q, p, q, N, part + 1024);
+  const T inv_dt2 = (T)(1.0 / (dt * dt));
+  for (int it = 0; it < iters; ++it) {
+    if ((e = launch_tti_step<T>(a, h, false, coef, p, pz, q, qz, pn, qn, g, shape, target_blocks,
+                                st)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL((k_pi_diff<T>), dim3(NB), dim3(256), 0, st, pn, qn, p, q, N, inv_dt2, part);
+    hipLaunchKernelGGL(k_pi_final, dim3(1), dim3(256), 0, st, part, NB, part + 1024);
+    hipLaunchKernelGGL((k_pi_scale<T>), dim3(NB), dim3(256), 0, st, p, q, pn, qn, N, part + 1024);
+  }
+  return hipGetLastError();
+}
+template hipError_t tti_power_iteration<float>(const StepArgs<float> &, double, double,
+                                               const float *, float *, float *, float *, float *,
+                                               float *, float *, float *, int, int, int, uint32_t,
+                                               double *, hipStream_t);
+template hipError_t tti_power_iteration<double>(const StepArgs<double> &, double, double,
+                                                const double *, double *, double *, double *,
+                                                double *, double *, double *, double *, int, int,
+                                                int, uint32_t, double *, hipStream_t);
+
+// part: 2 kScreenBlocks + 2 doubles; the result lands in part[2 kScreenBlocks ..]
+template <typename T>
+hipError_t launch_tti_screen(const T *m, const T *aniso, int64_t N, double *part, hipStream_t st) {
+  hipLaunchKernelGGL((k_tti_screen<T>), dim3(kScreenBlocks), dim3(256), 0, st, m, aniso, N, part);
+  hipLaunchKernelGGL(k_tti_screen_final, dim3(1), dim3(256), 0, st, part, kScreenBlocks,
+                     part + 2 * kScreenBlocks);
+  return hipGetLastError();
+}
+template hipError_t launch_tti_screen<float>(const float *, const float *, int64_t, double *,
+                                             hipStream_t);
+template hipError_t launch_tti_screen<double>(const double *, const double *, int64_t, double *,
+                                              hipStream_t);
+
 template hipError_t launch_tti_coef<float>(const float *, int64_t, float *, hipStream_t);
 template hipError_t launch_tti_coef<double>(const double *, int64_t, double *, hipStream_t);
 template hipError_t launch_tti_step<float>(const StepArgs<float> &, double, bool, const float *,

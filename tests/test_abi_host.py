@@ -267,3 +267,52 @@ def test_batch_create_validates_on_host(L):
     assert L.rtm_batch_create(bad, 2, ctypes.byref(h)) == 1
     f64 = (_lib.RtmDesc * 1)(_desc(field_dtype=_lib.RTM_F64, probe_dtype=_lib.RTM_F64))
     assert L.rtm_batch_create(f64, 1, ctypes.byref(h)) == 7
+
+
+def test_batched_stack_needs_one_grid_per_shared_gradient(L):
+    """fwi_gradient_batched refuses, before any HIP call, a gradient buffer
+    shared by shots on different grids, or one that is also another array of
+    a shot (fake device addresses)."""
+    from paper_2201_06914_amd import _lib
+    arr = (_lib.RtmDesc * 2)(_desc(nz=30, ny=26, nx=40), _desc(nz=24, ny=30, nx=50))
+    h = ctypes.c_void_p()
+    assert L.rtm_batch_create(arr, 2, ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    assert L.rtm_batch_workspace_bytes(h, ctypes.byref(n)) == 0
+    src = np.array([[8.0, 10.0, 20.0]])
+    rec = np.array([[9.0, 10.0, 20.0]] * 4)
+    sp = src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rp = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    io = (_lib.ShotIO * 2)()
+    for i in range(2):
+        base = (1 << 24) * (i + 1)
+        io[i].m, io[i].q, io[i].d_obs, io[i].Z = base, base + 256, base + 512, base + 768
+        io[i].Ubar, io[i].resid, io[i].grad = base + 1024, base + 1280, base + 1536
+        io[i].src_pos, io[i].rec_pos = sp, rp
+    io[1].grad = io[0].grad
+    fake = ctypes.c_void_p(1 << 30)
+    assert L.fwi_gradient_batched(h, io, fake, 0, fake, n.value, None) == 1
+    assert b"share a gradient buffer" in L.rtm_last_error()
+    io[1].grad = io[0].Ubar
+    assert L.fwi_gradient_batched(h, io, fake, 0, fake, n.value, None) == 1
+    assert b"also an input or output" in L.rtm_last_error()
+    L.rtm_batch_destroy(h)
+
+
+def test_f16s_probe_plan_accepts_int8_probes_only(L):
+    """The float16 operand path takes +-1 probes (RTM_I8); real probes are
+    refused before any launch (fake addresses)."""
+    from paper_2201_06914_amd import _lib
+    c, h = _create(L, probe_dtype=_lib.RTM_F16S)
+    assert c == 0, L.rtm_last_error()
+    n = ctypes.c_size_t()
+    assert L.rtm_plan_workspace_bytes(h, ctypes.byref(n)) == 0
+    fake = ctypes.c_void_p(1 << 20)
+    src = np.array([[8.0, 10.0, 20.0]])
+    sp = src.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.rtm_forward_probe(h, fake, sp, fake, None, None, fake, _lib.RTM_F32, 1, fake, None,
+                               fake, n.value, None) == 3
+    L.rtm_plan_destroy(h)
+    # F16S needs F32 fields
+    c, h = _create(L, probe_dtype=_lib.RTM_F16S, field_dtype=_lib.RTM_F64)
+    assert c == 3

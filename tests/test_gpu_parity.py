@@ -103,7 +103,7 @@ def s3():
     return wl, f, a, img
 
 
-@pytest.mark.parametrize("probe", ["f32", "bf16x2", "bf16"])
+@pytest.mark.parametrize("probe", ["f32", "bf16x2", "bf16", "f16s"])
 def test_3d_f32_forward_adjoint_image(s3, probe):
     wl, f, a, img = s3
     say(f"case: 3D small {wl.shape} nt={wl.nt} r={wl.r} probe={probe}")
@@ -124,6 +124,8 @@ def test_3d_f32_forward_adjoint_image(s3, probe):
         assert e["U"] < 5e-5 and e["V"] < 2e-5 and e["img"] < 2e-5
     elif probe == "bf16x2":
         assert e["U"] < 1e-4 and e["V"] < 1e-4 and e["img"] < 1e-3
+    elif probe == "f16s":   # float16 (11-bit mantissa) after a power-of-two scale
+        assert e["U"] < 1e-3 and e["V"] < 1e-3 and e["img"] < 1e-3
     else:
         assert e["U"] < 1e-2 and e["img"] < 5e-2   # reported, not the 1e-3 bar
 
@@ -320,6 +322,36 @@ def test_fused_imaging_matches_unfused_and_oracle(r, k_block, shape):
     assert "Vbar" not in b or b["Vbar"] is None
     assert e_ab < 1e-5 and e_bo < 1e-3
     assert float(a["misfit"].item()) == float(b["misfit"].item())
+
+
+@pytest.mark.parametrize("probe,r,k_block,shape,nt", [
+    ("bf16x2", 64, 128, (21, 19, 35), 300),   # two whole 128-step blocks and a short one
+    ("f16s", 32, 32, (26, 22, 40), 70),
+    ("f16s", 64, 128, (21, 19, 35), 300),
+    ("f16s", 128, 64, (24, 20, 48), 150)])
+def test_long_blocks_and_f16s_gradient_match_oracle(probe, r, k_block, shape, nt):
+    """Probe blocks of 128 steps (eight 16-step chunks, two groups of four in
+    the kernel) and the float16 operand with per-chunk power-of-two scales:
+    fused and separate imaging against each other and against the FP64
+    oracle's probed gradient (Eq. 3, same probes)."""
+    wl = synth.workload_small_3d(shape=shape, nt=nt, r=r, nb=4)
+    g = _grid(wl)
+    d_obs = np.zeros((wl.nt, wl.rec_pos.shape[0]), dtype=np.float32)
+    Jo, go, f, _ = oracle.probed_gradient(g, wl.m, wl.src_pos, wl.q, wl.rec_pos, d_obs, wl.Z)
+    say(f"case: {probe} r={r} k={k_block} {shape} nt={nt}")
+    plan = P.Plan.for_workload(wl, field="f32", probe=probe, k_block=k_block)
+    args = (plan, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32), wl.rec_pos,
+            dev(d_obs, torch.float32), dev(wl.Z, torch.int8))
+    a = P.fwi_gradient(*args)
+    b = P.fwi_gradient(*args, fused=True)
+    torch.cuda.synchronize()
+    ga, gb = host(a["grad"]), host(b["grad"])
+    e_ab, e_ao, e_bo = rel(gb, ga), rel(ga, go), rel(gb, go)
+    e_u = rel(rows(plan, a["Ubar"]), f["Ubar"])
+    say(f"  Ubar {e_u:.2e}  separate vs oracle {e_ao:.2e}  fused vs oracle {e_bo:.2e}  "
+        f"fused vs separate {e_ab:.2e}")
+    assert e_ab < 1e-5 and e_ao < 1e-3 and e_bo < 1e-3
+    assert e_u < (1e-4 if probe == "bf16x2" else 1e-3)
 
 
 def test_bar_layout_conversion():

@@ -196,3 +196,27 @@ def test_rf_beats_rademacher_on_gpu():
     ez, eq = rel(gz, ex), rel(gq, ex)
     say(f"  r = {r}: Rademacher {ez:.3f}, range finder {eq:.3f}")
     assert eq < 0.5 * ez
+
+
+@pytest.mark.parametrize("probe", ["f32", "bf16x2"])
+def test_rf_gradient_r_equals_nt_is_the_oracle_exact_gradient(probe):
+    """End to end against the oracle without the GPU's Q: with r = nt the
+    sketch Y = H Omega has full column rank, Q spans every time direction and
+    Q Q^T = I, so the range-finder gradient is the exact gradient of Eq. 2,
+    which the oracle computes from stored histories (no probes at all)."""
+    wl = synth.workload_small_3d(shape=(22, 20, 34), nt=64, nb=5)
+    g = Grid.of(wl)
+    r, seed = 64, 12
+    rng = np.random.default_rng(8)
+    d_obs = (0.05 * rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))).astype(np.float32)
+    J0, g0 = oracle.exact_gradient(g, wl.m, wl.src_pos, wl.q, wl.rec_pos, d_obs)
+    plan = _plan(wl, "f32", probe, r, 32)
+    out = P.fwi_gradient_rf(plan, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32),
+                            wl.rec_pos, dev(d_obs, torch.float32), seed)
+    torch.cuda.synchronize()
+    Q = host(out["Q"]).astype(np.float64)
+    eI = np.abs(Q @ Q.T - np.eye(wl.nt)).max()
+    e = rel(host(out["grad"]), g0)
+    eJ = abs(float(out["misfit"].item()) - J0) / J0
+    say(f"  rf {probe} r = nt: |Q Q^T - I| {eI:.2e}, grad vs exact {e:.2e}, misfit {eJ:.2e}")
+    assert eI < 1e-5 and e < 1e-4 and eJ < 1e-5

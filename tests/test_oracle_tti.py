@@ -146,3 +146,42 @@ def test_tti_sampled_cells_match_full_probing():
     fa = oracle.tti_adjoint(g, wl.m, an, wl.rec_pos, res, Z=wl.Z)["bar"]
     pa = oracle.tti_adjoint(g, wl.m, an, wl.rec_pos, res, Z=wl.Z, sample_idx=idx)["bar"]
     np.testing.assert_array_equal(pa, fa[:, :, idx])
+
+
+def _tti_matrix(sh, h, m, eps, dl, th, ph):
+    """Dense m^{-1} A of the oracle's TTI operator on a tiny grid, column by
+    column (A applied to unit vectors of (p, q))."""
+    N = int(np.prod(sh))
+    M = np.zeros((2 * N, 2 * N))
+    for j in range(2 * N):
+        e = np.zeros(2 * N)
+        e[j] = 1.0
+        op, oq = oracle.tti_apply(eps, dl, th, ph, e[:N].reshape(sh), e[N:].reshape(sh), h)
+        M[:N, j] = (op / m).ravel()
+        M[N:, j] = (oq / m).ravel()
+    return M
+
+
+def test_spectrum_within_the_frozen_coefficient_bound_and_delta_above_eps_grows():
+    """The library's TTI screen rests on a frozen-coefficient bound: with
+    delta <= eps the coupled operator's symbol at a cell has real
+    non-positive eigenvalues of magnitude at most max(1, 1 + 2 eps) / m times
+    the acoustic symbol (3 S / h^2 at Nyquist, S = 6.50159).  On a tiny grid
+    with cell-wise random m, eps, delta, tilt and azimuth, the dense operator
+    m^{-1} A has no eigenvalue with a positive real part (no growing mode)
+    and its spectral radius is below that bound; with delta > eps a positive
+    real eigenvalue appears (growth for any dt), which is why the screen
+    rejects such models."""
+    sh, h = (6, 7, 8), 12.5
+    rng = np.random.default_rng(9)
+    m = 1.0 / (1500.0 + 3000.0 * rng.random(sh)) ** 2
+    eps, dl, th, ph = _aniso(sh, 4)
+    lam = np.linalg.eigvals(_tti_matrix(sh, h, m, eps, dl, th, ph))
+    rho = np.abs(lam).max()
+    S = 6.501587301587302
+    bound = (np.maximum(1.0, 1.0 + 2.0 * eps) / m).max() * 3.0 * S / h ** 2
+    assert lam.real.max() <= 1e-9 * rho
+    assert rho <= bound and rho > 0.3 * bound, rho / bound
+    dl_bad = eps + 0.3 * np.random.default_rng(5).random(sh)
+    lam_bad = np.linalg.eigvals(_tti_matrix(sh, h, m, eps, dl_bad, th, ph))
+    assert lam_bad.real.max() > 1e-2 * np.abs(lam_bad).max()
