@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--prof-stride", type=int, default=50)
     ap.add_argument("--stencil-variant", type=int, default=None,
                     help="fix the stencil kernel variant instead of autotuning it")
+    ap.add_argument("--stencil-blocks", type=int, default=None,
+                    help="with --stencil-variant: the z-split target (default 2048)")
     ap.add_argument("--unfused", action="store_true",
                     help="store Vbar and run the separate imaging kernel (default: fused imaging)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -234,9 +236,10 @@ def bench_batched(nt: int):
     variant, blocks = tuned["best"]
     print(f"batched: tuned variant {variant}, z-split target {blocks}", file=sys.stderr,
           flush=True)
+    blocks_before = P.api.get_stencil_blocks()
     P.set_stencil_blocks(blocks)
     B = P.Batch(specs)
-    P.set_stencil_blocks(2048)
+    P.set_stencil_blocks(blocks_before)
     outs = B.outputs()
     J = torch.empty(len(shots), dtype=torch.float64, device="cuda")
     work = torch.empty(B.workspace_bytes, dtype=torch.uint8, device="cuda")
@@ -606,7 +609,8 @@ def main():
         tune = P.autotune_stencil(plan, m, work=work, steps=20)
     else:
         P.set_stencil_variant(a.stencil_variant)
-        tune = {"best": a.stencil_variant, "fixed": True}
+        P.set_stencil_blocks(a.stencil_blocks or 2048)
+        tune = {"best": a.stencil_variant, "blocks": a.stencil_blocks or 2048, "fixed": True}
     print(f"stencil variant {tune}", file=sys.stderr, flush=True)
 
     fused = not a.unfused
@@ -780,9 +784,11 @@ def main():
             round(tr["probe_adj"]) if tr else None,
             {"bytes_per_cell_per_block": 4 * k + (4 * r + 8 if fused else 8 * r)}),
         "stencil": entry(
-            f"k_stencil3d_tiled (variant {tune['best']})", st_ach, st_avg, st_n, st_bytes,
+            f"k_stencil3d_tiled (variant {tune['best']}, z-march alternating)", st_ach, st_avg,
+            st_n, st_bytes,
             st_avg * 2 * nt, round(tr["stencil"]) if tr else None,
-            {"bytes_per_cell": 16, "autotune_us": tune.get("us")}),
+            {"bytes_per_cell": 16, "z_split_target": tune.get("blocks"),
+             "autotune_us": tune.get("us")}),
     }
     dom = max(kern, key=lambda kk: kern[kk]["ms_per_step"])
     pr_bytes_step = fwd_b + adj_b

@@ -135,10 +135,11 @@ const char *rtm_status_str(rtm_status s);
  * of a plane loaded four planes ahead, with the column fronts.  Every choice
  * gives bitwise-identical levels.  Batched shots run the 64x16 variants 3,
  * 11, 7 or 12 (8..10 select 7, 13 selects 12, the others 1).
- * rtm_set_stencil_blocks: the tiled kernels (acoustic and TTI) split z until
- * a launch has at least this many workgroups of 256 threads' worth (default
- * 2048; a 512 thread shape aims at half as many); a batch's tile table (made
- * by rtm_batch_create) aims at twice as many. */
+ * rtm_set_stencil_blocks: the tiled acoustic kernels split z into the fewest
+ * chunks (of at least 16 planes) that give a launch this many workgroups of
+ * 256 threads' worth (default 2048; a 512 thread shape aims at half as
+ * many); a batch's tile table (made by rtm_batch_create) aims at twice as
+ * many.  The TTI kernels aim at 2048. */
 void rtm_set_stencil_variant(int variant);
 void rtm_set_stencil_blocks(int32_t blocks);
 /* Tuning hook, process wide: with on != 0 (default) the tiled stencil of the
@@ -355,9 +356,10 @@ void rtm_set_exact_fused(int32_t on);
  * rows of 64 columns for the in-plane pass / the z-marching pass: 1 = 8 / 8,
  * 2 = 4 / 4, 3 = 8 / 4; 4 and 5: as 3 for the transpose step, and the forward
  * step as one fused kernel of 4 or 8 rows; 6: both steps as one fused
- * kernel each (4 rows); 7 (default): both fused, the forward step on 4 rows
- * and the transpose step on 8 rows; 8: both fused on 8 rows; other values
- * select 7.
+ * kernel each (4 rows); 7: both fused, the forward step on 4 rows and the
+ * transpose step on 8 rows; 8: both fused on 8 rows; 9 (default) and 10: as
+ * 7 with the forward step keeping its planes in an LDS ring (p and q read
+ * once per step), on 4 and 8 rows; other values select 9.
  * rtm_set_stencil_variant(0) forces the one-thread-per-cell TTI kernels
  * instead.  Results agree to rounding. */
 void rtm_set_tti_shape(int32_t shape);

@@ -234,17 +234,26 @@ def set_stencil_alternate(on: bool) -> None:
     _lib.load().rtm_set_stencil_alternate(1 if on else 0)
 
 
+_STENCIL_BLOCKS = [2048]    # the value last set in this process (the library's default)
+
+
 def set_stencil_blocks(blocks: int) -> None:
     _lib.load().rtm_set_stencil_blocks(int(blocks))
+    _STENCIL_BLOCKS[0] = int(blocks) if blocks > 0 else 2048
+
+
+def get_stencil_blocks() -> int:
+    return _STENCIL_BLOCKS[0]
 
 
 def autotune_stencil(plan: Plan, m, work=None, steps: int = 20, apply: bool = True,
-                     cache: str | None = None) -> dict:
+                     cache: str | None = None, blocks=(768, 1024, 1536, 2048, 4096)) -> dict:
     """Times every stencil variant on this plan's grid (after checking each
-    against the one-thread-per-cell kernel bit for bit) and, with apply=True,
-    selects the fastest.  `cache`: a JSON file keyed by (arch, grid, dtype)
-    that stores the choice across runs (default: the RTM_TUNE_CACHE
-    environment variable, if set)."""
+    against the one-thread-per-cell kernel bit for bit, in both z-marching
+    directions) for each z-split target in `blocks`, and with apply=True
+    selects the fastest (variant, target) pair.  `cache`: a JSON file keyed by
+    (arch, grid, dtype) that stores the choice across runs (default: the
+    RTM_TUNE_CACHE environment variable, if set)."""
     import json
     import os
     if cache is None:
@@ -260,18 +269,29 @@ def autotune_stencil(plan: Plan, m, work=None, steps: int = 20, apply: bool = Tr
             if key in table:
                 if apply:
                     set_stencil_variant(table[key]["best"])
+                    set_stencil_blocks(table[key].get("blocks", 2048))
                 return dict(table[key], cached=True)
     work = _work(plan, work, m.device)
-    best = ctypes.c_int32()
-    us = (ctypes.c_float * N_STENCIL_VARIANTS)()
-    mism = (ctypes.c_int64 * N_STENCIL_VARIANTS)()
-    _check(_lib.load().rtm_autotune_stencil(plan.handle, _dev(m, plan.dtype, plan.N, "m"),
-                                            ctypes.c_void_p(work.data_ptr()), work.numel(),
-                                            int(steps), ctypes.byref(best), us, mism,
-                                            _stream(m.device)), "rtm_autotune_stencil")
+    blocks_before = get_stencil_blocks()
     last = N_STENCIL_VARIANTS if plan.spec.ndim == 3 else 1
-    res = {"best": int(best.value), "us": [round(float(us[i]), 2) for i in range(last)],
-           "mismatch": [int(mism[i]) for i in range(last)], "cached": False}
+    us_all, mism_all = {}, [0] * last
+    best = (None, None, float("inf"))
+    for b in blocks:
+        set_stencil_blocks(b)
+        bv = ctypes.c_int32()
+        us = (ctypes.c_float * N_STENCIL_VARIANTS)()
+        mism = (ctypes.c_int64 * N_STENCIL_VARIANTS)()
+        _check(_lib.load().rtm_autotune_stencil(plan.handle, _dev(m, plan.dtype, plan.N, "m"),
+                                                ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                                int(steps), ctypes.byref(bv), us, mism,
+                                                _stream(m.device)), "rtm_autotune_stencil")
+        us_all[b] = [round(float(us[i]), 2) for i in range(last)]
+        mism_all = [max(mism_all[i], int(mism[i])) for i in range(last)]
+        v = int(bv.value)
+        if us_all[b][v] < best[2]:
+            best = (v, b, us_all[b][v])
+    res = {"best": best[0], "blocks": best[1], "us": us_all, "mismatch": mism_all, "cached": False}
+    set_stencil_blocks(res["blocks"] if apply else blocks_before)
     if apply:
         set_stencil_variant(res["best"])
     if cache and key:

@@ -32,8 +32,9 @@ using namespace rtm;
 static thread_local std::string g_last_error;
 static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled variant id
 static int g_stencil_blocks = 2048; // tiled stencil: split z until this many workgroups
+static const int kTtiBlocks = 2048; // tiled TTI kernels: the same, fixed
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
-static int g_tti_shape = 7;         // tiled TTI tile shape (1..8)
+static int g_tti_shape = 9;         // tiled TTI tile shape (1..10)
 static int g_stencil_alternate = 1; // sweeps: tiled stencil marches z up / down on alternate steps
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
@@ -191,7 +192,7 @@ extern "C" void rtm_set_stencil_variant(int v) {
 extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
 extern "C" void rtm_set_stencil_alternate(int32_t on) { g_stencil_alternate = on ? 1 : 0; }
 
-extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 8) ? shape : 7; }
+extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 10) ? shape : 9; }
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
   g_stencil_blocks = blocks > 0 ? blocks : 2048;
@@ -1112,7 +1113,8 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
     a.next = lvA(n + 1);
     TimedLaunch tl;
     prof_begin(KT_STENCIL, n, st, &tl);
-    HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
+    HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st,
+                              g_stencil_alternate ? (n & 1) : 0));
     prof_end(st, &tl);
     if (src_t.ncell > 0) HIP_TRY(launch_inject<T>(a, src_t, q + (int64_t)n * src_t.npts, a.next, st));
     if (rec_t.npts > 0) HIP_TRY(launch_sample<T>(rec_t, a.next, resid + (int64_t)n * rec_t.npts, st));
@@ -1142,14 +1144,15 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
       EpiArgs<T> e;
       e.d2 = S + (int64_t)(n - n_lo) * ld;
       e.inv_dt2 = inv_dt2;
-      if (fused && launch_stencil_epi<T>(ndim, fa, variant, g_stencil_blocks, EPI_D2, e, st) ==
+      const int rf = g_stencil_alternate ? (n & 1) : 0;
+      if (fused && launch_stencil_epi<T>(ndim, fa, variant, g_stencil_blocks, EPI_D2, e, st, rf) ==
                        hipSuccess) {
         // u_tt written by the stencil's epilogue; the injection adds its share
         if (src_t.ncell > 0)
           HIP_TRY(launch_inject_epi<T>(fa, src_t, q + (int64_t)n * src_t.npts, fa.next, EPI_D2,
                                        e, st));
       } else {
-        HIP_TRY(launch_stencil<T>(ndim, fa, variant, g_stencil_blocks, st));
+        HIP_TRY(launch_stencil<T>(ndim, fa, variant, g_stencil_blocks, st, rf));
         if (src_t.ncell > 0)
           HIP_TRY(launch_inject<T>(fa, src_t, q + (int64_t)n * src_t.npts, fa.next, st));
         HIP_TRY(launch_second_diff<T>(fa.next, fa.cur, fa.prev, inv_dt2, N, e.d2, st));
@@ -1163,13 +1166,14 @@ static rtm_status exact_impl(const rtm_plan *P, const void *mv, const double *sr
       EpiArgs<T> e;
       e.s = S + (int64_t)(n - n_lo) * ld;
       e.g = grad;
-      if (fused && launch_stencil_epi<T>(ndim, a, variant, g_stencil_blocks, EPI_CORR, e, st) ==
+      const int ra = g_stencil_alternate ? (sa & 1) : 0;
+      if (fused && launch_stencil_epi<T>(ndim, a, variant, g_stencil_blocks, EPI_CORR, e, st, ra) ==
                        hipSuccess) {
         if (rec_t.ncell > 0)
           HIP_TRY(launch_inject_epi<T>(a, rec_t, resid + (int64_t)n * rec_t.npts, a.next,
                                        EPI_CORR, e, st));
       } else {
-        HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st));
+        HIP_TRY(launch_stencil<T>(ndim, a, variant, g_stencil_blocks, st, ra));
         if (rec_t.ncell > 0)
           HIP_TRY(launch_inject<T>(a, rec_t, resid + (int64_t)n * rec_t.npts, a.next, st));
         HIP_TRY(launch_correlate<T>(grad, e.s, a.next, N, st));
@@ -1756,7 +1760,7 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
     prof_begin(KT_TTI, s, st, &tl);
     HIP_TRY(launch_tti_step<T>(a, d.h, io.adjoint, coef, lv(ringP, s), lv(ringP, s - 1),
                                lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, shape,
-                               g_stencil_blocks, st));
+                               kTtiBlocks, st));
     prof_end(st, &tl);
     if (inj.ncell > 0 && vals) {
       HIP_TRY(launch_inject<T>(a, inj, vals + (int64_t)n * inj.npts, pn, st));
@@ -1984,7 +1988,7 @@ static rtm_status tti_rho_impl(const rtm_plan *P, const void *m, const void *ani
   HIP_TRY(launch_tti_coef<T>(static_cast<const T *>(aniso), N, coef, st));
   double *part = reinterpret_cast<double *>(w + P->red.off);
   HIP_TRY(tti_power_iteration<T>(a, P->d.h, P->d.dt, coef, ringP, ringQ, ringP + ld, ringQ + ld,
-                                 ringP + 2 * ld, ringQ + 2 * ld, g, shape, g_stencil_blocks, iters,
+                                 ringP + 2 * ld, ringQ + 2 * ld, g, shape, kTtiBlocks, iters,
                                  (uint32_t)(seed ^ (seed >> 32)), part, st));
   double w2 = 0.0;
   HIP_TRY(hipMemcpyAsync(&w2, part + 1024, sizeof w2, hipMemcpyDeviceToHost, st));

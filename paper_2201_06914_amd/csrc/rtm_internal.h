@@ -118,7 +118,7 @@ hipError_t launch_stencil(int ndim, const StepArgs<T> &a, int variant, int targe
 // when no tiled kernel serves the grid), and the matching injection
 template <typename T>
 hipError_t launch_stencil_epi(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
-                              int epi, const EpiArgs<T> &e, hipStream_t st);
+                              int epi, const EpiArgs<T> &e, hipStream_t st, int rev = 0);
 template <typename T>
 hipError_t launch_inject_epi(const StepArgs<T> &a, const PointTables<T> &pt, const T *vals,
                              T *field, int epi, const EpiArgs<T> &e, hipStream_t st);

@@ -12,6 +12,8 @@
 //                     sits in LDS, double buffered, and the z neighbours in a
 //                     9-deep register queue per column.  Loads of plane z+1
 //                     are issued before plane z is computed.
+#include <algorithm>
+
 #include "step_common.h"
 
 namespace rtm {
@@ -96,6 +98,24 @@ __device__ __forceinline__ void st_stream(T *p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
+// Raw buffer loads over one level (N values): an offset at or past the end
+// returns zero, so a cell outside the grid takes the offset `end` (a select)
+// instead of a branch around its load.  NT: the non-temporal hint.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t level_rsrc(const T *f, uint32_t end) {
+  // gfx9 buffer descriptor word 3: 32-bit data format, no swizzle
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(f), (short)0, (int)end, 0x00020000);
+}
+template <bool NT>
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t o, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)o, 0, NT ? 2 : 0));
+}
+template <bool NT>
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t o, double) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, (int)o, 0, NT ? 2 : 0));
+}
+
 // element at a 32-bit byte offset from a base held in scalar registers (the
 // tiled kernels run on levels below 4 GiB)
 template <typename T>
@@ -149,10 +169,20 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
     yr[j] = y0 + ty + j * TYT;
     in[j] = (x < a.nx) && (yr[j] < a.ny);
   }
+  const uint32_t end = (uint32_t)a.N * (uint32_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t ru = level_rsrc(u, end), rp = level_rsrc(a.prev, end),
+                               rm = level_rsrc(a.m, end);
+  // no short circuit: one select per load
   auto ldu = [&](int zz, int yy, int xx) -> T {
-    return (zz >= 0 && zz < a.nz && yy >= 0 && yy < a.ny && xx >= 0 && xx < a.nx)
-               ? *at(u, off(zz, yy, xx))
-               : T(0);
+    const bool ok = (zz >= 0) & (zz < a.nz) & (yy >= 0) & (yy < a.ny) & (xx >= 0) & (xx < a.nx);
+    return bload<false>(ru, ok ? off(zz, yy, xx) : end, T(0));
+  };
+  // the cell's previous level and model value (m = 1 off the grid, never used)
+  auto ldpm = [&](int zz, int j, T &pvo, T &mmo) {
+    const uint32_t o = in[j] ? off(zz, yr[j], x) : end;
+    pvo = bload<NT>(rp, o, T(0));
+    const T mv = bload<NT>(rm, o, T(0));
+    mmo = in[j] ? mv : T(1);
   };
   // halo bookkeeping: y-halo rows hy = ty + TYT*k (LDS rows 0..3 and TY+4..TY+7),
   // x-halo cells t = tid + NTH*k over TY rows x 8 columns
@@ -189,8 +219,7 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
     for (int k = 0; k < 8; ++k) q[j][k] = ldu(zs + dz * (k - 4), yr[j], x);
     front[j] = ldu(zs + 4 * dz, yr[j], x);
     const uint32_t o = off(zs, yr[j], x);
-    pv[j] = in[j] ? ld_stream<T, NT>(at(a.prev, o)) : T(0);
-    mm[j] = in[j] ? ld_stream<T, NT>(at(a.m, o)) : T(1);
+    ldpm(zs, j, pv[j], mm[j]);
     if constexpr (EPI == EPI_CORR) {
       es[j] = in[j] ? ld_stream<T, NT>(at(e.s, o)) : T(0);
       eg[j] = in[j] ? *at(e.g, o) : T(0);
@@ -254,8 +283,7 @@ __device__ __forceinline__ void tiled_body(const StepArgs<T> &a, int bx, int by,
       for (int j = 0; j < RY; ++j) {
         front[j] = ldu(z + 5 * dz, yr[j], x);
         const uint32_t o = off(z + dz, yr[j], x);
-        pv[j] = in[j] ? ld_stream<T, NT>(at(a.prev, o)) : T(0);
-        mm[j] = in[j] ? ld_stream<T, NT>(at(a.m, o)) : T(1);
+        ldpm(z + dz, j, pv[j], mm[j]);
         if constexpr (EPI == EPI_CORR) {
           es[j] = in[j] ? ld_stream<T, NT>(at(e.s, o)) : T(0);
           eg[j] = in[j] ? *at(e.g, o) : T(0);
@@ -344,9 +372,10 @@ static void launch_tiled(const StepArgs<T> &a, int target_blocks, hipStream_t st
   // split z so that the launch has at least target_blocks workgroups of 256
   // threads' worth (fewer, larger workgroups for the 512 / 1024 thread shapes)
   const int64_t want = (int64_t)target_blocks * 256 / (TX * TYT);
-  int nzc = 1;
-  while ((int64_t)ntx * nty * nzc < want && a.nz / (nzc * 2) >= 16) nzc *= 2;
-  const int zchunk = (a.nz + nzc - 1) / nzc;
+  const int64_t tiles = (int64_t)ntx * nty;
+  int nzc = (int)std::min<int64_t>((want + tiles - 1) / tiles, std::max(1, a.nz / 16));
+  if (nzc < 1) nzc = 1;
+  const int zchunk = (a.nz + nzc - 1) / nzc;  // chunks of at least 16 planes
   nzc = (a.nz + zchunk - 1) / zchunk;
   hipLaunchKernelGGL((k_stencil3d_tiled<T, TX, TYT, RY, NT, EPI, EH>), dim3(ntx * nty * nzc),
                      dim3(TX * TYT), 0, st, a, ntx, nty, nzc, zchunk, e, rev);
@@ -406,18 +435,18 @@ template hipError_t launch_stencil<double>(int, const StepArgs<double> &, int, i
 // separate kernels.
 template <typename T>
 hipError_t launch_stencil_epi(int ndim, const StepArgs<T> &a, int variant, int target_blocks,
-                              int epi, const EpiArgs<T> &e, hipStream_t st) {
+                              int epi, const EpiArgs<T> &e, hipStream_t st, int rev) {
   if (ndim != 3 || sizeof(T) != 4 || variant < kStencilTiled ||
       a.N * (int64_t)sizeof(T) >= (int64_t(1) << 32))
     return hipErrorInvalidValue;
   if constexpr (sizeof(T) == 4) {
     const bool nt = variant != 1;
     if (epi == EPI_D2) {
-      if (nt) launch_tiled<T, 64, 4, 4, true, EPI_D2>(a, target_blocks, st, e);
-      else launch_tiled<T, 64, 4, 4, false, EPI_D2>(a, target_blocks, st, e);
+      if (nt) launch_tiled<T, 64, 4, 4, true, EPI_D2>(a, target_blocks, st, e, rev);
+      else launch_tiled<T, 64, 4, 4, false, EPI_D2>(a, target_blocks, st, e, rev);
     } else if (epi == EPI_CORR) {
-      if (nt) launch_tiled<T, 64, 4, 4, true, EPI_CORR>(a, target_blocks, st, e);
-      else launch_tiled<T, 64, 4, 4, false, EPI_CORR>(a, target_blocks, st, e);
+      if (nt) launch_tiled<T, 64, 4, 4, true, EPI_CORR>(a, target_blocks, st, e, rev);
+      else launch_tiled<T, 64, 4, 4, false, EPI_CORR>(a, target_blocks, st, e, rev);
     } else {
       return hipErrorInvalidValue;
     }
@@ -425,9 +454,9 @@ hipError_t launch_stencil_epi(int ndim, const StepArgs<T> &a, int variant, int t
   return hipGetLastError();
 }
 template hipError_t launch_stencil_epi<float>(int, const StepArgs<float> &, int, int, int,
-                                              const EpiArgs<float> &, hipStream_t);
+                                              const EpiArgs<float> &, hipStream_t, int);
 template hipError_t launch_stencil_epi<double>(int, const StepArgs<double> &, int, int, int,
-                                               const EpiArgs<double> &, hipStream_t);
+                                               const EpiArgs<double> &, hipStream_t, int);
 
 // Injection whose increment d = dt^2 acc / (m + a) also updates an
 // exact-comparator epilogue output: EPI_D2 adds d / dt^2 to the stored u_tt,

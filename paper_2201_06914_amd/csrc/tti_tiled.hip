@@ -493,6 +493,136 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused(TtiArgs<T> t, int n
 }
 
 // ---------------------------------------------------------------------------
+// forward, fused, with a plane ring in LDS: as k_tti_ffused, but the lead
+// plane z + 4 (p, q with its x / y halo and corners) stays in a ring of six
+// LDS planes and serves as the current plane four iterations later, so p and
+// q leave HBM once per step (k_tti_ffused loads the current plane's halo and
+// corners a second time).  Six slots: iteration z writes slot (z + 4) mod 6
+// while a slower thread may still read slot z - 1 (its current plane) or
+// slot z + 3 (its lead plane); both differ from it.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, int MINW>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, int ntx, int nty,
+                                                                  int nzc, int zchunk) {
+  using G = Geo<TY>;
+  constexpr int NR = 6;
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
+  __shared__ T Lr[NR][2][G::PL];  // plane ring: p, q with halo and corners
+  __shared__ T H[2][TY * G::LX];  // D_y p, D_y q of the current plane, all 72 columns
+  const int64_t N = a.N;
+  T Qp[9], Qq[9], Xp[9], Yp[9], Xq[9], Yq[9];  // p, q, D_x p, D_y p, D_x q, D_y q
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Qp[k] = T(0);
+    Qq[k] = T(0);
+    Xp[k] = Yp[k] = Xq[k] = Yq[k] = T(0);
+  }
+  // prefetched values of the next iteration
+  T fp, fq;                                      // lead interior
+  T lyp[G::NHY], lyq[G::NHY], lxp, lxq, lcp, lcq; // lead halo and corners
+  T pp, qp, mm, c1, c2, nz, ny, nx;              // current cell
+  const bool corner = threadIdx.x >= G::NHX && threadIdx.x < G::NHX + 64;
+  auto fetch = [&](int z) {  // iteration z: lead plane z + 4, current cell at z
+    const int zl = z + 4;
+    fp = ldz(t.p, a, g.in, zl, g.y, g.x);
+    fq = ldz(t.q, a, g.in, zl, g.y, g.x);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      lyp[k] = ldz(t.p, a, g.hyon[k], zl, g.hyg[k], g.x);
+      lyq[k] = ldz(t.q, a, g.hyon[k], zl, g.hyg[k], g.x);
+    }
+    lxp = ldz(t.p, a, g.hxon, zl, g.hxg_y, g.hxg_x);
+    lxq = ldz(t.q, a, g.hxon, zl, g.hxg_y, g.hxg_x);
+    lcp = ldz(t.p, a, g.cnon, zl, g.cng_y, g.cng_x);
+    lcq = ldz(t.q, a, g.cnon, zl, g.cng_y, g.cng_x);
+    const bool oc = z >= z0 && g.in;
+    pp = ldz(t.pp, a, oc, z, g.y, g.x);
+    qp = ldz(t.qp, a, oc, z, g.y, g.x);
+    mm = ldz(a.m, a, oc, z, g.y, g.x);
+    c1 = ldz(t.coef, a, oc, z, g.y, g.x);
+    c2 = ldz(t.coef + N, a, oc, z, g.y, g.x);
+    nz = ldz(t.coef + 2 * N, a, oc, z, g.y, g.x);
+    ny = ldz(t.coef + 3 * N, a, oc, z, g.y, g.x);
+    nx = ldz(t.coef + 4 * N, a, oc, z, g.y, g.x);
+  };
+  auto slot = [](int plane) { return (plane + 12 * NR) % NR; };  // plane >= z0 - 4 >= -4
+  const int zs = z0 - 8;
+  fetch(zs);
+  for (int z = zs; z < z1; ++z) {
+    const bool out = z >= z0;  // uniform over the workgroup
+    Qp[8] = fp;
+    Qq[8] = fq;
+    const T cpp = pp, cqp = qp, cm = mm, cc1 = c1, cc2 = c2, cnz = nz, cny = ny, cnx = nx;
+    T *Llp = Lr[slot(z + 4)][0], *Llq = Lr[slot(z + 4)][1];
+    Llp[g.lc] = fp;
+    Llq[g.lc] = fq;
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      Llp[g.hyl[k]] = lyp[k];
+      Llq[g.hyl[k]] = lyq[k];
+    }
+    if (threadIdx.x < G::NHX) {
+      Llp[g.hxl] = lxp;
+      Llq[g.hxl] = lxq;
+    }
+    if (corner) {
+      Llp[g.cnl] = lcp;
+      Llq[g.cnl] = lcq;
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    // queue fronts: first differences of the lead plane
+    Xp[8] = d1l(t, Llp + g.lc, 1);
+    Yp[8] = d1l(t, Llp + g.lc, G::LX);
+    Xq[8] = d1l(t, Llq + g.lc, 1);
+    Yq[8] = d1l(t, Llq + g.lc, G::LX);
+    const T *Lp = Lr[slot(z)][0], *Lq = Lr[slot(z)][1];
+    if (out) {
+      const int hr = threadIdx.x / TX, hc = threadIdx.x % TX + 4;
+      H[0][hr * G::LX + hc] = d1l(t, Lp + g.lc, G::LX);
+      H[1][hr * G::LX + hc] = d1l(t, Lq + g.lc, G::LX);
+      if (threadIdx.x < G::NHX) {
+        const int r = threadIdx.x / 8, lcx = g.hxl - (4 + r) * G::LX;
+        H[0][r * G::LX + lcx] = d1l(t, Lp + g.hxl, G::LX);
+        H[1][r * G::LX + lcx] = d1l(t, Lq + g.hxl, G::LX);
+      }
+    }
+    __syncthreads();
+    if (out && g.in) {
+      const int hrow = (threadIdx.x / TX) * G::LX + threadIdx.x % TX + 4;
+      const T pzz = d2q(t, Qp), qzz = d2q(t, Qq);
+      const T pxx = d2l(t, Lp + g.lc, 1), qxx = d2l(t, Lq + g.lc, 1);
+      const T pyy = d2l(t, Lp + g.lc, G::LX), qyy = d2l(t, Lq + g.lc, G::LX);
+      const T pxy = d1l(t, H[0] + hrow, 1), qxy = d1l(t, H[1] + hrow, 1);
+      const T pxz = d1q(t, Xp), qxz = d1q(t, Xq);
+      const T pyz = d1q(t, Yp), qyz = d1q(t, Yq);
+      const T lp = (pzz + pyy) + pxx;
+      const T mix_p = (cnx * cny) * pxy + (cnx * cnz) * pxz + (cny * cnz) * pyz;
+      const T mix_q = (cnx * cny) * qxy + (cnx * cnz) * qxz + (cny * cnz) * qyz;
+      const T hzp = ((cnz * cnz) * pzz + (cny * cny) * pyy + (cnx * cnx) * pxx) + T(2) * mix_p;
+      const T hzq = ((cnz * cnz) * qzz + (cny * cny) * qyy + (cnx * cnx) * qxx) + T(2) * mix_q;
+      const T h0p = lp - hzp;
+      const T damp = sponge_a(a, z, g.y, g.x);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      sto(t.pn, o, tti_update(a, Qp[4], cpp, cm, cc1 * h0p + cc2 * hzq, damp));
+      sto(t.qn, o, tti_update(a, Qq[4], cqp, cm, cc2 * h0p + hzq, damp));
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      Qp[k] = Qp[k + 1];
+      Qq[k] = Qq[k + 1];
+      Xp[k] = Xp[k + 1];
+      Yp[k] = Yp[k + 1];
+      Xq[k] = Xq[k + 1];
+      Yq[k] = Yq[k + 1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // adjoint, in-plane: g0 = w1, g1 = w2, g2 = E_xz(w1), g3 = E_xz(w2),
 // g4 = E_xy(w1), g5 = E_xy(w2)
 // ---------------------------------------------------------------------------
@@ -881,7 +1011,8 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
 
 // one TTI step with the tiled kernels (prep with TYP rows, march with TYM
 // rows); g needs 4 (forward) / 6 (adjoint) slots of N
-template <typename T, int TYP, int TYM, bool FUSED = false, bool AFUSED = false>
+// FUSED: 1 = fused forward kernel, 2 = fused forward kernel with the LDS plane ring
+template <typename T, int TYP, int TYM, int FUSED = 0, bool AFUSED = false>
 static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
@@ -889,9 +1020,16 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
   const TtiGrid gm = tti_grid(a.nz, a.ny, a.nx, TYM, target_blocks);
   const dim3 bp(TX * TYP), bm(TX * TYM);
   const dim3 np(gp.ntx * gp.nty * gp.nzc), nm(gm.ntx * gm.nty * gm.nzc);
-  if constexpr (FUSED) {
+  if constexpr (FUSED == 1) {
     if (!adjoint) {
       hipLaunchKernelGGL((k_tti_ffused<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
+                         gm.zchunk);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (FUSED == 2) {
+    if (!adjoint) {
+      hipLaunchKernelGGL((k_tti_ffused_ring<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
                          gm.zchunk);
       return hipGetLastError();
     }
@@ -919,9 +1057,10 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 
 // tile shapes (prep / march rows of 64 columns): 1 = 8 / 8, 2 = 4 / 4,
 // 3 = 8 / 4, 4 = as 3 with the fused forward kernel (4 rows), 5 = as 3 with
-// the fused forward kernel (8 rows), 6 = both steps fused (4 rows), 7 (the
-// library's default) = both fused, forward 4 rows and transpose 8 rows,
-// 8 = both fused (8 rows)
+// the fused forward kernel (8 rows), 6 = both steps fused (4 rows), 7 = both
+// fused, forward 4 rows and transpose 8 rows,
+// 8 = both fused (8 rows), 9 (the library's default) / 10 = as 7 with the
+// forward kernel's LDS plane ring (forward on 4 / 8 rows)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -929,13 +1068,17 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
     case 1: return tti_step_tiled<T, 8, 8>(t, adjoint, target_blocks, st);
     case 2: return tti_step_tiled<T, 4, 4>(t, adjoint, target_blocks, st);
     case 5: return adjoint ? tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st)
-                           : tti_step_tiled<T, 8, 8, true>(t, adjoint, target_blocks, st);
+                           : tti_step_tiled<T, 8, 8, 1>(t, adjoint, target_blocks, st);
     case 3: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
-    case 4: return tti_step_tiled<T, 8, 4, true>(t, adjoint, target_blocks, st);
-    case 7: return adjoint ? tti_step_tiled<T, 8, 8, true, true>(t, adjoint, target_blocks, st)
-                           : tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);
-    case 8: return tti_step_tiled<T, 8, 8, true, true>(t, adjoint, target_blocks, st);
-    default: return tti_step_tiled<T, 8, 4, true, true>(t, adjoint, target_blocks, st);  // 6
+    case 4: return tti_step_tiled<T, 8, 4, 1>(t, adjoint, target_blocks, st);
+    case 7: return adjoint ? tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st)
+                           : tti_step_tiled<T, 8, 4, 1, true>(t, adjoint, target_blocks, st);
+    case 8: return tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st);
+    case 9: return adjoint ? tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st)
+                           : tti_step_tiled<T, 8, 4, 2, true>(t, adjoint, target_blocks, st);
+    case 10: return adjoint ? tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 8, 2, true>(t, adjoint, target_blocks, st);
+    default: return tti_step_tiled<T, 8, 4, 1, true>(t, adjoint, target_blocks, st);  // 6
   }
 }
 

@@ -134,6 +134,7 @@ def autotune_batch(specs, shots, variants=(1, 3, 7, 11, 12), blocks=(2048, 4096,
     tshots = [dict(sh, q=sh["q"][:nt].contiguous(), Z=sh["Z"][:nt].contiguous(),
                    d_obs=sh["d_obs"][:nt].contiguous()) for sh in shots]
     ms = {}
+    blocks_before = api.get_stencil_blocks()
     for b in blocks:
         api.set_stencil_blocks(b)
         B = api.Batch(tspecs)
@@ -147,7 +148,7 @@ def autotune_batch(specs, shots, variants=(1, 3, 7, 11, 12), blocks=(2048, 4096,
                                                                    work=work)) / nt, 4)
         del B, outs, work
         torch.cuda.empty_cache()
-    api.set_stencil_blocks(2048)
+    api.set_stencil_blocks(blocks_before)
     best = min(ms, key=ms.get)
     v, b = (int(x) for x in best.split("/"))
     res = {"best": [v, b], "ms_per_step": ms, "steps_timed": nt}

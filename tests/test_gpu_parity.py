@@ -375,11 +375,13 @@ def test_autotuner_race_check_all_variants_bitwise_equal():
     wl = synth.workload_small_3d(shape=(45, 37, 83), nt=10)
     plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=4)
     res = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=3, apply=False)
-    say(f"  autotune: best {res['best']} us {res['us']} mismatch {res['mismatch']}")
+    say(f"  autotune: best {res['best']} blocks {res['blocks']} us {res['us']} "
+        f"mismatch {res['mismatch']}")
     assert res["mismatch"] == [0] * len(res["mismatch"])
-    assert res["us"][res["best"]] == min(res["us"])   # on a grid this small variant 0 may win
+    # the pick is the fastest (variant, z-split target); on a grid this small
+    # variant 0 may win
+    assert res["us"][res["blocks"]][res["best"]] == min(min(u) for u in res["us"].values())
     for blocks in (64, 4096):          # z-chunking changes, results must not
-        P.set_stencil_blocks(blocks)
-        r2 = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=1, apply=False)
+        r2 = P.autotune_stencil(plan, dev(wl.m, torch.float32), steps=1, apply=False,
+                                blocks=(blocks,))
         assert r2["mismatch"] == [0] * len(r2["mismatch"])
-    P.set_stencil_blocks(2048)  # the default

@@ -38,7 +38,7 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(7)  # the default
+    P.set_tti_shape(9)  # the default
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
@@ -46,7 +46,8 @@ def variant(request):
                                            ((-1, 3), (40, 21, 70)), ((-1, 4), (40, 21, 70)),
                                            ((-1, 5), (40, 21, 70)), ((-1, 6), (40, 21, 70)),
                                            ((-1, 6), (18, 16, 20)), ((-1, 7), (40, 21, 70)),
-                                           ((-1, 8), (40, 21, 70))],
+                                           ((-1, 8), (40, 21, 70)), ((-1, 9), (40, 21, 70)),
+                                           ((-1, 9), (18, 16, 20)), ((-1, 10), (40, 21, 70))],
                          indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
@@ -128,7 +129,7 @@ def test_tti_f32_bf16x2_fused_gradient():
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
 
 
-@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8])
+@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10])
 def test_tti_f32_tiled_equals_simple_kernels(shape):
     """The tiled TTI step (mixed terms once per unordered pair, intermediates
     staged per plane) against the one-thread-per-cell step on the same FP32
@@ -153,7 +154,7 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
-            P.set_tti_shape(7)  # the default
+            P.set_tti_shape(9)  # the default
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
     say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
         " ".join(f"{k} {v:.2e}" for k, v in e.items()))
