@@ -234,8 +234,11 @@ def bench_batched(nt: int):
     from paper_2201_06914_amd.tune import autotune_batch
     tuned = autotune_batch(specs, shots)
     variant, blocks = tuned["best"]
-    print(f"batched: tuned variant {variant}, z-split target {blocks}", file=sys.stderr,
+    kb = tuned["k_block"]
+    print(f"batched: tuned variant {variant}, z-split target {blocks}, k {kb}", file=sys.stderr,
           flush=True)
+    import dataclasses
+    specs = [dataclasses.replace(sp, k_block=kb) for sp in specs]
     blocks_before = P.api.get_stencil_blocks()
     P.set_stencil_blocks(blocks)
     B = P.Batch(specs)
@@ -273,7 +276,8 @@ def bench_batched(nt: int):
     t_single = timed(one_by_one)
     print("batched: one-by-one done", file=sys.stderr, flush=True)
     return {"workload": f"16 shots, windows 128^3..256x320x320 ({cells} cells), nt={nt}, "
-                        f"r=64, k=32, bf16x2, fused imaging",
+                        f"r=64, k={kb} (autotuned), bf16x2, fused imaging",
+            "k_block": kb, "autotune_k_ms_per_step": tuned.get("k_ms_per_step"),
             "value": round(2.0 * cells * nt / (t_graph * 1e-3) / 1e9, 2),
             "unit": "Gcell-updates/s", "ms_per_gradient_graph": round(t_graph, 1),
             "ms_per_gradient_eager": round(t_eager, 1),
@@ -318,8 +322,14 @@ def bench_rsweep(n: int, nt: int, variant: int):
         out = fn()
         torch.cuda.synchronize()
         return out, (time.perf_counter() - t) * 1e3
-    # exact gradient, 4 shots
+    # this grid's own stencil choice (the headline's tuned z-split need not
+    # suit it); every run below, exact and probed, uses it
     pe = P.Plan(spec(16))
+    tuned = P.autotune_stencil(pe, mb, steps=10)
+    print(f"rsweep: stencil variant {tuned['best']}, z-split {tuned['blocks']}", file=sys.stderr,
+          flush=True)
+    variant = tuned["best"]
+    # exact gradient, 4 shots
     ewb = P.exact_workspace_bytes(pe)
     ework = torch.empty(ewb, dtype=torch.uint8, device="cuda")
 
@@ -406,6 +416,7 @@ def bench_rsweep(n: int, nt: int, variant: int):
         print(f"rsweep: range finder r={r} done", file=sys.stderr, flush=True)
     return {"workload": f"{n}^3 salt model, 4 shots, nt={nt}, h=12.5 m, 10 Hz, gradient at the "
                         f"smoothed model, d_obs modelled from the true model",
+            "stencil": {"variant": tuned["best"], "z_split_target": tuned["blocks"]},
             "range_finder": rf_rows,
             "exact_ms": round(t_exact, 1),
             "exact_memory_gb_per_shot": round(ewb / 1e9, 2),
@@ -437,9 +448,9 @@ def bench_fwi(n: int, nt: int, iters: int, r: int, variant: int):
                       "f32", "bf16x2", r, 32, 1, rec.shape[0])
     p_obs = P.Plan(spec)
     shots = [fwi.Shot(s, q, rec, P.rtm_forward_probe(p_obs, mt, s, q, rec)["d"]) for s in srcs]
+    P.autotune_stencil(p_obs, mb, steps=10)   # this grid's stencil choice, applied
     del p_obs
     torch.cuda.empty_cache()
-    P.set_stencil_variant(variant)
     out = {}
     for name, exact in (("probed", False), ("exact", True)):
         torch.cuda.synchronize()

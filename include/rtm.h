@@ -147,6 +147,20 @@ void rtm_set_stencil_blocks(int32_t blocks);
  * and downwards on odd ones, so a step begins on the planes the previous step
  * touched last; 0 marches upwards always.  Bitwise-identical results. */
 void rtm_set_stencil_alternate(int32_t on);
+/* Tuning hook, process wide: with on != 0 (default) the fast probe-GEMM
+ * kernels read and write the compressed fields with the non-temporal hint
+ * (each byte is touched once per block); 0 uses ordinary loads and stores.
+ * Same results. */
+void rtm_set_probe_nt(int32_t on);
+/* Tuning hook, process wide: with on != 0, fwi_gradient captures its launch
+ * sequence (everything after the point-table upload) into a HIP graph the
+ * first time it sees a set of arguments (plan, pointers, point counts,
+ * stream, kernel choices) and replays that graph on later calls with the
+ * same set (default 0: launches one by one).  Capture and replay run on an
+ * internal non-blocking stream of the device, ordered after `stream`'s
+ * earlier work and before its later work by events.  Up to 8 graphs are
+ * kept, the oldest dropped; results equal the eager launches bit for bit. */
+void rtm_set_graph(int32_t on);
 /* Autotuner and race check for the stencil: runs one step of every variant
  * (0..13 in 3D, 0 in 2D) from the same pattern levels in the ring of `work`,
  * counts elements that differ bitwise from variant 0 in either z-marching
@@ -357,9 +371,13 @@ void rtm_set_exact_fused(int32_t on);
  * 2 = 4 / 4, 3 = 8 / 4; 4 and 5: as 3 for the transpose step, and the forward
  * step as one fused kernel of 4 or 8 rows; 6: both steps as one fused
  * kernel each (4 rows); 7: both fused, the forward step on 4 rows and the
- * transpose step on 8 rows; 8: both fused on 8 rows; 9 (default) and 10: as
- * 7 with the forward step keeping its planes in an LDS ring (p and q read
- * once per step), on 4 and 8 rows; other values select 9.
+ * transpose step on 8 rows; 8: both fused on 8 rows; 9 and 10: as 7 with
+ * the forward step keeping its planes in an LDS ring (p and q read once per
+ * step), on 4 and 8 rows; 11 and 12: as 9 with the transpose step keeping
+ * its halo cells' values from the lead plane in register queues (no second
+ * load), on 8 and 4 rows; 13, 14 and 15 (default): as 11 with those queues in
+ * a per-thread LDS ring and 1, 2 or 3 planes per loop trip; other values
+ * select 15.
  * rtm_set_stencil_variant(0) forces the one-thread-per-cell TTI kernels
  * instead.  Results agree to rounding. */
 void rtm_set_tti_shape(int32_t shape);

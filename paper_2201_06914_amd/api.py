@@ -229,6 +229,16 @@ def set_stencil_variant(v: int) -> None:
 N_STENCIL_VARIANTS = 14
 
 
+def set_probe_nt(on: bool) -> None:
+    """Non-temporal compressed-field traffic in the probe kernels (default on)."""
+    _lib.load().rtm_set_probe_nt(1 if on else 0)
+
+
+def set_graph(on: bool) -> None:
+    """fwi_gradient captures and replays HIP graphs (per set of arguments)."""
+    _lib.load().rtm_set_graph(1 if on else 0)
+
+
 def set_stencil_alternate(on: bool) -> None:
     """Tiled stencil marches z up / down on alternate steps (default on)."""
     _lib.load().rtm_set_stencil_alternate(1 if on else 0)

@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,8 +35,9 @@ static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled va
 static int g_stencil_blocks = 2048; // tiled stencil: split z until this many workgroups
 static const int kTtiBlocks = 2048; // tiled TTI kernels: the same, fixed
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
-static int g_tti_shape = 9;         // tiled TTI tile shape (1..10)
+static int g_tti_shape = 15;        // tiled TTI tile shape (1..15)
 static int g_stencil_alternate = 1; // sweeps: tiled stencil marches z up / down on alternate steps
+static int g_graph = 0;             // fwi_gradient: capture and replay HIP graphs
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
@@ -191,8 +193,10 @@ extern "C" void rtm_set_stencil_variant(int v) {
 
 extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
 extern "C" void rtm_set_stencil_alternate(int32_t on) { g_stencil_alternate = on ? 1 : 0; }
+extern "C" void rtm_set_probe_nt(int32_t on) { set_probe_nt(on); }
+extern "C" void rtm_set_graph(int32_t on) { g_graph = on ? 1 : 0; }
 
-extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 10) ? shape : 9; }
+extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 15) ? shape : 15; }
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
   g_stencil_blocks = blocks > 0 ? blocks : 2048;
@@ -860,6 +864,84 @@ extern "C" rtm_status rtm_dot(const rtm_plan *P, const void *a, const void *b, i
   return RTM_OK;
 }
 
+// Graphs of single-shot launch sequences (rtm_set_graph): keyed by a hash of
+// everything baked into the launches (plan, pointers, point counts, kernel
+// choices); at most kGraphCache kept, the oldest dropped.  Shared by all
+// threads (a mutex guards the table; a replay itself is a stream launch).
+struct GraphEntry {
+  uint64_t key;
+  hipGraphExec_t exec;
+};
+static std::mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;
+static const size_t kGraphCache = 8;
+
+static uint64_t key_mix(uint64_t k, uint64_t v) { return (k ^ v) * 1099511628211ull; }
+
+// The graphs are captured and replayed on an internal non-blocking stream of
+// the current device (the caller's stream may be the legacy default stream,
+// which cannot be captured), ordered after the caller's stream and before its
+// later work by two events.
+struct GraphStream {
+  hipStream_t s = nullptr;
+  hipEvent_t in = nullptr, out = nullptr;
+};
+static GraphStream g_gstream[64];
+
+// runs `body` (stream-ordered launches on the stream it is given) eagerly on
+// st, or through a cached graph when graphs are on; capture is thread-local
+// and records no timing events
+template <typename F>
+static rtm_status run_launches(uint64_t key, hipStream_t st, F body) {
+  if (!g_graph) return body(st);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(RTM_E_UNSUPPORTED, "graphs: device index above 63");
+  key = key_mix(key, (uint64_t)g_stencil_variant + 1000);
+  key = key_mix(key, (uint64_t)g_stencil_blocks);
+  key = key_mix(key, (uint64_t)g_stencil_alternate + 77);
+  key = key_mix(key, (uint64_t)get_probe_nt() + 99);
+  key = key_mix(key, (uint64_t)dev);
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  GraphStream &gs = g_gstream[dev];
+  if (!gs.s) {
+    HIP_TRY(hipStreamCreateWithFlags(&gs.s, hipStreamNonBlocking));  // default priority
+    HIP_TRY(hipEventCreateWithFlags(&gs.in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&gs.out, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(gs.in, st));
+  HIP_TRY(hipStreamWaitEvent(gs.s, gs.in, 0));
+  hipGraphExec_t exec = nullptr;
+  for (const GraphEntry &e : g_graphs)
+    if (e.key == key) exec = e.exec;
+  if (!exec) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(gs.s, hipStreamCaptureModeThreadLocal));
+    const int saved = g_prof_stride;
+    g_prof_stride = 0;
+    rtm_status s = body(gs.s);
+    g_prof_stride = saved;
+    hipError_t e = hipStreamEndCapture(gs.s, &g);
+    if (s) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(RTM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(RTM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    if (g_graphs.size() >= kGraphCache) {
+      (void)hipGraphExecDestroy(g_graphs.front().exec);
+      g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back({key, exec});
+  }
+  HIP_TRY(hipGraphLaunch(exec, gs.s));
+  HIP_TRY(hipEventRecord(gs.out, gs.s));
+  HIP_TRY(hipStreamWaitEvent(st, gs.out, 0));
+  return RTM_OK;
+}
+
 template <typename T>
 static rtm_status gradient_impl(const rtm_plan *P, const void *m, const double *src_pos,
                                 const void *q, const double *rec_pos, const void *d_obs,
@@ -868,48 +950,66 @@ static rtm_status gradient_impl(const rtm_plan *P, const void *m, const double *
                                 double scale) {
   PointTables<T> src_t, rec_t;
   char *w = static_cast<char *>(work);
-  rtm_status s = upload_points<T>(P, w, st, src_pos, &src_t, rec_pos, &rec_t);
-  if (s) return s;
-  SweepIO f;
-  f.adjoint = false;
-  f.m = m;
-  f.inj_vals = q;
-  f.smp_out = resid;  // d_pred first, turned into the residual below
-  f.Z = Z;
-  f.zt = zt;
-  f.mode = PROBE_UTT;
-  f.bar = Ubar;
-  if ((s = run_sweep<T>(P, f, src_t, rec_t, w, st))) return s;
-  double *part = reinterpret_cast<double *>(w + P->red.off);
-  const int64_t nd = (int64_t)P->d.nt * P->d.nrec;
-  HIP_TRY(launch_residual_misfit<T>(static_cast<const T *>(resid), static_cast<const T *>(d_obs),
-                                    static_cast<T *>(resid), nd, part, misfit, st));
-  SweepIO b;
-  b.adjoint = true;
-  b.m = m;
-  b.inj_vals = resid;
-  b.Z = Z;
-  b.zt = zt;
-  b.mode = PROBE_NEW;
-  b.bar = Vbar;
-  PointTables<T> none;
-  if (!Vbar) {  // fused imaging: the adjoint blocks add straight into grad
-    HIP_TRY(launch_fill<T>(static_cast<T *>(grad), P->N, T(0), st));
-    b.fuse_U = Ubar;
-    b.fuse_img = grad;
-    b.fuse_scale = scale;
-    if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
-  } else {
-    if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
-    TimedLaunch ti;
-    prof_begin(KT_IMAGE, 0, st, &ti);
-    HIP_TRY(launch_image<T>(static_cast<const T *>(Ubar), static_cast<const T *>(Vbar), P->N,
-                            P->d.r, scale, static_cast<T *>(grad), st));
-    prof_end(st, &ti);
+  rtm_status s0 = upload_points<T>(P, w, st, src_pos, &src_t, rec_pos, &rec_t);
+  if (s0) return s0;
+  uint64_t key = 1469598103934665603ull;
+  {  // the plan's parameters (a new plan may reuse an old one's address)
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&P->d);
+    for (size_t i = 0; i < sizeof(P->d); ++i) key = key_mix(key, b[i]);
+    key = key_mix(key, (uint64_t)P->total);
   }
-  HIP_TRY(launch_flag_nonfinite<T>(static_cast<const T *>(grad), P->N, status_word(P, w), st));
-  HIP_TRY(launch_flag_nonfinite<double>(misfit, 1, status_word(P, w), st));
-  return RTM_OK;
+  for (const void *p : {(const void *)P, m, q, d_obs, Z, (const void *)Ubar, (const void *)Vbar,
+                        (const void *)resid, (const void *)grad, (const void *)misfit,
+                        (const void *)work})
+    key = key_mix(key, (uint64_t)(uintptr_t)p);
+  key = key_mix(key, (uint64_t)zt);
+  key = key_mix(key, (uint64_t)src_t.ncell * 4096 + (uint64_t)src_t.npts);
+  key = key_mix(key, (uint64_t)rec_t.ncell * 4096 + (uint64_t)rec_t.npts);
+  key = key_mix(key, (uint64_t)(scale * 1e6));
+  return run_launches(key, st, [&](hipStream_t ls) -> rtm_status {
+    hipStream_t st = ls;  // the stream the launches go to (caller's, or the capture stream)
+    rtm_status s;
+    SweepIO f;
+    f.adjoint = false;
+    f.m = m;
+    f.inj_vals = q;
+    f.smp_out = resid;  // d_pred first, turned into the residual below
+    f.Z = Z;
+    f.zt = zt;
+    f.mode = PROBE_UTT;
+    f.bar = Ubar;
+    if ((s = run_sweep<T>(P, f, src_t, rec_t, w, st))) return s;
+    double *part = reinterpret_cast<double *>(w + P->red.off);
+    const int64_t nd = (int64_t)P->d.nt * P->d.nrec;
+    HIP_TRY(launch_residual_misfit<T>(static_cast<const T *>(resid), static_cast<const T *>(d_obs),
+                                      static_cast<T *>(resid), nd, part, misfit, st));
+    SweepIO b;
+    b.adjoint = true;
+    b.m = m;
+    b.inj_vals = resid;
+    b.Z = Z;
+    b.zt = zt;
+    b.mode = PROBE_NEW;
+    b.bar = Vbar;
+    PointTables<T> none;
+    if (!Vbar) {  // fused imaging: the adjoint blocks add straight into grad
+      HIP_TRY(launch_fill<T>(static_cast<T *>(grad), P->N, T(0), st));
+      b.fuse_U = Ubar;
+      b.fuse_img = grad;
+      b.fuse_scale = scale;
+      if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
+    } else {
+      if ((s = run_sweep<T>(P, b, rec_t, none, w, st))) return s;
+      TimedLaunch ti;
+      prof_begin(KT_IMAGE, 0, st, &ti);
+      HIP_TRY(launch_image<T>(static_cast<const T *>(Ubar), static_cast<const T *>(Vbar), P->N,
+                              P->d.r, scale, static_cast<T *>(grad), st));
+      prof_end(st, &ti);
+    }
+    HIP_TRY(launch_flag_nonfinite<T>(static_cast<const T *>(grad), P->N, status_word(P, w), st));
+    HIP_TRY(launch_flag_nonfinite<double>(misfit, 1, status_word(P, w), st));
+    return RTM_OK;
+  });
 }
 
 extern "C" rtm_status fwi_gradient(const rtm_plan *P, const void *m, const double *src_pos,

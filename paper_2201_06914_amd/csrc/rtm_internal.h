@@ -192,6 +192,8 @@ hipError_t launch_probe_vec(const ProbeArgs<T> &p, const void *Z, bool z_is_i8,
 // (img[c] += scale * sum_i Uf[i][c] (Z_b^T S_b)[i][c]; p.bar unused).
 // Z is int8 +-1, or with zf32 real FP32 probes split into bf16 hi + lo (needs
 // split).
+void set_probe_nt(int on);
+int get_probe_nt();
 hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const void *Z, bool zf32, int op,
                              const float *Uf, float *img, float scale, hipStream_t st);
 // exact imaging: out = (un - 2 u0 + um) * inv_dt2 ; g -= s * lam

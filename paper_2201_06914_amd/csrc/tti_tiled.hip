@@ -168,6 +168,17 @@ __device__ __forceinline__ T tti_update(const StepArgs<T> &a, T u, T up, T m, T 
   return (T(2) * m * u - (m - damp) * up + a.dt2 * rhs) / (m + damp);
 }
 
+// the p and q updates of one cell share the denominator m + damp: one
+// division and two products instead of two divisions
+template <typename T>
+__device__ __forceinline__ void tti_update_pq(const StepArgs<T> &a, T m, T damp, T u, T up,
+                                              T rhs_p, T w, T wp, T rhs_q, T &pn, T &qn) {
+  const T inv = T(1) / (m + damp);
+  const T m2 = T(2) * m, md = m - damp;
+  pn = (m2 * u - md * up + a.dt2 * rhs_p) * inv;
+  qn = (m2 * w - md * wp + a.dt2 * rhs_q) * inv;
+}
+
 // block -> (tile, z-chunk), XCD-aware as in the acoustic kernel
 __device__ __forceinline__ void block_of(int ntx, int nty, int nzc, int zchunk, int nz, int &bx,
                                          int &by, int &z0, int &z1) {
@@ -607,8 +618,11 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, 
       const T h0p = lp - hzp;
       const T damp = sponge_a(a, z, g.y, g.x);
       const uint32_t o = cidx(a, z, g.y, g.x);
-      sto(t.pn, o, tti_update(a, Qp[4], cpp, cm, cc1 * h0p + cc2 * hzq, damp));
-      sto(t.qn, o, tti_update(a, Qq[4], cqp, cm, cc2 * h0p + hzq, damp));
+      T pn, qn;
+      tti_update_pq(a, cm, damp, Qp[4], cpp, cc1 * h0p + cc2 * hzq, Qq[4], cqp, cc2 * h0p + hzq,
+                    pn, qn);
+      sto(t.pn, o, pn);
+      sto(t.qn, o, qn);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -993,6 +1007,245 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int n
   }
 }
 
+// adjoint, fused, with delay queues for the halo: as k_tti_afused, but the
+// halo and corner cells of the current plane are not loaded again: their w1,
+// w2, n_x and n_y are taken at the lead stage (corners are loaded there too)
+// and kept in 5-deep register queues until their plane is the current one.
+// HLQ (FP32 only): those queues live in a per-thread ring of five LDS planes
+// instead of registers; each thread reads back only what it wrote itself, so
+// the ring needs no barrier, and the 60 registers it frees let the loop
+// carry U planes per trip.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, int MINW, int U, bool HLQ>
+__global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, int ntx, int nty,
+                                                             int nzc, int zchunk) {
+  using G = Geo<TY>;
+  const StepArgs<T> &a = t.a;
+  int bx, by, z0, z1;
+  block_of(ntx, nty, nzc, zchunk, a.nz, bx, by, z0, z1);
+  const TtiTile<TY> g = tile_of<TY>(a, bx, by);
+  // current plane: w1, n_x^2 w1, n_y^2 w1, n_x^2 w2, n_y^2 w2, n_x n_y w1, n_x n_y w2
+  // (NB buffers: plane z writes buffer z & 1 while others may still read z - 1's)
+  constexpr int NB = (sizeof(T) == 8 && TY == 8) ? 1 : 2;
+  __shared__ T LcB[NB][7][G::PL];
+  __shared__ T Ll[4][G::PL];      // lead plane: n_x n_z w1, n_x n_z w2, n_y n_z w1, n_y n_z w2
+  __shared__ T H[2][TY * G::LX];  // D_y (n_x n_y w1), D_y (n_x n_y w2)
+  constexpr bool HL = HLQ && sizeof(T) == 4;
+  typedef T V4 __attribute__((ext_vector_type(4)));  // (w1, w2, n_x, n_y) of a halo cell
+  constexpr int NHQ = G::NHY * G::NTHR + 128;        // y halo, then x halo or corner
+  __shared__ V4 Hq[HL ? 5 : 1][HL ? NHQ : 1];
+  auto hslot = [](int plane) { return (plane + 10) % 5; };  // plane >= z0 - 8 >= -8
+  const int hxi = G::NHY * G::NTHR + threadIdx.x;  // x-halo (tid < NHX) or corner slot
+  const bool corner = threadIdx.x >= G::NHX && threadIdx.x < G::NHX + 64;
+  const int64_t N = a.N;
+  const T *c1f = t.coef, *c2f = t.coef + N, *nzf = t.coef + 2 * N, *nyf = t.coef + 3 * N,
+          *nxf = t.coef + 4 * N;
+  struct In {
+    T lp, lq, c1, c2, nz, ny, nx;
+  };
+  auto load = [&](bool on, int z, int y, int x, bool withz) {
+    In c;
+    c.lp = ldz(t.p, a, on, z, y, x);
+    c.lq = ldz(t.q, a, on, z, y, x);
+    c.c1 = ldz(c1f, a, on, z, y, x);
+    c.c2 = ldz(c2f, a, on, z, y, x);
+    c.nz = withz ? ldz(nzf, a, on, z, y, x) : T(0);
+    c.ny = ldz(nyf, a, on, z, y, x);
+    c.nx = ldz(nxf, a, on, z, y, x);
+    return c;
+  };
+  T W[9], Z1[9], Z2[9], E1[9], E2[9];               // z queues
+  T Dw2[5], Dnx[5], Dny[5], Dlp[5], Dlq[5];         // delays: [4] lead plane, [0] plane z
+  // the halo and corner cells' w1, w2, n_x, n_y, kept from the lead stage
+  // until their plane is the current one (no second load of those cells)
+  T Hy[G::NHY][4][5], Hx[4][5], Hc[4][5];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W[k] = Z1[k] = Z2[k] = E1[k] = E2[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    Dw2[k] = Dnx[k] = Dny[k] = Dlp[k] = Dlq[k] = T(0);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+      for (int h = 0; h < G::NHY; ++h) Hy[h][f][k] = T(0);
+      Hx[f][k] = Hc[f][k] = T(0);
+    }
+  }
+  In li, ly[G::NHY], lx, lc;
+  T lpp, lqp, mm;
+  auto fetch = [&](int z) {
+    const int zl = z + 4;
+    li = load(g.in, zl, g.y, g.x, true);
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) ly[k] = load(g.hyon[k], zl, g.hyg[k], g.x, true);
+    lx = load(g.hxon, zl, g.hxg_y, g.hxg_x, true);
+    lc = load(g.cnon, zl, g.cng_y, g.cng_x, false);
+    const bool out = z >= z0;
+    const bool oc = out && g.in;
+    lpp = ldz(t.pp, a, oc, z, g.y, g.x);
+    lqp = ldz(t.qp, a, oc, z, g.y, g.x);
+    mm = ldz(a.m, a, oc, z, g.y, g.x);
+  };
+  auto w1of = [](const In &c) { return c.c1 * c.lp + c.c2 * c.lq; };
+  auto w2of = [](const In &c) { return c.c2 * c.lp + c.lq; };
+  // current-plane LDS values of one cell (halo cells: LDS offset l)
+  auto stage_cur = [&](T (*Lc)[G::PL], int l, T w1, T w2, T nx, T ny) {
+    Lc[0][l] = w1;
+    Lc[1][l] = (nx * nx) * w1;
+    Lc[2][l] = (ny * ny) * w1;
+    Lc[3][l] = (nx * nx) * w2;
+    Lc[4][l] = (ny * ny) * w2;
+    Lc[5][l] = (nx * ny) * w1;
+    Lc[6][l] = (nx * ny) * w2;
+  };
+  const int zs = z0 - 8;
+  fetch(zs);
+  // U planes per trip: the queue shifts of the unrolled planes become
+  // register renames (only the shifts across a trip remain moves)
+  auto step = [&](int z) {
+    const bool out = z >= z0;  // uniform over the workgroup
+    T(*Lc)[G::PL] = LcB[NB == 2 ? (z & 1) : 0];
+    // lead plane: queue fronts and LDS
+    {
+      const T w1 = w1of(li), w2 = w2of(li);
+      W[8] = w1;
+      Z1[8] = (li.nz * li.nz) * w1;
+      Z2[8] = (li.nz * li.nz) * w2;
+      Dw2[4] = w2;
+      Dnx[4] = li.nx;
+      Dny[4] = li.ny;
+      Dlp[4] = li.lp;
+      Dlq[4] = li.lq;
+      Ll[0][g.lc] = (li.nx * li.nz) * w1;
+      Ll[1][g.lc] = (li.nx * li.nz) * w2;
+      Ll[2][g.lc] = (li.ny * li.nz) * w1;
+      Ll[3][g.lc] = (li.ny * li.nz) * w2;
+    }
+#pragma unroll
+    for (int k = 0; k < G::NHY; ++k) {
+      const T v1 = w1of(ly[k]), v2 = w2of(ly[k]);
+      Ll[2][g.hyl[k]] = (ly[k].ny * ly[k].nz) * v1;
+      Ll[3][g.hyl[k]] = (ly[k].ny * ly[k].nz) * v2;
+      if constexpr (HL) {
+        Hq[hslot(z + 4)][k * G::NTHR + threadIdx.x] = V4{v1, v2, ly[k].nx, ly[k].ny};
+      } else {
+        Hy[k][0][4] = v1;
+        Hy[k][1][4] = v2;
+        Hy[k][2][4] = ly[k].nx;
+        Hy[k][3][4] = ly[k].ny;
+      }
+    }
+    {
+      const T v1 = w1of(lx), v2 = w2of(lx);
+      if (threadIdx.x < G::NHX) {
+        Ll[0][g.hxl] = (lx.nx * lx.nz) * v1;
+        Ll[1][g.hxl] = (lx.nx * lx.nz) * v2;
+      }
+      if constexpr (HL) {
+        if (threadIdx.x < G::NHX) Hq[hslot(z + 4)][hxi] = V4{v1, v2, lx.nx, lx.ny};
+        if (corner) Hq[hslot(z + 4)][hxi] = V4{w1of(lc), w2of(lc), lc.nx, lc.ny};
+      } else {
+        Hx[0][4] = v1;
+        Hx[1][4] = v2;
+        Hx[2][4] = lx.nx;
+        Hx[3][4] = lx.ny;
+        Hc[0][4] = w1of(lc);
+        Hc[1][4] = w2of(lc);
+        Hc[2][4] = lc.nx;
+        Hc[3][4] = lc.ny;
+      }
+    }
+    // current plane
+    const T clpp = lpp, clqp = lqp, cm = mm;
+    if (out) {
+      stage_cur(Lc, g.lc, W[4], Dw2[0], Dnx[0], Dny[0]);
+      if constexpr (HL) {
+#pragma unroll
+        for (int k = 0; k < G::NHY; ++k) {
+          const V4 h = Hq[hslot(z)][k * G::NTHR + threadIdx.x];
+          stage_cur(Lc, g.hyl[k], h.x, h.y, h.z, h.w);
+        }
+        if (threadIdx.x < G::NHX || corner) {
+          const V4 h = Hq[hslot(z)][hxi];
+          stage_cur(Lc, threadIdx.x < G::NHX ? g.hxl : g.cnl, h.x, h.y, h.z, h.w);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < G::NHY; ++k)
+          stage_cur(Lc, g.hyl[k], Hy[k][0][0], Hy[k][1][0], Hy[k][2][0], Hy[k][3][0]);
+        if (threadIdx.x < G::NHX) stage_cur(Lc, g.hxl, Hx[0][0], Hx[1][0], Hx[2][0], Hx[3][0]);
+        if (corner) stage_cur(Lc, g.cnl, Hc[0][0], Hc[1][0], Hc[2][0], Hc[3][0]);
+      }
+    }
+    if (z + 1 < z1) fetch(z + 1);
+    __syncthreads();
+    E1[8] = d1l(t, Ll[0] + g.lc, 1) + d1l(t, Ll[2] + g.lc, G::LX);
+    E2[8] = d1l(t, Ll[1] + g.lc, 1) + d1l(t, Ll[3] + g.lc, G::LX);
+    if (out) {
+      const int hr = threadIdx.x / TX, hc = threadIdx.x % TX + 4;
+      H[0][hr * G::LX + hc] = d1l(t, Lc[5] + g.lc, G::LX);
+      H[1][hr * G::LX + hc] = d1l(t, Lc[6] + g.lc, G::LX);
+      if (threadIdx.x < G::NHX) {
+        const int r = threadIdx.x / 8, lcx = g.hxl - (4 + r) * G::LX;
+        H[0][r * G::LX + lcx] = d1l(t, Lc[5] + g.hxl, G::LX);
+        H[1][r * G::LX + lcx] = d1l(t, Lc[6] + g.hxl, G::LX);
+      }
+    }
+    __syncthreads();
+    if (out && g.in) {
+      const int hrow = (threadIdx.x / TX) * G::LX + threadIdx.x % TX + 4;
+      const T lw1 = (d2q(t, W) + d2l(t, Lc[0] + g.lc, G::LX)) + d2l(t, Lc[0] + g.lc, 1);
+      const T hz1 = ((d2q(t, Z1) + d2l(t, Lc[2] + g.lc, G::LX)) + d2l(t, Lc[1] + g.lc, 1)) +
+                    T(2) * (d1l(t, H[0] + hrow, 1) + d1q(t, E1));
+      const T hz2 = ((d2q(t, Z2) + d2l(t, Lc[4] + g.lc, G::LX)) + d2l(t, Lc[3] + g.lc, 1)) +
+                    T(2) * (d1l(t, H[1] + hrow, 1) + d1q(t, E2));
+      const T damp = sponge_a(a, z, g.y, g.x);
+      const uint32_t o = cidx(a, z, g.y, g.x);
+      T pn, qn;
+      tti_update_pq(a, cm, damp, Dlp[0], clpp, lw1 - hz1, Dlq[0], clqp, hz2, pn, qn);
+      sto(t.pn, o, pn);
+      sto(t.qn, o, qn);
+    }
+    // one current-plane buffer: it is rewritten next iteration.  Two: the
+    // next iteration writes the other one; the lead plane and H are rewritten
+    // only after the next iteration's first / this iteration's second barrier
+    if constexpr (NB == 1) __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      W[k] = W[k + 1];
+      Z1[k] = Z1[k + 1];
+      Z2[k] = Z2[k + 1];
+      E1[k] = E1[k + 1];
+      E2[k] = E2[k + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Dw2[k] = Dw2[k + 1];
+      Dnx[k] = Dnx[k + 1];
+      Dny[k] = Dny[k + 1];
+      Dlp[k] = Dlp[k + 1];
+      Dlq[k] = Dlq[k + 1];
+      if constexpr (!HL) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+#pragma unroll
+          for (int h = 0; h < G::NHY; ++h) Hy[h][f][k] = Hy[h][f][k + 1];
+          Hx[f][k] = Hx[f][k + 1];
+          Hc[f][k] = Hc[f][k + 1];
+        }
+      }
+    }
+  };
+  int z = zs;
+  if constexpr (U > 1) {
+    for (; z + U <= z1; z += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(z + u);
+    }
+  }
+  for (; z < z1; ++z) step(z);
+}
+
 // grid of one tiled launch: (64 x ty) column tiles, z split in chunks until
 // target_blocks workgroups (chunks of at least 16 planes)
 struct TtiGrid {
@@ -1011,8 +1264,11 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
 
 // one TTI step with the tiled kernels (prep with TYP rows, march with TYM
 // rows); g needs 4 (forward) / 6 (adjoint) slots of N
-// FUSED: 1 = fused forward kernel, 2 = fused forward kernel with the LDS plane ring
-template <typename T, int TYP, int TYM, int FUSED = 0, bool AFUSED = false>
+// FUSED: 1 = fused forward kernel, 2 = fused forward kernel with the LDS plane ring;
+// AFUSED: 1 = fused transpose kernel, 2 = fused transpose kernel with halo delay
+// queues in registers, 3 = in LDS; UA: planes per loop trip of the delay-queue
+// kernel
+template <typename T, int TYP, int TYM, int FUSED = 0, int AFUSED = 0, int UA = 1>
 static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
@@ -1034,10 +1290,17 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
       return hipGetLastError();
     }
   }
-  if constexpr (AFUSED) {
+  if constexpr (AFUSED == 1) {
     if (adjoint) {
       hipLaunchKernelGGL((k_tti_afused<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
                          gm.zchunk);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (AFUSED == 2 || AFUSED == 3) {
+    if (adjoint) {
+      hipLaunchKernelGGL((k_tti_afused_dq<T, TYM, 1, UA, AFUSED == 3>), nm, bm, 0, st, t, gm.ntx,
+                         gm.nty, gm.nzc, gm.zchunk);
       return hipGetLastError();
     }
   }
@@ -1059,8 +1322,11 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 // 3 = 8 / 4, 4 = as 3 with the fused forward kernel (4 rows), 5 = as 3 with
 // the fused forward kernel (8 rows), 6 = both steps fused (4 rows), 7 = both
 // fused, forward 4 rows and transpose 8 rows,
-// 8 = both fused (8 rows), 9 (the library's default) / 10 = as 7 with the
-// forward kernel's LDS plane ring (forward on 4 / 8 rows)
+// 8 = both fused (8 rows), 9 / 10 = as 7 with the
+// forward kernel's LDS plane ring (forward on 4 / 8 rows), 11 / 12 = as 9 with
+// the transpose kernel's halo delay queues (transpose on 8 / 4 rows), 13 / 14 /
+// 15 (the library's default) = as 11 with the transpose kernel's halo queues in
+// LDS and 1 / 2 / 3 planes per loop trip
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -1071,14 +1337,24 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
                            : tti_step_tiled<T, 8, 8, 1>(t, adjoint, target_blocks, st);
     case 3: return tti_step_tiled<T, 8, 4>(t, adjoint, target_blocks, st);
     case 4: return tti_step_tiled<T, 8, 4, 1>(t, adjoint, target_blocks, st);
-    case 7: return adjoint ? tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st)
-                           : tti_step_tiled<T, 8, 4, 1, true>(t, adjoint, target_blocks, st);
-    case 8: return tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st);
-    case 9: return adjoint ? tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st)
-                           : tti_step_tiled<T, 8, 4, 2, true>(t, adjoint, target_blocks, st);
-    case 10: return adjoint ? tti_step_tiled<T, 8, 8, 1, true>(t, adjoint, target_blocks, st)
-                            : tti_step_tiled<T, 8, 8, 2, true>(t, adjoint, target_blocks, st);
-    default: return tti_step_tiled<T, 8, 4, 1, true>(t, adjoint, target_blocks, st);  // 6
+    case 7: return adjoint ? tti_step_tiled<T, 8, 8, 1, 1>(t, adjoint, target_blocks, st)
+                           : tti_step_tiled<T, 8, 4, 1, 1>(t, adjoint, target_blocks, st);
+    case 8: return tti_step_tiled<T, 8, 8, 1, 1>(t, adjoint, target_blocks, st);
+    case 9: return adjoint ? tti_step_tiled<T, 8, 8, 1, 1>(t, adjoint, target_blocks, st)
+                           : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
+    case 10: return adjoint ? tti_step_tiled<T, 8, 8, 1, 1>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 8, 2, 1>(t, adjoint, target_blocks, st);
+    case 11: return adjoint ? tti_step_tiled<T, 8, 8, 1, 2>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
+    case 12: return adjoint ? tti_step_tiled<T, 8, 4, 1, 2>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
+    case 13: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 1>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
+    case 14: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 2>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
+    case 15: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 3>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
+    default: return tti_step_tiled<T, 8, 4, 1, 1>(t, adjoint, target_blocks, st);  // 6
   }
 }
 

@@ -111,19 +111,21 @@ def autotune_k_block(spec: api.PlanSpec, m, src_pos, q, rec_pos, Z, candidates=(
 
 
 def autotune_batch(specs, shots, variants=(1, 3, 7, 11, 12), blocks=(2048, 4096, 8192),
-                   steps: int = 128, cache: str | None = None) -> dict:
-    """Times the batched gradient over the first `steps` time steps for every
-    (stencil variant, z-split target) pair, recreating the batch for each
-    target (the tile table is fixed when a batch is created).  shots: the
-    per-shot input dicts of Batch.fwi_gradient.  Applies nothing; returns
-    {"best": (variant, blocks), "ms": {...}}.  Apply with
-    api.set_stencil_blocks(blocks) before creating the batch and
+                   steps: int = 128, cache: str | None = None, k_blocks=(32, 64, 128)) -> dict:
+    """Times the batched gradient over the first `steps` time steps (a
+    multiple of every k) for every (stencil variant, z-split target) pair,
+    recreating the batch for each target (the tile table is fixed when a
+    batch is created), then, with the best pair, every probe-block length in
+    k_blocks whose memory fits.  shots: the per-shot input dicts of
+    Batch.fwi_gradient.  Applies nothing; returns {"best": (variant, blocks),
+    "k_block": k, ...}.  Apply with api.set_stencil_blocks(blocks) before
+    creating the batch (with k_block = k in its descriptors) and
     api.set_stencil_variant(variant) before running it."""
     if cache is None:
         cache = os.environ.get("RTM_TUNE_CACHE") or None
     dev = shots[0]["m"].device
     key = ("batch|" + _arch(dev) + "|" + ";".join("x".join(map(str, s.shape)) for s in specs)
-           + f"|{specs[0].field}|{specs[0].probe}|r{specs[0].r}")
+           + f"|{specs[0].field}|{specs[0].probe}|r{specs[0].r}|k{','.join(map(str, k_blocks))}")
     hit = _cache_get(cache, key)
     if hit:
         hit = dict(hit, cached=True)
@@ -148,9 +150,32 @@ def autotune_batch(specs, shots, variants=(1, 3, 7, 11, 12), blocks=(2048, 4096,
                                                                    work=work)) / nt, 4)
         del B, outs, work
         torch.cuda.empty_cache()
-    api.set_stencil_blocks(blocks_before)
     best = min(ms, key=ms.get)
     v, b = (int(x) for x in best.split("/"))
-    res = {"best": [v, b], "ms_per_step": ms, "steps_timed": nt}
+    # then the probe-block length with that stencil choice (memory permitting)
+    kms = {}
+    if k_blocks:
+        free, _ = torch.cuda.mem_get_info(dev)
+        api.set_stencil_blocks(b)
+        api.set_stencil_variant(v)
+        for k in k_blocks:
+            kspecs = [dataclasses.replace(sp, k_block=k) for sp in tspecs]
+            B = api.Batch(kspecs)
+            need = B.workspace_bytes + sum(sp.r * ((n + 31) // 32 * 32) * 4
+                                           for sp, n in zip(kspecs, B.N))
+            if need > 0.9 * free:
+                continue
+            outs = B.outputs(dev, stack=False)
+            J = torch.empty(len(shots), dtype=torch.float64, device=dev)
+            work = torch.empty(B.workspace_bytes, dtype=torch.uint8, device=dev)
+            B.fwi_gradient(tshots, outs=outs, misfit=J, work=work)
+            kms[k] = round(_timed(lambda: B.fwi_gradient(tshots, outs=outs, misfit=J,
+                                                         work=work)) / nt, 4)
+            del B, outs, work
+            torch.cuda.empty_cache()
+    api.set_stencil_blocks(blocks_before)
+    kbest = min(kms, key=kms.get) if kms else specs[0].k_block
+    res = {"best": [v, b], "k_block": kbest, "ms_per_step": ms, "k_ms_per_step": kms,
+           "steps_timed": nt}
     _cache_put(cache, key, res)
     return dict(res, best=(v, b), cached=False)

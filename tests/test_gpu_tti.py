@@ -38,7 +38,7 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(9)  # the default
+    P.set_tti_shape(15)  # the default
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
@@ -47,12 +47,19 @@ def variant(request):
                                            ((-1, 5), (40, 21, 70)), ((-1, 6), (40, 21, 70)),
                                            ((-1, 6), (18, 16, 20)), ((-1, 7), (40, 21, 70)),
                                            ((-1, 8), (40, 21, 70)), ((-1, 9), (40, 21, 70)),
-                                           ((-1, 9), (18, 16, 20)), ((-1, 10), (40, 21, 70))],
+                                           ((-1, 9), (18, 16, 20)), ((-1, 10), (40, 21, 70)),
+                                           ((-1, 11), (40, 21, 70)), ((-1, 11), (18, 16, 20)),
+                                           ((-1, 12), (40, 21, 70)), ((-1, 13), (37, 21, 70)),
+                                           ((-1, 14), (37, 21, 70)), ((-1, 15), (37, 21, 70)),
+                                           ((-1, 15), (18, 16, 20))],
                          indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
     (tile shapes 1..3: 64 x 8 and 64 x 4 columns; 4, 5: fused forward step; 6:
-    both steps fused; 7, 8: both fused, the transpose step on 64 x 8 tiles)."""
+    both steps fused; 7, 8: both fused, the transpose step on 64 x 8 tiles).
+    (37, 21, 70): z-chunks of 27 and 26 planes with the warm-up, so the
+    transpose kernels carrying 2 or 3 planes per loop trip (shapes 14, 15) run
+    their remainder loop in one chunk or both."""
     wl, an = synth.workload_tti(shape=shape, nt=50, r=8, sigma=2.0, nb=4, f0=15.0,
                                 rec_stride=7, dtype=np.float64)
     g = Grid.of(wl)
@@ -129,7 +136,7 @@ def test_tti_f32_bf16x2_fused_gradient():
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
 
 
-@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10])
+@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 15])
 def test_tti_f32_tiled_equals_simple_kernels(shape):
     """The tiled TTI step (mixed terms once per unordered pair, intermediates
     staged per plane) against the one-thread-per-cell step on the same FP32
@@ -154,8 +161,36 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
-            P.set_tti_shape(9)  # the default
+            P.set_tti_shape(15)  # the default
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
     say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
         " ".join(f"{k} {v:.2e}" for k, v in e.items()))
     assert e["resid"] < 1e-6 and max(e.values()) < 5e-5
+
+
+def test_tti_f32_lds_queue_kernels_equal_shape_11():
+    """Shapes 13-15 keep the transpose's halo queues in LDS and carry 1-3
+    planes per loop trip: the same arithmetic in the same order as shape 11's
+    register queues, so the FP32 results are equal bit for bit.  (37, 27, 75):
+    z-chunks of 27 and 26 planes with the warm-up, so the loops carrying 2 or 3
+    planes per trip run their remainder in one chunk or both."""
+    wl, an = synth.workload_tti(shape=(37, 27, 75), nt=70, r=32, sigma=3.0, nb=5, f0=12.0,
+                                rec_stride=4)
+    rng = np.random.default_rng(9)
+    d_obs = (0.05 * rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))).astype(np.float32)
+    plan = _plan(wl, "f32", "bf16x2", k_block=32)
+    args = (plan, dev(wl.m, torch.float32), dev(an, torch.float32), wl.src_pos,
+            dev(wl.q, torch.float32), wl.rec_pos, dev(d_obs, torch.float32),
+            dev(wl.Z, torch.int8))
+    out = {}
+    try:
+        for shape in (11, 13, 14, 15):
+            P.set_tti_shape(shape)
+            out[shape] = P.fwi_gradient_tti(*args, fused=True)
+            torch.cuda.synchronize()
+    finally:
+        P.set_tti_shape(15)  # the default
+    for shape in (13, 14, 15):
+        for k in ("resid", "Ubar", "grad"):
+            assert torch.equal(out[shape][k], out[11][k]), (shape, k)
+    say("  TTI shapes 13-15 equal shape 11 bit for bit (resid, Ubar, grad)")
