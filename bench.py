@@ -25,14 +25,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# vector-ALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 FP32 VALU
+# instruction per SIMD every 4 cycles (16 lanes; the packed-FP32 forms that
+# double the vendor's FP32 vector figure are not used)
+VALU_PEAK_GINSTS = 256 * 4 * 2.4 / 4
+PMC_SOURCE = ("stored rocprofv3 --pmc record profiles/pmc_traffic.json, taken on these kernel "
+              "sources (hash match), not measured in this run")
 
 
-def measured_traffic(part: str, grid, **params):
-    """HBM bytes per dispatch measured with rocprofv3 --pmc (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy of known size) for one workload
-    ("acoustic", "tti" or "gathers"), keyed by kernel, if the kernel sources
-    are unchanged since the counters were taken and the workload (grid and
-    params) matches; else None."""
+def _pmc_kernels(part: str, grid, **params):
+    """Per-dispatch counters of one workload ("acoustic", "tti" or "gathers")
+    from the stored rocprofv3 --pmc record, keyed by kernel, if the kernel
+    sources are unchanged since the counters were taken and the workload (grid
+    and params) matches; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
@@ -48,7 +53,31 @@ def measured_traffic(part: str, grid, **params):
     if rec.get("source_hash") != h.hexdigest()[:16] or not w or w.get("grid") != list(grid) \
             or any(w.get(k) != v for k, v in params.items()):
         return None
-    return {key: v["read_bytes"] + v["write_bytes"] for key, v in w["kernels"].items()}
+    return w["kernels"]
+
+
+def measured_traffic(part: str, grid, **params):
+    """HBM bytes per dispatch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
+    of known size) from the stored PMC record, keyed by kernel, or None."""
+    ks = _pmc_kernels(part, grid, **params)
+    if ks is None:
+        return None
+    return {key: v["read_bytes"] + v["write_bytes"] for key, v in ks.items()}
+
+
+def valu_entry(part: str, grid, key: str, avg_launch_us: float, cells: int, **params):
+    """The kernel's vector-ALU issue rate: SQ_INSTS_VALU per dispatch (wave64
+    instructions, stored PMC record) over the launch time measured in this
+    run, against VALU_PEAK_GINSTS; None without a matching record."""
+    ks = _pmc_kernels(part, grid, **params)
+    if not ks or key not in ks or "valu_insts" not in ks[key] or not avg_launch_us:
+        return None
+    n = ks[key]["valu_insts"]
+    ach = n / (avg_launch_us * 1e-6) / 1e9
+    return {"bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GINSTS,
+            "unit": "G wave64 VALU instructions/s", "frac": round(ach / VALU_PEAK_GINSTS, 4),
+            "insts_per_launch": n, "lane_insts_per_cell": round(n * 64 / cells, 1),
+            "source": PMC_SOURCE}
 
 
 def parse():
@@ -505,26 +534,46 @@ def bench_tti(shape, nt: int, r: int, stride: int):
                              work=work)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t) * 1e3
-    step_ms, cnt = P.profile_read("tti_step")
+    f_ms, f_n = P.profile_read("tti_step")
+    a_ms, a_n = P.profile_read("tti_step_adj")
     P.profile_enable(0)
     N = int(np.prod(shape))
-    avg_us = step_ms / max(cnt, 1) * 1e3
+    f_us = f_ms / max(f_n, 1) * 1e3
+    a_us = a_ms / max(a_n, 1) * 1e3
+    avg_us = 0.5 * (f_us + a_us)
     # algorithmic bytes of one step per cell: read p, q, their previous
     # levels, m and the five coefficients; write the two new levels (FP32)
     bpc = 12 * 4
-    gbs = bpc * N / (avg_us * 1e-6) / 1e9
     finite = bool(torch.isfinite(out["grad"]).all().item())
     print("tti: gradient done", file=sys.stderr, flush=True)
     tr = measured_traffic("tti", shape, r=r, k=32)
-    traffic = round(0.5 * (tr["tti_ffused"] + tr["tti_afused"])) if tr else None
+
+    def entry(kernel, key, us, n):
+        gbs = bpc * N / (us * 1e-6) / 1e9
+        e = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(tr[key]) if tr else None,
+             "traffic_source": PMC_SOURCE if tr else None, "kernel": kernel,
+             "avg_launch_us": round(us, 1), "launches_timed": n, "bytes_per_cell": bpc}
+        v = valu_entry("tti", shape, key, us, N, r=r, k=32)
+        if v:
+            e["valu"] = v
+        return e
+    kern = {"tti_forward": entry("k_tti_ffused_ring (forward step, LDS plane ring)",
+                                 "tti_ffused", f_us, f_n),
+            "tti_transpose": entry("k_tti_afused_dq (transpose step, LDS halo queues, 3 planes "
+                                   "per loop trip)", "tti_afused", a_us, a_n)}
+    gbs = bpc * N / (avg_us * 1e-6) / 1e9
     return {"workload": f"TTI {shape[0]}x{shape[1]}x{shape[2]}, nt={nt}, r={r} on p and q, "
                         f"k=32, bf16x2, fused imaging, one shot",
             "value": round(2.0 * N * nt / (ms * 1e-3) / 1e9, 2), "unit": "Gcell-updates/s",
             "ms_per_gradient": round(ms, 1),
-            "step_avg_us": round(avg_us, 1), "step_count_timed": cnt,
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
-                         "unit": "GB/s", "frac": round(gbs / 8000.0, 4), "traffic": traffic,
-                         "bytes_per_cell": bpc},
+            "step_avg_us": round(avg_us, 1), "step_count_timed": f_n + a_n,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": round(0.5 * (tr["tti_ffused"] + tr["tti_afused"])) if tr
+                         else None, "bytes_per_cell": bpc,
+                         "note": "mean of the forward and transpose steps"},
+            "roofline_kernels": kern,
             "misfit": float(out["misfit"].item()), "grad_finite": finite}
 
 
@@ -801,6 +850,13 @@ def main():
             {"bytes_per_cell": 16, "z_split_target": tune.get("blocks"),
              "autotune_us": tune.get("us")}),
     }
+    if fused:
+        for name, key in (("probe_forward", "probe_fwd"), ("probe_adjoint", "probe_adj"),
+                          ("stencil", "stencil")):
+            v = valu_entry("acoustic", (384, 512, 512), key, kern[name]["avg_launch_us"], N,
+                           r=r, k=k)
+            if v:
+                kern[name]["valu"] = v
     dom = max(kern, key=lambda kk: kern[kk]["ms_per_step"])
     pr_bytes_step = fwd_b + adj_b
     path_bytes = 2 * nt * st_bytes + pr_bytes_step

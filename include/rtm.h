@@ -178,8 +178,8 @@ rtm_status rtm_autotune_stencil(const rtm_plan *plan, const void *m, void *work,
  * every probe-GEMM and image launch (0 turns it off).
  * rtm_profile_read(kind, ...) waits for the recorded events of one kind
  * (0 stencil, 1 forward probe GEMM, 2 image, 3 adjoint probe GEMM, 4 TTI
- * step), returns their summed duration in ms and their count, and forgets
- * them. */
+ * forward step, 5 TTI transpose step), returns their summed duration in ms
+ * and their count, and forgets them. */
 void rtm_profile_enable(int32_t stride);
 rtm_status rtm_profile_read(int32_t kind, double *total_ms, int64_t *count);
 /* Reference for the roofline figures: a streaming device-to-device copy of

@@ -315,7 +315,8 @@ def autotune_stencil(plan: Plan, m, work=None, steps: int = 20, apply: bool = Tr
     return res
 
 
-KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2, "probe_adj": 3, "tti_step": 4}
+KERNEL_KINDS = {"stencil": 0, "probe": 1, "image": 2, "probe_adj": 3, "tti_step": 4,
+                "tti_step_adj": 5}
 
 
 def profile_enable(stride: int) -> None:

@@ -41,7 +41,10 @@ static int g_graph = 0;             // fwi_gradient: capture and replay HIP grap
 
 // Opt-in kernel timing: HIP events recorded on the sweep's stream around every
 // `stride`-th launch of the stencil and every probe-GEMM / image launch.
-enum { KT_STENCIL = 0, KT_PROBE = 1, KT_IMAGE = 2, KT_PROBE_ADJ = 3, KT_TTI = 4, KT_N = 5 };
+enum {
+  KT_STENCIL = 0, KT_PROBE = 1, KT_IMAGE = 2, KT_PROBE_ADJ = 3, KT_TTI = 4, KT_TTI_ADJ = 5,
+  KT_N = 6
+};
 struct TimedLaunch {
   int kind;
   hipEvent_t a, b;
@@ -52,7 +55,7 @@ static std::vector<TimedLaunch> g_prof;
 static void prof_begin(int kind, int step, hipStream_t st, TimedLaunch *t) {
   t->kind = -1;
   if (g_prof_stride <= 0) return;
-  if ((kind == KT_STENCIL || kind == KT_TTI) && step % g_prof_stride) return;
+  if ((kind == KT_STENCIL || kind == KT_TTI || kind == KT_TTI_ADJ) && step % g_prof_stride) return;
   if (hipEventCreate(&t->a) != hipSuccess) return;
   if (hipEventCreate(&t->b) != hipSuccess) {
     (void)hipEventDestroy(t->a);
@@ -1857,7 +1860,7 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
     const int n = io.adjoint ? d.nt - 1 - s : s;
     T *pn = lv(ringP, s + 1), *qn = lv(ringQ, s + 1);
     TimedLaunch tl;
-    prof_begin(KT_TTI, s, st, &tl);
+    prof_begin(io.adjoint ? KT_TTI_ADJ : KT_TTI, s, st, &tl);
     HIP_TRY(launch_tti_step<T>(a, d.h, io.adjoint, coef, lv(ringP, s), lv(ringP, s - 1),
                                lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, shape,
                                kTtiBlocks, st));
