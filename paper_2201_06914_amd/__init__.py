@@ -18,4 +18,4 @@ from .api import (Plan, PlanSpec, RtmError, bar_index, cfl_bound, fwi_gradient, 
                   rtm_orthonormalize, fwi_gradient_rf, rtm_offset_gathers,
                   stream_status, rtm_forward_probe_range, fwi_gradient_noalloc,
                   rtm_residual, tti_spectral_radius, set_stencil_alternate,
-                  set_probe_nt, set_graph)
+                  set_probe_nt, set_probe_grid, set_graph)

@@ -234,6 +234,13 @@ def set_probe_nt(on: bool) -> None:
     _lib.load().rtm_set_probe_nt(1 if on else 0)
 
 
+def set_probe_grid(update: int, fused: int) -> None:
+    """Workgroups of one probe-GEMM launch for the in-place update kernels and
+    for the fused adjoint imaging kernel: -1 automatic (default), 0 one per
+    four tiles, > 0 at most that many."""
+    _lib.load().rtm_set_probe_grid(int(update), int(fused))
+
+
 def set_graph(on: bool) -> None:
     """fwi_gradient captures and replays HIP graphs (per set of arguments)."""
     _lib.load().rtm_set_graph(1 if on else 0)

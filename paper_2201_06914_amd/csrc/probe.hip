@@ -448,6 +448,34 @@ __global__ __launch_bounds__(256) void k_probe_mfma_edge(ProbeArgs<float> p,
 int g_probe_nt = 1;
 void set_probe_nt(int on) { g_probe_nt = on ? 1 : 0; }
 int get_probe_nt() { return g_probe_nt; }
+// process wide (rtm_set_probe_grid): the workgroups of one probe launch, for
+// the kernels that update a compressed field in place (forward, unfused
+// adjoint) and for the fused adjoint imaging kernel.  -1 (default): the update
+// kernels of blocks of at most 32 steps take one workgroup per four tiles (no
+// stride); the others are sized so that every wave takes 6 KS tiles (update)
+// or 48 (fused), with at least 2048 workgroups (or one per four tiles on small
+// grids).  0: no stride; > 0: at most that many workgroups.
+// Each workgroup first stages its probe block in LDS, a cost that grows with
+// the block length; the in-place update runs faster when the resident
+// workgroups stay on one band of tiles than when long-lived waves drift apart
+// over the field.  At 384 x 512 x 512, r = 128, per launch, on the two kinds
+// of 51.5 GB allocation seen (the physical placement of the compressed field
+// moves the striding kernels by 15 %, see the notes on placement):
+//   forward, k = 32:  no stride 20.1-20.5 ms on both; 12 tiles per wave 21.7 /
+//                     18.6 ms; 2048 workgroups 22.9 / 19.9 ms
+//   forward, k = 64:  24 tiles per wave 23.8 ms, 2048 workgroups 24.5 ms, no
+//                     stride 32.5 ms
+//   forward, k = 128: 48 tiles per wave 31.4 ms, 2048 workgroups 31.1 ms, no
+//                     stride 54.2 ms
+//   fused, k = 32 / 64 / 128: 48 tiles per wave 10.1 / 14.7 / 20.9 ms, 2048
+//                     workgroups 10.2-10.3 / 14.6-14.7 / 22.3 ms, no stride
+//                     12.7 / 15.4 / 21.8 ms
+int g_probe_grid[2] = {-1, -1};
+void set_probe_grid(int cap_update, int cap_fused) {
+  g_probe_grid[0] = cap_update < 0 ? -1 : cap_update;
+  g_probe_grid[1] = cap_fused < 0 ? -1 : cap_fused;
+}
+int get_probe_grid(int fused) { return g_probe_grid[fused ? 1 : 0]; }
 
 struct FuseArgs {
   const float *Uf = nullptr;
@@ -462,8 +490,18 @@ static void launch_probe_kernels(const ProbeArgs<float> &p, const void *Z, int M
   const int64_t ntiles = (p.N + 31) / 32;
   const int64_t nfull = p.N / 32;
   auto grid_for = [](int64_t tiles) -> unsigned {
-    const int64_t want = (tiles + 3) / 4;
-    return (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+    const int64_t want = (tiles + 3) / 4;  // one workgroup per four tiles
+    const int set = g_probe_grid[FUSED ? 1 : 0];
+    int64_t cap = set > 0 ? set : want;
+    if (set < 0 && (FUSED || KS > 2)) {  // automatic: a fixed number of tiles
+                                         // per wave, and no fewer than 2048
+                                         // workgroups (small grids: fill the chip)
+      const int64_t tpw = FUSED ? 48 : 6 * KS;
+      cap = (tiles + 4 * tpw - 1) / (4 * tpw);
+      if (cap < 2048) cap = 2048;
+    }  // automatic, in-place update with blocks of at most 32 steps: no stride
+    if (cap > want) cap = want;
+    return (unsigned)(cap > 0 ? cap : 1);
   };
   // the fast kernel reads and writes whole 32-row tiles and whole 16-step chunks
   const bool fastk = p.kb == 16 * KS && p.r % 32 == 0;

@@ -197,6 +197,9 @@ extern "C" void rtm_set_stencil_variant(int v) {
 extern "C" void rtm_set_exact_fused(int32_t on) { g_exact_fused = on ? 1 : 0; }
 extern "C" void rtm_set_stencil_alternate(int32_t on) { g_stencil_alternate = on ? 1 : 0; }
 extern "C" void rtm_set_probe_nt(int32_t on) { set_probe_nt(on); }
+extern "C" void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_workgroups_fused) {
+  set_probe_grid(max_workgroups_update, max_workgroups_fused);
+}
 extern "C" void rtm_set_graph(int32_t on) { g_graph = on ? 1 : 0; }
 
 extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 15) ? shape : 15; }
@@ -904,6 +907,8 @@ static rtm_status run_launches(uint64_t key, hipStream_t st, F body) {
   key = key_mix(key, (uint64_t)g_stencil_blocks);
   key = key_mix(key, (uint64_t)g_stencil_alternate + 77);
   key = key_mix(key, (uint64_t)get_probe_nt() + 99);
+  key = key_mix(key, (uint64_t)get_probe_grid(0) + 555);
+  key = key_mix(key, (uint64_t)get_probe_grid(1) + 556);
   key = key_mix(key, (uint64_t)dev);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   GraphStream &gs = g_gstream[dev];

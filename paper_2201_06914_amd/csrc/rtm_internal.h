@@ -194,6 +194,8 @@ hipError_t launch_probe_vec(const ProbeArgs<T> &p, const void *Z, bool z_is_i8,
 // split).
 void set_probe_nt(int on);
 int get_probe_nt();
+void set_probe_grid(int cap_update, int cap_fused);
+int get_probe_grid(int fused);
 hipError_t launch_probe_mfma(const ProbeArgs<float> &p, const void *Z, bool zf32, int op,
                              const float *Uf, float *img, float scale, hipStream_t st);
 // exact imaging: out = (un - 2 u0 + um) * inv_dt2 ; g -= s * lam
