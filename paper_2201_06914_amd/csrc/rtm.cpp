@@ -35,7 +35,7 @@ static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled va
 static int g_stencil_blocks = 2048; // tiled stencil: split z until this many workgroups
 static const int kTtiBlocks = 2048; // tiled TTI kernels: the same, fixed
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
-static int g_tti_shape = 15;        // tiled TTI tile shape (1..15)
+static int g_tti_shape = 16;        // tiled TTI tile shape (1..16)
 static int g_stencil_alternate = 1; // sweeps: tiled stencil marches z up / down on alternate steps
 static int g_graph = 0;             // fwi_gradient: capture and replay HIP graphs
 
@@ -202,7 +202,7 @@ extern "C" void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_wo
 }
 extern "C" void rtm_set_graph(int32_t on) { g_graph = on ? 1 : 0; }
 
-extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 15) ? shape : 15; }
+extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 16) ? shape : 16; }
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
   g_stencil_blocks = blocks > 0 ? blocks : 2048;

@@ -512,7 +512,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused(TtiArgs<T> t, int n
 // while a slower thread may still read slot z - 1 (its current plane) or
 // slot z + 3 (its lead plane); both differ from it.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, int MINW>
+template <typename T, int TY, int MINW, int U = 1>
 __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, int ntx, int nty,
                                                                   int nzc, int zchunk) {
   using G = Geo<TY>;
@@ -562,7 +562,9 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, 
   auto slot = [](int plane) { return (plane + 12 * NR) % NR; };  // plane >= z0 - 4 >= -4
   const int zs = z0 - 8;
   fetch(zs);
-  for (int z = zs; z < z1; ++z) {
+  // U planes per trip: the queue shifts of the unrolled planes become
+  // register renames (only the shifts across a trip remain moves)
+  auto step = [&](int z) {
     const bool out = z >= z0;  // uniform over the workgroup
     Qp[8] = fp;
     Qq[8] = fq;
@@ -633,7 +635,15 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, 
       Xq[k] = Xq[k + 1];
       Yq[k] = Yq[k + 1];
     }
+  };
+  int z = zs;
+  if constexpr (U > 1) {
+    for (; z + U <= z1; z += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) step(z + u);
+    }
   }
+  for (; z < z1; ++z) step(z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1266,9 +1276,12 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
 // rows); g needs 4 (forward) / 6 (adjoint) slots of N
 // FUSED: 1 = fused forward kernel, 2 = fused forward kernel with the LDS plane ring;
 // AFUSED: 1 = fused transpose kernel, 2 = fused transpose kernel with halo delay
-// queues in registers, 3 = in LDS; UA: planes per loop trip of the delay-queue
-// kernel
-template <typename T, int TYP, int TYM, int FUSED = 0, int AFUSED = 0, int UA = 1>
+// queues in registers, 3 = in LDS; UA / UF: planes per loop trip of the
+// delay-queue / ring kernel (UF > 1 caps the ring kernel at 168 VGPRs, three
+// waves per SIMD: two planes per trip then spill 6 registers and run 639 us
+// against 666-672 us at 300 x 400 x 400; uncapped they need 176 and run at two
+// waves per SIMD, 802 us; three planes spill 17 and run 747 us)
+template <typename T, int TYP, int TYM, int FUSED = 0, int AFUSED = 0, int UA = 1, int UF = 1>
 static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
@@ -1285,7 +1298,7 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
   }
   if constexpr (FUSED == 2) {
     if (!adjoint) {
-      hipLaunchKernelGGL((k_tti_ffused_ring<T, TYM, 1>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
+      hipLaunchKernelGGL((k_tti_ffused_ring<T, TYM, (UF > 1 ? 3 : 1), UF>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
                          gm.zchunk);
       return hipGetLastError();
     }
@@ -1325,8 +1338,9 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 // 8 = both fused (8 rows), 9 / 10 = as 7 with the
 // forward kernel's LDS plane ring (forward on 4 / 8 rows), 11 / 12 = as 9 with
 // the transpose kernel's halo delay queues (transpose on 8 / 4 rows), 13 / 14 /
-// 15 (the library's default) = as 11 with the transpose kernel's halo queues in
-// LDS and 1 / 2 / 3 planes per loop trip
+// 15 = as 11 with the transpose kernel's halo queues in LDS and 1 / 2 / 3
+// planes per loop trip, 16 (the library's default) = as 15 with the forward
+// ring kernel carrying two planes per loop trip
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -1354,6 +1368,8 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
                             : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
     case 15: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 3>(t, adjoint, target_blocks, st)
                             : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
+    case 16: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 3>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1, 1, 2>(t, adjoint, target_blocks, st);
     default: return tti_step_tiled<T, 8, 4, 1, 1>(t, adjoint, target_blocks, st);  // 6
   }
 }

@@ -38,7 +38,7 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(15)  # the default
+    P.set_tti_shape(16)  # the default
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
@@ -51,7 +51,8 @@ def variant(request):
                                            ((-1, 11), (40, 21, 70)), ((-1, 11), (18, 16, 20)),
                                            ((-1, 12), (40, 21, 70)), ((-1, 13), (37, 21, 70)),
                                            ((-1, 14), (37, 21, 70)), ((-1, 15), (37, 21, 70)),
-                                           ((-1, 15), (18, 16, 20))],
+                                           ((-1, 15), (18, 16, 20)), ((-1, 16), (37, 21, 70)),
+                                           ((-1, 16), (18, 16, 20))],
                          indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
@@ -136,7 +137,7 @@ def test_tti_f32_bf16x2_fused_gradient():
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
 
 
-@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 15])
+@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 15, 16])
 def test_tti_f32_tiled_equals_simple_kernels(shape):
     """The tiled TTI step (mixed terms once per unordered pair, intermediates
     staged per plane) against the one-thread-per-cell step on the same FP32
@@ -161,7 +162,7 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
-            P.set_tti_shape(15)  # the default
+            P.set_tti_shape(16)  # the default
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
     say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
         " ".join(f"{k} {v:.2e}" for k, v in e.items()))
@@ -170,8 +171,9 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
 
 def test_tti_f32_lds_queue_kernels_equal_shape_11():
     """Shapes 13-15 keep the transpose's halo queues in LDS and carry 1-3
-    planes per loop trip: the same arithmetic in the same order as shape 11's
-    register queues, so the FP32 results are equal bit for bit.  (37, 27, 75):
+    planes per loop trip, 16 also carries two planes per trip in the forward
+    step: the same arithmetic in the same order as shape 11, so the FP32
+    results are equal bit for bit.  (37, 27, 75):
     z-chunks of 27 and 26 planes with the warm-up, so the loops carrying 2 or 3
     planes per trip run their remainder in one chunk or both."""
     wl, an = synth.workload_tti(shape=(37, 27, 75), nt=70, r=32, sigma=3.0, nb=5, f0=12.0,
@@ -184,13 +186,13 @@ def test_tti_f32_lds_queue_kernels_equal_shape_11():
             dev(wl.Z, torch.int8))
     out = {}
     try:
-        for shape in (11, 13, 14, 15):
+        for shape in (11, 13, 14, 15, 16):
             P.set_tti_shape(shape)
             out[shape] = P.fwi_gradient_tti(*args, fused=True)
             torch.cuda.synchronize()
     finally:
-        P.set_tti_shape(15)  # the default
-    for shape in (13, 14, 15):
+        P.set_tti_shape(16)  # the default
+    for shape in (13, 14, 15, 16):
         for k in ("resid", "Ubar", "grad"):
             assert torch.equal(out[shape][k], out[11][k]), (shape, k)
-    say("  TTI shapes 13-15 equal shape 11 bit for bit (resid, Ubar, grad)")
+    say("  TTI shapes 13-16 equal shape 11 bit for bit (resid, Ubar, grad)")
