@@ -153,15 +153,17 @@ void rtm_set_stencil_alternate(int32_t on);
  * Same results. */
 void rtm_set_probe_nt(int32_t on);
 /* Tuning hook, process wide: the workgroups (4 waves, one 32-cell tile per
- * wave at a time; each wave strides over the remaining tiles) of one
- * probe-GEMM launch, for the kernels that update a compressed field in place
- * (forward, unfused adjoint) and for the fused adjoint imaging kernel.  -1
- * (default): update kernels of blocks of at most 32 steps take one
- * workgroup per four tiles (no stride); the others are sized so that each
- * wave takes 6 tiles per 16 steps of the block (update) or 48 tiles (fused),
- * with at least 2048 workgroups (or one per four tiles on small grids).  0:
- * no stride; > 0: at most that many workgroups.  Same results (every tile's arithmetic is the
- * same). */
+ * wave at a time) of one probe-GEMM launch, for the kernels that update a
+ * compressed field in place (forward, unfused adjoint) and for the fused
+ * adjoint imaging kernel.  -1 (default, automatic): update kernels of blocks
+ * of at most 32 steps take one workgroup per four tiles (no stride), those of
+ * longer blocks in single-shot sweeps take tiles in order from a work-queue
+ * counter in the plan's workspace; the fused kernel (and longer blocks
+ * elsewhere) is sized so that each wave strides over 48 tiles (6 per 16
+ * steps of the block for update kernels), with at least 2048 workgroups (or
+ * one per four tiles on small grids).  -2: work queue where the sweep has a
+ * counter; 0: no stride; > 0: at most that many workgroups, striding.  Same
+ * results (every tile's arithmetic is the same). */
 void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_workgroups_fused);
 /* Tuning hook, process wide: with on != 0, fwi_gradient captures its launch
  * sequence (everything after the point-table upload) into a HIP graph the

@@ -236,8 +236,8 @@ def set_probe_nt(on: bool) -> None:
 
 def set_probe_grid(update: int, fused: int) -> None:
     """Workgroups of one probe-GEMM launch for the in-place update kernels and
-    for the fused adjoint imaging kernel: -1 automatic (default), 0 one per
-    four tiles, > 0 at most that many."""
+    for the fused adjoint imaging kernel: -1 automatic (default), -2 work
+    queue, 0 one per four tiles, > 0 at most that many."""
     _lib.load().rtm_set_probe_grid(int(update), int(fused))
 
 

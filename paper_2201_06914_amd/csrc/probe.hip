@@ -248,6 +248,12 @@ __device__ __forceinline__ void stb(T *p, T v) {
   else *p = v;
 }
 
+constexpr int kQueueChunk = 4;  // tiles per work-queue grab
+
+__global__ void k_queue_reset(int *q) {
+  if (threadIdx.x == 0) *q = 0;
+}
+
 template <int KS, int OP, int MODE, bool FUSED, int MTC, bool QF, bool NTB = false>
 __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
                                                          const void *__restrict__ Z, int MT,
@@ -262,8 +268,18 @@ __global__ __launch_bounds__(256) void k_probe_mfma_fast(ProbeArgs<float> p,
   const int col = lane & 31;
   const int half = lane >> 5;
   const int loff = half * 4 * 32 + col;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tile_end;
-       tile += (int64_t)gridDim.x * 4) {
+  // tiles: each wave strides over them, or (p.queue) takes chunks of kQueueChunk
+  // consecutive tiles from a counter, so the tiles in flight stay in one band
+  // that moves through the field in order; every wave leaves once a chunk
+  // starts past tile_end
+  auto grab = [&]() -> int64_t {
+    int chunk = 0;
+    if (lane == 0) chunk = atomicAdd(p.queue, 1);
+    return (int64_t)__builtin_amdgcn_readfirstlane(chunk) * kQueueChunk;
+  };
+  for (int64_t tile = p.queue ? grab() : (int64_t)blockIdx.x * 4 + wave; tile < tile_end;
+       tile = p.queue ? (((tile + 1) % kQueueChunk) ? tile + 1 : grab())
+                      : tile + (int64_t)gridDim.x * 4) {
     const int64_t c = tile * 32 + col;
     const int64_t tbase = tile * (int64_t)p.r * 32;
     // short blocks: build every step chunk's operand once per tile; long
@@ -450,30 +466,35 @@ void set_probe_nt(int on) { g_probe_nt = on ? 1 : 0; }
 int get_probe_nt() { return g_probe_nt; }
 // process wide (rtm_set_probe_grid): the workgroups of one probe launch, for
 // the kernels that update a compressed field in place (forward, unfused
-// adjoint) and for the fused adjoint imaging kernel.  -1 (default): the update
-// kernels of blocks of at most 32 steps take one workgroup per four tiles (no
-// stride); the others are sized so that every wave takes 6 KS tiles (update)
-// or 48 (fused), with at least 2048 workgroups (or one per four tiles on small
-// grids).  0: no stride; > 0: at most that many workgroups.
+// adjoint) and for the fused adjoint imaging kernel.  -1 (default,
+// automatic): the update kernels of blocks of at most 32 steps take one
+// workgroup per four tiles (no stride), those of longer blocks take tiles in
+// order from a work queue in the sweep's workspace (2048 workgroups; without
+// a queue, as the fused kernel); the fused kernel is sized so that every wave
+// takes 48 tiles, with at least 2048 workgroups (or one per four tiles on
+// small grids).  -2: work queue; 0: no stride; > 0: at most that many
+// workgroups, striding.
 // Each workgroup first stages its probe block in LDS, a cost that grows with
-// the block length; the in-place update runs faster when the resident
-// workgroups stay on one band of tiles than when long-lived waves drift apart
-// over the field.  At 384 x 512 x 512, r = 128, per launch, on the two kinds
-// of 51.5 GB allocation seen (the physical placement of the compressed field
-// moves the striding kernels by 15 %, see the notes on placement):
-//   forward, k = 32:  no stride 20.1-20.5 ms on both; 12 tiles per wave 21.7 /
-//                     18.6 ms; 2048 workgroups 22.9 / 19.9 ms
-//   forward, k = 64:  24 tiles per wave 23.8 ms, 2048 workgroups 24.5 ms, no
-//                     stride 32.5 ms
-//   forward, k = 128: 48 tiles per wave 31.4 ms, 2048 workgroups 31.1 ms, no
-//                     stride 54.2 ms
-//   fused, k = 32 / 64 / 128: 48 tiles per wave 10.1 / 14.7 / 20.9 ms, 2048
-//                     workgroups 10.2-10.3 / 14.6-14.7 / 22.3 ms, no stride
-//                     12.7 / 15.4 / 21.8 ms
+// the block length; the in-place update runs faster when the tiles in flight
+// form one band that moves through the field in order than when long-lived
+// waves drift apart over it.  At 384 x 512 x 512, r = 128, per launch, on the
+// two kinds of 51.5 GB allocation seen (the physical placement of the
+// compressed field moves the striding kernels by 15 %, see the notes on
+// placement):
+//   forward, k = 32:  no stride 20.1-20.5 ms on both; work queue 21.1 ms;
+//                     12 tiles per wave 21.7 / 18.6 ms; 2048 workgroups
+//                     22.9 / 19.9 ms
+//   forward, k = 64:  work queue 21.2 ms, 24 tiles per wave 22.9-23.8 ms,
+//                     2048 workgroups 24.5 ms, no stride 32.5 ms
+//   forward, k = 128: work queue 28.4 ms, 48 tiles per wave 30.2-31.4 ms,
+//                     2048 workgroups 31.1 ms, no stride 54.2 ms
+//   fused, k = 32 / 128: 48 tiles per wave 10.1 / 20.9-25.0 ms, 2048
+//                     workgroups 10.2-10.3 / 22.3 ms, no stride 12.7 / 21.8 ms,
+//                     work queue 12.0 / 34.4 ms
 int g_probe_grid[2] = {-1, -1};
 void set_probe_grid(int cap_update, int cap_fused) {
-  g_probe_grid[0] = cap_update < 0 ? -1 : cap_update;
-  g_probe_grid[1] = cap_fused < 0 ? -1 : cap_fused;
+  g_probe_grid[0] = cap_update < -2 ? -1 : cap_update;
+  g_probe_grid[1] = cap_fused < -2 ? -1 : cap_fused;
 }
 int get_probe_grid(int fused) { return g_probe_grid[fused ? 1 : 0]; }
 
@@ -489,40 +510,52 @@ static void launch_probe_kernels(const ProbeArgs<float> &p, const void *Z, int M
   const size_t shm = sizeof(bf16x8) * (size_t)MT * KS * 64 * (QF ? 2 : 1);
   const int64_t ntiles = (p.N + 31) / 32;
   const int64_t nfull = p.N / 32;
-  auto grid_for = [](int64_t tiles) -> unsigned {
+  const int set = g_probe_grid[FUSED ? 1 : 0];
+  // automatic: update kernels of blocks of at most 32 steps take one workgroup
+  // per four tiles (no stride), those of longer blocks a work queue (when the
+  // sweep provides a counter); the fused kernel, and longer blocks without a
+  // counter, a fixed number of tiles per wave, with at least 2048 workgroups
+  const bool queue = p.queue && (set == -2 || (set == -1 && !FUSED && KS > 2));
+  auto grid_for = [set, queue](int64_t tiles) -> unsigned {
     const int64_t want = (tiles + 3) / 4;  // one workgroup per four tiles
-    const int set = g_probe_grid[FUSED ? 1 : 0];
     int64_t cap = set > 0 ? set : want;
-    if (set < 0 && (FUSED || KS > 2)) {  // automatic: a fixed number of tiles
-                                         // per wave, and no fewer than 2048
-                                         // workgroups (small grids: fill the chip)
+    if (queue) {
+      cap = 2048;  // the waves take the tiles in order from the counter
+    } else if (set < 0 && (FUSED || KS > 2)) {
       const int64_t tpw = FUSED ? 48 : 6 * KS;
       cap = (tiles + 4 * tpw - 1) / (4 * tpw);
-      if (cap < 2048) cap = 2048;
-    }  // automatic, in-place update with blocks of at most 32 steps: no stride
+      if (cap < 2048) cap = 2048;  // small grids: fill the chip
+    }
     if (cap > want) cap = want;
     return (unsigned)(cap > 0 ? cap : 1);
   };
+  // work queue (fast kernel only): reset the counter, then launch
+  ProbeArgs<float> pq = p;
+  if (queue) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, p.queue);
+  } else {
+    pq.queue = nullptr;
+  }
   // the fast kernel reads and writes whole 32-row tiles and whole 16-step chunks
   const bool fastk = p.kb == 16 * KS && p.r % 32 == 0;
   int64_t done = 0;
   if (fastk && nfull > 0 && MT % 4 == 0 && !FUSED) {
     if (g_probe_nt)
       hipLaunchKernelGGL((k_probe_mfma_fast<KS, OP, MODE, FUSED, 4, QF, true>),
-                         dim3(grid_for(nfull)), dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale,
+                         dim3(grid_for(nfull)), dim3(256), shm, st, pq, Z, MT, f.Uf, f.img, f.scale,
                          nfull);
     else
       hipLaunchKernelGGL((k_probe_mfma_fast<KS, OP, MODE, FUSED, 4, QF>), dim3(grid_for(nfull)),
-                         dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
+                         dim3(256), shm, st, pq, Z, MT, f.Uf, f.img, f.scale, nfull);
     done = nfull;
   } else if (fastk && nfull > 0 && MT % 2 == 0) {
     if (g_probe_nt)
       hipLaunchKernelGGL((k_probe_mfma_fast<KS, OP, MODE, FUSED, 2, QF, true>),
-                         dim3(grid_for(nfull)), dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale,
+                         dim3(grid_for(nfull)), dim3(256), shm, st, pq, Z, MT, f.Uf, f.img, f.scale,
                          nfull);
     else
       hipLaunchKernelGGL((k_probe_mfma_fast<KS, OP, MODE, FUSED, 2, QF>), dim3(grid_for(nfull)),
-                         dim3(256), shm, st, p, Z, MT, f.Uf, f.img, f.scale, nfull);
+                         dim3(256), shm, st, pq, Z, MT, f.Uf, f.img, f.scale, nfull);
     done = nfull;
   }
   if (done < ntiles)

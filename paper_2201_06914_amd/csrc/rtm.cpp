@@ -121,6 +121,7 @@ struct rtm_plan {
   int R = 0;
   size_t esz = 0;
   Region ring, red, status;  // status: the non-finite watch word (uint32)
+  Region queue;              // work-queue counter of the probe launches (int32)
   PointRegion src, rec;
   size_t tab_off = 0, tab_bytes = 0;
   size_t total = 0;
@@ -288,6 +289,7 @@ extern "C" rtm_status rtm_plan_create(const rtm_desc *desc, rtm_plan **out) {
   place(cur, p->ring, (size_t)p->R * p->ld * p->esz);
   place(cur, p->red, sizeof(double) * (kReduceBlocks + 8));
   place(cur, p->status, sizeof(uint32_t));
+  place(cur, p->queue, sizeof(int32_t));
   p->tab_off = cur;
   place_points(cur, p->src, d.nsrc, p->esz);
   place_points(cur, p->rec, d.nrec, p->esz);
@@ -545,6 +547,7 @@ static rtm_status run_sweep(const rtm_plan *P, const SweepIO &io, const PointTab
       p.bar = bar;
       p.inv_dt2 = (T)(1.0 / (d.dt * d.dt));
       p.mode = io.mode;
+      p.queue = reinterpret_cast<int *>(work + P->queue.off);
       if (io.sketch_Y) {
         ProbeArgs<T> ps = p;
         ps.mode = PROBE_UTT;
@@ -1411,6 +1414,7 @@ struct rtm_batch {
   std::vector<rtm_plan *> P;
   std::vector<size_t> ring_off;
   Region red, status, shots, io_fwd, io_adj, tiles;
+  Region queue;  // work-queue counter of the probe launches (int32)
   BatchPointRegion src, rec;
   size_t tab_off = 0, tab_bytes = 0, total = 0;
   std::vector<int4> tile_host;
@@ -1507,6 +1511,7 @@ extern "C" rtm_status rtm_batch_create(const rtm_desc *shots, int32_t nshots, rt
   }
   place(cur, b->red, sizeof(double) * (kReduceBlocks + 8) * nshots);
   place(cur, b->status, sizeof(uint32_t));
+  place(cur, b->queue, sizeof(int32_t));
   b->tab_off = cur;
   place(cur, b->shots, sizeof(ShotStep<float>) * nshots);
   place(cur, b->io_fwd, sizeof(ShotIO<float>) * nshots);
@@ -1634,6 +1639,7 @@ static rtm_status batch_enqueue(const rtm_batch *b, const rtm_shot_io *io, doubl
       p.bar = adj ? nullptr : static_cast<float *>(io[i].Ubar);
       p.inv_dt2 = (float)(1.0 / (d.dt * d.dt));
       p.mode = adj ? PROBE_NEW : PROBE_UTT;
+      p.queue = reinterpret_cast<int *>(w + b->queue.off);
       HIP_TRY(launch_probe_mfma(p, io[i].Z, false, probe_op(d.probe_dtype),
                                 adj ? static_cast<const float *>(io[i].Ubar) : nullptr,
                                 adj ? static_cast<float *>(io[i].grad) : nullptr,

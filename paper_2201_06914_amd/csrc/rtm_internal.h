@@ -107,6 +107,9 @@ struct ProbeArgs {
   T *bar;            // tile-major [ceil(N/32)][r][32]
   T inv_dt2;
   int mode;
+  // optional work-queue counter (device int) for the probe launches that hand
+  // out tiles in order; nullptr: each wave strides over the tiles
+  int *queue = nullptr;
 };
 
 // launchers (stream-ordered; return the launch status)

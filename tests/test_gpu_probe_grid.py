@@ -1,7 +1,8 @@
 """Grid caps of the probe-GEMM launches (rtm_set_probe_grid): every tile's
-arithmetic is the same whether a wave strides over many tiles or each
-workgroup takes four tiles and exits, so the compressed fields, the image
-and the gradient are equal bit for bit across caps."""
+arithmetic is the same whether a wave strides over many tiles, each
+workgroup takes four tiles and exits, or the waves take tiles from a work
+queue, so the compressed fields, the image and the gradient are equal bit
+for bit across caps."""
 import numpy as np
 import pytest
 import torch
@@ -26,7 +27,7 @@ def test_probe_grid_caps_give_identical_results(fused):
     out = {}
     try:
         # 8: every wave strides over ~90 tiles; 0: no stride; then the defaults
-        for caps in ((8, 8), (0, 0), (-1, -1), (2048, 2048)):
+        for caps in ((8, 8), (0, 0), (-1, -1), (2048, 2048), (-2, -2)):
             P.set_probe_grid(*caps)
             o = P.fwi_gradient(plan, m, wl.src_pos, q, wl.rec_pos, d_obs, Z, fused=fused)
             torch.cuda.synchronize()
@@ -40,4 +41,4 @@ def test_probe_grid_caps_give_identical_results(fused):
         if not fused:
             assert torch.equal(o["Vbar"], ref["Vbar"]), caps
         assert torch.equal(o["Ubar"], ref["Ubar"]), caps
-    say("  probe grid caps (8, 8), (0, 0), automatic, (2048, 2048): equal bit for bit")
+    say("  probe grid caps (8, 8), (0, 0), automatic, (2048, 2048), work queue: equal bit for bit")
