@@ -139,7 +139,7 @@ const char *rtm_status_str(rtm_status s);
  * chunks (of at least 16 planes) that give a launch this many workgroups of
  * 256 threads' worth (default 2048; a 512 thread shape aims at half as
  * many); a batch's tile table (made by rtm_batch_create) aims at twice as
- * many.  The TTI kernels aim at 2048. */
+ * many.  The TTI kernels have their own targets (rtm_set_tti_blocks). */
 void rtm_set_stencil_variant(int variant);
 void rtm_set_stencil_blocks(int32_t blocks);
 /* Tuning hook, process wide: with on != 0 (default) the tiled stencil of the
@@ -395,6 +395,11 @@ void rtm_set_exact_fused(int32_t on);
  * rtm_set_stencil_variant(0) forces the one-thread-per-cell TTI kernels
  * instead.  Results agree to rounding. */
 void rtm_set_tti_shape(int32_t shape);
+/* Tuning hook, process wide: the tiled TTI kernels split z into the fewest
+ * chunks (of at least 16 planes) that give a launch this many workgroups,
+ * for the forward step and for the transpose step (<= 0: the defaults, 2800
+ * and 1750). */
+void rtm_set_tti_blocks(int32_t forward, int32_t transpose);
 rtm_status fwi_gradient_exact(const rtm_plan *plan, const void *m, const double *src_pos,
                               const void *q, const double *rec_pos, const void *d_obs,
                               int32_t checkpoint_every, void *resid, void *grad, double *misfit,

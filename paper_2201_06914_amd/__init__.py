@@ -14,7 +14,7 @@ from .api import (Plan, PlanSpec, RtmError, bar_index, cfl_bound, fwi_gradient, 
                   fwi_gradient_exact, exact_workspace_bytes,
                   autotune_stencil, set_stencil_blocks, Batch,
                   rtm_tti_forward_probe, rtm_tti_adjoint_probe, fwi_gradient_tti,
-                  set_exact_fused, set_tti_shape, rf_workspace_bytes, rtm_sketch,
+                  set_exact_fused, set_tti_shape, set_tti_blocks, rf_workspace_bytes, rtm_sketch,
                   rtm_orthonormalize, fwi_gradient_rf, rtm_offset_gathers,
                   stream_status, rtm_forward_probe_range, fwi_gradient_noalloc,
                   rtm_residual, tti_spectral_radius, set_stencil_alternate,

@@ -24,7 +24,7 @@ EXPORTS = (
     "rtm_sketch", "rtm_orthonormalize", "fwi_gradient_rf", "rtm_offset_gathers",
     "rtm_stream_status", "rtm_forward_probe_range", "fwi_gradient_noalloc",
     "rtm_device_copy", "rtm_residual", "rtm_batch_stream_status", "rtm_tti_spectral_radius",
-    "rtm_set_stencil_alternate", "rtm_set_probe_nt", "rtm_set_probe_grid", "rtm_set_graph",
+    "rtm_set_stencil_alternate", "rtm_set_probe_nt", "rtm_set_probe_grid", "rtm_set_graph", "rtm_set_tti_blocks",
 )
 
 RTM_NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -129,6 +129,8 @@ def load() -> ctypes.CDLL:
     L.rtm_set_probe_nt.argtypes = [i32]
     L.rtm_set_probe_nt.restype = None
     L.rtm_set_probe_grid.argtypes = [i32, i32]
+    L.rtm_set_tti_blocks.argtypes = [i32, i32]
+    L.rtm_set_tti_blocks.restype = None
     L.rtm_set_probe_grid.restype = None
     L.rtm_set_graph.argtypes = [i32]
     L.rtm_set_graph.restype = None

@@ -695,6 +695,12 @@ def set_exact_fused(on: bool) -> None:
     _lib.load().rtm_set_exact_fused(1 if on else 0)
 
 
+def set_tti_blocks(forward: int, transpose: int) -> None:
+    """z-split targets (workgroups per launch) of the tiled TTI forward and
+    transpose steps (<= 0: the default)."""
+    _lib.load().rtm_set_tti_blocks(int(forward), int(transpose))
+
+
 def set_tti_shape(shape: int) -> None:
     _lib.load().rtm_set_tti_shape(int(shape))
 

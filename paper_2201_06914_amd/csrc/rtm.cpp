@@ -33,7 +33,12 @@ using namespace rtm;
 static thread_local std::string g_last_error;
 static int g_stencil_variant = -1;  // -1 auto, else kStencilSimple / a tiled variant id
 static int g_stencil_blocks = 2048; // tiled stencil: split z until this many workgroups
-static const int kTtiBlocks = 2048; // tiled TTI kernels: the same, fixed
+// tiled TTI kernels' z-split targets (forward, transpose).  At 300 x 400 x 400
+// the forward step (700 tiles, three workgroups per CU) is fastest with 4
+// chunks (650 us; 1 chunk 684-691 us), the transpose (350 tiles, one
+// workgroup per CU) with 5 (1110 us; 8 chunks 1129-1133 us, 4 chunks 1146 us):
+// chunk warm-up (8 planes each) against the last round's idle CUs
+static int g_tti_blocks[2] = {2800, 1750};
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
 static int g_tti_shape = 16;        // tiled TTI tile shape (1..16)
 static int g_stencil_alternate = 1; // sweeps: tiled stencil marches z up / down on alternate steps
@@ -204,6 +209,10 @@ extern "C" void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_wo
 extern "C" void rtm_set_graph(int32_t on) { g_graph = on ? 1 : 0; }
 
 extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 16) ? shape : 16; }
+extern "C" void rtm_set_tti_blocks(int32_t forward, int32_t transpose) {
+  g_tti_blocks[0] = forward > 0 ? forward : 2800;
+  g_tti_blocks[1] = transpose > 0 ? transpose : 1750;
+}
 
 extern "C" void rtm_set_stencil_blocks(int32_t blocks) {
   g_stencil_blocks = blocks > 0 ? blocks : 2048;
@@ -1874,7 +1883,7 @@ static rtm_status run_tti_sweep(const rtm_plan *P, const TtiIO &io, const PointT
     prof_begin(io.adjoint ? KT_TTI_ADJ : KT_TTI, s, st, &tl);
     HIP_TRY(launch_tti_step<T>(a, d.h, io.adjoint, coef, lv(ringP, s), lv(ringP, s - 1),
                                lv(ringQ, s), lv(ringQ, s - 1), pn, qn, g, shape,
-                               kTtiBlocks, st));
+                               g_tti_blocks[io.adjoint ? 1 : 0], st));
     prof_end(st, &tl);
     if (inj.ncell > 0 && vals) {
       HIP_TRY(launch_inject<T>(a, inj, vals + (int64_t)n * inj.npts, pn, st));
@@ -2102,7 +2111,7 @@ static rtm_status tti_rho_impl(const rtm_plan *P, const void *m, const void *ani
   HIP_TRY(launch_tti_coef<T>(static_cast<const T *>(aniso), N, coef, st));
   double *part = reinterpret_cast<double *>(w + P->red.off);
   HIP_TRY(tti_power_iteration<T>(a, P->d.h, P->d.dt, coef, ringP, ringQ, ringP + ld, ringQ + ld,
-                                 ringP + 2 * ld, ringQ + 2 * ld, g, shape, kTtiBlocks, iters,
+                                 ringP + 2 * ld, ringQ + 2 * ld, g, shape, g_tti_blocks[0], iters,
                                  (uint32_t)(seed ^ (seed >> 32)), part, st));
   double w2 = 0.0;
   HIP_TRY(hipMemcpyAsync(&w2, part + 1024, sizeof w2, hipMemcpyDeviceToHost, st));

@@ -1256,8 +1256,8 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
   for (; z < z1; ++z) step(z);
 }
 
-// grid of one tiled launch: (64 x ty) column tiles, z split in chunks until
-// target_blocks workgroups (chunks of at least 16 planes)
+// grid of one tiled launch: (64 x ty) column tiles, z split into the fewest
+// chunks (of at least 16 planes) that give target_blocks workgroups
 struct TtiGrid {
   int ntx, nty, nzc, zchunk;
 };
@@ -1265,8 +1265,11 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
   TtiGrid g;
   g.ntx = (nx + TX - 1) / TX;
   g.nty = (ny + ty - 1) / ty;
-  int nzc = 1;
-  while (g.ntx * g.nty * nzc < target_blocks && nz / (nzc * 2) >= 16) nzc *= 2;
+  const int tiles = g.ntx * g.nty;
+  int nzc = (target_blocks + tiles - 1) / tiles;
+  const int most = nz / 16 > 1 ? nz / 16 : 1;
+  if (nzc > most) nzc = most;
+  if (nzc < 1) nzc = 1;
   g.zchunk = (nz + nzc - 1) / nzc;
   g.nzc = (nz + g.zchunk - 1) / g.zchunk;
   return g;
