@@ -155,13 +155,13 @@ void rtm_set_probe_nt(int32_t on);
 /* Tuning hook, process wide: the workgroups (4 waves, one 32-cell tile per
  * wave at a time) of one probe-GEMM launch, for the kernels that update a
  * compressed field in place (forward, unfused adjoint) and for the fused
- * adjoint imaging kernel.  -1 (default, automatic): update kernels of blocks
- * of at most 32 steps take one workgroup per four tiles (no stride), those of
- * longer blocks in single-shot sweeps take tiles in order from a work-queue
- * counter in the plan's workspace; the fused kernel (and longer blocks
- * elsewhere) is sized so that each wave strides over 48 tiles (6 per 16
- * steps of the block for update kernels), with at least 2048 workgroups (or
- * one per four tiles on small grids).  -2: work queue where the sweep has a
+ * adjoint imaging kernel.  -1 (default, automatic): update kernels of +-1
+ * probes and blocks of at most 32 steps take one workgroup per four tiles
+ * (no stride), those of longer blocks in acoustic sweeps take tiles in order
+ * from a work-queue counter in the workspace; the fused kernel, real probes
+ * and longer blocks elsewhere are sized so that each wave strides over 48
+ * tiles (6 per 16 steps of the block for update kernels), with at least 2048
+ * workgroups (or one per four tiles on small grids).  -2: work queue where the sweep has a
  * counter; 0: no stride; > 0: at most that many workgroups, striding.  Same
  * results (every tile's arithmetic is the same). */
 void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_workgroups_fused);

@@ -467,8 +467,8 @@ int get_probe_nt() { return g_probe_nt; }
 // process wide (rtm_set_probe_grid): the workgroups of one probe launch, for
 // the kernels that update a compressed field in place (forward, unfused
 // adjoint) and for the fused adjoint imaging kernel.  -1 (default,
-// automatic): the update kernels of blocks of at most 32 steps take one
-// workgroup per four tiles (no stride), those of longer blocks take tiles in
+// automatic): the update kernels of +-1 probes and blocks of at most 32 steps
+// take one workgroup per four tiles (no stride), those of longer blocks take tiles in
 // order from a work queue in the sweep's workspace (2048 workgroups; without
 // a queue, as the fused kernel); the fused kernel is sized so that every wave
 // takes 48 tiles, with at least 2048 workgroups (or one per four tiles on
@@ -491,6 +491,9 @@ int get_probe_nt() { return g_probe_nt; }
 //   fused, k = 32 / 128: 48 tiles per wave 10.1 / 20.9-25.0 ms, 2048
 //                     workgroups 10.2-10.3 / 22.3 ms, no stride 12.7 / 21.8 ms,
 //                     work queue 12.0 / 34.4 ms
+// Real probes (range finder), forward, 300^3, r = 64, k = 32: 12 tiles per
+// wave (about 17.6K workgroups) 2.78-2.92 ms, no stride 3.2-4.0 ms, work
+// queue 3.2 ms.
 int g_probe_grid[2] = {-1, -1};
 void set_probe_grid(int cap_update, int cap_fused) {
   g_probe_grid[0] = cap_update < -2 ? -1 : cap_update;
@@ -511,17 +514,18 @@ static void launch_probe_kernels(const ProbeArgs<float> &p, const void *Z, int M
   const int64_t ntiles = (p.N + 31) / 32;
   const int64_t nfull = p.N / 32;
   const int set = g_probe_grid[FUSED ? 1 : 0];
-  // automatic: update kernels of blocks of at most 32 steps take one workgroup
-  // per four tiles (no stride), those of longer blocks a work queue (when the
-  // sweep provides a counter); the fused kernel, and longer blocks without a
-  // counter, a fixed number of tiles per wave, with at least 2048 workgroups
-  const bool queue = p.queue && (set == -2 || (set == -1 && !FUSED && KS > 2));
+  // automatic: update kernels of +-1 probes and blocks of at most 32 steps
+  // take one workgroup per four tiles (no stride), those of longer blocks a
+  // work queue (when the sweep provides a counter); the fused kernel, real
+  // probes (whose staging costs twice as much) and longer blocks without a
+  // counter a fixed number of tiles per wave, with at least 2048 workgroups
+  const bool queue = p.queue && (set == -2 || (set == -1 && !FUSED && !QF && KS > 2));
   auto grid_for = [set, queue](int64_t tiles) -> unsigned {
     const int64_t want = (tiles + 3) / 4;  // one workgroup per four tiles
     int64_t cap = set > 0 ? set : want;
     if (queue) {
       cap = 2048;  // the waves take the tiles in order from the counter
-    } else if (set < 0 && (FUSED || KS > 2)) {
+    } else if (set < 0 && (FUSED || QF || KS > 2)) {
       const int64_t tpw = FUSED ? 48 : 6 * KS;
       cap = (tiles + 4 * tpw - 1) / (4 * tpw);
       if (cap < 2048) cap = 2048;  // small grids: fill the chip
