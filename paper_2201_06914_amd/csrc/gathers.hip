@@ -67,7 +67,7 @@ struct GatherThread {
   bool comp;
   __device__ explicit GatherThread(const GatherArgs &a) {
     int b = blockIdx.x;
-    if ((a.nblk & 7) == 0) b = (b & 7) * (a.nblk >> 3) + (b >> 3);  // XCD-aware: a row's
+    b = xcd_block(b, a.nblk);  // XCD-aware: a row's
     const int row = b / a.nseg;                                       // segments share an L2
     xs = (b % a.nseg) * GX;
     rb = (int64_t)row * a.nx;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_offset_gathers_mfma(const float *__rest
   __shared__ __align__(16) float SB[BUFN + 64];
   __shared__ __align__(16) float SC[BUFN + 64];
   int blk = blockIdx.x;
-  if ((a.nblk & 7) == 0) blk = (blk & 7) * (a.nblk >> 3) + (blk >> 3);  // XCD-aware
+  blk = xcd_block(blk, a.nblk);  // XCD-aware
   const int seg = blk % a.nseg;
   const int64_t rb = (int64_t)(blk / a.nseg) * a.nx;
   const int a0 = seg * W;

@@ -240,4 +240,16 @@ constexpr int kStencilSimple = 0;
 constexpr int kStencilTiled = 1;     // first LDS-tiled variant
 constexpr int kStencilVariants = 13;  // last variant id
 
+// XCD-aware block order: hardware workgroup ids go round-robin over the 8
+// XCDs (id b to XCD b mod 8); XCD x receives ids x, x + 8, ... and this maps
+// them to one contiguous run of logical blocks, so that neighbouring tiles
+// (which share halo rows) run on the same XCD and meet in its L2.  A
+// bijection of [0, nblk) for any nblk.
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int x = b & 7;
+  int off = 0;
+  for (int j = 0; j < x; ++j) off += (nblk - j + 7) >> 3;
+  return off + (b >> 3);
+}
+
 }  // namespace rtm

@@ -336,7 +336,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_tiled(StepArgs<T> a, int 
   // XCDs; give each XCD a contiguous run of tiles so halo re-reads hit its L2.
   const int nblk = ntx * nty * nzc;
   int b = blockIdx.x;
-  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  b = xcd_block(b, nblk);
   const int bx = b % ntx;
   const int by = (b / ntx) % nty;
   const int bz = b / (ntx * nty);
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(TX *TYT) void k_stencil3d_batched(const ShotStep<T>
                                                                const int4 *__restrict__ tiles,
                                                                int ntiles, int s, int rev) {
   int b = blockIdx.x;
-  if ((ntiles & 7) == 0) b = (b & 7) * (ntiles >> 3) + (b >> 3);
+  b = xcd_block(b, ntiles);
   const int4 t = tiles[b];  // (shot, bx | by << 16, z0, z1)
   StepArgs<T> a = shots[t.x].a;
   const ShotStep<T> &sh = shots[t.x];

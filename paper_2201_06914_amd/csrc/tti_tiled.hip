@@ -184,7 +184,7 @@ __device__ __forceinline__ void block_of(int ntx, int nty, int nzc, int zchunk, 
                                          int &by, int &z0, int &z1) {
   const int nblk = ntx * nty * nzc;
   int b = blockIdx.x;
-  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  b = xcd_block(b, nblk);
   bx = b % ntx;
   by = (b / ntx) % nty;
   z0 = (b / (ntx * nty)) * zchunk;
