@@ -13,13 +13,17 @@ from gpu_util import dev, require_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("case", ["3d-f32-bf16x2-fused", "2d-f64"])
+@pytest.mark.parametrize("case", ["3d-f32-bf16x2-fused", "3d-f32-bf16x2-k64", "2d-f64"])
 def test_graph_replays_equal_eager(case):
+    """k64: 64-step blocks, whose forward probe launches take their tiles from a
+    work queue (a counter reset by a kernel before each launch)."""
     require_gpu()
     import paper_2201_06914_amd as P
     if case.startswith("3d"):
-        wl = synth.workload_small_3d(shape=(30, 26, 44), nt=70, r=16)
-        plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2")
+        k64 = case.endswith("k64")
+        wl = synth.workload_small_3d(shape=(30, 26, 44), nt=140 if k64 else 70,
+                                     r=32 if k64 else 16)
+        plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=64 if k64 else None)
         dt, fused = torch.float32, True
     else:
         wl = synth.workload_small_2d(shape=(40, 52), nt=90, r=8)
