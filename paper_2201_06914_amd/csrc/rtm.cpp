@@ -208,7 +208,9 @@ extern "C" void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_wo
 }
 extern "C" void rtm_set_graph(int32_t on) { g_graph = on ? 1 : 0; }
 
-extern "C" void rtm_set_tti_shape(int32_t shape) { g_tti_shape = (shape >= 1 && shape <= 16) ? shape : 16; }
+extern "C" void rtm_set_tti_shape(int32_t shape) {
+  g_tti_shape = (shape >= 1 && shape <= 16) ? shape : 16;
+}
 extern "C" void rtm_set_tti_blocks(int32_t forward, int32_t transpose) {
   g_tti_blocks[0] = forward > 0 ? forward : 2800;
   g_tti_blocks[1] = transpose > 0 ? transpose : 1750;

@@ -1280,7 +1280,7 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
 // FUSED: 1 = fused forward kernel, 2 = fused forward kernel with the LDS plane ring;
 // AFUSED: 1 = fused transpose kernel, 2 = fused transpose kernel with halo delay
 // queues in registers, 3 = in LDS; UA / UF: planes per loop trip of the
-// delay-queue / ring kernel (UF > 1 caps the ring kernel at 168 VGPRs, three
+// delay-queue / ring kernel (UF > 1 caps the FP32 ring kernel at 168 VGPRs, three
 // waves per SIMD: two planes per trip then spill 6 registers and run 639 us
 // against 666-672 us at 300 x 400 x 400; uncapped they need 176 and run at two
 // waves per SIMD, 802 us; three planes spill 17 and run 747 us)
@@ -1301,8 +1301,9 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
   }
   if constexpr (FUSED == 2) {
     if (!adjoint) {
-      hipLaunchKernelGGL((k_tti_ffused_ring<T, TYM, (UF > 1 ? 3 : 1), UF>), nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc,
-                         gm.zchunk);
+      constexpr int MINW = (UF > 1 && sizeof(T) == 4) ? 3 : 1;
+      hipLaunchKernelGGL((k_tti_ffused_ring<T, TYM, MINW, UF>), nm, bm, 0, st, t, gm.ntx, gm.nty,
+                         gm.nzc, gm.zchunk);
       return hipGetLastError();
     }
   }
