@@ -161,9 +161,9 @@ void rtm_set_probe_nt(int32_t on);
  * from a work-queue counter in the workspace; the fused kernel, real probes
  * and longer blocks elsewhere are sized so that each wave strides over 48
  * tiles (6 per 16 steps of the block for update kernels), with at least 2048
- * workgroups (or one per four tiles on small grids).  -2: work queue where the sweep has a
- * counter; 0: no stride; > 0: at most that many workgroups, striding.  Same
- * results (every tile's arithmetic is the same). */
+ * workgroups (or one per four tiles on small grids).  -2: work queue where
+ * the sweep has a counter; 0: no stride; > 0: at most that many workgroups,
+ * striding.  Same results (every tile's arithmetic is the same). */
 void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_workgroups_fused);
 /* Tuning hook, process wide: with on != 0, fwi_gradient captures its launch
  * sequence (everything after the point-table upload) into a HIP graph the
