@@ -13,17 +13,20 @@ from gpu_util import dev, require_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("fused", [True, False], ids=["fused", "separate"])
-def test_probe_grid_caps_give_identical_results(fused):
+@pytest.mark.parametrize("fused,probe,k", [(True, "bf16x2", 32), (False, "bf16x2", 32),
+                                           (True, "bf16x2", 64), (False, "bf16x2", 64),
+                                           (False, "f16s", 64), (True, "f16s", 32)])
+def test_probe_grid_caps_give_identical_results(fused, probe, k):
     require_gpu()
     import paper_2201_06914_amd as P
-    # 2880 full 32-cell tiles plus none ragged; r = 64 (two row-tile pairs)
-    wl = synth.workload_small_3d(shape=(40, 36, 64), nt=70, r=64)
-    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=32)
+    # 2880 full 32-cell tiles plus none ragged; r = 64 (two row-tile pairs);
+    # k = 64: the automatic launches of the forward blocks use the work queue
+    wl = synth.workload_small_3d(shape=(40, 36, 64), nt=140 if k == 64 else 70, r=64)
+    plan = P.Plan.for_workload(wl, field="f32", probe=probe, k_block=k)
     m, q, Z = dev(wl.m, torch.float32), dev(wl.q, torch.float32), dev(wl.Z, torch.int8)
     d_obs = dev(0.01 * np.random.default_rng(5).standard_normal((wl.nt, wl.rec_pos.shape[0])),
                 torch.float32)
-    say(f"case: probe grid caps, {wl.shape}, r={wl.r}, fused={fused}")
+    say(f"case: probe grid caps, {wl.shape}, r={wl.r}, k={k}, {probe}, fused={fused}")
     out = {}
     try:
         # 8: every wave strides over ~90 tiles; 0: no stride; then the defaults
