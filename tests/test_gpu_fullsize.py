@@ -54,16 +54,19 @@ def c2_truncated():
     return wl, idx, d_obs, Jo, go, f, a
 
 
-@pytest.mark.parametrize("fused", [False, True], ids=["separate-image", "fused-image"])
-def test_fullsize_layered_3d_gradient_truncated(c2_truncated, fused):
+@pytest.mark.parametrize("fused,k", [(False, 32), (True, 32), (True, 64)],
+                         ids=["separate-image", "fused-image", "fused-image-k64"])
+def test_fullsize_layered_3d_gradient_truncated(c2_truncated, fused, k):
     """fused=True is the benchmark's adjoint kernel (imaging folded into the
     probe blocks, Vbar never stored) at a size where each wave's grid-stride
-    loop visits many 32-cell tiles."""
+    loop visits many 32-cell tiles.  k = 64: one 64-step block, whose forward
+    probe launch takes its tiles from the work queue (the oracle's probed
+    gradient does not depend on the block length)."""
     wl, idx, d_obs, Jo, go, f, a = c2_truncated
     nt = wl.nt
-    say(f"case: full-size {wl.shape} nt={nt} r={wl.r} k={wl.k_block} bf16x2 fwi_gradient "
+    say(f"case: full-size {wl.shape} nt={nt} r={wl.r} k={k} bf16x2 fwi_gradient "
         f"fused={fused}")
-    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2")
+    plan = P.Plan.for_workload(wl, field="f32", probe="bf16x2", k_block=k)
     out = P.fwi_gradient(plan, dev(wl.m, torch.float32), wl.src_pos, dev(wl.q, torch.float32),
                          wl.rec_pos, dev(d_obs, torch.float32), dev(wl.Z, torch.int8),
                          fused=fused)
