@@ -117,14 +117,18 @@ def test_tti_gpu_dot_test_and_isotropic_limit():
     assert e < 1e-12
 
 
-def test_tti_f32_bf16x2_fused_gradient():
+@pytest.mark.parametrize("k", [16, 64])
+def test_tti_f32_bf16x2_fused_gradient(k):
+    """k = 64: one 64-step block and a 16-step one; the probe launches of the
+    64-step block stride over a fixed number of tiles per wave (the TTI sweeps
+    have no work-queue counter)."""
     wl, an = synth.workload_tti(shape=(30, 26, 36), nt=80, r=16, sigma=3.0, nb=5, f0=12.0,
                                 rec_stride=3)
     g = Grid.of(wl)
     d_obs = np.zeros((wl.nt, wl.rec_pos.shape[0]), dtype=np.float32)
     J, gp, _, _ = oracle.tti_probed_gradient(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos, d_obs,
                                              wl.Z)
-    plan = _plan(wl, "f32", "bf16x2")
+    plan = _plan(wl, "f32", "bf16x2", k_block=k)
     args = (plan, dev(wl.m, torch.float32), dev(an, torch.float32), wl.src_pos,
             dev(wl.q, torch.float32), wl.rec_pos, dev(d_obs, torch.float32),
             dev(wl.Z, torch.int8))
