@@ -558,7 +558,7 @@ def bench_tti(shape, nt: int, r: int, stride: int):
         if v:
             e["valu"] = v
         return e
-    kern = {"tti_forward": entry("k_tti_ffused_ring (forward step, LDS plane ring, 2 planes per "
+    kern = {"tti_forward": entry("k_tti_ffused_ring (forward step, LDS plane ring, 3 planes per "
                                  "loop trip)",
                                  "tti_ffused", f_us, f_n),
             "tti_transpose": entry("k_tti_afused_dq (transpose step, LDS halo queues, 3 planes "

@@ -389,9 +389,10 @@ void rtm_set_exact_fused(int32_t on);
  * step), on 4 and 8 rows; 11 and 12: as 9 with the transpose step keeping
  * its halo cells' values from the lead plane in register queues (no second
  * load), on 8 and 4 rows; 13, 14 and 15: as 11 with those queues in a
- * per-thread LDS ring and 1, 2 or 3 planes per loop trip; 16 (default): as
- * 15 with the forward step carrying two planes per loop trip; other values
- * select 16.
+ * per-thread LDS ring and 1, 2 or 3 planes per loop trip; 16: as 15 with
+ * the forward step carrying two planes per loop trip; 17 (default): as 16
+ * with three planes per trip and each cell's own values loaded in its own
+ * iteration; other values select 17.
  * rtm_set_stencil_variant(0) forces the one-thread-per-cell TTI kernels
  * instead.  Results agree to rounding. */
 void rtm_set_tti_shape(int32_t shape);

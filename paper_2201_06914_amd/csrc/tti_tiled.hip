@@ -512,7 +512,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused(TtiArgs<T> t, int n
 // while a slower thread may still read slot z - 1 (its current plane) or
 // slot z + 3 (its lead plane); both differ from it.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, int MINW, int U = 1>
+template <typename T, int TY, int MINW, int U = 1, bool LC = false>
 __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, int ntx, int nty,
                                                                   int nzc, int zchunk) {
   using G = Geo<TY>;
@@ -531,12 +531,25 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, 
     Qq[k] = T(0);
     Xp[k] = Yp[k] = Xq[k] = Yq[k] = T(0);
   }
-  // prefetched values of the next iteration
+  // prefetched values of the next iteration (LC: the current cell's values
+  // are loaded at the start of their own iteration instead, so that one set
+  // of them is live rather than two)
   T fp, fq;                                      // lead interior
   T lyp[G::NHY], lyq[G::NHY], lxp, lxq, lcp, lcq; // lead halo and corners
   T pp, qp, mm, c1, c2, nz, ny, nx;              // current cell
   const bool corner = threadIdx.x >= G::NHX && threadIdx.x < G::NHX + 64;
-  auto fetch = [&](int z) {  // iteration z: lead plane z + 4, current cell at z
+  auto fetch_cur = [&](int z) {  // the current cell at z
+    const bool oc = z >= z0 && g.in;
+    pp = ldz(t.pp, a, oc, z, g.y, g.x);
+    qp = ldz(t.qp, a, oc, z, g.y, g.x);
+    mm = ldz(a.m, a, oc, z, g.y, g.x);
+    c1 = ldz(t.coef, a, oc, z, g.y, g.x);
+    c2 = ldz(t.coef + N, a, oc, z, g.y, g.x);
+    nz = ldz(t.coef + 2 * N, a, oc, z, g.y, g.x);
+    ny = ldz(t.coef + 3 * N, a, oc, z, g.y, g.x);
+    nx = ldz(t.coef + 4 * N, a, oc, z, g.y, g.x);
+  };
+  auto fetch = [&](int z) {  // iteration z: lead plane z + 4 (and the current cell at z)
     const int zl = z + 4;
     fp = ldz(t.p, a, g.in, zl, g.y, g.x);
     fq = ldz(t.q, a, g.in, zl, g.y, g.x);
@@ -549,15 +562,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, 
     lxq = ldz(t.q, a, g.hxon, zl, g.hxg_y, g.hxg_x);
     lcp = ldz(t.p, a, g.cnon, zl, g.cng_y, g.cng_x);
     lcq = ldz(t.q, a, g.cnon, zl, g.cng_y, g.cng_x);
-    const bool oc = z >= z0 && g.in;
-    pp = ldz(t.pp, a, oc, z, g.y, g.x);
-    qp = ldz(t.qp, a, oc, z, g.y, g.x);
-    mm = ldz(a.m, a, oc, z, g.y, g.x);
-    c1 = ldz(t.coef, a, oc, z, g.y, g.x);
-    c2 = ldz(t.coef + N, a, oc, z, g.y, g.x);
-    nz = ldz(t.coef + 2 * N, a, oc, z, g.y, g.x);
-    ny = ldz(t.coef + 3 * N, a, oc, z, g.y, g.x);
-    nx = ldz(t.coef + 4 * N, a, oc, z, g.y, g.x);
+    if constexpr (!LC) fetch_cur(z);
   };
   auto slot = [](int plane) { return (plane + 12 * NR) % NR; };  // plane >= z0 - 4 >= -4
   const int zs = z0 - 8;
@@ -566,6 +571,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_ffused_ring(TtiArgs<T> t, 
   // register renames (only the shifts across a trip remain moves)
   auto step = [&](int z) {
     const bool out = z >= z0;  // uniform over the workgroup
+    if constexpr (LC) fetch_cur(z);
     Qp[8] = fp;
     Qq[8] = fq;
     const T cpp = pp, cqp = qp, cm = mm, cc1 = c1, cc2 = c2, cnz = nz, cny = ny, cnx = nx;
@@ -1280,11 +1286,16 @@ static TtiGrid tti_grid(int nz, int ny, int nx, int ty, int target_blocks) {
 // FUSED: 1 = fused forward kernel, 2 = fused forward kernel with the LDS plane ring;
 // AFUSED: 1 = fused transpose kernel, 2 = fused transpose kernel with halo delay
 // queues in registers, 3 = in LDS; UA / UF: planes per loop trip of the
-// delay-queue / ring kernel (UF > 1 caps the FP32 ring kernel at 168 VGPRs, three
-// waves per SIMD: two planes per trip then spill 6 registers and run 639 us
-// against 666-672 us at 300 x 400 x 400; uncapped they need 176 and run at two
-// waves per SIMD, 802 us; three planes spill 17 and run 747 us)
-template <typename T, int TYP, int TYM, int FUSED = 0, int AFUSED = 0, int UA = 1, int UF = 1>
+// delay-queue / ring kernel (UF > 1 caps the FP32 ring kernel at 168 VGPRs,
+// three waves per SIMD; at 300 x 400 x 400: one plane per trip 666-672 us;
+// two planes 635 us, 1 spilled register; uncapped they need 176 VGPRs and run
+// at two waves per SIMD, 802 us); LC: the ring kernel loads each current
+// cell's eight values at the start of its own iteration instead of one
+// iteration ahead (one set live instead of two): two planes 625 us without
+// spills, three planes 610 us with 3 spilled registers (17 without LC, 747
+// us), four planes spill 21
+template <typename T, int TYP, int TYM, int FUSED = 0, int AFUSED = 0, int UA = 1, int UF = 1,
+          bool LC = false>
 static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_blocks,
                                  hipStream_t st) {
   const StepArgs<T> &a = t.a;
@@ -1302,7 +1313,7 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
   if constexpr (FUSED == 2) {
     if (!adjoint) {
       constexpr int MINW = (UF > 1 && sizeof(T) == 4) ? 3 : 1;
-      hipLaunchKernelGGL((k_tti_ffused_ring<T, TYM, MINW, UF>), nm, bm, 0, st, t, gm.ntx, gm.nty,
+      hipLaunchKernelGGL((k_tti_ffused_ring<T, TYM, MINW, UF, LC>), nm, bm, 0, st, t, gm.ntx, gm.nty,
                          gm.nzc, gm.zchunk);
       return hipGetLastError();
     }
@@ -1343,8 +1354,10 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 // forward kernel's LDS plane ring (forward on 4 / 8 rows), 11 / 12 = as 9 with
 // the transpose kernel's halo delay queues (transpose on 8 / 4 rows), 13 / 14 /
 // 15 = as 11 with the transpose kernel's halo queues in LDS and 1 / 2 / 3
-// planes per loop trip, 16 (the library's default) = as 15 with the forward
-// ring kernel carrying two planes per loop trip
+// planes per loop trip, 16 = as 15 with the forward ring kernel carrying two
+// planes per loop trip, 17 (the library's default) = as 16 with three planes
+// per trip and each current cell's values loaded at the start of its own
+// iteration
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -1374,6 +1387,8 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
                             : tti_step_tiled<T, 8, 4, 2, 1>(t, adjoint, target_blocks, st);
     case 16: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 3>(t, adjoint, target_blocks, st)
                             : tti_step_tiled<T, 8, 4, 2, 1, 1, 2>(t, adjoint, target_blocks, st);
+    case 17: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 3>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1, 1, 3, true>(t, adjoint, target_blocks, st);
     default: return tti_step_tiled<T, 8, 4, 1, 1>(t, adjoint, target_blocks, st);  // 6
   }
 }

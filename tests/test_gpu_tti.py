@@ -38,7 +38,7 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(16)  # the default
+    P.set_tti_shape(17)  # the default
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
@@ -52,7 +52,8 @@ def variant(request):
                                            ((-1, 12), (40, 21, 70)), ((-1, 13), (37, 21, 70)),
                                            ((-1, 14), (37, 21, 70)), ((-1, 15), (37, 21, 70)),
                                            ((-1, 15), (18, 16, 20)), ((-1, 16), (37, 21, 70)),
-                                           ((-1, 16), (18, 16, 20))],
+                                           ((-1, 16), (18, 16, 20)), ((-1, 17), (37, 21, 70)),
+                                           ((-1, 17), (18, 16, 20))],
                          indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
@@ -141,7 +142,7 @@ def test_tti_f32_bf16x2_fused_gradient(k):
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
 
 
-@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 15, 16])
+@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 15, 16, 17])
 def test_tti_f32_tiled_equals_simple_kernels(shape):
     """The tiled TTI step (mixed terms once per unordered pair, intermediates
     staged per plane) against the one-thread-per-cell step on the same FP32
@@ -166,7 +167,7 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
-            P.set_tti_shape(16)  # the default
+            P.set_tti_shape(17)  # the default
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
     say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
         " ".join(f"{k} {v:.2e}" for k, v in e.items()))
@@ -175,9 +176,9 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
 
 def test_tti_f32_lds_queue_kernels_equal_shape_11():
     """Shapes 13-15 keep the transpose's halo queues in LDS and carry 1-3
-    planes per loop trip, 16 also carries two planes per trip in the forward
-    step: the same arithmetic in the same order as shape 11, so the FP32
-    results are equal bit for bit.  (37, 27, 75):
+    planes per loop trip, 16 and 17 also carry two or three planes per trip in
+    the forward step: the same arithmetic in the same order as shape 11, so
+    the FP32 results are equal bit for bit.  (37, 27, 75):
     z-chunks of 27 and 26 planes with the warm-up, so the loops carrying 2 or 3
     planes per trip run their remainder in one chunk or both."""
     wl, an = synth.workload_tti(shape=(37, 27, 75), nt=70, r=32, sigma=3.0, nb=5, f0=12.0,
@@ -190,13 +191,13 @@ def test_tti_f32_lds_queue_kernels_equal_shape_11():
             dev(wl.Z, torch.int8))
     out = {}
     try:
-        for shape in (11, 13, 14, 15, 16):
+        for shape in (11, 13, 14, 15, 16, 17):
             P.set_tti_shape(shape)
             out[shape] = P.fwi_gradient_tti(*args, fused=True)
             torch.cuda.synchronize()
     finally:
-        P.set_tti_shape(16)  # the default
-    for shape in (13, 14, 15, 16):
+        P.set_tti_shape(17)  # the default
+    for shape in (13, 14, 15, 16, 17):
         for k in ("resid", "Ubar", "grad"):
             assert torch.equal(out[shape][k], out[11][k]), (shape, k)
-    say("  TTI shapes 13-16 equal shape 11 bit for bit (resid, Ubar, grad)")
+    say("  TTI shapes 13-17 equal shape 11 bit for bit (resid, Ubar, grad)")
