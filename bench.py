@@ -561,7 +561,8 @@ def bench_tti(shape, nt: int, r: int, stride: int):
     kern = {"tti_forward": entry("k_tti_ffused_ring (forward step, LDS plane ring, 3 planes per "
                                  "loop trip)",
                                  "tti_ffused", f_us, f_n),
-            "tti_transpose": entry("k_tti_afused_dq (transpose step, LDS halo queues, 3 planes "
+            "tti_transpose": entry("k_tti_afused_dq (transpose step, LDS halo queues, one "
+                                   "barrier per plane, p equation merged per axis, 6 planes "
                                    "per loop trip)", "tti_afused", a_us, a_n)}
     gbs = bpc * N / (avg_us * 1e-6) / 1e9
     return {"workload": f"TTI {shape[0]}x{shape[1]}x{shape[2]}, nt={nt}, r={r} on p and q, "

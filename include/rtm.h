@@ -390,9 +390,14 @@ void rtm_set_exact_fused(int32_t on);
  * its halo cells' values from the lead plane in register queues (no second
  * load), on 8 and 4 rows; 13, 14 and 15: as 11 with those queues in a
  * per-thread LDS ring and 1, 2 or 3 planes per loop trip; 16: as 15 with
- * the forward step carrying two planes per loop trip; 17 (default): as 16
- * with three planes per trip and each cell's own values loaded in its own
- * iteration; other values select 17.
+ * the forward step carrying two planes per loop trip; 17: as 16 with three
+ * planes per trip and each cell's own values loaded in its own iteration;
+ * 18: as 17 with one workgroup barrier per plane in the transpose step (each
+ * wave forms its own row's x-halo of D_y (n_x n_y w), the lead plane's LDS
+ * fields double buffered); 19, 20 and 21 (default): as 18 with the
+ * transpose's p equation summed as one second difference per axis of
+ * (1 - n_a^2) w1 (equal to the other forms up to rounding) and 3, 4 or 6
+ * planes per loop trip; other values select 21.
  * rtm_set_stencil_variant(0) forces the one-thread-per-cell TTI kernels
  * instead.  Results agree to rounding. */
 void rtm_set_tti_shape(int32_t shape);

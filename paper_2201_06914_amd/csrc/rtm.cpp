@@ -40,7 +40,7 @@ static int g_stencil_blocks = 2048; // tiled stencil: split z until this many wo
 // chunk warm-up (8 planes each) against the last round's idle CUs
 static int g_tti_blocks[2] = {2800, 1750};
 static int g_exact_fused = 1;       // exact comparator: fused stencil epilogues
-static int g_tti_shape = 17;        // tiled TTI tile shape (1..17)
+static int g_tti_shape = 21;        // tiled TTI tile shape (1..21)
 static int g_stencil_alternate = 1; // sweeps: tiled stencil marches z up / down on alternate steps
 static int g_graph = 0;             // fwi_gradient: capture and replay HIP graphs
 
@@ -209,7 +209,7 @@ extern "C" void rtm_set_probe_grid(int32_t max_workgroups_update, int32_t max_wo
 extern "C" void rtm_set_graph(int32_t on) { g_graph = on ? 1 : 0; }
 
 extern "C" void rtm_set_tti_shape(int32_t shape) {
-  g_tti_shape = (shape >= 1 && shape <= 17) ? shape : 17;
+  g_tti_shape = (shape >= 1 && shape <= 21) ? shape : 21;
 }
 extern "C" void rtm_set_tti_blocks(int32_t forward, int32_t transpose) {
   g_tti_blocks[0] = forward > 0 ? forward : 2800;

@@ -1031,8 +1031,20 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused(TtiArgs<T> t, int n
 // instead of registers; each thread reads back only what it wrote itself, so
 // the ring needs no barrier, and the 60 registers it frees let the loop
 // carry U planes per trip.
+// OBQ (with HLQ, FP32 only): one workgroup barrier per plane instead of two.
+// Each wave (one tile row) also forms D_y (n_x n_y w) at its own row's eight
+// x-halo columns, so the D_x of that product reads only what the wave itself
+// wrote (a wave-level fence, no barrier), and the lead plane's LDS fields are
+// double buffered: a wave may write plane z + 1's while another still reads
+// plane z's.
+// MG: the p equation's right side, Lap w1 - Hz w1, is taken as one sum over
+// the axes of D_aa ((1 - n_a^2) w1) (the second differences are linear), so
+// each axis needs one second difference of w1 instead of two, and w1 itself
+// leaves the LDS plane (six fields) and the z queues (its own cell's w1 waits
+// in a five-deep delay instead).  The arithmetic differs from the other forms
+// in rounding only.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, int MINW, int U, bool HLQ>
+template <typename T, int TY, int MINW, int U, bool HLQ, bool OBQ = false, bool MG = false>
 __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, int ntx, int nty,
                                                              int nzc, int zchunk) {
   using G = Geo<TY>;
@@ -1043,10 +1055,14 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
   // current plane: w1, n_x^2 w1, n_y^2 w1, n_x^2 w2, n_y^2 w2, n_x n_y w1, n_x n_y w2
   // (NB buffers: plane z writes buffer z & 1 while others may still read z - 1's)
   constexpr int NB = (sizeof(T) == 8 && TY == 8) ? 1 : 2;
-  __shared__ T LcB[NB][7][G::PL];
-  __shared__ T Ll[4][G::PL];      // lead plane: n_x n_z w1, n_x n_z w2, n_y n_z w1, n_y n_z w2
-  __shared__ T H[2][TY * G::LX];  // D_y (n_x n_y w1), D_y (n_x n_y w2)
+  // MG: (1 - n_x^2) w1, (1 - n_y^2) w1, n_x^2 w2, n_y^2 w2, n_x n_y w1, n_x n_y w2
+  constexpr int NF = MG ? 6 : 7, FX1 = MG ? 4 : 5, FX2 = MG ? 5 : 6;
+  __shared__ T LcB[NB][NF][G::PL];
   constexpr bool HL = HLQ && sizeof(T) == 4;
+  constexpr bool OB = OBQ && HL && NB == 2;
+  // lead plane: n_x n_z w1, n_x n_z w2, n_y n_z w1, n_y n_z w2
+  __shared__ T LlB[OB ? 2 : 1][4][G::PL];
+  __shared__ T H[2][TY * G::LX];  // D_y (n_x n_y w1), D_y (n_x n_y w2)
   typedef T V4 __attribute__((ext_vector_type(4)));  // (w1, w2, n_x, n_y) of a halo cell
   constexpr int NHQ = G::NHY * G::NTHR + 128;        // y halo, then x halo or corner
   __shared__ V4 Hq[HL ? 5 : 1][HL ? NHQ : 1];
@@ -1070,8 +1086,8 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
     c.nx = ldz(nxf, a, on, z, y, x);
     return c;
   };
-  T W[9], Z1[9], Z2[9], E1[9], E2[9];               // z queues
-  T Dw2[5], Dnx[5], Dny[5], Dlp[5], Dlq[5];         // delays: [4] lead plane, [0] plane z
+  T W[9], Z1[9], Z2[9], E1[9], E2[9];               // z queues (MG: W = (1 - n_z^2) w1)
+  T Dw1[5], Dw2[5], Dnx[5], Dny[5], Dlp[5], Dlq[5];  // delays: [4] lead plane, [0] plane z
   // the halo and corner cells' w1, w2, n_x, n_y, kept from the lead stage
   // until their plane is the current one (no second load of those cells)
   T Hy[G::NHY][4][5], Hx[4][5], Hc[4][5];
@@ -1079,7 +1095,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
   for (int k = 0; k < 9; ++k) W[k] = Z1[k] = Z2[k] = E1[k] = E2[k] = T(0);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    Dw2[k] = Dnx[k] = Dny[k] = Dlp[k] = Dlq[k] = T(0);
+    Dw1[k] = Dw2[k] = Dnx[k] = Dny[k] = Dlp[k] = Dlq[k] = T(0);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
 #pragma unroll
@@ -1106,6 +1122,15 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
   auto w2of = [](const In &c) { return c.c2 * c.lp + c.lq; };
   // current-plane LDS values of one cell (halo cells: LDS offset l)
   auto stage_cur = [&](T (*Lc)[G::PL], int l, T w1, T w2, T nx, T ny) {
+    if constexpr (MG) {
+      Lc[0][l] = (T(1) - nx * nx) * w1;
+      Lc[1][l] = (T(1) - ny * ny) * w1;
+      Lc[2][l] = (nx * nx) * w2;
+      Lc[3][l] = (ny * ny) * w2;
+      Lc[4][l] = (nx * ny) * w1;
+      Lc[5][l] = (nx * ny) * w2;
+      return;
+    }
     Lc[0][l] = w1;
     Lc[1][l] = (nx * nx) * w1;
     Lc[2][l] = (ny * ny) * w1;
@@ -1121,11 +1146,17 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
   auto step = [&](int z) {
     const bool out = z >= z0;  // uniform over the workgroup
     T(*Lc)[G::PL] = LcB[NB == 2 ? (z & 1) : 0];
+    T(*Ll)[G::PL] = LlB[OB ? (z & 1) : 0];
     // lead plane: queue fronts and LDS
     {
       const T w1 = w1of(li), w2 = w2of(li);
-      W[8] = w1;
-      Z1[8] = (li.nz * li.nz) * w1;
+      if constexpr (MG) {
+        W[8] = (T(1) - li.nz * li.nz) * w1;
+        Dw1[4] = w1;
+      } else {
+        W[8] = w1;
+        Z1[8] = (li.nz * li.nz) * w1;
+      }
       Z2[8] = (li.nz * li.nz) * w2;
       Dw2[4] = w2;
       Dnx[4] = li.nx;
@@ -1173,8 +1204,12 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
     }
     // current plane
     const T clpp = lpp, clqp = lqp, cm = mm;
+    // MG: the next plane's loads go out before the current plane is staged
+    if constexpr (MG) {
+      if (z + 1 < z1) fetch(z + 1);
+    }
     if (out) {
-      stage_cur(Lc, g.lc, W[4], Dw2[0], Dnx[0], Dny[0]);
+      stage_cur(Lc, g.lc, MG ? Dw1[0] : W[4], Dw2[0], Dnx[0], Dny[0]);
       if constexpr (HL) {
 #pragma unroll
         for (int k = 0; k < G::NHY; ++k) {
@@ -1193,32 +1228,59 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
         if (corner) stage_cur(Lc, g.cnl, Hc[0][0], Hc[1][0], Hc[2][0], Hc[3][0]);
       }
     }
-    if (z + 1 < z1) fetch(z + 1);
+    if constexpr (!MG) {
+      if (z + 1 < z1) fetch(z + 1);
+    }
     __syncthreads();
     E1[8] = d1l(t, Ll[0] + g.lc, 1) + d1l(t, Ll[2] + g.lc, G::LX);
     E2[8] = d1l(t, Ll[1] + g.lc, 1) + d1l(t, Ll[3] + g.lc, G::LX);
     if (out) {
       const int hr = threadIdx.x / TX, hc = threadIdx.x % TX + 4;
-      H[0][hr * G::LX + hc] = d1l(t, Lc[5] + g.lc, G::LX);
-      H[1][hr * G::LX + hc] = d1l(t, Lc[6] + g.lc, G::LX);
-      if (threadIdx.x < G::NHX) {
+      H[0][hr * G::LX + hc] = d1l(t, Lc[FX1] + g.lc, G::LX);
+      H[1][hr * G::LX + hc] = d1l(t, Lc[FX2] + g.lc, G::LX);
+      if constexpr (OB) {
+        // lanes 0..7: this row's x-halo columns 0..3 and TX + 4 .. TX + 7
+        const int lane = threadIdx.x % TX;
+        if (lane < 8) {
+          const int lcx = lane < 4 ? lane : TX + lane;
+          const int lo = (4 + hr) * G::LX + lcx;
+          H[0][hr * G::LX + lcx] = d1l(t, Lc[FX1] + lo, G::LX);
+          H[1][hr * G::LX + lcx] = d1l(t, Lc[FX2] + lo, G::LX);
+        }
+      } else if (threadIdx.x < G::NHX) {
         const int r = threadIdx.x / 8, lcx = g.hxl - (4 + r) * G::LX;
-        H[0][r * G::LX + lcx] = d1l(t, Lc[5] + g.hxl, G::LX);
-        H[1][r * G::LX + lcx] = d1l(t, Lc[6] + g.hxl, G::LX);
+        H[0][r * G::LX + lcx] = d1l(t, Lc[FX1] + g.hxl, G::LX);
+        H[1][r * G::LX + lcx] = d1l(t, Lc[FX2] + g.hxl, G::LX);
       }
     }
-    __syncthreads();
+    if constexpr (OB) {
+      // the row of H is written and read by this wave alone
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
     if (out && g.in) {
       const int hrow = (threadIdx.x / TX) * G::LX + threadIdx.x % TX + 4;
-      const T lw1 = (d2q(t, W) + d2l(t, Lc[0] + g.lc, G::LX)) + d2l(t, Lc[0] + g.lc, 1);
-      const T hz1 = ((d2q(t, Z1) + d2l(t, Lc[2] + g.lc, G::LX)) + d2l(t, Lc[1] + g.lc, 1)) +
-                    T(2) * (d1l(t, H[0] + hrow, 1) + d1q(t, E1));
-      const T hz2 = ((d2q(t, Z2) + d2l(t, Lc[4] + g.lc, G::LX)) + d2l(t, Lc[3] + g.lc, 1)) +
-                    T(2) * (d1l(t, H[1] + hrow, 1) + d1q(t, E2));
+      T rp, hz2;
+      if constexpr (MG) {
+        rp = ((d2q(t, W) + d2l(t, Lc[1] + g.lc, G::LX)) + d2l(t, Lc[0] + g.lc, 1)) -
+             T(2) * (d1l(t, H[0] + hrow, 1) + d1q(t, E1));
+        hz2 = ((d2q(t, Z2) + d2l(t, Lc[3] + g.lc, G::LX)) + d2l(t, Lc[2] + g.lc, 1)) +
+              T(2) * (d1l(t, H[1] + hrow, 1) + d1q(t, E2));
+      } else {
+        const T lw1 = (d2q(t, W) + d2l(t, Lc[0] + g.lc, G::LX)) + d2l(t, Lc[0] + g.lc, 1);
+        const T hz1 = ((d2q(t, Z1) + d2l(t, Lc[2] + g.lc, G::LX)) + d2l(t, Lc[1] + g.lc, 1)) +
+                      T(2) * (d1l(t, H[0] + hrow, 1) + d1q(t, E1));
+        hz2 = ((d2q(t, Z2) + d2l(t, Lc[4] + g.lc, G::LX)) + d2l(t, Lc[3] + g.lc, 1)) +
+              T(2) * (d1l(t, H[1] + hrow, 1) + d1q(t, E2));
+        rp = lw1 - hz1;
+      }
       const T damp = sponge_a(a, z, g.y, g.x);
       const uint32_t o = cidx(a, z, g.y, g.x);
       T pn, qn;
-      tti_update_pq(a, cm, damp, Dlp[0], clpp, lw1 - hz1, Dlq[0], clqp, hz2, pn, qn);
+      tti_update_pq(a, cm, damp, Dlp[0], clpp, rp, Dlq[0], clqp, hz2, pn, qn);
       sto(t.pn, o, pn);
       sto(t.qn, o, qn);
     }
@@ -1236,6 +1298,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+      Dw1[k] = Dw1[k + 1];
       Dw2[k] = Dw2[k + 1];
       Dnx[k] = Dnx[k + 1];
       Dny[k] = Dny[k + 1];
@@ -1325,10 +1388,10 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
       return hipGetLastError();
     }
   }
-  if constexpr (AFUSED == 2 || AFUSED == 3) {
+  if constexpr (AFUSED >= 2) {
     if (adjoint) {
-      hipLaunchKernelGGL((k_tti_afused_dq<T, TYM, 1, UA, AFUSED == 3>), nm, bm, 0, st, t, gm.ntx,
-                         gm.nty, gm.nzc, gm.zchunk);
+      hipLaunchKernelGGL((k_tti_afused_dq<T, TYM, 1, UA, AFUSED >= 3, AFUSED >= 4, AFUSED == 5>),
+                         nm, bm, 0, st, t, gm.ntx, gm.nty, gm.nzc, gm.zchunk);
       return hipGetLastError();
     }
   }
@@ -1355,9 +1418,14 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 // the transpose kernel's halo delay queues (transpose on 8 / 4 rows), 13 / 14 /
 // 15 = as 11 with the transpose kernel's halo queues in LDS and 1 / 2 / 3
 // planes per loop trip, 16 = as 15 with the forward ring kernel carrying two
-// planes per loop trip, 17 (the library's default) = as 16 with three planes
-// per trip and each current cell's values loaded at the start of its own
-// iteration
+// planes per loop trip, 17 = as 16 with three planes per trip and each
+// current cell's values loaded at the start of its own iteration (the forward
+// step of every later shape), 18 = as 17 with one workgroup barrier per plane
+// in the transpose, 19 / 20 / 21 (the library's default) = as 18 with the transpose's p equation
+// taken as one second difference per axis of (1 - n_a^2) w1 and 3 / 4 / 6
+// planes per loop trip in the transpose.  Transpose step at 300 x 400 x 400
+// (FP32): 17: 1111 us, 18: 1095 us, 19: 1047 us, 20: 1032 us, 21: 1022 us
+// (two and five planes per trip: 1047 and 1039 us)
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
@@ -1388,6 +1456,14 @@ hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, i
     case 16: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 3>(t, adjoint, target_blocks, st)
                             : tti_step_tiled<T, 8, 4, 2, 1, 1, 2>(t, adjoint, target_blocks, st);
     case 17: return adjoint ? tti_step_tiled<T, 8, 8, 1, 3, 3>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1, 1, 3, true>(t, adjoint, target_blocks, st);
+    case 18: return adjoint ? tti_step_tiled<T, 8, 8, 1, 4, 3>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1, 1, 3, true>(t, adjoint, target_blocks, st);
+    case 19: return adjoint ? tti_step_tiled<T, 8, 8, 1, 5, 3>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1, 1, 3, true>(t, adjoint, target_blocks, st);
+    case 20: return adjoint ? tti_step_tiled<T, 8, 8, 1, 5, 4>(t, adjoint, target_blocks, st)
+                            : tti_step_tiled<T, 8, 4, 2, 1, 1, 3, true>(t, adjoint, target_blocks, st);
+    case 21: return adjoint ? tti_step_tiled<T, 8, 8, 1, 5, 6>(t, adjoint, target_blocks, st)
                             : tti_step_tiled<T, 8, 4, 2, 1, 1, 3, true>(t, adjoint, target_blocks, st);
     default: return tti_step_tiled<T, 8, 4, 1, 1>(t, adjoint, target_blocks, st);  // 6
   }

@@ -38,7 +38,7 @@ def variant(request):
     P.set_tti_shape(sh)
     yield request.param
     P.set_stencil_variant(-1)
-    P.set_tti_shape(17)  # the default
+    P.set_tti_shape(21)  # the default
 
 
 @pytest.mark.parametrize("variant,shape", [((-1, 1), (18, 16, 20)), ((0, 1), (18, 16, 20)),
@@ -53,7 +53,9 @@ def variant(request):
                                            ((-1, 14), (37, 21, 70)), ((-1, 15), (37, 21, 70)),
                                            ((-1, 15), (18, 16, 20)), ((-1, 16), (37, 21, 70)),
                                            ((-1, 16), (18, 16, 20)), ((-1, 17), (37, 21, 70)),
-                                           ((-1, 17), (18, 16, 20))],
+                                           ((-1, 17), (18, 16, 20)), ((-1, 18), (37, 21, 70)),
+                                           ((-1, 19), (37, 21, 70)), ((-1, 19), (18, 16, 20)),
+                                           ((-1, 20), (37, 21, 70)), ((-1, 21), (37, 21, 70))],
                          indirect=["variant"])
 def test_tti_f64_forward_adjoint_gradient_match_oracle(variant, shape):
     """(40, 21, 70): two z-chunks, ragged tiles in x and y for the tiled kernels
@@ -142,7 +144,7 @@ def test_tti_f32_bf16x2_fused_gradient(k):
     assert e_f < 1e-3 and e_u < 1e-5 and e_J < 1e-5
 
 
-@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 15, 16, 17])
+@pytest.mark.parametrize("shape", [3, 4, 6, 7, 8, 9, 10, 11, 12, 13, 15, 16, 17, 18, 19, 20, 21])
 def test_tti_f32_tiled_equals_simple_kernels(shape):
     """The tiled TTI step (mixed terms once per unordered pair, intermediates
     staged per plane) against the one-thread-per-cell step on the same FP32
@@ -167,7 +169,7 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
             torch.cuda.synchronize()
         finally:
             P.set_stencil_variant(-1)
-            P.set_tti_shape(17)  # the default
+            P.set_tti_shape(21)  # the default
     e = {k: rel(host(out[-1][k]), host(out[0][k])) for k in ("resid", "Ubar", "Vbar", "grad")}
     say(f"  TTI tiled (shape {shape}) vs simple (f32): " +
         " ".join(f"{k} {v:.2e}" for k, v in e.items()))
@@ -177,7 +179,8 @@ def test_tti_f32_tiled_equals_simple_kernels(shape):
 def test_tti_f32_lds_queue_kernels_equal_shape_11():
     """Shapes 13-15 keep the transpose's halo queues in LDS and carry 1-3
     planes per loop trip, 16 and 17 also carry two or three planes per trip in
-    the forward step: the same arithmetic in the same order as shape 11, so
+    the forward step, 18 takes one workgroup barrier per plane in the
+    transpose: the same arithmetic in the same order as shape 11, so
     the FP32 results are equal bit for bit.  (37, 27, 75):
     z-chunks of 27 and 26 planes with the warm-up, so the loops carrying 2 or 3
     planes per trip run their remainder in one chunk or both."""
@@ -191,13 +194,54 @@ def test_tti_f32_lds_queue_kernels_equal_shape_11():
             dev(wl.Z, torch.int8))
     out = {}
     try:
-        for shape in (11, 13, 14, 15, 16, 17):
+        for shape in (11, 13, 14, 15, 16, 17, 18):
             P.set_tti_shape(shape)
             out[shape] = P.fwi_gradient_tti(*args, fused=True)
             torch.cuda.synchronize()
     finally:
-        P.set_tti_shape(17)  # the default
-    for shape in (13, 14, 15, 16, 17):
+        P.set_tti_shape(21)  # the default
+    for shape in (13, 14, 15, 16, 17, 18):
         for k in ("resid", "Ubar", "grad"):
             assert torch.equal(out[shape][k], out[11][k]), (shape, k)
-    say("  TTI shapes 13-17 equal shape 11 bit for bit (resid, Ubar, grad)")
+    say("  TTI shapes 13-18 equal shape 11 bit for bit (resid, Ubar, grad)")
+
+
+def test_tti_f32_merged_transpose_forms_agree():
+    """Shapes 19-21 sum the transpose's p equation as one second difference
+    per axis of (1 - n_a^2) w1 and carry 3, 4 or 6 planes per loop trip: equal
+    to each other bit for bit.  Against shape 18 (the same step with the
+    Laplacian and the H_z sum formed apart and subtracted) they differ by
+    rounding only, so both are held to the FP64 oracle's probed gradient on
+    the same probes, at the bar of the FP32 fused TTI gradient (1e-3; here
+    about 2.1e-4 merged and 1.3e-4 unmerged).  The forward step is shared, so
+    the data and Ubar agree exactly.  (37, 27, 75): z-chunks of 27 and 26
+    planes with the warm-up, so each loop runs a remainder."""
+    wl, an = synth.workload_tti(shape=(37, 27, 75), nt=70, r=32, sigma=3.0, nb=5, f0=12.0,
+                                rec_stride=4)
+    rng = np.random.default_rng(9)
+    d_obs = (0.05 * rng.standard_normal((wl.nt, wl.rec_pos.shape[0]))).astype(np.float32)
+    g = Grid.of(wl)
+    _, gp, _, _ = oracle.tti_probed_gradient(g, wl.m, an, wl.src_pos, wl.q, wl.rec_pos,
+                                             d_obs.astype(np.float64), wl.Z)
+    plan = _plan(wl, "f32", "bf16x2", k_block=32)
+    args = (plan, dev(wl.m, torch.float32), dev(an, torch.float32), wl.src_pos,
+            dev(wl.q, torch.float32), wl.rec_pos, dev(d_obs, torch.float32),
+            dev(wl.Z, torch.int8))
+    out = {}
+    try:
+        for shape in (18, 19, 20, 21):
+            P.set_tti_shape(shape)
+            out[shape] = P.fwi_gradient_tti(*args, fused=True)
+            torch.cuda.synchronize()
+    finally:
+        P.set_tti_shape(21)  # the default
+    for shape in (20, 21):
+        for k in ("resid", "Ubar", "grad"):
+            assert torch.equal(out[shape][k], out[19][k]), (shape, k)
+    assert torch.equal(out[19]["resid"], out[18]["resid"])
+    assert torch.equal(out[19]["Ubar"], out[18]["Ubar"])
+    e18, e19 = rel(host(out[18]["grad"]), gp), rel(host(out[19]["grad"]), gp)
+    e = rel(host(out[19]["grad"]), host(out[18]["grad"]))
+    say(f"  TTI shapes 19-21 equal bit for bit; vs the FP64 oracle: merged {e19:.2e}, "
+        f"unmerged {e18:.2e} (apart {e:.2e})")
+    assert e19 < 1e-3 and e18 < 1e-3
