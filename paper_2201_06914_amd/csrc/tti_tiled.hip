@@ -1103,15 +1103,19 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_tti_afused_dq(TtiArgs<T> t, in
       Hx[f][k] = Hc[f][k] = T(0);
     }
   }
-  In li, ly[G::NHY], lx, lc;
+  In li, ly[G::NHY], lx = {}, lc = {};
   T lpp, lqp, mm;
+  // the x-halo cells belong to the first NHX threads and the corners to the
+  // next 64: whole waves for 64 x 8 tiles, so the other waves skip their loads
+  constexpr bool WXH = G::NHX % 64 == 0;
+  const bool hasx = threadIdx.x < G::NHX, hasc = corner;
   auto fetch = [&](int z) {
     const int zl = z + 4;
     li = load(g.in, zl, g.y, g.x, true);
 #pragma unroll
     for (int k = 0; k < G::NHY; ++k) ly[k] = load(g.hyon[k], zl, g.hyg[k], g.x, true);
-    lx = load(g.hxon, zl, g.hxg_y, g.hxg_x, true);
-    lc = load(g.cnon, zl, g.cng_y, g.cng_x, false);
+    if (!WXH || hasx) lx = load(g.hxon, zl, g.hxg_y, g.hxg_x, true);
+    if (!WXH || hasc) lc = load(g.cnon, zl, g.cng_y, g.cng_x, false);
     const bool out = z >= z0;
     const bool oc = out && g.in;
     lpp = ldz(t.pp, a, oc, z, g.y, g.x);
@@ -1425,7 +1429,8 @@ static hipError_t tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int target_b
 // taken as one second difference per axis of (1 - n_a^2) w1 and 3 / 4 / 6
 // planes per loop trip in the transpose.  Transpose step at 300 x 400 x 400
 // (FP32): 17: 1111 us, 18: 1095 us, 19: 1047 us, 20: 1032 us, 21: 1022 us
-// (two and five planes per trip: 1047 and 1039 us)
+// (two and five planes per trip: 1047 and 1039 us); with the waves that hold
+// no x-halo or corner cell skipping those loads, 19: 992 us, 21: 967-972 us
 template <typename T>
 hipError_t launch_tti_step_tiled(const TtiArgs<T> &t, bool adjoint, int shape, int target_blocks,
                                  hipStream_t st) {
