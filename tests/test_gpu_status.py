@@ -1,7 +1,7 @@
-"""The non-finite watch word (rtm_stream_status) on the GPU: clean sweeps
-report OK; a NaN in the model, an infinity in the observed data or a NaN in
-the anisotropy reaches the checked values and is reported; the next clean
-call on the same workspace clears it."""
+"""The non-finite watch words (rtm_stream_status, rtm_batch_stream_status) on
+the GPU: clean sweeps report OK; a NaN in the model, an infinity in the
+observed data or a NaN in the anisotropy reaches the checked values and is
+reported; the next clean call on the same workspace clears it."""
 import numpy as np
 import pytest
 import torch
@@ -93,3 +93,41 @@ def test_unstable_run_is_flagged():
         res[tag] = P.stream_status(pl, work)
     say(f"  finite: {res}")
     assert res["honest"] and not res["c_max / 3"]
+
+
+def test_batched_nan_in_one_shot_flagged_then_cleared():
+    """The batched gradient's own watch word (rtm_batch_stream_status): clean
+    shots leave it clear; a NaN in one shot's model reaches that shot's
+    gradient and misfit and sets it; the next clean call on the same
+    workspace clears it again (with and without graph replay)."""
+    shapes = [(20, 18, 40), (24, 22, 33)]
+    wls = synth.workload_batched(nt=48, r=16, k_block=16, shapes=shapes)
+    shots, specs = [], []
+    for wl in wls:
+        wl.nb = 4
+        rec = wl.rec_pos[::7]
+        d_obs = np.zeros((wl.nt, rec.shape[0]), dtype=np.float32)
+        specs.append(P.PlanSpec(3, wl.shape, wl.h, wl.dt, wl.nt, wl.nb, wl.c_ref, wl.R, 4725.0,
+                                "f32", "bf16x2", wl.r, wl.k_block, 1, rec.shape[0]))
+        shots.append(dict(m=dev(wl.m, torch.float32), src_pos=wl.src_pos,
+                          q=dev(wl.q, torch.float32), rec_pos=rec,
+                          d_obs=dev(d_obs, torch.float32), Z=dev(wl.Z, torch.int8)))
+    B = P.Batch(specs)
+    work = torch.empty(B.workspace_bytes, dtype=torch.uint8, device="cuda")
+    res = {}
+    for graph in (False, True):
+        outs = B.outputs("cuda")
+        B.fwi_gradient(shots, outs=outs, work=work, use_graph=graph)
+        res[("clean", graph)] = B.stream_status(work)
+        good = shots[1]["m"].clone()
+        nz, ny, nx = shapes[1]
+        shots[1]["m"].view(nz, ny, nx)[nz // 2, ny // 2, nx // 2] = float("nan")
+        B.fwi_gradient(shots, outs=outs, work=work, use_graph=graph)
+        res[("nan", graph)] = B.stream_status(work)
+        shots[1]["m"].copy_(good)
+        B.fwi_gradient(shots, outs=outs, work=work, use_graph=graph)
+        res[("again", graph)] = B.stream_status(work)
+    say("  batched watch word: " + ", ".join(f"{k[0]}{'/graph' if k[1] else ''} {v}"
+                                              for k, v in res.items()))
+    for graph in (False, True):
+        assert res[("clean", graph)] and not res[("nan", graph)] and res[("again", graph)]
